@@ -1,0 +1,223 @@
+/*
+ * gspm.h -- C ABI of the MI355X (gfx950) differentiable Gaussian pointmap rasterizer.
+ *
+ * The library renders a set of 3D Gaussians into V views (keyframes) and returns, per
+ * view, the composited colour (Sec. 3.1, Eq. 2), depth (Sec. 3.2.1, Eq. 3), alpha and
+ * the "3D Gaussian pointmap" (the alpha-composited Gaussian centres, in the world or
+ * camera frame, or the depth back-projection of Sec. 3.2.1, Eq. 4-5).  Its backward
+ * pass returns gradients with respect to the Gaussian parameters (position, rotation,
+ * scale, opacity and colour, Sec. 3.1) and to each view's SE(3) pose through the
+ * projected means and covariances (Sec. 3.2.2, Eq. 11).  A per-patch least-squares
+ * scale aligns a prior pointmap to the rendered one (Sec. 3.3.1), and the mapping loss
+ * of Eq. 17 (photometric Eq. 10 + pointmap Eq. 15 terms) has a fused gradient kernel.
+ *
+ * Conventions shared by every call:
+ *   - All arrays are float32 device memory unless marked "host".  Gaussian parameters
+ *     are planar structure-of-arrays: means[3][n], log_scales[3][n], quats[4][n]
+ *     (w, x, y, z, any norm), opacity_logit[n], rgb[3][n] (degree-0 colour, no
+ *     activation).  Activated values: scale = exp(log_scale), rotation = the unit
+ *     quaternion's matrix, opacity = sigmoid(logit).
+ *   - Poses T_cw are device [V][12], row-major 3x4 [R | t] mapping world to camera
+ *     (x right, y down, z forward).  Keeping them on the device lets a captured HIP
+ *     graph see pose updates made in place.
+ *   - Intrinsics are host structs.  Pixel (i, j) (i = column, j = row) is sampled at
+ *     exactly (i, j), as Eq. 4 writes it.
+ *   - Images of the V views are packed back to back in view order; view v starts at
+ *     pixel offset P_v = sum_{u < v} W_u H_u, so its planar channel c of a 3-channel
+ *     image sits at element 3 P_v + c H_v W_v + j W_v + i, and a 1-channel image at
+ *     P_v + j W_v + i.
+ *   - Every call is asynchronous on the given stream (a hipStream_t passed as void*;
+ *     NULL is the null stream).  Argument errors are detected on the host before any
+ *     launch and returned immediately; nothing is launched then.
+ *   - Ownership: the caller owns every input, output, gradient and frame-state buffer.
+ *     A context owns only scratch memory (sort buffers, per-record gradients, partial
+ *     sums); it grows that scratch with hipMalloc when a call needs more, so calls that
+ *     must not allocate (graph capture) should follow gspm_reserve with large enough
+ *     capacities.
+ *   - Gradient outputs are accumulated (+=), so one Gaussian set can be shared across
+ *     calls; the caller zeroes them.
+ *   - A context is not thread safe and its calls must be ordered on one stream.
+ */
+#ifndef GSPM_H
+#define GSPM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define GSPM_API __attribute__((visibility("default")))
+#else
+#define GSPM_API
+#endif
+
+typedef enum {
+    GSPM_OK = 0,
+    GSPM_ERR_INVALID_ARG = 1, /* a pointer, size or setting is out of range */
+    GSPM_ERR_CAPACITY = 2,    /* the tile-pair list did not fit the frame state */
+    GSPM_ERR_HIP = 3,         /* a HIP runtime call failed (message in gspm_last_error) */
+    GSPM_ERR_INTERNAL = 4
+} gspm_status;
+
+#define GSPM_MAX_VIEWS 32
+
+typedef struct gspm_ctx gspm_ctx;
+
+/* Gaussian set (device, planar SoA as described above). */
+typedef struct {
+    const float *means;
+    const float *log_scales;
+    const float *quats;
+    const float *opacity_logit;
+    const float *rgb;
+    int64_t n;
+} gspm_gaussians;
+
+/* Pinhole intrinsics of one view (host): K = [[fx, 0, cx], [0, fy, cy], [0, 0, 1]] (Eq. 4). */
+typedef struct {
+    int32_t width, height;
+    float fx, fy, cx, cy;
+} gspm_intrinsics;
+
+/* The window of views rendered by one call. */
+typedef struct {
+    int32_t n_views;              /* 1 .. GSPM_MAX_VIEWS */
+    const gspm_intrinsics *intr;  /* host [n_views] */
+    const float *T_cw;            /* device [n_views][12] */
+} gspm_views;
+
+/* Rasterizer settings.  The paper fixes none of these numerically; each one is the
+ * caller's choice.  Defaults used by the Python layer are given in brackets. */
+typedef struct {
+    int32_t tile;            /* tile edge in pixels: 8, 16 or 32 [16] */
+    int32_t sort_digit_bits; /* radix-sort digit width, 4..8 [8] */
+    int32_t pointmap_frame;  /* 0 world-frame composited centres, 1 camera frame,
+                                2 depth back-projection D K^-1 [i, j, 1]^T (Eq. 5) [1] */
+    int32_t reserved;
+    float near_z;            /* Gaussians with camera depth <= near_z are dropped [0.2] */
+    float alpha_min;         /* fragments with alpha < alpha_min are skipped [1/255] */
+    float alpha_max;         /* alpha is clamped to alpha_max [0.99] */
+    float t_min;             /* compositing stops before transmittance drops below t_min [1e-4] */
+    float eps2d;             /* low-pass added to the 2D covariance, px^2 [0.3] */
+    float jac_clamp;         /* x/z, y/z clamped to jac_clamp * half FOV in the Jacobian [1.3] */
+    float bg[3];             /* background colour added as T_final * bg [0] */
+} gspm_settings;
+
+/* Per-view packed output planes (device): rgb [3][H][W], depth [H][W] (Eq. 3, not
+ * normalised by alpha), alpha [H][W] = 1 - T_final, pointmap [3][H][W]. */
+typedef struct {
+    float *rgb;
+    float *depth;
+    float *alpha;
+    float *pointmap;
+} gspm_images;
+
+/* Same planes, read-only (forward outputs and upstream gradients of the backward). */
+typedef struct {
+    const float *rgb;
+    const float *depth;
+    const float *alpha;
+    const float *pointmap;
+} gspm_const_images;
+
+/* Gradient outputs (device, accumulated), same shapes as gspm_gaussians.  Any pointer
+ * may be NULL to skip that parameter. */
+typedef struct {
+    float *means;
+    float *log_scales;
+    float *quats;
+    float *opacity_logit;
+    float *rgb;
+} gspm_gaussian_grads;
+
+/* ---- context ----------------------------------------------------------------------- */
+
+GSPM_API gspm_status gspm_create(gspm_ctx **out);
+GSPM_API void gspm_destroy(gspm_ctx *ctx);
+
+/* Grow the context's scratch so that later calls with at most max_records
+ * Gaussian-view records (n * n_views), max_pairs tile pairs and max_tiles tiles
+ * allocate nothing.  Sizes never shrink. */
+GSPM_API gspm_status gspm_reserve(gspm_ctx *ctx, int64_t max_records, int64_t max_pairs, int64_t max_tiles);
+
+/* Bytes of the caller-owned frame state that carries everything the backward needs
+ * from its forward (projected records, sorted tile pairs, tile ranges, per-pixel
+ * transmittance and last fragment).  max_pairs bounds the tile-pair list. */
+GSPM_API int64_t gspm_frame_state_bytes(const gspm_views *views, int64_t n_gaussians, int64_t max_pairs,
+                               int32_t tile);
+
+/* ---- rendering (Sec. 3.1 Eq. 1-2, Sec. 3.2.1 Eq. 3-5) ------------------------------- */
+
+/* Render all views.  frame_state: device buffer of frame_state_bytes >=
+ * gspm_frame_state_bytes(views, g->n, max_pairs, s->tile), written by this call.
+ * If the views need more than max_pairs tile pairs the images are incomplete and the
+ * frame state records the overflow: gspm_frame_status then returns GSPM_ERR_CAPACITY
+ * with the number of pairs needed. */
+GSPM_API gspm_status gspm_render_forward(gspm_ctx *ctx, const gspm_gaussians *g, const gspm_views *views,
+                                const gspm_settings *s, const gspm_images *out, void *frame_state,
+                                int64_t frame_state_bytes, void *stream);
+
+/* Synchronise the stream and read the frame state's header: *pairs = tile pairs the
+ * forward produced (or needed).  Returns GSPM_ERR_CAPACITY on overflow. */
+GSPM_API gspm_status gspm_frame_status(const void *frame_state, void *stream, int64_t *pairs);
+
+/* ---- gradients (Sec. 3.1 parameters; Sec. 3.2.2 Eq. 11 pose) ------------------------ */
+
+/* Backward of gspm_render_forward for upstream gradients grad_out (same planes as the
+ * outputs; any plane may be NULL for zero).  fwd_out are the forward's outputs (rgb,
+ * depth, alpha and pointmap are read).  grads: accumulated parameter gradients.
+ * pose_grad: device [V][6] accumulated, or NULL; it is d L / d xi at xi = 0 for the
+ * left perturbation T_cw <- Exp(xi) T_cw, xi = (rho, phi) with the translation first. */
+GSPM_API gspm_status gspm_render_backward(gspm_ctx *ctx, const gspm_gaussians *g, const gspm_views *views,
+                                 const gspm_settings *s, const gspm_const_images *fwd_out,
+                                 const gspm_const_images *grad_out, const void *frame_state,
+                                 const gspm_gaussian_grads *grads, float *pose_grad, void *stream);
+
+/* Pose-only backward (Gaussians frozen, the tracking loop of Sec. 3.2.2): writes
+ * pose_grad [V][6] (accumulated) and skips the colour and opacity terms. */
+GSPM_API gspm_status gspm_pose_backward(gspm_ctx *ctx, const gspm_gaussians *g, const gspm_views *views,
+                               const gspm_settings *s, const gspm_const_images *fwd_out,
+                               const gspm_const_images *grad_out, const void *frame_state,
+                               float *pose_grad, void *stream);
+
+/* ---- patch scale and mapping loss (Sec. 3.3.1, Eq. 10, 15, 17) --------------------- */
+
+/* Per-patch least-squares scale aligning a prior pointmap Xp to the rendered one Xr:
+ * for every patch x patch block of every view (partial at the right/bottom border),
+ * scale = sum(Xr . Xp) / sum(|Xp|^2) over pixels with mask != 0 (mask NULL = all), or
+ * 1 when sum(|Xp|^2) = 0.  Xr, Xp: packed [3][H][W] per view; mask: packed [H][W] or
+ * NULL.  scale_out (float) and count_out (int32, may be NULL): per view
+ * [ceil(H/patch)][ceil(W/patch)], packed in view order. */
+GSPM_API gspm_status gspm_patch_scale_align(const gspm_views *views, const float *Xr, const float *Xp,
+                                   const float *mask, int32_t patch, float *scale_out,
+                                   int32_t *count_out, void *stream);
+
+/* Mapping loss of Eq. 17 without the isotropic term, per view k:
+ *   L_k = alpha * mean|rgb - rgb_target| + (1 - alpha) * mean|pm - s Xp|
+ * with s the per-patch scale of gspm_patch_scale_align computed in the same pass
+ * (between pm and Xp, held constant) and means over 3 H W elements.  Writes
+ * scale_out as above, loss_out [V] (device, overwritten), and the gradients
+ * grad_rgb, grad_pm (packed planes, overwritten; sign(0) = 0). */
+GSPM_API gspm_status gspm_window_loss(const gspm_views *views, const float *rgb, const float *rgb_target,
+                             const float *pm, const float *Xp, int32_t patch, float alpha,
+                             float *scale_out, float *loss_out, float *grad_rgb, float *grad_pm,
+                             void *stream);
+
+/* T_cw[v] <- Exp(xi[v]) T_cw[v] for every view (device arrays [V][12], [V][6]). */
+GSPM_API gspm_status gspm_pose_retract(int32_t n_views, float *T_cw, const float *xi, void *stream);
+
+/* ---- diagnostics -------------------------------------------------------------------- */
+
+/* Message of the last error on this thread ("" if none). */
+GSPM_API const char *gspm_last_error(void);
+
+/* Library version string. */
+GSPM_API const char *gspm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GSPM_H */

@@ -1,0 +1,417 @@
+// Host side of the C ABI declared in include/gspm.h: argument validation, scratch
+// management and the launch sequences of the forward, backward and loss calls.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+
+#include "gspm_common.h"
+
+using namespace gspm;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+gspm_status fail(gspm_status st, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+gspm_status fail(gspm_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+gspm_status hip_fail(hipError_t e, const char *where) {
+    return fail(GSPM_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+#define GSPM_HIP(call)                                  \
+    do {                                                \
+        hipError_t e_ = (call);                         \
+        if (e_ != hipSuccess) return hip_fail(e_, #call); \
+    } while (0)
+
+struct DevBuf {
+    void *p = nullptr;
+    int64_t bytes = 0;
+};
+
+hipError_t grow(DevBuf &b, int64_t bytes) {
+    if (bytes <= b.bytes) return hipSuccess;
+    if (b.p) {
+        hipError_t e = hipFree(b.p);
+        if (e != hipSuccess) return e;
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    bytes = align256(bytes > 256 ? bytes : 256);
+    hipError_t e = hipMalloc(&b.p, (size_t)bytes);
+    if (e != hipSuccess) return e;
+    b.bytes = bytes;
+    return hipSuccess;
+}
+
+bool finite_pos(float x) { return isfinite(x) && x > 0.0f; }
+
+}  // namespace
+
+struct gspm_ctx {
+    // Per record (n * V).
+    DevBuf counts, trect, dkey, dval, dkey_tmp, dval_tmp, dkey_s, dval_s, offsets, grad2d;
+    // Per pair (capacity).
+    DevBuf pkey, pval, pkey_tmp, pval_tmp, pkey_s;
+    // Small scratch.
+    DevBuf hist, scan_part, misc, pose_part;
+};
+
+namespace {
+
+struct Prepared {
+    ViewTable vt;
+    RasterSettings rs;
+    int64_t n_tiles, n_pixels, n_records;
+};
+
+gspm_status check_gaussians(const gspm_gaussians *g) {
+    if (!g) return fail(GSPM_ERR_INVALID_ARG, "gaussians is NULL");
+    if (g->n < 0) return fail(GSPM_ERR_INVALID_ARG, "n = %lld < 0", (long long)g->n);
+    if (g->n > 0 && (!g->means || !g->log_scales || !g->quats || !g->opacity_logit || !g->rgb))
+        return fail(GSPM_ERR_INVALID_ARG, "a Gaussian parameter pointer is NULL");
+    return GSPM_OK;
+}
+
+gspm_status build_views(const gspm_views *views, int32_t tile, ViewTable &vt, int64_t &n_tiles, int64_t &n_pixels) {
+    if (!views) return fail(GSPM_ERR_INVALID_ARG, "views is NULL");
+    if (views->n_views < 1 || views->n_views > GSPM_MAX_VIEWS)
+        return fail(GSPM_ERR_INVALID_ARG, "n_views = %d outside [1, %d]", views->n_views, GSPM_MAX_VIEWS);
+    if (!views->intr || !views->T_cw) return fail(GSPM_ERR_INVALID_ARG, "views->intr or views->T_cw is NULL");
+    memset(&vt, 0, sizeof(vt));
+    vt.n_views = views->n_views;
+    vt.tile = tile;
+    int64_t toff = 0, poff = 0;
+    for (int v = 0; v < views->n_views; ++v) {
+        const gspm_intrinsics &k = views->intr[v];
+        if (k.width <= 0 || k.height <= 0 || k.width > 16384 || k.height > 16384)
+            return fail(GSPM_ERR_INVALID_ARG, "view %d: size %dx%d outside [1, 16384]", v, k.width, k.height);
+        if (!finite_pos(k.fx) || !finite_pos(k.fy) || !isfinite(k.cx) || !isfinite(k.cy))
+            return fail(GSPM_ERR_INVALID_ARG, "view %d: intrinsics must be finite with fx, fy > 0", v);
+        vt.width[v] = k.width;
+        vt.height[v] = k.height;
+        vt.tiles_x[v] = (k.width + tile - 1) / tile;
+        vt.tile_off[v] = (int32_t)toff;
+        vt.pix_off[v] = poff;
+        vt.fx[v] = k.fx; vt.fy[v] = k.fy; vt.cx[v] = k.cx; vt.cy[v] = k.cy;
+        toff += (int64_t)vt.tiles_x[v] * ((k.height + tile - 1) / tile);
+        poff += (int64_t)k.width * k.height;
+    }
+    if (toff > (1ll << 30)) return fail(GSPM_ERR_INVALID_ARG, "too many tiles (%lld)", (long long)toff);
+    vt.tile_off[views->n_views] = (int32_t)toff;
+    vt.pix_off[views->n_views] = poff;
+    n_tiles = toff;
+    n_pixels = poff;
+    return GSPM_OK;
+}
+
+gspm_status prepare(const gspm_gaussians *g, const gspm_views *views, const gspm_settings *s, Prepared &P) {
+    gspm_status st = check_gaussians(g);
+    if (st) return st;
+    if (!s) return fail(GSPM_ERR_INVALID_ARG, "settings is NULL");
+    if (s->tile != 8 && s->tile != 16 && s->tile != 32)
+        return fail(GSPM_ERR_INVALID_ARG, "tile = %d, expected 8, 16 or 32", s->tile);
+    if (s->sort_digit_bits < 4 || s->sort_digit_bits > 8)
+        return fail(GSPM_ERR_INVALID_ARG, "sort_digit_bits = %d outside [4, 8]", s->sort_digit_bits);
+    if (s->pointmap_frame < 0 || s->pointmap_frame > 2)
+        return fail(GSPM_ERR_INVALID_ARG, "pointmap_frame = %d, expected 0, 1 or 2", s->pointmap_frame);
+    if (!(s->alpha_min > 0.0f && s->alpha_min < 1.0f) || !(s->alpha_max >= s->alpha_min && s->alpha_max < 1.0f))
+        return fail(GSPM_ERR_INVALID_ARG, "need 0 < alpha_min <= alpha_max < 1");
+    if (!(s->t_min > 0.0f && s->t_min < 1.0f)) return fail(GSPM_ERR_INVALID_ARG, "need 0 < t_min < 1");
+    if (!(s->near_z > 0.0f) || !isfinite(s->near_z)) return fail(GSPM_ERR_INVALID_ARG, "need near_z > 0");
+    if (!(s->eps2d >= 0.0f) || !isfinite(s->eps2d)) return fail(GSPM_ERR_INVALID_ARG, "need eps2d >= 0");
+    if (!(s->jac_clamp > 0.0f) || !isfinite(s->jac_clamp)) return fail(GSPM_ERR_INVALID_ARG, "need jac_clamp > 0");
+    for (int c = 0; c < 3; ++c)
+        if (!isfinite(s->bg[c])) return fail(GSPM_ERR_INVALID_ARG, "bg must be finite");
+    st = build_views(views, s->tile, P.vt, P.n_tiles, P.n_pixels);
+    if (st) return st;
+    P.n_records = g->n * views->n_views;
+    if (P.n_records >= (1ll << 31)) return fail(GSPM_ERR_INVALID_ARG, "n * n_views must be < 2^31");
+    P.rs.near_z = s->near_z;
+    P.rs.alpha_min = s->alpha_min;
+    P.rs.alpha_max = s->alpha_max;
+    P.rs.t_min = s->t_min;
+    P.rs.eps2d = s->eps2d;
+    P.rs.jac_clamp = s->jac_clamp;
+    P.rs.bg[0] = s->bg[0]; P.rs.bg[1] = s->bg[1]; P.rs.bg[2] = s->bg[2];
+    P.rs.frame = s->pointmap_frame;
+    return GSPM_OK;
+}
+
+int tile_bits(int64_t n_tiles) {
+    int b = 1;
+    while (b < 32 && ((int64_t)1 << b) < n_tiles) ++b;
+    return b;
+}
+
+hipError_t ensure_records(gspm_ctx *c, int64_t R, int digit_bits) {
+    const int64_t w = R > 0 ? R : 1;
+    hipError_t e;
+    if ((e = grow(c->counts, 4 * w))) return e;
+    if ((e = grow(c->trect, 8 * w))) return e;
+    if ((e = grow(c->dkey, 4 * w))) return e;
+    if ((e = grow(c->dval, 4 * w))) return e;
+    if ((e = grow(c->dkey_tmp, 4 * w))) return e;
+    if ((e = grow(c->dval_tmp, 4 * w))) return e;
+    if ((e = grow(c->dkey_s, 4 * w))) return e;
+    if ((e = grow(c->dval_s, 4 * w))) return e;
+    if ((e = grow(c->offsets, 4 * w))) return e;
+    if ((e = grow(c->hist, 4 * (radix_hist_words(w, digit_bits) + 1)))) return e;
+    if ((e = grow(c->scan_part, 4 * 1024))) return e;
+    if ((e = grow(c->misc, 256))) return e;
+    return hipSuccess;
+}
+
+hipError_t ensure_pairs(gspm_ctx *c, int64_t cap, int digit_bits) {
+    const int64_t w = cap > 0 ? cap : 1;
+    hipError_t e;
+    if ((e = grow(c->pkey, 4 * w))) return e;
+    if ((e = grow(c->pval, 4 * w))) return e;
+    if ((e = grow(c->pkey_tmp, 4 * w))) return e;
+    if ((e = grow(c->pval_tmp, 4 * w))) return e;
+    if ((e = grow(c->pkey_s, 4 * w))) return e;
+    if ((e = grow(c->hist, 4 * (radix_hist_words(w, digit_bits) + 1)))) return e;
+    return hipSuccess;
+}
+
+template <typename T>
+T *at(void *base, int64_t off) {
+    return reinterpret_cast<T *>(reinterpret_cast<char *>(base) + off);
+}
+template <typename T>
+const T *at(const void *base, int64_t off) {
+    return reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + off);
+}
+
+gspm_status backward_common(gspm_ctx *ctx, const gspm_gaussians *g, const gspm_views *views, const gspm_settings *s,
+                            const gspm_const_images *fwd_out, const gspm_const_images *grad_out,
+                            const void *frame_state, const gspm_gaussian_grads *grads, float *pose_grad,
+                            bool pose_only, void *stream) {
+    if (!ctx) return fail(GSPM_ERR_INVALID_ARG, "ctx is NULL");
+    Prepared P;
+    gspm_status st = prepare(g, views, s, P);
+    if (st) return st;
+    if (!frame_state) return fail(GSPM_ERR_INVALID_ARG, "frame_state is NULL");
+    if (!fwd_out || !fwd_out->rgb || !fwd_out->depth || !fwd_out->pointmap)
+        return fail(GSPM_ERR_INVALID_ARG, "forward outputs rgb, depth and pointmap are required");
+    if (!grad_out) return fail(GSPM_ERR_INVALID_ARG, "grad_out is NULL");
+    if (pose_only && !pose_grad) return fail(GSPM_ERR_INVALID_ARG, "pose_grad is NULL");
+    hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+    const FrameLayout L = frame_layout(P.n_tiles, P.n_pixels, P.n_records, 0);
+    const int64_t R = P.n_records;
+    GSPM_HIP(grow(ctx->grad2d, 4 * kG2 * (R > 0 ? R : 1)));
+    const int64_t nb = pose_partial_blocks(g->n);
+    GSPM_HIP(grow(ctx->pose_part, 8 * 6 * (nb > 0 ? nb : 1) * P.vt.n_views));
+    float *g2 = static_cast<float *>(ctx->grad2d.p);
+    GSPM_HIP(launch_fill_f32(g2, 0.0f, kG2 * R, hs));
+    GSPM_HIP(launch_raster_backward(P.vt, P.rs, at<uint2>(frame_state, L.ranges), at<uint32_t>(frame_state, L.pair_vals),
+                                    at<float>(frame_state, L.records), at<uint32_t>(frame_state, L.last),
+                                    at<float>(frame_state, L.t_final), *fwd_out, *grad_out, g2, pose_only, hs));
+    gspm_gaussian_grads none = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    const gspm_gaussian_grads &out = (pose_only || !grads) ? none : *grads;
+    GSPM_HIP(launch_preprocess_backward(*g, P.vt, views->T_cw, P.rs, g2, out, pose_grad != nullptr,
+                                        static_cast<double *>(ctx->pose_part.p), hs));
+    if (pose_grad)
+        GSPM_HIP(launch_pose_reduce(static_cast<double *>(ctx->pose_part.p), nb, P.vt.n_views, pose_grad, hs));
+    return GSPM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gspm_status gspm_create(gspm_ctx **out) {
+    if (!out) return fail(GSPM_ERR_INVALID_ARG, "out is NULL");
+    *out = new (std::nothrow) gspm_ctx();
+    if (!*out) return fail(GSPM_ERR_INTERNAL, "out of host memory");
+    return GSPM_OK;
+}
+
+void gspm_destroy(gspm_ctx *ctx) {
+    if (!ctx) return;
+    DevBuf *bufs[] = {&ctx->counts, &ctx->trect, &ctx->dkey, &ctx->dval, &ctx->dkey_tmp, &ctx->dval_tmp,
+                      &ctx->dkey_s, &ctx->dval_s, &ctx->offsets, &ctx->grad2d, &ctx->pkey, &ctx->pval,
+                      &ctx->pkey_tmp, &ctx->pval_tmp, &ctx->pkey_s, &ctx->hist, &ctx->scan_part, &ctx->misc,
+                      &ctx->pose_part};
+    for (DevBuf *b : bufs)
+        if (b->p) (void)hipFree(b->p);
+    delete ctx;
+}
+
+gspm_status gspm_reserve(gspm_ctx *ctx, int64_t max_records, int64_t max_pairs, int64_t max_tiles) {
+    if (!ctx) return fail(GSPM_ERR_INVALID_ARG, "ctx is NULL");
+    if (max_records < 0 || max_pairs < 0 || max_tiles < 0) return fail(GSPM_ERR_INVALID_ARG, "negative size");
+    if (max_pairs >= (1ll << 31) || max_records >= (1ll << 31))
+        return fail(GSPM_ERR_INVALID_ARG, "sizes must be < 2^31");
+    (void)max_tiles;
+    GSPM_HIP(ensure_records(ctx, max_records, 8));
+    GSPM_HIP(ensure_pairs(ctx, max_pairs, 8));
+    GSPM_HIP(grow(ctx->grad2d, 4 * kG2 * (max_records > 0 ? max_records : 1)));
+    return GSPM_OK;
+}
+
+int64_t gspm_frame_state_bytes(const gspm_views *views, int64_t n_gaussians, int64_t max_pairs, int32_t tile) {
+    if (tile != 8 && tile != 16 && tile != 32) {
+        fail(GSPM_ERR_INVALID_ARG, "tile = %d, expected 8, 16 or 32", tile);
+        return -1;
+    }
+    if (n_gaussians < 0 || max_pairs < 0) {
+        fail(GSPM_ERR_INVALID_ARG, "negative size");
+        return -1;
+    }
+    ViewTable vt;
+    int64_t nt, np;
+    if (build_views(views, tile, vt, nt, np) != GSPM_OK) return -1;
+    return frame_layout(nt, np, n_gaussians * views->n_views, max_pairs).total;
+}
+
+gspm_status gspm_render_forward(gspm_ctx *ctx, const gspm_gaussians *g, const gspm_views *views,
+                                const gspm_settings *s, const gspm_images *out, void *frame_state,
+                                int64_t frame_state_bytes, void *stream) {
+    if (!ctx) return fail(GSPM_ERR_INVALID_ARG, "ctx is NULL");
+    Prepared P;
+    gspm_status st = prepare(g, views, s, P);
+    if (st) return st;
+    if (!out || !out->rgb || !out->depth || !out->alpha || !out->pointmap)
+        return fail(GSPM_ERR_INVALID_ARG, "all four output planes are required");
+    if (!frame_state) return fail(GSPM_ERR_INVALID_ARG, "frame_state is NULL");
+    const FrameLayout L0 = frame_layout(P.n_tiles, P.n_pixels, P.n_records, 0);
+    if (frame_state_bytes < L0.total)
+        return fail(GSPM_ERR_INVALID_ARG, "frame_state_bytes = %lld < %lld (no room for pairs)",
+                    (long long)frame_state_bytes, (long long)L0.total);
+    int64_t cap = (frame_state_bytes - L0.pair_vals) / 4;
+    if (cap >= (1ll << 31)) cap = (1ll << 31) - 1;
+    hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+    const int db = s->sort_digit_bits;
+    const int64_t R = P.n_records;
+    GSPM_HIP(ensure_records(ctx, R, db));
+    GSPM_HIP(ensure_pairs(ctx, cap, db));
+
+    FrameHeader *hdr = at<FrameHeader>(frame_state, L0.header);
+    uint2 *ranges = at<uint2>(frame_state, L0.ranges);
+    float *records = at<float>(frame_state, L0.records);
+    uint32_t *pair_vals = at<uint32_t>(frame_state, L0.pair_vals);
+    uint32_t *total = static_cast<uint32_t *>(ctx->misc.p);
+    uint32_t *counts = static_cast<uint32_t *>(ctx->counts.p);
+    uint32_t *hist = static_cast<uint32_t *>(ctx->hist.p);
+    uint32_t *part = static_cast<uint32_t *>(ctx->scan_part.p);
+
+    // 1. Project every (Gaussian, view) record.
+    GSPM_HIP(launch_preprocess(*g, P.vt, views->T_cw, P.rs, records, counts, static_cast<uint32_t *>(ctx->trect.p),
+                               static_cast<uint32_t *>(ctx->dkey.p), static_cast<uint32_t *>(ctx->dval.p), hs));
+    if (R > 0) {
+        // 2. Order records by float32 depth (stable: ties keep record order).
+        GSPM_HIP(radix_sort(static_cast<uint32_t *>(ctx->dkey.p), static_cast<uint32_t *>(ctx->dval.p),
+                            static_cast<uint32_t *>(ctx->dkey_tmp.p), static_cast<uint32_t *>(ctx->dval_tmp.p),
+                            static_cast<uint32_t *>(ctx->dkey_s.p), static_cast<uint32_t *>(ctx->dval_s.p), R, nullptr,
+                            32, db, hist, part, hs));
+        // 3. Offsets of each record's tile pairs, in depth order.
+        GSPM_HIP(launch_scan_indirect(counts, static_cast<uint32_t *>(ctx->dval_s.p), R,
+                                      static_cast<uint32_t *>(ctx->offsets.p), total, part, hs));
+    } else {
+        GSPM_HIP(launch_fill_u32(total, 0u, 1, hs));
+    }
+    // 4. Emit (tile, record) pairs; the header gets the pair count and overflow flag.
+    GSPM_HIP(launch_fill_u32(reinterpret_cast<uint32_t *>(ranges), 0u, 2 * P.n_tiles, hs));
+    GSPM_HIP(launch_keygen(static_cast<uint32_t *>(ctx->dval_s.p), counts, static_cast<uint32_t *>(ctx->offsets.p),
+                           static_cast<uint32_t *>(ctx->trect.p), R, g->n > 0 ? g->n : 1, P.vt,
+                           static_cast<uint32_t *>(ctx->pkey.p), static_cast<uint32_t *>(ctx->pval.p), hdr,
+                           (uint32_t)cap, total, hs));
+    // 5. Stable sort by tile id; 6. per-tile ranges.
+    if (cap > 0) {
+        GSPM_HIP(radix_sort(static_cast<uint32_t *>(ctx->pkey.p), static_cast<uint32_t *>(ctx->pval.p),
+                            static_cast<uint32_t *>(ctx->pkey_tmp.p), static_cast<uint32_t *>(ctx->pval_tmp.p),
+                            static_cast<uint32_t *>(ctx->pkey_s.p), pair_vals, cap, &hdr->pairs,
+                            tile_bits(P.n_tiles), db, hist, part, hs));
+        GSPM_HIP(launch_ranges(static_cast<uint32_t *>(ctx->pkey_s.p), hdr, ranges, P.n_tiles, cap, hs));
+    }
+    // 7. Composite.
+    GSPM_HIP(launch_raster_forward(P.vt, P.rs, ranges, pair_vals, records, out->rgb, out->depth, out->alpha,
+                                   out->pointmap, at<float>(frame_state, L0.t_final), at<uint32_t>(frame_state, L0.last),
+                                   hs));
+    return GSPM_OK;
+}
+
+gspm_status gspm_frame_status(const void *frame_state, void *stream, int64_t *pairs) {
+    if (!frame_state) return fail(GSPM_ERR_INVALID_ARG, "frame_state is NULL");
+    hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+    GSPM_HIP(hipStreamSynchronize(hs));
+    FrameHeader h;
+    GSPM_HIP(hipMemcpy(&h, frame_state, sizeof(h), hipMemcpyDeviceToHost));
+    if (h.magic != kFrameMagic) return fail(GSPM_ERR_INVALID_ARG, "frame_state was not written by a forward");
+    if (pairs) *pairs = h.pairs;
+    if (h.overflow)
+        return fail(GSPM_ERR_CAPACITY, "tile pairs %u exceed the frame state's capacity %u", h.pairs, h.capacity);
+    return GSPM_OK;
+}
+
+gspm_status gspm_render_backward(gspm_ctx *ctx, const gspm_gaussians *g, const gspm_views *views,
+                                 const gspm_settings *s, const gspm_const_images *fwd_out,
+                                 const gspm_const_images *grad_out, const void *frame_state,
+                                 const gspm_gaussian_grads *grads, float *pose_grad, void *stream) {
+    if (!grads && !pose_grad) return fail(GSPM_ERR_INVALID_ARG, "nothing to compute: grads and pose_grad are NULL");
+    return backward_common(ctx, g, views, s, fwd_out, grad_out, frame_state, grads, pose_grad, false, stream);
+}
+
+gspm_status gspm_pose_backward(gspm_ctx *ctx, const gspm_gaussians *g, const gspm_views *views,
+                               const gspm_settings *s, const gspm_const_images *fwd_out,
+                               const gspm_const_images *grad_out, const void *frame_state, float *pose_grad,
+                               void *stream) {
+    return backward_common(ctx, g, views, s, fwd_out, grad_out, frame_state, nullptr, pose_grad, true, stream);
+}
+
+static gspm_status patch_common(const gspm_views *views, const float *Xr, const float *Xp, const float *mask,
+                                int32_t patch, const float *rgb, const float *rgb_target, float alpha,
+                                float *scale_out, int32_t *count_out, float *loss_out, float *grad_rgb,
+                                float *grad_pm, void *stream) {
+    ViewTable vt;
+    int64_t nt, np;
+    gspm_status st = build_views(views, 16, vt, nt, np);
+    if (st) return st;
+    if (patch < 1 || patch > 256) return fail(GSPM_ERR_INVALID_ARG, "patch = %d outside [1, 256]", patch);
+    if (!Xr || !Xp || !scale_out) return fail(GSPM_ERR_INVALID_ARG, "Xr, Xp and scale_out are required");
+    GSPM_HIP(launch_patch_loss(vt, Xr, Xp, mask, patch, rgb, rgb_target, alpha, scale_out, count_out, loss_out,
+                               grad_rgb, grad_pm, reinterpret_cast<hipStream_t>(stream)));
+    return GSPM_OK;
+}
+
+gspm_status gspm_patch_scale_align(const gspm_views *views, const float *Xr, const float *Xp, const float *mask,
+                                   int32_t patch, float *scale_out, int32_t *count_out, void *stream) {
+    return patch_common(views, Xr, Xp, mask, patch, nullptr, nullptr, 0.0f, scale_out, count_out, nullptr, nullptr,
+                        nullptr, stream);
+}
+
+gspm_status gspm_window_loss(const gspm_views *views, const float *rgb, const float *rgb_target, const float *pm,
+                             const float *Xp, int32_t patch, float alpha, float *scale_out, float *loss_out,
+                             float *grad_rgb, float *grad_pm, void *stream) {
+    if (!rgb || !rgb_target || !loss_out || !grad_rgb || !grad_pm)
+        return fail(GSPM_ERR_INVALID_ARG, "rgb, rgb_target, loss_out, grad_rgb and grad_pm are required");
+    if (!(alpha >= 0.0f && alpha <= 1.0f)) return fail(GSPM_ERR_INVALID_ARG, "alpha must lie in [0, 1]");
+    return patch_common(views, pm, Xp, nullptr, patch, rgb, rgb_target, alpha, scale_out, nullptr, loss_out,
+                        grad_rgb, grad_pm, stream);
+}
+
+gspm_status gspm_pose_retract(int32_t n_views, float *T_cw, const float *xi, void *stream) {
+    if (n_views < 1 || n_views > GSPM_MAX_VIEWS) return fail(GSPM_ERR_INVALID_ARG, "n_views out of range");
+    if (!T_cw || !xi) return fail(GSPM_ERR_INVALID_ARG, "T_cw and xi are required");
+    GSPM_HIP(launch_pose_retract(n_views, T_cw, xi, reinterpret_cast<hipStream_t>(stream)));
+    return GSPM_OK;
+}
+
+const char *gspm_last_error(void) { return g_last_error.c_str(); }
+
+const char *gspm_version(void) { return "gspm 0.1 gfx950"; }
+
+}  // extern "C"

@@ -1,0 +1,315 @@
+// Tile binning: exclusive scan of per-record tile counts, (tile, record) pair emission,
+// a stable LSD radix sort and per-tile ranges.
+//
+// Every Gaussian-view record is first sorted by its float32 camera depth (the paper
+// composites "sorted by z_k", Sec. 3.2.1, Eq. 3); pairs are then emitted in that order
+// and stably sorted by global tile id, so each tile's list comes out ordered by
+// (depth, record index) without ever carrying depth bits in the large pair sort.  The
+// pair count is only known on the device: all kernels after the scan read it from
+// device memory and use fixed grids, so the whole sequence can be captured in a graph.
+#include "gspm_common.h"
+
+namespace gspm {
+
+namespace {
+
+// ------------------------------- scan --------------------------------------------------
+
+constexpr int kScanBlock = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanBlock * kScanItems;
+
+__device__ inline uint32_t load_count(const uint32_t *counts, const uint32_t *idx, int64_t p) {
+    return idx ? counts[idx[p]] : counts[p];
+}
+
+// Block-wide exclusive scan of one value per thread; returns the prefix, *total the sum.
+__device__ inline uint32_t block_exclusive_scan(uint32_t x, uint32_t *lds, uint32_t &total) {
+    const int lane = lane_id(), wid = threadIdx.x / kWave;
+    const uint32_t inc = wave_inclusive_scan(x);
+    if (lane == kWave - 1) lds[wid] = inc;
+    __syncthreads();
+    uint32_t wave_base = 0, tot = 0;
+    for (int k = 0; k < kScanBlock / kWave; ++k) {
+        const uint32_t t = lds[k];
+        if (k < wid) wave_base += t;
+        tot += t;
+    }
+    __syncthreads();
+    total = tot;
+    return wave_base + inc - x;
+}
+
+__global__ void __launch_bounds__(kScanBlock)
+k_scan_reduce(const uint32_t *__restrict__ counts, const uint32_t *__restrict__ idx, int64_t n, int64_t chunk,
+              uint32_t *__restrict__ part) {
+    __shared__ uint32_t lds[kScanBlock / kWave];
+    const int64_t b0 = (int64_t)blockIdx.x * chunk;
+    const int64_t b1 = b0 + chunk < n ? b0 + chunk : n;
+    uint32_t acc = 0;
+    for (int64_t p = b0 + threadIdx.x; p < b1; p += kScanBlock) acc += load_count(counts, idx, p);
+    uint32_t tot;
+    block_exclusive_scan(acc, lds, tot);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(1024) k_scan_partials(uint32_t *part, int nb, uint32_t *total) {
+    __shared__ uint32_t lds[1024 / kWave];
+    const int t = threadIdx.x;
+    const uint32_t x = t < nb ? part[t] : 0u;
+    const int lane = lane_id(), wid = t / kWave;
+    const uint32_t inc = wave_inclusive_scan(x);
+    if (lane == kWave - 1) lds[wid] = inc;
+    __syncthreads();
+    uint32_t base = 0, tot = 0;
+    for (int k = 0; k < 1024 / kWave; ++k) {
+        if (k < wid) base += lds[k];
+        tot += lds[k];
+    }
+    if (t < nb) part[t] = base + inc - x;
+    if (t == 0) *total = tot;
+}
+
+__global__ void __launch_bounds__(kScanBlock)
+k_scan_apply(const uint32_t *__restrict__ counts, const uint32_t *__restrict__ idx, int64_t n, int64_t chunk,
+             const uint32_t *__restrict__ part, uint32_t *__restrict__ out) {
+    __shared__ uint32_t lds[kScanBlock / kWave];
+    const int64_t b0 = (int64_t)blockIdx.x * chunk;
+    const int64_t b1 = b0 + chunk < n ? b0 + chunk : n;
+    uint32_t running = part[blockIdx.x];
+    for (int64_t base = b0; base < b1; base += kScanTile) {
+        uint32_t v[kScanItems];
+        uint32_t sum = 0;
+        const int64_t p0 = base + (int64_t)threadIdx.x * kScanItems;
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            const int64_t p = p0 + k;
+            v[k] = p < b1 ? load_count(counts, idx, p) : 0u;
+            sum += v[k];
+        }
+        uint32_t tot;
+        uint32_t pre = running + block_exclusive_scan(sum, lds, tot);
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            const int64_t p = p0 + k;
+            if (p < b1) out[p] = pre;
+            pre += v[k];
+        }
+        running += tot;
+    }
+}
+
+// ------------------------------- radix sort -------------------------------------------
+
+constexpr int kSortBlock = 256;
+constexpr int kSortWaves = kSortBlock / kWave;
+
+__device__ inline void wave_range(int64_t n, int64_t nw, int64_t w, int64_t &b, int64_t &e) {
+    int64_t chunk = (n + nw - 1) / nw;
+    chunk = (chunk + kWave - 1) / kWave * kWave;
+    b = w * chunk;
+    e = b + chunk < n ? b + chunk : n;
+}
+
+template <int DB>
+__global__ void __launch_bounds__(kSortBlock)
+k_radix_upsweep(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ n_dev, int64_t n_max, int shift,
+                uint32_t *__restrict__ hist, int64_t nw) {
+    constexpr int R = 1 << DB;
+    __shared__ uint32_t cnt[kSortWaves][R];
+    const int wid = threadIdx.x / kWave, lane = lane_id();
+    for (int d = lane; d < R; d += kWave) cnt[wid][d] = 0u;
+    __syncthreads();
+    int64_t n = n_max;
+    if (n_dev) n = (int64_t)*n_dev < n_max ? (int64_t)*n_dev : n_max;
+    const int64_t w = (int64_t)blockIdx.x * kSortWaves + wid;
+    int64_t b, e;
+    wave_range(n, nw, w, b, e);
+    for (int64_t i = b + lane; i < e; i += kWave) {
+        const uint32_t d = (keys[i] >> shift) & (R - 1);
+        atomicAdd(&cnt[wid][d], 1u);
+    }
+    __syncthreads();
+    for (int d = lane; d < R; d += kWave) hist[(int64_t)d * nw + w] = cnt[wid][d];
+}
+
+template <int DB>
+__global__ void __launch_bounds__(kSortBlock)
+k_radix_downsweep(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
+                  uint32_t *__restrict__ vout, const uint32_t *__restrict__ n_dev, int64_t n_max, int shift,
+                  const uint32_t *__restrict__ hist, int64_t nw) {
+    constexpr int R = 1 << DB;
+    __shared__ uint32_t cnt[kSortWaves][R];
+    const int wid = threadIdx.x / kWave, lane = lane_id();
+    const int64_t w = (int64_t)blockIdx.x * kSortWaves + wid;
+    for (int d = lane; d < R; d += kWave) cnt[wid][d] = hist[(int64_t)d * nw + w];
+    __syncthreads();
+    int64_t n = n_max;
+    if (n_dev) n = (int64_t)*n_dev < n_max ? (int64_t)*n_dev : n_max;
+    int64_t b, e;
+    wave_range(n, nw, w, b, e);
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int64_t base = b; base < e; base += kWave) {
+        const int64_t i = base + lane;
+        const bool act = i < e;
+        const uint32_t k = act ? kin[i] : 0u;
+        const uint32_t val = act ? vin[i] : 0u;
+        const uint32_t d = (k >> shift) & (R - 1);
+        uint64_t m = __ballot(act);
+#pragma unroll
+        for (int bit = 0; bit < DB; ++bit) {
+            const bool set = (d >> bit) & 1u;
+            const uint64_t bb = __ballot(set);
+            m &= set ? bb : ~bb;
+        }
+        if (act) {
+            const uint32_t rank = (uint32_t)__popcll(m & lt);
+            const uint32_t base_d = cnt[wid][d];
+            const uint32_t pos = base_d + rank;
+            kout[pos] = k;
+            vout[pos] = val;
+            if (rank == 0) cnt[wid][d] = base_d + (uint32_t)__popcll(m);
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// ------------------------------- pairs and ranges -------------------------------------
+
+__global__ void __launch_bounds__(256)
+k_keygen(const uint32_t *__restrict__ sorted_rec, const uint32_t *__restrict__ counts,
+         const uint32_t *__restrict__ offsets, const uint32_t *__restrict__ trect, int64_t n_records,
+         int64_t n_per_view, ViewTable vt, uint32_t *__restrict__ pkey, uint32_t *__restrict__ pval,
+         FrameHeader *__restrict__ hdr, uint32_t cap, const uint32_t *__restrict__ total) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p == 0) {
+        const uint32_t t = *total;
+        hdr->pairs = t;
+        hdr->overflow = t > cap ? 1u : 0u;
+        hdr->capacity = cap;
+        hdr->magic = kFrameMagic;
+    }
+    if (p >= n_records) return;
+    const uint32_t r = sorted_rec[p];
+    const uint32_t c = counts[r];
+    if (c == 0) return;
+    const uint32_t o = offsets[p];
+    const int v = (int)(r / n_per_view);
+    const uint32_t rx = trect[2 * (int64_t)r], ry = trect[2 * (int64_t)r + 1];
+    const uint32_t x0 = rx & 0xffffu, x1 = rx >> 16, y0 = ry & 0xffffu, y1 = ry >> 16;
+    const uint32_t base = (uint32_t)vt.tile_off[v];
+    const uint32_t tx = (uint32_t)vt.tiles_x[v];
+    uint32_t k = o;
+    for (uint32_t y = y0; y <= y1; ++y)
+        for (uint32_t x = x0; x <= x1; ++x, ++k) {
+            if (k >= cap) return;
+            pkey[k] = base + y * tx + x;
+            pval[k] = r;
+        }
+}
+
+__global__ void __launch_bounds__(256)
+k_ranges(const uint32_t *__restrict__ keys, const FrameHeader *__restrict__ hdr, uint2 *__restrict__ ranges,
+         int64_t n_max) {
+    const int64_t n = (int64_t)hdr->pairs < n_max ? (int64_t)hdr->pairs : n_max;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t k = keys[i];
+        if (i == 0 || keys[i - 1] != k) ranges[k].x = (uint32_t)i;
+        if (i == n - 1 || keys[i + 1] != k) ranges[k].y = (uint32_t)(i + 1);
+    }
+}
+
+}  // namespace
+
+// ------------------------------- host wrappers ----------------------------------------
+
+static int64_t scan_blocks(int64_t n) {
+    int64_t nb = (n + kScanTile - 1) / kScanTile;
+    if (nb > 1024) nb = 1024;
+    return nb < 1 ? 1 : nb;
+}
+
+int64_t scan_partials(int64_t n) { return scan_blocks(n); }
+
+hipError_t launch_scan_indirect(const uint32_t *counts, const uint32_t *idx, int64_t n, uint32_t *offsets,
+                                uint32_t *total, uint32_t *part, hipStream_t s) {
+    const int64_t nb = scan_blocks(n);
+    const int64_t chunk = (n + nb - 1) / nb;
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanBlock), 0, s, counts, idx, n, chunk, part);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, part, (int)nb, total);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kScanBlock), 0, s, counts, idx, n, chunk, part,
+                       offsets);
+    return hipGetLastError();
+}
+
+static int64_t sort_blocks(int64_t n_max) {
+    // About 16 steps of 64 keys per wave at capacity, between 1 and 1024 blocks.
+    int64_t nb = (n_max + kSortBlock * 16 - 1) / (kSortBlock * 16);
+    if (nb > 1024) nb = 1024;
+    return nb < 1 ? 1 : nb;
+}
+
+int64_t radix_hist_words(int64_t n_max, int digit_bits) {
+    return ((int64_t)1 << digit_bits) * sort_blocks(n_max) * kSortWaves;
+}
+
+template <int DB>
+static void sort_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, int64_t n_max,
+                      const uint32_t *n_dev, int shift, uint32_t *hist, uint32_t *scan_part, hipStream_t s) {
+    const int64_t nb = sort_blocks(n_max);
+    const int64_t nw = nb * kSortWaves;
+    hipLaunchKernelGGL(k_radix_upsweep<DB>, dim3((unsigned)nb), dim3(kSortBlock), 0, s, kin, n_dev, n_max, shift,
+                       hist, nw);
+    const int64_t hw = ((int64_t)1 << DB) * nw;
+    (void)launch_scan_indirect(hist, nullptr, hw, hist, hist + hw, scan_part, s);
+    hipLaunchKernelGGL(k_radix_downsweep<DB>, dim3((unsigned)nb), dim3(kSortBlock), 0, s, kin, vin, kout, vout,
+                       n_dev, n_max, shift, hist, nw);
+}
+
+hipError_t radix_sort(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_tmp, uint32_t *vals_tmp,
+                      uint32_t *keys_out, uint32_t *vals_out, int64_t n_max, const uint32_t *n_dev, int bits,
+                      int digit_bits, uint32_t *hist, uint32_t *scan_part, hipStream_t s) {
+    if (n_max <= 0) return hipSuccess;
+    if (bits < 1) bits = 1;
+    const int passes = (bits + digit_bits - 1) / digit_bits;
+    const uint32_t *kin = keys_in, *vin = vals_in;
+    for (int p = 0; p < passes; ++p) {
+        // The last pass writes to *_out; earlier passes alternate so that this holds.
+        const bool to_out = ((passes - 1 - p) % 2) == 0;
+        uint32_t *ko = to_out ? keys_out : keys_tmp;
+        uint32_t *vo = to_out ? vals_out : vals_tmp;
+        const int shift = p * digit_bits;
+        switch (digit_bits) {
+            case 4: sort_pass<4>(kin, vin, ko, vo, n_max, n_dev, shift, hist, scan_part, s); break;
+            case 5: sort_pass<5>(kin, vin, ko, vo, n_max, n_dev, shift, hist, scan_part, s); break;
+            case 6: sort_pass<6>(kin, vin, ko, vo, n_max, n_dev, shift, hist, scan_part, s); break;
+            case 7: sort_pass<7>(kin, vin, ko, vo, n_max, n_dev, shift, hist, scan_part, s); break;
+            default: sort_pass<8>(kin, vin, ko, vo, n_max, n_dev, shift, hist, scan_part, s); break;
+        }
+        kin = ko;
+        vin = vo;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_keygen(const uint32_t *sorted_rec, const uint32_t *counts, const uint32_t *offsets,
+                         const uint32_t *trect, int64_t n_records, int64_t n_per_view, const ViewTable &vt,
+                         uint32_t *pkey, uint32_t *pval, FrameHeader *hdr, uint32_t capacity,
+                         const uint32_t *total, hipStream_t s) {
+    const int64_t nb = n_records > 0 ? (n_records + 255) / 256 : 1;
+    hipLaunchKernelGGL(k_keygen, dim3((unsigned)nb), dim3(256), 0, s, sorted_rec, counts, offsets, trect, n_records,
+                       n_per_view, vt, pkey, pval, hdr, capacity, total);
+    return hipGetLastError();
+}
+
+hipError_t launch_ranges(const uint32_t *sorted_keys, const FrameHeader *hdr, uint2 *ranges, int64_t n_tiles,
+                         int64_t n_max, hipStream_t s) {
+    (void)n_tiles;
+    if (n_max <= 0) return hipSuccess;
+    int64_t nb = (n_max + 255) / 256;
+    if (nb > 8192) nb = 8192;
+    hipLaunchKernelGGL(k_ranges, dim3((unsigned)nb), dim3(256), 0, s, sorted_keys, hdr, ranges, n_max);
+    return hipGetLastError();
+}
+
+}  // namespace gspm

@@ -1,0 +1,192 @@
+// Internal declarations shared by the HIP translation units of libgspm (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/gspm.h"
+
+namespace gspm {
+
+constexpr int kMaxViews = GSPM_MAX_VIEWS;
+constexpr int kWave = 64;
+
+// Per-launch table of the views of a window, passed by value as a kernel argument so
+// that a captured graph holds it.  Tiles of all views form one global tile space
+// (view v owns [tile_off[v], tile_off[v+1])); pixels are packed the same way.
+struct ViewTable {
+    int32_t n_views;
+    int32_t tile;
+    int32_t width[kMaxViews];
+    int32_t height[kMaxViews];
+    int32_t tiles_x[kMaxViews];
+    int32_t tile_off[kMaxViews + 1];
+    int64_t pix_off[kMaxViews + 1];
+    float fx[kMaxViews], fy[kMaxViews], cx[kMaxViews], cy[kMaxViews];
+};
+
+struct RasterSettings {
+    float near_z, alpha_min, alpha_max, t_min, eps2d, jac_clamp;
+    float bg[3];
+    int32_t frame;  // 0 world, 1 camera, 2 depth back-projection
+};
+
+// Projected record of one (Gaussian, view) pair: 64 bytes, 4 x float4.
+//   r0 = (u_hi, v_hi, u_lo, v_lo)     mean2D as a float32 pair (u = u_hi + u_lo)
+//   r1 = (A, B, C, opacity)           exponent base 2: alpha = opacity * 2^(A dx^2 + B dx dy + C dy^2)
+//   r2 = (c_r, c_g, c_b, z)           colour and camera depth
+//   r3 = (p_x, p_y, p_z, 0)           composited point (world centre or camera centre)
+// A = -0.5 log2(e) Q_xx, B = -log2(e) Q_xy, C = -0.5 log2(e) Q_yy for the conic Q.
+constexpr int kRecFloats = 16;
+
+// Per-record image-plane gradient accumulator (16 floats, 13 used):
+//   0 u, 1 v, 2 A, 3 B, 4 C, 5 opacity, 6 z, 7..9 colour, 10..12 point.
+constexpr int kG2 = 16;
+constexpr int kG2Used = 13;
+
+// Frame-state layout (caller-owned device buffer).
+struct FrameHeader {
+    uint32_t pairs;     // tile pairs produced (or needed, on overflow)
+    uint32_t overflow;  // nonzero if pairs > capacity
+    uint32_t capacity;
+    uint32_t tile;
+    uint32_t n_views;
+    uint32_t n_tiles;
+    uint64_t n_pixels;
+    uint64_t n_records;
+    uint32_t magic;
+    uint32_t pad[5];
+};
+constexpr uint32_t kFrameMagic = 0x47535046u;  // "GSPF"
+
+struct FrameLayout {
+    int64_t header, ranges, t_final, last, records, pair_vals, total;
+};
+
+inline int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
+
+inline FrameLayout frame_layout(int64_t n_tiles, int64_t n_pixels, int64_t n_records, int64_t cap) {
+    FrameLayout L;
+    int64_t o = 0;
+    L.header = o;    o += align256(sizeof(FrameHeader));
+    L.ranges = o;    o += align256(n_tiles * 8);
+    L.t_final = o;   o += align256(n_pixels * 4);
+    L.last = o;      o += align256(n_pixels * 4);
+    L.records = o;   o += align256(n_records * kRecFloats * 4);
+    L.pair_vals = o; o += align256(cap * 4);
+    L.total = o;
+    return L;
+}
+
+// ---------------------------------------------------------------------------------------
+// Device helpers.
+
+__device__ inline int lane_id() { return __lane_id(); }
+
+// Sum over the 64 lanes of a wave using DPP row operations; the total lands in lane 63.
+#define GSPM_DPP(x, ctrl, rmask)                                                            \
+    __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, (x)), \
+                                                          (ctrl), (rmask), 0xf, false))
+
+__device__ inline float wave_sum_to_lane63(float x) {
+    x += GSPM_DPP(x, 0xb1, 0xf);   // quad_perm [1,0,3,2]
+    x += GSPM_DPP(x, 0x4e, 0xf);   // quad_perm [2,3,0,1]
+    x += GSPM_DPP(x, 0x114, 0xf);  // row_shr:4
+    x += GSPM_DPP(x, 0x118, 0xf);  // row_shr:8
+    x += GSPM_DPP(x, 0x142, 0xa);  // row_bcast:15 into rows 1 and 3
+    x += GSPM_DPP(x, 0x143, 0xc);  // row_bcast:31 into rows 2 and 3
+    return x;
+}
+
+__device__ inline float wave_total(float x) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, wave_sum_to_lane63(x)), 63));
+}
+
+// Wave-wide inclusive prefix sum of a uint32 (Hillis-Steele over cross-lane reads).
+__device__ inline uint32_t wave_inclusive_scan(uint32_t x) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        uint32_t y = __shfl_up(x, d, kWave);
+        if (lane >= d) x += y;
+    }
+    return x;
+}
+
+__device__ inline int find_view(const ViewTable &vt, int32_t global_tile) {
+    int v = 0;
+#pragma unroll 1
+    for (int k = 1; k < vt.n_views; ++k)
+        if (global_tile >= vt.tile_off[k]) v = k;
+    return v;
+}
+
+// Alpha of a fragment exactly as the forward and backward kernels evaluate it.
+__device__ inline float frag_alpha(float dx, float dy, float A, float B, float C, float opac,
+                                   float alpha_max, float &g2) {
+    const float e = fmaf(dx, fmaf(A, dx, B * dy), C * dy * dy);
+    g2 = __builtin_amdgcn_exp2f(e);
+    return fminf(alpha_max, opac * g2);
+}
+
+// ---------------------------------------------------------------------------------------
+// Host-side launch wrappers (defined in the .hip files).
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t n, hipStream_t s);
+hipError_t launch_fill_f32(float *p, float value, int64_t n, hipStream_t s);
+
+hipError_t launch_preprocess(const gspm_gaussians &g, const ViewTable &vt, const float *T_cw,
+                             const RasterSettings &rs, float *records, uint32_t *counts,
+                             uint32_t *trect, uint32_t *dkey, uint32_t *dval, hipStream_t s);
+
+// Exclusive scan of counts[idx[p]] for p < n (idx may be NULL for the identity); writes
+// offsets[p] and the total to *total.  part: scratch of at least scan_partials(n) words.
+int64_t scan_partials(int64_t n);
+hipError_t launch_scan_indirect(const uint32_t *counts, const uint32_t *idx, int64_t n,
+                                uint32_t *offsets, uint32_t *total, uint32_t *part, hipStream_t s);
+
+// Stable LSD radix sort of (key, value) uint32 pairs over the low `bits` key bits.
+// n_dev: device count (may be NULL: n_max is then exact).  Buffers: keys/vals in,
+// tmp, out (the sorted result ends in keys_out/vals_out).  hist: scratch of
+// radix_hist_words(n_max, digit_bits) words.
+int64_t radix_hist_words(int64_t n_max, int digit_bits);
+hipError_t radix_sort(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_tmp,
+                      uint32_t *vals_tmp, uint32_t *keys_out, uint32_t *vals_out, int64_t n_max,
+                      const uint32_t *n_dev, int bits, int digit_bits, uint32_t *hist,
+                      uint32_t *scan_part, hipStream_t s);
+
+hipError_t launch_keygen(const uint32_t *sorted_rec, const uint32_t *counts, const uint32_t *offsets,
+                         const uint32_t *trect, int64_t n_records, int64_t n_per_view,
+                         const ViewTable &vt, uint32_t *pkey, uint32_t *pval, FrameHeader *hdr,
+                         uint32_t capacity, const uint32_t *total, hipStream_t s);
+
+hipError_t launch_ranges(const uint32_t *sorted_keys, const FrameHeader *hdr, uint2 *ranges,
+                         int64_t n_tiles, int64_t n_max, hipStream_t s);
+
+hipError_t launch_raster_forward(const ViewTable &vt, const RasterSettings &rs, const uint2 *ranges,
+                                 const uint32_t *pair_vals, const float *records, float *rgb,
+                                 float *depth, float *alpha, float *pointmap, float *t_final,
+                                 uint32_t *last, hipStream_t s);
+
+hipError_t launch_raster_backward(const ViewTable &vt, const RasterSettings &rs, const uint2 *ranges,
+                                  const uint32_t *pair_vals, const float *records, const uint32_t *last,
+                                  const float *t_final, const gspm_const_images &fwd,
+                                  const gspm_const_images &up, float *grad2d, bool pose_only,
+                                  hipStream_t s);
+
+hipError_t launch_preprocess_backward(const gspm_gaussians &g, const ViewTable &vt, const float *T_cw,
+                                      const RasterSettings &rs, const float *grad2d,
+                                      const gspm_gaussian_grads &out, bool want_pose,
+                                      double *pose_partials, hipStream_t s);
+int64_t pose_partial_blocks(int64_t n);
+hipError_t launch_pose_reduce(const double *pose_partials, int64_t n_blocks, int n_views,
+                              float *pose_grad, hipStream_t s);
+
+hipError_t launch_patch_loss(const ViewTable &vt, const float *Xr, const float *Xp, const float *mask,
+                             int patch, const float *rgb, const float *rgb_target, float alpha,
+                             float *scale_out, int32_t *count_out, float *loss_out, float *grad_rgb,
+                             float *grad_pm, hipStream_t s);
+
+hipError_t launch_pose_retract(int n_views, float *T_cw, const float *xi, hipStream_t s);
+
+}  // namespace gspm

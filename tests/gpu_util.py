@@ -1,0 +1,124 @@
+"""Helpers for the GPU-vs-oracle parity tests.
+
+Tolerances (stated by the method's accuracy targets, applied per view and channel):
+
+* images: |x - r| <= 1e-4 (|r| + 1e-3 max|r|) on every pixel the oracle does not flag as
+  ambiguous (a float32 decision within rounding of a threshold);
+* gradients, per tensor: ||g - r||_2 / ||r||_2 <= 2e-3, and |g - r| <= 2e-3 (|r| + rms(r))
+  for at least 99.99% of the elements.
+"""
+from __future__ import annotations
+
+import math
+import sys
+
+import numpy as np
+
+IMG_RTOL = 1e-4
+GRAD_RTOL = 2e-3
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(scene, torch):
+    params = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in scene.params()]
+    T = torch.from_numpy(np.ascontiguousarray(scene.T_cw)).cuda()
+    return params, T
+
+
+def check_image(name, got, ref, ok_mask):
+    """got, ref: [..., H, W] arrays; ok_mask: [H, W] bool of pixels to compare."""
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    scale = np.abs(ref).max() if ref.size else 0.0
+    tol = IMG_RTOL * (np.abs(ref) + 1e-3 * scale)
+    bad = (np.abs(got - ref) > tol) & ok_mask
+    if bad.any():
+        idx = np.argwhere(bad)[:5]
+        det = [(tuple(i), float(got[tuple(i)]), float(ref[tuple(i)])) for i in idx]
+        raise AssertionError(f"{name}: {int(bad.sum())} pixels outside tolerance, e.g. {det}")
+
+
+def check_grad(name, got, ref, frac=0.9999):
+    got = np.asarray(got, dtype=np.float64).reshape(-1)
+    ref = np.asarray(ref, dtype=np.float64).reshape(-1)
+    nr = np.linalg.norm(ref)
+    rel = np.linalg.norm(got - ref) / nr if nr > 0 else np.linalg.norm(got)
+    rms = math.sqrt(float(np.mean(ref ** 2))) if ref.size else 0.0
+    bad = np.abs(got - ref) > GRAD_RTOL * (np.abs(ref) + rms)
+    ok_frac = 1.0 - bad.mean() if ref.size else 1.0
+    if not (rel <= GRAD_RTOL and ok_frac >= frac):
+        idx = np.argwhere(bad).reshape(-1)[:5]
+        raise AssertionError(f"{name}: rel L2 {rel:.3e}, elementwise ok {ok_frac:.6f}; e.g. "
+                             f"{[(int(i), float(got[i]), float(ref[i])) for i in idx]}")
+    return rel
+
+
+def oracle_view_images(O, params_o, cam, T12, S, pixels=None):
+    """Oracle render of a full view or of the given pixels (returns per-pixel dict)."""
+    view = O.make_view(cam, T12)
+    pix = O.full_pixels(cam) if pixels is None else pixels
+    return O.render(params_o, view, S, pix), pix
+
+
+def gpu_pixels(packed, cam, off, channels, pix):
+    """Gather pixels [npix][2] of view at packed offset `off` -> [npix] or [npix][C]."""
+    H, W = cam.height, cam.width
+    i, j = pix[:, 0], pix[:, 1]
+    if channels == 1:
+        img = packed[off:off + H * W].reshape(H, W)
+        return img[j, i]
+    img = packed[3 * off:3 * off + 3 * H * W].reshape(3, H, W)
+    return img[:, j, i].T
+
+
+def crops(cam, size, n, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        x0 = int(rng.integers(0, max(1, cam.width - size)))
+        y0 = int(rng.integers(0, max(1, cam.height - size)))
+        out.append((x0, y0, min(size, cam.width - x0), min(size, cam.height - y0)))
+    return out
+
+
+def crop_mask(cam, boxes):
+    m = np.zeros((cam.height, cam.width), dtype=bool)
+    for (x0, y0, w, h) in boxes:
+        m[y0:y0 + h, x0:x0 + w] = True
+    return m
+
+
+def frame_layout(n_tiles, n_pixels, n_records):
+    """Byte offsets inside a frame state (internal layout of libgspm, for tests only)."""
+    a = lambda x: (x + 255) & ~255  # noqa: E731
+    o = 0
+    lay = {}
+    lay["header"] = o; o += a(64)
+    lay["ranges"] = o; o += a(n_tiles * 8)
+    lay["t_final"] = o; o += a(n_pixels * 4)
+    lay["last"] = o; o += a(n_pixels * 4)
+    lay["records"] = o; o += a(n_records * 64)
+    lay["pair_vals"] = o
+    return lay
+
+
+def tile_edge_near(bounds, B, W, H, tol):
+    """True where a support bound is within tol of a value at which the tile rectangle
+    (or the visibility) changes: u - rx at k B - 1 (ceil crosses into tile k), u + rx at
+    k B (floor crosses), and the image borders."""
+    lo_x, hi_x, lo_y, hi_y = bounds[:, 0], bounds[:, 1], bounds[:, 2], bounds[:, 3]
+
+    def near(x, offs, extra):
+        r = np.zeros(x.shape, dtype=bool)
+        k = np.round((x - offs) / B)
+        r |= np.abs(x - (k * B + offs)) <= tol
+        for e in extra:
+            r |= np.abs(x - e) <= tol
+        return r
+
+    return (near(lo_x, -1.0, [0.0, W - 1.0, W]) | near(hi_x, 0.0, [-1.0, 0.0, W - 1.0]) |
+            near(lo_y, -1.0, [0.0, H - 1.0, H]) | near(hi_y, 0.0, [-1.0, 0.0, H - 1.0]))

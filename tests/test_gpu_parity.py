@@ -1,0 +1,241 @@
+"""GPU (HIP, gfx950) vs FP64 oracle: forward images, tile lists and gradients.
+
+Every test calls the library through its C ABI (via the ctypes binding) on seeded
+synthetic inputs and compares with the oracle on the same inputs.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2507_03737_amd import scenes
+from tests import gpu_util as U
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2507_03737_amd import binding
+    binding.load()
+    return binding
+
+
+def _posed(sc, deg=3.0, meters=0.1, seed=5):
+    sc.T_cw = np.stack([scenes.perturb_pose(T, deg, meters, seed + k) for k, T in enumerate(sc.T_cw)])
+    return sc
+
+
+def _render_gpu(lib, sc, cfg):
+    from paper_2507_03737_amd.render import Rasterizer, Window
+    params, T = U.to_dev(sc, torch)
+    win = Window(sc.cams, T)
+    rast = Rasterizer(win, sc.n, cfg)
+    out, fs = rast.forward(params)
+    torch.cuda.synchronize()
+    return rast, params, out, fs
+
+
+def _oracle_settings(O, cfg):
+    return O.Settings(near_z=cfg.near_z, alpha_min=cfg.alpha_min, alpha_max=cfg.alpha_max, t_min=cfg.t_min,
+                      eps2d=cfg.eps2d, jac_clamp=cfg.jac_clamp, bg=cfg.bg)
+
+
+def _check_view_forward(O, sc, v, out, off, cfg, pixels=None, tag=""):
+    cam = sc.cams[v]
+    S = _oracle_settings(O, cfg)
+    po = O.Params.from_scene(sc)
+    ref, pix = U.oracle_view_images(O, po, cam, sc.T_cw[v], S, pixels)
+    ok = ref["ambiguous"] == 0
+    key = {0: "pm_world", 1: "pm_cam", 2: "pm_eq5"}[cfg.pointmap_frame]
+    host = {k: t.detach().cpu().numpy() for k, t in out.items()}
+    got_rgb = U.gpu_pixels(host["rgb"], cam, off, 3, pix)
+    got_pm = U.gpu_pixels(host["pointmap"], cam, off, 3, pix)
+    U.check_image(f"{tag} rgb", got_rgb.T, ref["rgb"].T, ok[None])
+    U.check_image(f"{tag} depth", U.gpu_pixels(host["depth"], cam, off, 1, pix), ref["depth"], ok)
+    U.check_image(f"{tag} alpha", U.gpu_pixels(host["alpha"], cam, off, 1, pix), ref["alpha"], ok)
+    U.check_image(f"{tag} pointmap", got_pm.T, ref[key].T, ok[None])
+    return ref
+
+
+@pytest.mark.parametrize("frame", [0, 1, 2])
+def test_forward_c0(lib, oracle, frame):
+    U.log(f"[gpu] forward c0 frame={frame}")
+    sc = _posed(scenes.make_scene("c0"))
+    cfg = lib.RasterConfig(pointmap_frame=frame)
+    rast, params, out, fs = _render_gpu(lib, sc, cfg)
+    ref = _check_view_forward(oracle, sc, 0, out, 0, cfg, tag=f"c0/f{frame}")
+    assert (ref["ambiguous"] != 0).mean() < 0.01
+
+
+@pytest.mark.parametrize("tile", [8, 16, 32])
+def test_forward_tiles_and_ragged(lib, oracle, tile):
+    """Tile sizes 8/16/32 on a view whose size is not a multiple of any of them."""
+    U.log(f"[gpu] forward ragged tile={tile}")
+    sc = scenes.make_scene("c0", seed=7, n=1500)
+    cam = sc.cams[0]
+    sc.cams = [scenes.Camera(157, 93, cam.fx, cam.fy, 78.5, 46.5)]
+    cfg = lib.RasterConfig(tile=tile, pointmap_frame=1)
+    rast, params, out, fs = _render_gpu(lib, sc, cfg)
+    _check_view_forward(oracle, sc, 0, out, 0, cfg, tag=f"ragged/t{tile}")
+
+
+def test_tile_lists_exact(lib, oracle):
+    """Per-tile (record) lists equal the oracle's brute-force lists, ordered by
+    (float32 depth, index), except Gaussians whose support bound lies within 1e-4 px
+    (plus float64 rounding) of a value where the tile rectangle changes."""
+    U.log("[gpu] tile lists c0")
+    O = oracle
+    sc = _posed(scenes.make_scene("c0"))
+    cfg = lib.RasterConfig(pointmap_frame=1)
+    rast, params, out, fs = _render_gpu(lib, sc, cfg)
+    cam = sc.cams[0]
+    B = cfg.tile
+    n_tiles = math.ceil(cam.width / B) * math.ceil(cam.height / B)
+    lay = U.frame_layout(n_tiles, cam.width * cam.height, sc.n)
+    raw = fs.cpu().numpy()
+    pairs = int(raw[:4].view(np.uint32)[0])
+    ranges = raw[lay["ranges"]:lay["ranges"] + 8 * n_tiles].view(np.uint32).reshape(n_tiles, 2)
+    vals = raw[lay["pair_vals"]:lay["pair_vals"] + 4 * pairs].view(np.uint32)
+    S = _oracle_settings(O, cfg)
+    po = O.Params.from_scene(sc)
+    proj = O.project(po, O.make_view(cam, sc.T_cw[0]), S)
+    pa = O.proj_numpy(proj)
+    tiles_o, gs_o = O.tile_pairs(proj, po.n, cam.width, cam.height, B)
+    exempt = U.tile_edge_near(pa["bounds"], B, cam.width, cam.height, 1e-4) & (pa["visible"] == 1)
+    z32 = pa["z"].astype(np.float32)
+    assert pairs == len(tiles_o) or exempt.any()
+    n_exempt_tiles = 0
+    for t in range(n_tiles):
+        got = [int(x) for x in vals[ranges[t, 0]:ranges[t, 1]] if not exempt[x]]
+        sel = gs_o[tiles_o == t]
+        ref = sorted((int(g) for g in sel if not exempt[g]), key=lambda g: (z32[g], g))
+        assert got == ref, f"tile {t}"
+        n_exempt_tiles += int(exempt[sel].any())
+    U.log(f"  pairs={pairs} exempt_gaussians={int(exempt.sum())} tiles_with_exempt={n_exempt_tiles}")
+
+
+def _upstream(sc, seed, ok_masks, alpha=True):
+    ups = scenes.upstream_grads(sc, seed=seed, alpha=alpha)
+    for up, ok in zip(ups, ok_masks):
+        for k in ("rgb", "pointmap"):
+            up[k] = np.ascontiguousarray(up[k] * ok[None])
+        for k in ("depth", "alpha"):
+            up[k] = np.ascontiguousarray(up[k] * ok)
+    return ups
+
+
+def _pack(ups, key, channels):
+    return np.concatenate([u[key].reshape(-1) for u in ups]).astype(np.float32)
+
+
+def _gpu_backward(lib, rast, params, out, fs, ups, pose=True):
+    up = {k: torch.from_numpy(_pack(ups, k, c)).cuda() for k, c in (("rgb", 3), ("depth", 1), ("alpha", 1),
+                                                                     ("pointmap", 3))}
+    grads = rast.zero_grads(params)
+    pg = torch.zeros(rast.win.n_views, 6, device="cuda") if pose else None
+    rast.backward_into(params, out, up, fs, grads, pg)
+    torch.cuda.synchronize()
+    g = {k: t.cpu().numpy() for k, t in grads.items()}
+    if pose:
+        g["pose"] = pg.cpu().numpy()
+    return g
+
+
+def _oracle_backward(O, sc, cfg, ups, pixel_sets=None):
+    S = _oracle_settings(O, cfg)
+    po = O.Params.from_scene(sc)
+    tot = None
+    poses = []
+    for v, cam in enumerate(sc.cams):
+        pix = O.full_pixels(cam) if pixel_sets is None else pixel_sets[v]
+        view = O.make_view(cam, sc.T_cw[v])
+        up = O.pixel_upstream(ups[v], pix)
+        g = O.backward(po, view, S, pix, up, pointmap_frame=cfg.pointmap_frame)
+        poses.append(g.pop("pose"))
+        tot = g if tot is None else {k: tot[k] + g[k] for k in tot}
+    tot["pose"] = np.stack(poses)
+    return tot
+
+
+@pytest.mark.parametrize("frame", [0, 1, 2])
+def test_backward_c0(lib, oracle, frame):
+    U.log(f"[gpu] backward c0 frame={frame}")
+    O = oracle
+    sc = _posed(scenes.make_scene("c0"))
+    cfg = lib.RasterConfig(pointmap_frame=frame)
+    rast, params, out, fs = _render_gpu(lib, sc, cfg)
+    ref = O.render_image(O.Params.from_scene(sc), sc.cams[0], sc.T_cw[0], _oracle_settings(O, cfg))
+    ups = _upstream(sc, 21, [ref["ambiguous"] == 0])
+    g = _gpu_backward(lib, rast, params, out, fs, ups)
+    r = _oracle_backward(O, sc, cfg, ups)
+    for k in ("means", "log_scales", "quats", "opacity_logit", "rgb"):
+        rel = U.check_grad(f"c0/f{frame} {k}", g[k], r[k])
+        U.log(f"  {k}: rel {rel:.2e}")
+    U.check_grad(f"c0/f{frame} pose", g["pose"], r["pose"], frac=1.0)
+    U.log(f"  pose gpu {g['pose'][0]} oracle {r['pose'][0]}")
+
+
+def test_pose_backward_matches_full_backward(lib, oracle):
+    U.log("[gpu] pose-only backward c0")
+    sc = _posed(scenes.make_scene("c0"))
+    cfg = lib.RasterConfig(pointmap_frame=1)
+    rast, params, out, fs = _render_gpu(lib, sc, cfg)
+    ref = oracle.render_image(oracle.Params.from_scene(sc), sc.cams[0], sc.T_cw[0], _oracle_settings(oracle, cfg))
+    ups = _upstream(sc, 22, [ref["ambiguous"] == 0])
+    up = {k: torch.from_numpy(_pack(ups, k, c)).cuda() for k, c in (("rgb", 3), ("depth", 1), ("alpha", 1),
+                                                                     ("pointmap", 3))}
+    pg = torch.zeros(1, 6, device="cuda")
+    rast.pose_backward_into(params, out, up, fs, pg)
+    torch.cuda.synchronize()
+    r = _oracle_backward(oracle, sc, cfg, ups)
+    U.check_grad("pose-only", pg.cpu().numpy(), r["pose"], frac=1.0)
+
+
+def test_empty_and_culled(lib, oracle):
+    """No Gaussians, and Gaussians that are all behind the camera: background only."""
+    U.log("[gpu] empty / all culled")
+    from paper_2507_03737_amd.render import Rasterizer, Window
+    cam = scenes.Camera(40, 30, 30.0, 30.0, 20.0, 15.0)
+    T = torch.tensor(np.eye(3, 4, dtype=np.float32).reshape(1, 12)).cuda()
+    cfg = lib.RasterConfig(bg=(0.25, 0.5, 0.75))
+    win = Window([cam], T)
+    for n in (0, 50):
+        sc = scenes.make_scene("c0", seed=3, n=max(n, 1))
+        params = [torch.from_numpy(np.ascontiguousarray(a[..., :n])).cuda() for a in sc.params()]
+        if n:
+            params[0][2] = -5.0  # behind the camera
+        rast = Rasterizer(win, n, cfg)
+        out, fs = rast.forward(params)
+        assert rast.pairs == 0
+        rgb = out["rgb"].view(3, 30, 40).cpu().numpy()
+        for c, b in enumerate(cfg.bg):
+            assert np.all(rgb[c] == np.float32(b))
+        assert float(out["alpha"].abs().max()) == 0.0 and float(out["depth"].abs().max()) == 0.0
+        up = {"rgb": torch.ones(3 * 1200, device="cuda")}
+        grads = rast.zero_grads(params)
+        pg = torch.zeros(1, 6, device="cuda")
+        rast.backward_into(params, out, up, fs, grads, pg)
+        torch.cuda.synchronize()
+        assert all(float(t.abs().max()) == 0.0 for t in grads.values() if t.numel()) and float(pg.abs().max()) == 0.0
+
+
+def test_capacity_overflow_reports_and_recovers(lib):
+    U.log("[gpu] capacity overflow")
+    from paper_2507_03737_amd.render import Rasterizer, Window
+    sc = scenes.make_scene("c0")
+    params, T = U.to_dev(sc, torch)
+    rast = Rasterizer(Window(sc.cams, T), sc.n, lib.RasterConfig(), max_pairs=100)
+    out = rast.new_outputs()
+    fs = rast.new_frame_state()
+    rast.forward_into(params, out, fs)
+    with pytest.raises(lib.CapacityError) as ei:
+        lib.frame_status(fs, lib.stream_handle())
+    need = ei.value.pairs
+    assert need > 100
+    out2, fs2 = rast.forward(params)  # grows and retries
+    assert rast.pairs == need and rast.max_pairs >= need
