@@ -163,6 +163,14 @@ GSPM_API gspm_status gspm_render_forward(gspm_ctx *ctx, const gspm_gaussians *g,
  * forward produced (or needed).  Returns GSPM_ERR_CAPACITY on overflow. */
 GSPM_API gspm_status gspm_frame_status(const void *frame_state, void *stream, int64_t *pairs);
 
+/* Synchronise the stream and report the work of a forward: out[0] = tile pairs,
+ * out[1] = contributing fragments (Gaussian-pixel pairs composited with alpha >=
+ * alpha_min before the transmittance floor), out[2] = sum over pixels of the list
+ * entries evaluated up to each pixel's last contributing fragment.  The frame state must
+ * come from a forward with the same views, n_gaussians and tile. */
+GSPM_API gspm_status gspm_frame_work(gspm_ctx *ctx, const gspm_views *views, int64_t n_gaussians, int32_t tile,
+                                     const void *frame_state, void *stream, int64_t *out);
+
 /* ---- gradients (Sec. 3.1 parameters; Sec. 3.2.2 Eq. 11 pose) ------------------------ */
 
 /* Backward of gspm_render_forward for upstream gradients grad_out (same planes as the
@@ -209,6 +217,28 @@ GSPM_API gspm_status gspm_window_loss(const gspm_views *views, const float *rgb,
 GSPM_API gspm_status gspm_pose_retract(int32_t n_views, float *T_cw, const float *xi, void *stream);
 
 /* ---- diagnostics -------------------------------------------------------------------- */
+
+/* Launch phases timed by the context when timing is on. */
+typedef enum {
+    GSPM_PHASE_PREPROCESS = 0, /* projection of every (Gaussian, view) record */
+    GSPM_PHASE_DEPTH_SORT = 1, /* radix sort of records by depth */
+    GSPM_PHASE_BINNING = 2,    /* pair-count scan, pair emission, range extraction */
+    GSPM_PHASE_TILE_SORT = 3,  /* radix sort of tile pairs */
+    GSPM_PHASE_RASTER_FWD = 4, /* forward compositing kernel */
+    GSPM_PHASE_RASTER_BWD = 5, /* backward compositing kernel */
+    GSPM_PHASE_PARAM_BWD = 6,  /* image-plane -> parameter and pose gradients */
+    GSPM_PHASE_COUNT = 7
+} gspm_phase;
+
+/* Turn per-phase HIP event timing on or off for a context.  While on, each forward and
+ * backward records a start/end event pair around every phase on its stream (do not
+ * turn it on for calls captured into a graph). */
+GSPM_API gspm_status gspm_timing_enable(gspm_ctx *ctx, int32_t on);
+
+/* Wait for the recorded events, add each phase's elapsed milliseconds to ms_out
+ * [GSPM_PHASE_COUNT] and its number of timed launches to counts_out (either may be
+ * NULL), and forget the recorded events. */
+GSPM_API gspm_status gspm_timing_collect(gspm_ctx *ctx, double *ms_out, int64_t *counts_out);
 
 /* Message of the last error on this thread ("" if none). */
 GSPM_API const char *gspm_last_error(void);

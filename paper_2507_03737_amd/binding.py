@@ -67,8 +67,11 @@ class GaussianGrads(ctypes.Structure):
 EXPORTS = (
     "gspm_create", "gspm_destroy", "gspm_reserve", "gspm_frame_state_bytes", "gspm_render_forward",
     "gspm_frame_status", "gspm_render_backward", "gspm_pose_backward", "gspm_patch_scale_align",
-    "gspm_window_loss", "gspm_pose_retract", "gspm_last_error", "gspm_version",
+    "gspm_window_loss", "gspm_pose_retract", "gspm_timing_enable", "gspm_timing_collect", "gspm_frame_work",
+    "gspm_last_error", "gspm_version",
 )
+
+PHASES = ("preprocess", "depth_sort", "binning", "tile_sort", "raster_fwd", "raster_bwd", "param_bwd")
 
 _lib = None
 
@@ -96,6 +99,9 @@ def load(path: str = LIB_PATH):
     L.gspm_patch_scale_align.argtypes = [P(Views), vp, vp, vp, ctypes.c_int32, vp, vp, vp]
     L.gspm_window_loss.argtypes = [P(Views), vp, vp, vp, vp, ctypes.c_int32, ctypes.c_float, vp, vp, vp, vp, vp]
     L.gspm_pose_retract.argtypes = [ctypes.c_int32, vp, vp, vp]
+    L.gspm_frame_work.argtypes = [vp, P(Views), ctypes.c_int64, ctypes.c_int32, vp, vp, P(ctypes.c_int64)]
+    L.gspm_timing_enable.argtypes = [vp, ctypes.c_int32]
+    L.gspm_timing_collect.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     L.gspm_last_error.restype = ctypes.c_char_p
     L.gspm_version.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -170,6 +176,16 @@ class Context:
     def reserve(self, max_records, max_pairs, max_tiles=0):
         check(load().gspm_reserve(self.h, int(max_records), int(max_pairs), int(max_tiles)))
 
+    def timing(self, on: bool):
+        check(load().gspm_timing_enable(self.h, 1 if on else 0))
+
+    def collect_timing(self):
+        """Per-phase (total ms, launches) since the last collect; synchronises."""
+        ms = (ctypes.c_double * len(PHASES))()
+        cnt = (ctypes.c_int64 * len(PHASES))()
+        check(load().gspm_timing_collect(self.h, ms, cnt))
+        return {p: (ms[k], int(cnt[k])) for k, p in enumerate(PHASES)}
+
     def close(self):
         if self.h:
             load().gspm_destroy(self.h)
@@ -201,6 +217,13 @@ def frame_status(frame_state, stream) -> int:
         raise CapacityError(st, last_error(), int(pairs.value))
     check(st)
     return int(pairs.value)
+
+
+def frame_work(ctx: Context, views: Views, n, tile, frame_state, stream):
+    """(tile pairs, contributing fragments, evaluated-list bound) of a forward; synchronises."""
+    out = (ctypes.c_int64 * 3)()
+    check(load().gspm_frame_work(ctx.h, ctypes.byref(views), int(n), int(tile), ptr(frame_state), stream, out))
+    return int(out[0]), int(out[1]), int(out[2])
 
 
 def render_backward(ctx, g, views, cfg, fwd: Images, up: Images, frame_state, grads: GaussianGrads | None,

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <string>
+#include <vector>
 
 #include "gspm_common.h"
 
@@ -61,6 +62,11 @@ bool finite_pos(float x) { return isfinite(x) && x > 0.0f; }
 }  // namespace
 
 struct gspm_ctx {
+    // Phase timing: pairs of events recorded around each phase while enabled.
+    bool timing = false;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    std::vector<int> phase_of;  // per recorded pair
     // Per record (n * V).
     DevBuf counts, trect, dkey, dval, dkey_tmp, dval_tmp, dkey_s, dval_s, offsets, grad2d;
     // Per pair (capacity).
@@ -70,6 +76,34 @@ struct gspm_ctx {
 };
 
 namespace {
+
+// Records a start event on construction and an end event on stop() when timing is on.
+struct PhaseTimer {
+    gspm_ctx *ctx;
+    hipStream_t s;
+    int phase;
+    hipEvent_t end = nullptr;
+    PhaseTimer(gspm_ctx *c, hipStream_t st, int ph) : ctx(c), s(st), phase(ph) {
+        if (!ctx->timing) return;
+        if (ctx->used + 2 > ctx->pool.size()) {
+            for (int k = 0; k < 64; ++k) {
+                hipEvent_t e;
+                if (hipEventCreate(&e) != hipSuccess) return;
+                ctx->pool.push_back(e);
+            }
+        }
+        hipEvent_t b = ctx->pool[ctx->used];
+        end = ctx->pool[ctx->used + 1];
+        ctx->used += 2;
+        ctx->phase_of.push_back(phase);
+        (void)hipEventRecord(b, s);
+    }
+    void stop() {
+        if (end) (void)hipEventRecord(end, s);
+        end = nullptr;
+    }
+    ~PhaseTimer() { stop(); }
+};
 
 struct Prepared {
     ViewTable vt;
@@ -216,9 +250,12 @@ gspm_status backward_common(gspm_ctx *ctx, const gspm_gaussians *g, const gspm_v
     GSPM_HIP(grow(ctx->pose_part, 8 * 6 * (nb > 0 ? nb : 1) * P.vt.n_views));
     float *g2 = static_cast<float *>(ctx->grad2d.p);
     GSPM_HIP(launch_fill_f32(g2, 0.0f, kG2 * R, hs));
+    PhaseTimer t_rb(ctx, hs, GSPM_PHASE_RASTER_BWD);
     GSPM_HIP(launch_raster_backward(P.vt, P.rs, at<uint2>(frame_state, L.ranges), at<uint32_t>(frame_state, L.pair_vals),
                                     at<float>(frame_state, L.records), at<uint32_t>(frame_state, L.last),
                                     at<float>(frame_state, L.t_final), *fwd_out, *grad_out, g2, pose_only, hs));
+    t_rb.stop();
+    PhaseTimer t_pb(ctx, hs, GSPM_PHASE_PARAM_BWD);
     gspm_gaussian_grads none = {nullptr, nullptr, nullptr, nullptr, nullptr};
     const gspm_gaussian_grads &out = (pose_only || !grads) ? none : *grads;
     GSPM_HIP(launch_preprocess_backward(*g, P.vt, views->T_cw, P.rs, g2, out, pose_grad != nullptr,
@@ -247,6 +284,7 @@ void gspm_destroy(gspm_ctx *ctx) {
                       &ctx->pose_part};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
+    for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
     delete ctx;
 }
 
@@ -309,14 +347,21 @@ gspm_status gspm_render_forward(gspm_ctx *ctx, const gspm_gaussians *g, const gs
     uint32_t *part = static_cast<uint32_t *>(ctx->scan_part.p);
 
     // 1. Project every (Gaussian, view) record.
+    PhaseTimer t_pre(ctx, hs, GSPM_PHASE_PREPROCESS);
     GSPM_HIP(launch_preprocess(*g, P.vt, views->T_cw, P.rs, records, counts, static_cast<uint32_t *>(ctx->trect.p),
                                static_cast<uint32_t *>(ctx->dkey.p), static_cast<uint32_t *>(ctx->dval.p), hs));
+    t_pre.stop();
     if (R > 0) {
         // 2. Order records by float32 depth (stable: ties keep record order).
+        PhaseTimer t_ds(ctx, hs, GSPM_PHASE_DEPTH_SORT);
         GSPM_HIP(radix_sort(static_cast<uint32_t *>(ctx->dkey.p), static_cast<uint32_t *>(ctx->dval.p),
                             static_cast<uint32_t *>(ctx->dkey_tmp.p), static_cast<uint32_t *>(ctx->dval_tmp.p),
                             static_cast<uint32_t *>(ctx->dkey_s.p), static_cast<uint32_t *>(ctx->dval_s.p), R, nullptr,
                             32, db, hist, part, hs));
+        t_ds.stop();
+    }
+    PhaseTimer t_bin(ctx, hs, GSPM_PHASE_BINNING);
+    if (R > 0) {
         // 3. Offsets of each record's tile pairs, in depth order.
         GSPM_HIP(launch_scan_indirect(counts, static_cast<uint32_t *>(ctx->dval_s.p), R,
                                       static_cast<uint32_t *>(ctx->offsets.p), total, part, hs));
@@ -329,18 +374,23 @@ gspm_status gspm_render_forward(gspm_ctx *ctx, const gspm_gaussians *g, const gs
                            static_cast<uint32_t *>(ctx->trect.p), R, g->n > 0 ? g->n : 1, P.vt,
                            static_cast<uint32_t *>(ctx->pkey.p), static_cast<uint32_t *>(ctx->pval.p), hdr,
                            (uint32_t)cap, total, hs));
+    t_bin.stop();
     // 5. Stable sort by tile id; 6. per-tile ranges.
     if (cap > 0) {
+        PhaseTimer t_ts(ctx, hs, GSPM_PHASE_TILE_SORT);
         GSPM_HIP(radix_sort(static_cast<uint32_t *>(ctx->pkey.p), static_cast<uint32_t *>(ctx->pval.p),
                             static_cast<uint32_t *>(ctx->pkey_tmp.p), static_cast<uint32_t *>(ctx->pval_tmp.p),
                             static_cast<uint32_t *>(ctx->pkey_s.p), pair_vals, cap, &hdr->pairs,
                             tile_bits(P.n_tiles), db, hist, part, hs));
+        t_ts.stop();
+        PhaseTimer t_rg(ctx, hs, GSPM_PHASE_BINNING);
         GSPM_HIP(launch_ranges(static_cast<uint32_t *>(ctx->pkey_s.p), hdr, ranges, P.n_tiles, cap, hs));
     }
     // 7. Composite.
+    PhaseTimer t_fwd(ctx, hs, GSPM_PHASE_RASTER_FWD);
     GSPM_HIP(launch_raster_forward(P.vt, P.rs, ranges, pair_vals, records, out->rgb, out->depth, out->alpha,
                                    out->pointmap, at<float>(frame_state, L0.t_final), at<uint32_t>(frame_state, L0.last),
-                                   hs));
+                                   at<uint32_t>(frame_state, L0.contrib), hs));
     return GSPM_OK;
 }
 
@@ -354,6 +404,32 @@ gspm_status gspm_frame_status(const void *frame_state, void *stream, int64_t *pa
     if (pairs) *pairs = h.pairs;
     if (h.overflow)
         return fail(GSPM_ERR_CAPACITY, "tile pairs %u exceed the frame state's capacity %u", h.pairs, h.capacity);
+    return GSPM_OK;
+}
+
+gspm_status gspm_frame_work(gspm_ctx *ctx, const gspm_views *views, int64_t n_gaussians, int32_t tile,
+                            const void *frame_state, void *stream, int64_t *out) {
+    if (!ctx || !frame_state || !out) return fail(GSPM_ERR_INVALID_ARG, "ctx, frame_state and out are required");
+    if (tile != 8 && tile != 16 && tile != 32) return fail(GSPM_ERR_INVALID_ARG, "tile must be 8, 16 or 32");
+    if (n_gaussians < 0) return fail(GSPM_ERR_INVALID_ARG, "n_gaussians < 0");
+    ViewTable vt;
+    int64_t nt, np;
+    gspm_status st = build_views(views, tile, vt, nt, np);
+    if (st) return st;
+    const FrameLayout L = frame_layout(nt, np, n_gaussians * views->n_views, 0);
+    hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+    GSPM_HIP(grow(ctx->misc, 256));
+    unsigned long long *acc = reinterpret_cast<unsigned long long *>(static_cast<char *>(ctx->misc.p) + 64);
+    unsigned long long host[2];
+    GSPM_HIP(launch_sum_u64(at<uint32_t>(frame_state, L.contrib), np, acc, hs));
+    GSPM_HIP(launch_sum_u64(at<uint32_t>(frame_state, L.last), np, acc + 1, hs));
+    FrameHeader h;
+    GSPM_HIP(hipMemcpyAsync(host, acc, sizeof(host), hipMemcpyDeviceToHost, hs));
+    GSPM_HIP(hipMemcpyAsync(&h, frame_state, sizeof(h), hipMemcpyDeviceToHost, hs));
+    GSPM_HIP(hipStreamSynchronize(hs));
+    out[0] = h.pairs;
+    out[1] = (int64_t)host[0];
+    out[2] = (int64_t)host[1];
     return GSPM_OK;
 }
 
@@ -407,6 +483,28 @@ gspm_status gspm_pose_retract(int32_t n_views, float *T_cw, const float *xi, voi
     if (n_views < 1 || n_views > GSPM_MAX_VIEWS) return fail(GSPM_ERR_INVALID_ARG, "n_views out of range");
     if (!T_cw || !xi) return fail(GSPM_ERR_INVALID_ARG, "T_cw and xi are required");
     GSPM_HIP(launch_pose_retract(n_views, T_cw, xi, reinterpret_cast<hipStream_t>(stream)));
+    return GSPM_OK;
+}
+
+gspm_status gspm_timing_enable(gspm_ctx *ctx, int32_t on) {
+    if (!ctx) return fail(GSPM_ERR_INVALID_ARG, "ctx is NULL");
+    ctx->timing = on != 0;
+    return GSPM_OK;
+}
+
+gspm_status gspm_timing_collect(gspm_ctx *ctx, double *ms_out, int64_t *counts_out) {
+    if (!ctx) return fail(GSPM_ERR_INVALID_ARG, "ctx is NULL");
+    for (size_t k = 0; k < ctx->phase_of.size(); ++k) {
+        hipEvent_t b = ctx->pool[2 * k], e = ctx->pool[2 * k + 1];
+        GSPM_HIP(hipEventSynchronize(e));
+        float ms = 0.0f;
+        GSPM_HIP(hipEventElapsedTime(&ms, b, e));
+        const int ph = ctx->phase_of[k];
+        if (ms_out) ms_out[ph] += ms;
+        if (counts_out) counts_out[ph] += 1;
+    }
+    ctx->phase_of.clear();
+    ctx->used = 0;
     return GSPM_OK;
 }
 

@@ -219,7 +219,25 @@ k_ranges(const uint32_t *__restrict__ keys, const FrameHeader *__restrict__ hdr,
     }
 }
 
+__global__ void __launch_bounds__(256) k_sum_u64(const uint32_t *__restrict__ x, int64_t n,
+                                                unsigned long long *__restrict__ out) {
+    unsigned long long acc = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        acc += x[i];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane_id() == 0 && acc) atomicAdd(out, acc);
+}
+
 }  // namespace
+
+hipError_t launch_sum_u64(const uint32_t *x, int64_t n, unsigned long long *out, hipStream_t s) {
+    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(out), 0u, 2, s);
+    if (e != hipSuccess || n <= 0) return e;
+    int64_t nb = (n + 255) / 256;
+    if (nb > 1024) nb = 1024;
+    hipLaunchKernelGGL(k_sum_u64, dim3((unsigned)nb), dim3(256), 0, s, x, n, out);
+    return hipGetLastError();
+}
 
 // ------------------------------- host wrappers ----------------------------------------
 

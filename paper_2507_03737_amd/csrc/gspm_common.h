@@ -60,7 +60,7 @@ struct FrameHeader {
 constexpr uint32_t kFrameMagic = 0x47535046u;  // "GSPF"
 
 struct FrameLayout {
-    int64_t header, ranges, t_final, last, records, pair_vals, total;
+    int64_t header, ranges, t_final, last, contrib, records, pair_vals, total;
 };
 
 inline int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
@@ -72,6 +72,7 @@ inline FrameLayout frame_layout(int64_t n_tiles, int64_t n_pixels, int64_t n_rec
     L.ranges = o;    o += align256(n_tiles * 8);
     L.t_final = o;   o += align256(n_pixels * 4);
     L.last = o;      o += align256(n_pixels * 4);
+    L.contrib = o;   o += align256(n_pixels * 4);
     L.records = o;   o += align256(n_records * kRecFloats * 4);
     L.pair_vals = o; o += align256(cap * 4);
     L.total = o;
@@ -160,13 +161,15 @@ hipError_t launch_keygen(const uint32_t *sorted_rec, const uint32_t *counts, con
                          const ViewTable &vt, uint32_t *pkey, uint32_t *pval, FrameHeader *hdr,
                          uint32_t capacity, const uint32_t *total, hipStream_t s);
 
+hipError_t launch_sum_u64(const uint32_t *x, int64_t n, unsigned long long *out, hipStream_t s);
+
 hipError_t launch_ranges(const uint32_t *sorted_keys, const FrameHeader *hdr, uint2 *ranges,
                          int64_t n_tiles, int64_t n_max, hipStream_t s);
 
 hipError_t launch_raster_forward(const ViewTable &vt, const RasterSettings &rs, const uint2 *ranges,
                                  const uint32_t *pair_vals, const float *records, float *rgb,
                                  float *depth, float *alpha, float *pointmap, float *t_final,
-                                 uint32_t *last, hipStream_t s);
+                                 uint32_t *last, uint32_t *contrib, hipStream_t s);
 
 hipError_t launch_raster_backward(const ViewTable &vt, const RasterSettings &rs, const uint2 *ranges,
                                   const uint32_t *pair_vals, const float *records, const uint32_t *last,

@@ -70,7 +70,7 @@ __global__ void __launch_bounds__(TILE *TILE)
 k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
              const float4 *__restrict__ rec, float *__restrict__ out_rgb, float *__restrict__ out_depth,
              float *__restrict__ out_alpha, float *__restrict__ out_pm, float *__restrict__ t_final,
-             uint32_t *__restrict__ last) {
+             uint32_t *__restrict__ last, uint32_t *__restrict__ contrib) {
     constexpr int NT = TILE * TILE;
     __shared__ float4 s0[NT], s1[NT], s2[NT], s3[NT];
     const TilePos tp = tile_pos<TILE>(vt);
@@ -79,7 +79,7 @@ k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
     const float amin = rs.alpha_min, amax = rs.alpha_max, tmin = rs.t_min;
 
     float T = 1.0f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f, X0 = 0.f, X1 = 0.f, X2 = 0.f;
-    uint32_t n_last = 0;
+    uint32_t n_last = 0, n_contrib = 0;
     bool done = !tp.inside;
     for (uint32_t base = rg.x; base < rg.y; base += NT) {
         const uint32_t k = base + threadIdx.x;
@@ -108,6 +108,7 @@ k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
                 X2 = fmaf(w, s3[q].x, X2);
                 T = Tn;
                 n_last = base - rg.x + (uint32_t)q + 1u;
+                ++n_contrib;
             }
         }
         if (!__syncthreads_or(done ? 0 : 1)) break;
@@ -131,6 +132,7 @@ k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
     out_pm[o3 + 2 * plane] = X2;
     t_final[pix] = T;
     last[pix] = n_last;
+    contrib[pix] = n_contrib;
 }
 
 __device__ inline float load_or0(const float *p, int64_t i) { return p ? p[i] : 0.0f; }
@@ -257,19 +259,20 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
 template <int TILE>
 static void fwd_launch(const ViewTable &vt, const RasterSettings &rs, const uint2 *ranges, const uint32_t *vals,
                        const float *records, float *rgb, float *depth, float *alpha, float *pm, float *t_final,
-                       uint32_t *last, hipStream_t s) {
+                       uint32_t *last, uint32_t *contrib, hipStream_t s) {
     const int n_tiles = vt.tile_off[vt.n_views];
     hipLaunchKernelGGL((k_raster_fwd<TILE>), dim3(n_tiles), dim3(TILE * TILE), 0, s, vt, rs, ranges, vals,
-                       reinterpret_cast<const float4 *>(records), rgb, depth, alpha, pm, t_final, last);
+                       reinterpret_cast<const float4 *>(records), rgb, depth, alpha, pm, t_final, last, contrib);
 }
 
 hipError_t launch_raster_forward(const ViewTable &vt, const RasterSettings &rs, const uint2 *ranges,
                                  const uint32_t *pair_vals, const float *records, float *rgb, float *depth,
-                                 float *alpha, float *pointmap, float *t_final, uint32_t *last, hipStream_t s) {
+                                 float *alpha, float *pointmap, float *t_final, uint32_t *last, uint32_t *contrib,
+                                 hipStream_t s) {
     switch (vt.tile) {
-        case 8: fwd_launch<8>(vt, rs, ranges, pair_vals, records, rgb, depth, alpha, pointmap, t_final, last, s); break;
-        case 32: fwd_launch<32>(vt, rs, ranges, pair_vals, records, rgb, depth, alpha, pointmap, t_final, last, s); break;
-        default: fwd_launch<16>(vt, rs, ranges, pair_vals, records, rgb, depth, alpha, pointmap, t_final, last, s); break;
+        case 8: fwd_launch<8>(vt, rs, ranges, pair_vals, records, rgb, depth, alpha, pointmap, t_final, last, contrib, s); break;
+        case 32: fwd_launch<32>(vt, rs, ranges, pair_vals, records, rgb, depth, alpha, pointmap, t_final, last, contrib, s); break;
+        default: fwd_launch<16>(vt, rs, ranges, pair_vals, records, rgb, depth, alpha, pointmap, t_final, last, contrib, s); break;
     }
     return hipGetLastError();
 }

@@ -117,6 +117,10 @@ class Rasterizer:
             except B.CapacityError as e:
                 self.max_pairs = int(e.pairs * 1.25) + 1024
 
+    def work(self, frame_state, stream=None):
+        """(tile pairs, contributing fragments F, evaluated-list bound) of a forward."""
+        return B.frame_work(self.ctx, self.win.c(), self.n, self.cfg.tile, frame_state, B.stream_handle(stream))
+
     def backward_into(self, params, fwd, up, frame_state, grads=None, pose_grad=None, stream=None):
         g = _params(params)
         f = B.Images(B.ptr(fwd["rgb"]), B.ptr(fwd["depth"]), B.ptr(fwd["alpha"]), B.ptr(fwd["pointmap"]))
