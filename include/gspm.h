@@ -193,7 +193,7 @@ GSPM_API gspm_status gspm_pose_backward(gspm_ctx *ctx, const gspm_gaussians *g, 
 /* ---- patch scale and mapping loss (Sec. 3.3.1, Eq. 10, 15, 17) --------------------- */
 
 /* Per-patch least-squares scale aligning a prior pointmap Xp to the rendered one Xr:
- * for every patch x patch block of every view (partial at the right/bottom border),
+ * patch in [1, 64]; for every patch x patch block of every view (partial at the right/bottom border),
  * scale = sum(Xr . Xp) / sum(|Xp|^2) over pixels with mask != 0 (mask NULL = all), or
  * 1 when sum(|Xp|^2) = 0.  Xr, Xp: packed [3][H][W] per view; mask: packed [H][W] or
  * NULL.  scale_out (float) and count_out (int32, may be NULL): per view
@@ -207,8 +207,9 @@ GSPM_API gspm_status gspm_patch_scale_align(const gspm_views *views, const float
  * with s the per-patch scale of gspm_patch_scale_align computed in the same pass
  * (between pm and Xp, held constant) and means over 3 H W elements.  Writes
  * scale_out as above, loss_out [V] (device, overwritten), and the gradients
- * grad_rgb, grad_pm (packed planes, overwritten; sign(0) = 0). */
-GSPM_API gspm_status gspm_window_loss(const gspm_views *views, const float *rgb, const float *rgb_target,
+ * grad_rgb, grad_pm (packed planes, overwritten; sign(0) = 0).  The context provides
+ * scratch for the per-view loss partial sums. */
+GSPM_API gspm_status gspm_window_loss(gspm_ctx *ctx, const gspm_views *views, const float *rgb, const float *rgb_target,
                              const float *pm, const float *Xp, int32_t patch, float alpha,
                              float *scale_out, float *loss_out, float *grad_rgb, float *grad_pm,
                              void *stream);

@@ -37,8 +37,10 @@
  * Ambiguity flags.  A float32 implementation may take a different discrete decision
  * than this oracle where a value sits on a threshold.  Each pixel is flagged when,
  * within a first-order float32 error bound (times a safety factor), a fragment's alpha
- * is at alpha_min or alpha_max, a transmittance step is at t_min, or two contributing
- * fragments have the same float32 depth.  Parity tests compare unflagged pixels only.
+ * is at alpha_min or alpha_max or a transmittance step is at t_min, or when two
+ * consecutive contributing fragments would swap places under an ordering by (float32
+ * depth, index): equal float32 depths, different double depths, indices in the opposite
+ * order.  Parity tests compare unflagged pixels only.
  */
 #include <math.h>
 #include <stdint.h>
@@ -331,6 +333,8 @@ static int64_t composite(const orc_gaussians *G, const orc_proj *P, const orc_vi
     int64_t nf = 0;
     int amb = 0;
     float last_z32 = 0.0f;
+    double last_z64 = 0.0;
+    int64_t last_g = -1;
     int have_last = 0;
     int64_t looked = 0;
     for (int64_t k = 0; k < nc; ++k) {
@@ -352,12 +356,17 @@ static int64_t composite(const orc_gaussians *G, const orc_proj *P, const orc_vi
         if (alpha > S->alpha_max) { alpha = S->alpha_max; clamped = 1; }
         const double Tn = T * (1.0 - alpha);
         const double errTn = errT + (clamped ? 0.0 : erra * alpha / (1.0 - alpha)) + 4.0 * ORC_EPS32;
-        if (fabs(Tn - S->t_min) <= 4.0 * errTn * S->t_min) amb |= 2;
+        if (fabs(Tn - S->t_min) <= errTn * S->t_min) amb |= 2;
         if (Tn < S->t_min) break;
-        /* Depth tie in float32 between consecutive contributing fragments. */
+        /* An implementation that orders by (float32 depth, index) reverses two
+         * consecutive contributing fragments exactly when their depths differ in double
+         * precision, round to the same float32 value and their indices are in the
+         * opposite order. */
         const float z32 = (float)p->z;
-        if (have_last && z32 == last_z32) amb |= 8;
+        if (have_last && z32 == last_z32 && p->z != last_z64 && cand[k].g < last_g) amb |= 8;
         last_z32 = z32;
+        last_z64 = p->z;
+        last_g = cand[k].g;
         have_last = 1;
 
         const double w = alpha * T;

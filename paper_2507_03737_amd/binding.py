@@ -97,7 +97,7 @@ def load(path: str = LIB_PATH):
                                        P(GaussianGrads), vp, vp]
     L.gspm_pose_backward.argtypes = [vp, P(Gaussians), P(Views), P(Settings), P(Images), P(Images), vp, vp, vp]
     L.gspm_patch_scale_align.argtypes = [P(Views), vp, vp, vp, ctypes.c_int32, vp, vp, vp]
-    L.gspm_window_loss.argtypes = [P(Views), vp, vp, vp, vp, ctypes.c_int32, ctypes.c_float, vp, vp, vp, vp, vp]
+    L.gspm_window_loss.argtypes = [vp, P(Views), vp, vp, vp, vp, ctypes.c_int32, ctypes.c_float, vp, vp, vp, vp, vp]
     L.gspm_pose_retract.argtypes = [ctypes.c_int32, vp, vp, vp]
     L.gspm_frame_work.argtypes = [vp, P(Views), ctypes.c_int64, ctypes.c_int32, vp, vp, P(ctypes.c_int64)]
     L.gspm_timing_enable.argtypes = [vp, ctypes.c_int32]
@@ -243,8 +243,9 @@ def patch_scale_align(views: Views, Xr, Xp, mask, patch, scale_out, count_out, s
                                         ptr(scale_out), ptr(count_out), stream))
 
 
-def window_loss(views: Views, rgb, rgb_target, pm, Xp, patch, alpha, scale_out, loss_out, grad_rgb, grad_pm, stream):
-    check(load().gspm_window_loss(ctypes.byref(views), ptr(rgb), ptr(rgb_target), ptr(pm), ptr(Xp), int(patch),
+def window_loss(ctx: Context, views: Views, rgb, rgb_target, pm, Xp, patch, alpha, scale_out, loss_out, grad_rgb,
+                grad_pm, stream):
+    check(load().gspm_window_loss(ctx.h, ctypes.byref(views), ptr(rgb), ptr(rgb_target), ptr(pm), ptr(Xp), int(patch),
                                   float(alpha), ptr(scale_out), ptr(loss_out), ptr(grad_rgb), ptr(grad_pm), stream))
 
 

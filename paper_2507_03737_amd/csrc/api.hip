@@ -72,7 +72,7 @@ struct gspm_ctx {
     // Per pair (capacity).
     DevBuf pkey, pval, pkey_tmp, pval_tmp, pkey_s;
     // Small scratch.
-    DevBuf hist, scan_part, misc, pose_part;
+    DevBuf hist, scan_part, misc, pose_part, loss_part;
 };
 
 namespace {
@@ -281,7 +281,7 @@ void gspm_destroy(gspm_ctx *ctx) {
     DevBuf *bufs[] = {&ctx->counts, &ctx->trect, &ctx->dkey, &ctx->dval, &ctx->dkey_tmp, &ctx->dval_tmp,
                       &ctx->dkey_s, &ctx->dval_s, &ctx->offsets, &ctx->grad2d, &ctx->pkey, &ctx->pval,
                       &ctx->pkey_tmp, &ctx->pval_tmp, &ctx->pkey_s, &ctx->hist, &ctx->scan_part, &ctx->misc,
-                      &ctx->pose_part};
+                      &ctx->pose_part, &ctx->loss_part};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
@@ -448,34 +448,40 @@ gspm_status gspm_pose_backward(gspm_ctx *ctx, const gspm_gaussians *g, const gsp
     return backward_common(ctx, g, views, s, fwd_out, grad_out, frame_state, nullptr, pose_grad, true, stream);
 }
 
-static gspm_status patch_common(const gspm_views *views, const float *Xr, const float *Xp, const float *mask,
-                                int32_t patch, const float *rgb, const float *rgb_target, float alpha,
-                                float *scale_out, int32_t *count_out, float *loss_out, float *grad_rgb,
+static gspm_status patch_common(gspm_ctx *ctx, const gspm_views *views, const float *Xr, const float *Xp,
+                                const float *mask, int32_t patch, const float *rgb, const float *rgb_target,
+                                float alpha, float *scale_out, int32_t *count_out, float *loss_out, float *grad_rgb,
                                 float *grad_pm, void *stream) {
     ViewTable vt;
     int64_t nt, np;
     gspm_status st = build_views(views, 16, vt, nt, np);
     if (st) return st;
-    if (patch < 1 || patch > 256) return fail(GSPM_ERR_INVALID_ARG, "patch = %d outside [1, 256]", patch);
+    if (patch < 1 || patch > 64) return fail(GSPM_ERR_INVALID_ARG, "patch = %d outside [1, 64]", patch);
     if (!Xr || !Xp || !scale_out) return fail(GSPM_ERR_INVALID_ARG, "Xr, Xp and scale_out are required");
-    GSPM_HIP(launch_patch_loss(vt, Xr, Xp, mask, patch, rgb, rgb_target, alpha, scale_out, count_out, loss_out,
+    double *part = nullptr;
+    if (grad_rgb) {
+        GSPM_HIP(grow(ctx->loss_part, 8 * (patch_loss_partials(vt, patch) + 1)));
+        part = static_cast<double *>(ctx->loss_part.p);
+    }
+    GSPM_HIP(launch_patch_loss(vt, Xr, Xp, mask, patch, rgb, rgb_target, alpha, scale_out, count_out, part, loss_out,
                                grad_rgb, grad_pm, reinterpret_cast<hipStream_t>(stream)));
     return GSPM_OK;
 }
 
 gspm_status gspm_patch_scale_align(const gspm_views *views, const float *Xr, const float *Xp, const float *mask,
                                    int32_t patch, float *scale_out, int32_t *count_out, void *stream) {
-    return patch_common(views, Xr, Xp, mask, patch, nullptr, nullptr, 0.0f, scale_out, count_out, nullptr, nullptr,
-                        nullptr, stream);
+    return patch_common(nullptr, views, Xr, Xp, mask, patch, nullptr, nullptr, 0.0f, scale_out, count_out, nullptr,
+                        nullptr, nullptr, stream);
 }
 
-gspm_status gspm_window_loss(const gspm_views *views, const float *rgb, const float *rgb_target, const float *pm,
-                             const float *Xp, int32_t patch, float alpha, float *scale_out, float *loss_out,
-                             float *grad_rgb, float *grad_pm, void *stream) {
+gspm_status gspm_window_loss(gspm_ctx *ctx, const gspm_views *views, const float *rgb, const float *rgb_target,
+                             const float *pm, const float *Xp, int32_t patch, float alpha, float *scale_out,
+                             float *loss_out, float *grad_rgb, float *grad_pm, void *stream) {
+    if (!ctx) return fail(GSPM_ERR_INVALID_ARG, "ctx is NULL");
     if (!rgb || !rgb_target || !loss_out || !grad_rgb || !grad_pm)
         return fail(GSPM_ERR_INVALID_ARG, "rgb, rgb_target, loss_out, grad_rgb and grad_pm are required");
     if (!(alpha >= 0.0f && alpha <= 1.0f)) return fail(GSPM_ERR_INVALID_ARG, "alpha must lie in [0, 1]");
-    return patch_common(views, pm, Xp, nullptr, patch, rgb, rgb_target, alpha, scale_out, nullptr, loss_out,
+    return patch_common(ctx, views, pm, Xp, nullptr, patch, rgb, rgb_target, alpha, scale_out, nullptr, loss_out,
                         grad_rgb, grad_pm, stream);
 }
 

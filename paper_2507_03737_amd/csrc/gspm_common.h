@@ -103,6 +103,61 @@ __device__ inline float wave_total(float x) {
     return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, wave_sum_to_lane63(x)), 63));
 }
 
+#define GSPM_DPP_MOV(x, ctrl)                                                              \
+    __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, (x)), \
+                                                          (ctrl), 0xf, 0xf, true))
+
+// gfx950 cross-half lane swaps.  After permlane32_swap(a, b): a = (a[0:32], b[0:32]) and
+// b = (a[32:64], b[32:64]); after permlane16_swap(a, b) the odd 16-lane rows of a and
+// the even rows of b are exchanged.  (Written as single instructions: this compiler's
+// two-result builtins return the first result twice.)  The s_nop pairs give the wait
+// states a VALU result needs before and after a lane-permute instruction.
+__device__ inline void permlane32_swap(float &a, float &b) {
+    asm volatile("s_nop 1\n\tv_permlane32_swap_b32 %0, %1\n\ts_nop 1" : "+v"(a), "+v"(b));
+}
+__device__ inline void permlane16_swap(float &a, float &b) {
+    asm volatile("s_nop 1\n\tv_permlane16_swap_b32 %0, %1\n\ts_nop 1" : "+v"(a), "+v"(b));
+}
+
+// Reduce-scatter of 16 per-lane values over a wave of 64 lanes.  On return, every lane
+// of quad q (lanes 4q .. 4q+3) holds the wave-wide sum of v[q & 15].  Lane bits 5 and 4
+// are folded with the cross-half swaps, bits 3 and 2 with DPP row rotations/shifts, and
+// bits 1 and 0 are fully reduced inside the quad.  Each fold halves the number of live
+// values, so the whole reduction costs 15 exchanges instead of 6 per value.
+__device__ inline float wave_reduce_scatter16(const float (&v)[16]) {
+    const int lane = lane_id();
+    float a[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        float x = v[k], y = v[k + 8];
+        permlane32_swap(x, y);
+        a[k] = x + y;  // lanes 0-31: total of v[k]; lanes 32-63: total of v[k + 8]
+    }
+    float b[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        float x = a[k], y = a[k + 4];
+        permlane16_swap(x, y);
+        b[k] = x + y;  // even rows keep a[k], odd rows a[k + 4]
+    }
+    const bool b3 = (lane >> 3) & 1, b2 = (lane >> 2) & 1;
+    float c[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const float send = b3 ? b[k] : b[k + 2];
+        const float keep = b3 ? b[k + 2] : b[k];
+        c[k] = keep + GSPM_DPP_MOV(send, 0x128);  // row_ror:8 == lane xor 8 within a row
+    }
+    const float send = b2 ? c[0] : c[1];
+    const float keep = b2 ? c[1] : c[0];
+    const float from_hi = GSPM_DPP_MOV(send, 0x104);  // row_shl:4: lane l reads lane l + 4
+    const float from_lo = GSPM_DPP_MOV(send, 0x114);  // row_shr:4: lane l reads lane l - 4
+    float d = keep + (b2 ? from_lo : from_hi);
+    d += GSPM_DPP_MOV(d, 0x4e);  // quad_perm [2,3,0,1]
+    d += GSPM_DPP_MOV(d, 0xb1);  // quad_perm [1,0,3,2]
+    return d;
+}
+
 // Wave-wide inclusive prefix sum of a uint32 (Hillis-Steele over cross-lane reads).
 __device__ inline uint32_t wave_inclusive_scan(uint32_t x) {
     const int lane = lane_id();
@@ -185,10 +240,11 @@ int64_t pose_partial_blocks(int64_t n);
 hipError_t launch_pose_reduce(const double *pose_partials, int64_t n_blocks, int n_views,
                               float *pose_grad, hipStream_t s);
 
+int64_t patch_loss_partials(const ViewTable &vt, int patch);
 hipError_t launch_patch_loss(const ViewTable &vt, const float *Xr, const float *Xp, const float *mask,
                              int patch, const float *rgb, const float *rgb_target, float alpha,
-                             float *scale_out, int32_t *count_out, float *loss_out, float *grad_rgb,
-                             float *grad_pm, hipStream_t s);
+                             float *scale_out, int32_t *count_out, double *loss_part, float *loss_out,
+                             float *grad_rgb, float *grad_pm, hipStream_t s);
 
 hipError_t launch_pose_retract(int n_views, float *T_cw, const float *xi, hipStream_t s);
 

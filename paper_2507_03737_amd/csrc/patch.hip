@@ -3,112 +3,160 @@
 // gradient of the mapping loss (Eq. 17 without the isotropic term: the photometric L1
 // of Eq. 10 and the pointmap L1 of Eq. 15 against the scale-aligned prior).
 //
-// One wave per patch.  Pass 1 reduces sum(Xr . Xp), sum |Xp|^2 and the pixel count in
-// float64; pass 2 (loss only) revisits the same pixels, which are now in cache, and
-// writes sign-based L1 gradients.  Both passes touch each pixel's planes once, so the
-// kernel streams at HBM rate.
+// One wave per strip of floor(64 / P) horizontally adjacent P x P patches: lane l owns
+// image column x0 + l and walks the P rows of the strip, so every load and store is a
+// 256-byte row segment.  Column sums (float64) are folded per patch through LDS, the
+// scale is formed, and the same lanes revisit their (now cached) pixels to write the
+// sign-based L1 gradients.  Loss partials go to one slot per wave and are summed per view
+// in a fixed order by a second small kernel.
 #include "gspm_common.h"
 
 namespace gspm {
 
 namespace {
 
-__device__ inline double wave_sum_d(double x) {
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-    return x;
-}
+constexpr int kPatchBlock = 256;
+constexpr int kPatchWaves = kPatchBlock / kWave;
 
 __device__ inline float sgn(float x) { return x > 0.f ? 1.f : (x < 0.f ? -1.f : 0.f); }
 
-struct PatchTable {
+struct StripTable {
     int32_t n_views;
-    int32_t npx[kMaxViews];          // patches per row
+    int32_t patch, per_wave;          // P, patches per wave strip
+    int32_t npx[kMaxViews];           // patches per row
+    int32_t strips_x[kMaxViews];      // strips per patch row
     int32_t patch_off[kMaxViews + 1];
+    int32_t wave_off[kMaxViews + 1];
 };
 
-__global__ void __launch_bounds__(256)
-k_patch_loss(ViewTable vt, PatchTable pt, int P, const float *__restrict__ Xr, const float *__restrict__ Xp,
+__global__ void __launch_bounds__(kPatchBlock)
+k_patch_loss(ViewTable vt, StripTable st, const float *__restrict__ Xr, const float *__restrict__ Xp,
              const float *__restrict__ mask, const float *__restrict__ rgb, const float *__restrict__ target,
              float alpha, float *__restrict__ scale_out, int32_t *__restrict__ count_out,
-             float *__restrict__ loss_out, float *__restrict__ grad_rgb, float *__restrict__ grad_pm) {
-    const int lane = lane_id();
-    const int64_t gp = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-    if (gp >= pt.patch_off[pt.n_views]) return;  // wave-uniform
+             double *__restrict__ loss_part, float *__restrict__ grad_rgb, float *__restrict__ grad_pm) {
+    __shared__ double lds[kPatchWaves][3][kWave];
+    __shared__ float scale_lds[kPatchWaves][kWave];
+    const int lane = lane_id(), wid = threadIdx.x / kWave;
+    const int64_t gw = (int64_t)blockIdx.x * kPatchWaves + wid;
+    const bool live = gw < st.wave_off[st.n_views];
     int v = 0;
-    for (int k = 1; k < pt.n_views; ++k)
-        if (gp >= pt.patch_off[k]) v = k;
-    const int lp = (int)(gp - pt.patch_off[v]);
+    for (int k = 1; k < st.n_views; ++k)
+        if (gw >= st.wave_off[k]) v = k;
+    const int P = st.patch, per = st.per_wave;
+    const int lw = live ? (int)(gw - st.wave_off[v]) : 0;
+    const int py = lw / st.strips_x[v], sx = lw % st.strips_x[v];
     const int W = vt.width[v], H = vt.height[v];
-    const int x0 = (lp % pt.npx[v]) * P, y0 = (lp / pt.npx[v]) * P;
-    const int64_t plane = (int64_t)W * H;
-    const int64_t o1 = vt.pix_off[v], o3 = 3 * vt.pix_off[v];
-    const int npix = P * P;
+    const int g = lane / P;                     // patch within the strip
+    const int px = sx * per + g;                // patch column
+    const int x = sx * per * P + lane;          // image column of this lane
+    const bool col = live && g < per && px < st.npx[v] && x < W;
+    const int y0 = py * P, y1 = min(H, y0 + P);
+    const int64_t plane = (int64_t)W * H, o1 = vt.pix_off[v], o3 = 3 * vt.pix_off[v];
 
     double sxy = 0.0, syy = 0.0, cnt = 0.0;
-    for (int q = lane; q < npix; q += kWave) {
-        const int i = x0 + q % P, j = y0 + q / P;
-        if (i >= W || j >= H) continue;
-        const int64_t e = (int64_t)j * W + i;
-        if (mask && mask[o1 + e] == 0.f) continue;
-        const float r0 = Xr[o3 + e], r1 = Xr[o3 + plane + e], r2 = Xr[o3 + 2 * plane + e];
-        const float p0 = Xp[o3 + e], p1 = Xp[o3 + plane + e], p2 = Xp[o3 + 2 * plane + e];
-        sxy += (double)r0 * p0 + (double)r1 * p1 + (double)r2 * p2;
-        syy += (double)p0 * p0 + (double)p1 * p1 + (double)p2 * p2;
-        cnt += 1.0;
-    }
-    sxy = wave_sum_d(sxy);
-    syy = wave_sum_d(syy);
-    cnt = wave_sum_d(cnt);
-    const float s = syy > 0.0 ? (float)(sxy / syy) : 1.0f;
-    if (lane == 0) {
-        scale_out[gp] = s;
-        if (count_out) count_out[gp] = (int32_t)cnt;
-    }
-    if (!grad_rgb) return;
-
-    const float inv_n = 1.0f / (float)(3 * plane);
-    const float wp = alpha * inv_n, wg = (1.0f - alpha) * inv_n;
-    double lsum = 0.0;
-    for (int q = lane; q < npix; q += kWave) {
-        const int i = x0 + q % P, j = y0 + q / P;
-        if (i >= W || j >= H) continue;
-        const int64_t e = (int64_t)j * W + i;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const int64_t a = o3 + c * plane + e;
-            const float dp = rgb[a] - target[a];
-            const float dg = Xr[a] - s * Xp[a];
-            grad_rgb[a] = wp * sgn(dp);
-            grad_pm[a] = wg * sgn(dg);
-            lsum += (double)wp * fabsf(dp) + (double)wg * fabsf(dg);
+    if (col) {
+        for (int y = y0; y < y1; ++y) {
+            const int64_t e = (int64_t)y * W + x;
+            if (mask && mask[o1 + e] == 0.f) continue;
+            const float r0 = Xr[o3 + e], r1 = Xr[o3 + plane + e], r2 = Xr[o3 + 2 * plane + e];
+            const float p0 = Xp[o3 + e], p1 = Xp[o3 + plane + e], p2 = Xp[o3 + 2 * plane + e];
+            sxy += (double)r0 * p0 + (double)r1 * p1 + (double)r2 * p2;
+            syy += (double)p0 * p0 + (double)p1 * p1 + (double)p2 * p2;
+            cnt += 1.0;
         }
     }
-    lsum = wave_sum_d(lsum);
-    if (lane == 0) atomicAdd(loss_out + v, (float)lsum);
+    lds[wid][0][lane] = sxy;
+    lds[wid][1][lane] = syy;
+    lds[wid][2][lane] = cnt;
+    __syncthreads();
+    if (live && lane < per) {
+        const int pcol = sx * per + lane;
+        if (pcol < st.npx[v]) {
+            double a = 0.0, b = 0.0, c = 0.0;
+            for (int k = 0; k < P; ++k) {
+                a += lds[wid][0][lane * P + k];
+                b += lds[wid][1][lane * P + k];
+                c += lds[wid][2][lane * P + k];
+            }
+            const float s = b > 0.0 ? (float)(a / b) : 1.0f;
+            const int64_t pid = st.patch_off[v] + (int64_t)py * st.npx[v] + pcol;
+            scale_out[pid] = s;
+            if (count_out) count_out[pid] = (int32_t)c;
+            scale_lds[wid][lane] = s;
+        }
+    }
+    __syncthreads();
+    if (!grad_rgb) return;
+
+    double lsum = 0.0;
+    if (col) {
+        const float s = scale_lds[wid][g];
+        const float inv_n = 1.0f / (float)(3 * plane);
+        const float wp = alpha * inv_n, wg = (1.0f - alpha) * inv_n;
+        for (int y = y0; y < y1; ++y) {
+            const int64_t e = (int64_t)y * W + x;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const int64_t a = o3 + c * plane + e;
+                const float dp = rgb[a] - target[a];
+                const float dg = Xr[a] - s * Xp[a];
+                grad_rgb[a] = wp * sgn(dp);
+                grad_pm[a] = wg * sgn(dg);
+                lsum += (double)wp * fabsf(dp) + (double)wg * fabsf(dg);
+            }
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off, 64);
+    if (live && lane == 0) loss_part[gw] = lsum;
+}
+
+// loss[v] = sum of the wave partials of view v, in wave order.
+__global__ void __launch_bounds__(256) k_loss_reduce(StripTable st, const double *__restrict__ part,
+                                                     float *__restrict__ loss) {
+    __shared__ double lds[4];
+    const int v = blockIdx.x;
+    double acc = 0.0;
+    for (int w = st.wave_off[v] + threadIdx.x; w < st.wave_off[v + 1]; w += blockDim.x) acc += part[w];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane_id() == 0) lds[threadIdx.x / 64] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) loss[v] = (float)(lds[0] + lds[1] + lds[2] + lds[3]);
+}
+
+StripTable strip_table(const ViewTable &vt, int patch) {
+    StripTable st;
+    st.n_views = vt.n_views;
+    st.patch = patch;
+    st.per_wave = kWave / patch;
+    st.patch_off[0] = 0;
+    st.wave_off[0] = 0;
+    for (int v = 0; v < vt.n_views; ++v) {
+        const int npx = (vt.width[v] + patch - 1) / patch, npy = (vt.height[v] + patch - 1) / patch;
+        st.npx[v] = npx;
+        st.strips_x[v] = (npx + st.per_wave - 1) / st.per_wave;
+        st.patch_off[v + 1] = st.patch_off[v] + npx * npy;
+        st.wave_off[v + 1] = st.wave_off[v] + st.strips_x[v] * npy;
+    }
+    return st;
 }
 
 }  // namespace
 
+int64_t patch_loss_partials(const ViewTable &vt, int patch) {
+    return strip_table(vt, patch).wave_off[vt.n_views];
+}
+
 hipError_t launch_patch_loss(const ViewTable &vt, const float *Xr, const float *Xp, const float *mask, int patch,
                              const float *rgb, const float *rgb_target, float alpha, float *scale_out,
-                             int32_t *count_out, float *loss_out, float *grad_rgb, float *grad_pm, hipStream_t s) {
-    PatchTable pt;
-    pt.n_views = vt.n_views;
-    pt.patch_off[0] = 0;
-    for (int v = 0; v < vt.n_views; ++v) {
-        const int npx = (vt.width[v] + patch - 1) / patch, npy = (vt.height[v] + patch - 1) / patch;
-        pt.npx[v] = npx;
-        pt.patch_off[v + 1] = pt.patch_off[v] + npx * npy;
-    }
-    const int64_t total = pt.patch_off[vt.n_views];
-    if (total <= 0) return hipSuccess;
-    if (grad_rgb) {
-        hipError_t e = launch_fill_f32(loss_out, 0.0f, vt.n_views, s);
-        if (e != hipSuccess) return e;
-    }
-    const int per_block = 256 / kWave;
-    hipLaunchKernelGGL(k_patch_loss, dim3((unsigned)((total + per_block - 1) / per_block)), dim3(256), 0, s, vt, pt,
-                       patch, Xr, Xp, mask, rgb, rgb_target, alpha, scale_out, count_out, loss_out, grad_rgb, grad_pm);
+                             int32_t *count_out, double *loss_part, float *loss_out, float *grad_rgb,
+                             float *grad_pm, hipStream_t s) {
+    const StripTable st = strip_table(vt, patch);
+    const int64_t waves = st.wave_off[vt.n_views];
+    if (waves <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_patch_loss, dim3((unsigned)((waves + kPatchWaves - 1) / kPatchWaves)), dim3(kPatchBlock), 0,
+                       s, vt, st, Xr, Xp, mask, rgb, rgb_target, alpha, scale_out, count_out, loss_part, grad_rgb,
+                       grad_pm);
+    if (grad_rgb) hipLaunchKernelGGL(k_loss_reduce, dim3(vt.n_views), dim3(256), 0, s, st, loss_part, loss_out);
     return hipGetLastError();
 }
 

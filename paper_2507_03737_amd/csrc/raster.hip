@@ -12,8 +12,9 @@
 // state is stored: only the per-pixel count of list entries up to the last contributing
 // fragment.  The suffix sums that the alpha derivative needs are recovered as
 // (sum over all fragments) - (prefix sum), the total coming from the forward's outputs.
-// Per-record gradients are summed across the 64 lanes of a wave with DPP row
-// operations, then 13 lanes issue one float atomic each.
+// Per-record gradients (13 values) are summed across the 64 lanes of a wave with one
+// reduce-scatter (cross-half lane swaps and DPP), after which 13 lanes each hold one
+// total and issue one float atomic.
 #include "gspm_common.h"
 
 namespace gspm {
@@ -206,9 +207,9 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
             float g2;
             const float al = frag_alpha(dx, dy, a.z, a.w, b.x, b.y, amax, g2);
             const bool valid = (rel0 + (uint32_t)q < my_last) && !(al < amin);
-            float v[kG2Used];
+            float v[16];
 #pragma unroll
-            for (int t = 0; t < kG2Used; ++t) v[t] = 0.f;
+            for (int t = 0; t < 16; ++t) v[t] = 0.f;
             if (valid) {
                 const float4 c = s2[q];
                 const float pz = s3[q].x;
@@ -216,7 +217,7 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
                 const float s = gC0 * b.w + gC1 * c.x + gC2 * c.y + gD * b.z + gA + gX0 * c.z + gX1 * c.w + gX2 * pz;
                 Pfx = fmaf(w, s, Pfx);
                 const float one_m = __fsub_rn(1.0f, al);
-                const float dLda = T * s - (Gtot - Pfx + bgterm) / one_m;
+                const float dLda = T * s - (Gtot - Pfx + bgterm) * __builtin_amdgcn_rcpf(one_m);
                 if (!(b.y * g2 > amax)) {
                     const float Gl = dLda * al * kLn2;
                     v[0] = -Gl * (2.0f * a.z * dx + a.w * dy);
@@ -238,16 +239,11 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
                 T = __fmul_rn(T, one_m);
             }
             if (__ballot(valid) == 0ull) continue;
-            float mine = 0.f;
-#pragma unroll
-            for (int t = 0; t < kG2Used; ++t) {
-                if (POSE_ONLY && (t == 5 || t == 7 || t == 8 || t == 9)) continue;
-                const float tot = wave_total(v[t]);
-                mine = (lane == t) ? tot : mine;
-            }
-            if (lane < kG2Used && mine != 0.f) {
+            const float tot = wave_reduce_scatter16(v);
+            const int idx = (lane >> 2) & 15;
+            if ((lane & 3) == 0 && idx < kG2Used && tot != 0.f) {
                 const uint32_t r = __float_as_uint(s3[q].y);
-                unsafeAtomicAdd(grad2d + (int64_t)r * kG2 + lane, mine);
+                unsafeAtomicAdd(grad2d + (int64_t)r * kG2 + idx, tot);
             }
         }
         __syncthreads();

@@ -150,7 +150,7 @@ class Rasterizer:
         return scale, count
 
     def window_loss_into(self, rgb, target, pm, Xp, patch, alpha, scale, loss, grad_rgb, grad_pm, stream=None):
-        B.window_loss(self.win.c(), rgb, target, pm, Xp, patch, alpha, scale, loss, grad_rgb, grad_pm,
+        B.window_loss(self.ctx, self.win.c(), rgb, target, pm, Xp, patch, alpha, scale, loss, grad_rgb, grad_pm,
                       B.stream_handle(stream))
 
 

@@ -102,8 +102,11 @@ def test_backward_and_loss_argument_errors(L):
                                   None) == B.GSPM_ERR_INVALID_ARG
     assert L.gspm_patch_scale_align(ctypes.byref(v), 1, 1, None, 0, 1, None, None) == B.GSPM_ERR_INVALID_ARG
     assert L.gspm_patch_scale_align(ctypes.byref(v), None, 1, None, 8, 1, None, None) == B.GSPM_ERR_INVALID_ARG
-    assert L.gspm_window_loss(ctypes.byref(v), 1, 1, 1, 1, 8, ctypes.c_float(1.5), 1, 1, 1, 1,
+    assert L.gspm_window_loss(ctx, ctypes.byref(v), 1, 1, 1, 1, 8, ctypes.c_float(1.5), 1, 1, 1, 1,
                               None) == B.GSPM_ERR_INVALID_ARG
+    assert L.gspm_window_loss(None, ctypes.byref(v), 1, 1, 1, 1, 8, ctypes.c_float(0.5), 1, 1, 1, 1,
+                              None) == B.GSPM_ERR_INVALID_ARG
+    assert L.gspm_patch_scale_align(ctypes.byref(v), 1, 1, None, 65, 1, None, None) == B.GSPM_ERR_INVALID_ARG
     assert L.gspm_pose_retract(0, 1, 1, None) == B.GSPM_ERR_INVALID_ARG
     L.gspm_destroy(ctx)
 

@@ -1,0 +1,221 @@
+"""GPU tests of the windowed (multi-view) path, the patch scale / loss kernel, graph
+capture, the autograd function, and full-size parity on sampled crops."""
+import numpy as np
+import pytest
+
+from paper_2507_03737_amd import scenes
+from tests import gpu_util as U
+from tests.test_gpu_parity import (_gpu_backward, _oracle_backward, _oracle_settings, _pack, _posed,
+                                   _render_gpu, _upstream)
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2507_03737_amd import binding
+    binding.load()
+    return binding
+
+
+def _window_scene(n=3000, seed=11):
+    """Three views of uneven size around one cloud of Gaussians."""
+    sc = scenes.make_scene("c0", seed=seed, n=n)
+    sc.cams = [scenes.Camera(160, 120, 128.0, 128.0, 80.0, 60.0), scenes.Camera(123, 77, 100.0, 100.0, 61.5, 38.5),
+               scenes.Camera(200, 64, 150.0, 150.0, 100.0, 32.0)]
+    T0 = sc.T_cw[0]
+    sc.T_cw = np.stack([scenes.perturb_pose(T0, 2.0 * k, 0.2 * k, 40 + k) for k in range(3)])
+    return sc
+
+
+def test_window_forward_backward_vs_oracle(lib, oracle):
+    U.log("[gpu] 3-view window fwd/bwd vs oracle")
+    O = oracle
+    sc = _window_scene()
+    cfg = lib.RasterConfig(pointmap_frame=1)
+    rast, params, out, fs = _render_gpu(lib, sc, cfg)
+    S = _oracle_settings(O, cfg)
+    po = O.Params.from_scene(sc)
+    oks = []
+    from tests.test_gpu_parity import _check_view_forward
+    for v, cam in enumerate(sc.cams):
+        ref = _check_view_forward(O, sc, v, out, rast.win.pix_off[v], cfg, tag=f"win v{v}")
+        oks.append(ref["ambiguous"].reshape(cam.height, cam.width) == 0)
+    ups = _upstream(sc, 5, oks)
+    g = _gpu_backward(lib, rast, params, out, fs, ups)
+    r = _oracle_backward(O, sc, cfg, ups)
+    for k in ("means", "log_scales", "quats", "opacity_logit", "rgb"):
+        U.log(f"  {k}: rel {U.check_grad('win ' + k, g[k], r[k]):.2e}")
+    for v in range(3):
+        U.check_grad(f"win pose v{v}", g["pose"][v], r["pose"][v], frac=1.0)
+
+
+def test_batched_equals_per_view(lib):
+    U.log("[gpu] batched window == per-view renders")
+    from paper_2507_03737_amd.render import Rasterizer, Window
+    sc = _window_scene(seed=12)
+    cfg = lib.RasterConfig(pointmap_frame=1)
+    rast, params, out, fs = _render_gpu(lib, sc, cfg)
+    ups = _upstream(sc, 6, [np.ones((c.height, c.width), bool) for c in sc.cams])
+    gb = _gpu_backward(lib, rast, params, out, fs, ups)
+    tot = None
+    for v, cam in enumerate(sc.cams):
+        r1 = Rasterizer(rast.win.subwindow(v), sc.n, cfg)
+        o1, f1 = r1.forward(params)
+        for key, ch in (("rgb", 3), ("depth", 1), ("alpha", 1), ("pointmap", 3)):
+            a = out[key][ch * rast.win.pix_off[v]:ch * rast.win.pix_off[v + 1]]
+            assert torch.equal(a, o1[key]), (v, key)
+        g1 = _gpu_backward(lib, r1, params, o1, f1, [ups[v]])
+        tot = g1 if tot is None else {k: (tot[k] + g1[k]) if k != "pose" else np.concatenate([tot[k], g1[k]])
+                                      for k in tot}
+    for k in ("means", "log_scales", "quats", "opacity_logit", "rgb", "pose"):
+        np.testing.assert_allclose(gb[k], tot[k], rtol=1e-4, atol=1e-5 * np.abs(tot[k]).max())
+
+
+def test_patch_scale_and_loss_vs_oracle(lib, oracle):
+    U.log("[gpu] patch scale + window loss vs oracle")
+    from paper_2507_03737_amd.render import Rasterizer, Window
+    O = oracle
+    cams = [scenes.Camera(157, 93, 100.0, 100.0, 78.0, 46.0), scenes.Camera(64, 64, 50.0, 50.0, 32.0, 32.0),
+            scenes.Camera(200, 37, 120.0, 120.0, 100.0, 18.0)]
+    rng = np.random.default_rng(9)
+    for P in (8, 10, 16):
+        imgs = []
+        for c in cams:
+            Xr = rng.normal(0, 5, (3, c.height, c.width)).astype(np.float32)
+            s = O.expand_patches(rng.uniform(0.8, 1.25, (-(-c.height // P), -(-c.width // P))), P, c.height, c.width)
+            Xp = (Xr * s[None] + rng.normal(0, 0.05, Xr.shape)).astype(np.float32)
+            rgb = rng.uniform(0, 1, Xr.shape).astype(np.float32)
+            tgt = rgb + rng.normal(0, 0.1, Xr.shape).astype(np.float32)
+            tgt[:, :2, :3] = rgb[:, :2, :3]  # exact zeros of the residual: sign(0) = 0
+            mask = (rng.uniform(size=(c.height, c.width)) > 0.2).astype(np.float32)
+            imgs.append((Xr, Xp, rgb, tgt, mask))
+        T = torch.tensor(np.tile(np.eye(3, 4, dtype=np.float32).reshape(1, 12), (3, 1))).cuda()
+        rast = Rasterizer(Window(cams, T), 1, lib.RasterConfig())
+        cat = lambda i: torch.from_numpy(np.concatenate([im[i].reshape(-1) for im in imgs])).cuda()  # noqa: E731
+        Xr_d, Xp_d, rgb_d, tgt_d, mask_d = cat(0), cat(1), cat(2), cat(3), cat(4)
+        scale, count = rast.patch_scale(Xr_d, Xp_d, P, mask=mask_d)
+        n_pat = rast.win.n_patches(P)
+        sc2 = torch.empty(n_pat, device="cuda")
+        loss = torch.empty(3, device="cuda")
+        grgb = torch.empty_like(rgb_d)
+        gpm = torch.empty_like(Xr_d)
+        rast.window_loss_into(rgb_d, tgt_d, Xr_d, Xp_d, P, 0.98, sc2, loss, grgb, gpm)
+        torch.cuda.synchronize()
+        scale, count, sc2 = scale.cpu().numpy(), count.cpu().numpy(), sc2.cpu().numpy()
+        loss, grgb, gpm = loss.cpu().numpy(), grgb.cpu().numpy(), gpm.cpu().numpy()
+        po = 0
+        pix = 0
+        for v, (c, (Xr, Xp, rgb, tgt, mask)) in enumerate(zip(cams, imgs)):
+            s_ref, c_ref = O.patch_scale(Xr, Xp, P, mask=mask)
+            npt = s_ref.size
+            np.testing.assert_allclose(scale[po:po + npt], s_ref.reshape(-1), rtol=2e-6)
+            np.testing.assert_array_equal(count[po:po + npt], c_ref.reshape(-1))
+            s_all, _ = O.patch_scale(Xr, Xp, P)
+            np.testing.assert_allclose(sc2[po:po + npt], s_all.reshape(-1), rtol=2e-6)
+            L, g_rgb, g_pm = O.l1_window_loss(rgb, tgt, Xr, Xp, s_all, P, 0.98)
+            np.testing.assert_allclose(loss[v], L, rtol=1e-5)
+            n3 = 3 * c.height * c.width
+            # Same signs; the weights alpha / (3 H W) differ only by float32 rounding.
+            np.testing.assert_allclose(grgb[3 * pix:3 * pix + n3], g_rgb.reshape(-1), rtol=1e-6, atol=0)
+            # The pointmap residual's sign is decided in float32 on the GPU: compare where the
+            # residual is clear of float32 rounding of s * Xp.
+            sx = O.expand_patches(s_all, P, c.height, c.width)[None] * Xp
+            clear = (np.abs(Xr - sx) > 1e-5 * (np.abs(sx) + 1.0)).reshape(-1)
+            np.testing.assert_allclose(gpm[3 * pix:3 * pix + n3][clear], g_pm.reshape(-1)[clear], rtol=1e-6, atol=0)
+            po += npt
+            pix += c.height * c.width
+
+
+def test_graph_replay_matches_eager(lib):
+    """A captured mapping iteration replays identically to eager runs, also after the
+    poses are changed in place between replays (the graph reads them from device memory)."""
+    U.log("[gpu] graph capture / replay")
+    from paper_2507_03737_amd.render import MappingStep, Rasterizer, Window
+    sc = _window_scene(seed=13)
+    params, T = U.to_dev(sc, torch)
+    win = Window(sc.cams, T)
+    cfg = lib.RasterConfig(pointmap_frame=1)
+    rast = Rasterizer(win, sc.n, cfg)
+    out, _ = rast.forward(params)
+    target = (out["rgb"] + 0.05 * torch.randn_like(out["rgb"])).contiguous()
+    prior = (out["pointmap"] * 1.1).contiguous()
+    rast.max_pairs = rast.pairs * 2 + 1000
+    step = MappingStep(rast, params, target, prior)
+    eager = MappingStep(rast, params, target, prior)
+    step.capture()
+    xi = torch.zeros(3, 6, device="cuda")
+    for it in range(3):
+        step.replay()
+        torch.cuda.synchronize()
+        eager.run()
+        torch.cuda.synchronize()
+        step.check()
+        for k in ("rgb", "depth", "alpha", "pointmap"):
+            assert torch.equal(step.out[k], eager.out[k]), (it, k)
+        assert torch.equal(step.loss, eager.loss)
+        for k in step.grads:
+            torch.testing.assert_close(step.grads[k], eager.grads[k], rtol=1e-4, atol=1e-6)
+        torch.testing.assert_close(step.pose_grad, eager.pose_grad, rtol=1e-4, atol=1e-4)
+        # Move the cameras in place: the next replay must see it.
+        xi.normal_(0.0, 0.01)
+        lib.pose_retract(3, T, xi, lib.stream_handle())
+    # The last replay rendered the moved poses, not the captured ones.
+    assert not torch.equal(step.out["rgb"], out["rgb"])
+
+
+def test_autograd_function(lib):
+    U.log("[gpu] autograd function")
+    from paper_2507_03737_amd.render import Rasterizer, Window, rasterize
+    sc = _window_scene(seed=14, n=1500)
+    params, T = U.to_dev(sc, torch)
+    win = Window(sc.cams, T)
+    rast = Rasterizer(win, sc.n, lib.RasterConfig(pointmap_frame=1))
+    leaves = [p.clone().requires_grad_(True) for p in params]
+    xi = torch.zeros(3, 6, device="cuda", requires_grad=True)
+    rgb, depth, alpha, pm = rasterize(rast, *leaves, xi)
+    w = [torch.randn_like(t) for t in (rgb, depth, alpha, pm)]
+    loss = sum((a * b).sum() for a, b in zip((rgb, depth, alpha, pm), w))
+    loss.backward()
+    out, fs = rast.forward(params)
+    up = {"rgb": w[0], "depth": w[1], "alpha": w[2], "pointmap": w[3]}
+    grads = rast.zero_grads(params)
+    pose = torch.zeros(3, 6, device="cuda")
+    rast.backward_into(params, out, up, fs, grads, pose)
+    torch.cuda.synchronize()
+    for leaf, k in zip(leaves, ("means", "log_scales", "quats", "opacity_logit", "rgb")):
+        torch.testing.assert_close(leaf.grad, grads[k], rtol=1e-4, atol=1e-5)
+    torch.testing.assert_close(xi.grad, pose, rtol=1e-4, atol=1e-3)
+
+
+def test_c1_full_size_crops(lib, oracle):
+    """c1 (300k Gaussians, 1216x352) at full size in the benchmark's launch shape:
+    forward on sampled crops, and backward with upstream gradients confined to them."""
+    U.log("[gpu] c1 full size, sampled crops")
+    O = oracle
+    sc = scenes.make_scene("c1")
+    cfg = lib.RasterConfig(pointmap_frame=1)
+    rast, params, out, fs = _render_gpu(lib, sc, cfg)
+    cam = sc.cams[0]
+    boxes = U.crops(cam, 24, 6, seed=3) + [(0, cam.height - 24, 24, 24), (cam.width // 2, cam.height - 30, 24, 24)]
+    pix = np.concatenate([O.crop_pixels(*b) for b in boxes])
+    ref = _check_view_forward_pixels(O, sc, out, cfg, pix)
+    ok = np.zeros((cam.height, cam.width), bool)
+    ok[pix[:, 1], pix[:, 0]] = ref["ambiguous"] == 0
+    U.log(f"  crop pixels {pix.shape[0]}, ambiguous {(ref['ambiguous'] != 0).mean():.4f}, "
+          f"fragments/px {ref['n_frag'].mean():.1f}")
+    ups = _upstream(sc, 8, [ok])
+    g = _gpu_backward(lib, rast, params, out, fs, ups)
+    r = _oracle_backward(O, sc, cfg, ups, pixel_sets=[pix])
+    for k in ("means", "log_scales", "quats", "opacity_logit", "rgb"):
+        U.log(f"  {k}: rel {U.check_grad('c1 ' + k, g[k], r[k]):.2e}")
+    U.check_grad("c1 pose", g["pose"], r["pose"], frac=1.0)
+
+
+def _check_view_forward_pixels(O, sc, out, cfg, pix):
+    from tests.test_gpu_parity import _check_view_forward
+    return _check_view_forward(O, sc, 0, out, 0, cfg, pixels=pix, tag="c1 crops")
