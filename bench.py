@@ -138,6 +138,7 @@ def main():
     ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4"])
     ap.add_argument("--seed", type=int, default=None)
     ap.add_argument("--tile", type=int, default=16)
+    ap.add_argument("--ppl", type=int, default=2, help="pixels per lane of the raster kernels")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
@@ -160,6 +161,7 @@ def main():
     log(f"[bench] building {args.workload} inputs")
     sc, win, cfg, opt, target, prior = build_inputs(args.workload, seed, torch, dev)
     cfg.tile = args.tile
+    cfg.pixels_per_lane = args.ppl
 
     # ---- batched window -------------------------------------------------------------------
     rast = Rasterizer(win, sc.n, cfg)
@@ -266,6 +268,7 @@ def main():
                                "2x640x480), render + patch-scale L1 loss + backward to all params and poses",
                          "c4": "c4 16 keyframes 1920x1080, 3M Gaussians"}[args.workload],
             "n_gaussians": sc.n, "views": [[c.width, c.height] for c in sc.cams], "tile": cfg.tile,
+            "pixels_per_lane": cfg.pixels_per_lane,
             "patch": 8, "loss_alpha": 0.98, "pointmap_frame": "camera",
         },
         "fwd_bwd_ms_per_iter": {"batched_eager": ms_batched, "batched_graph": ms_graph, "per_view_eager": ms_per_view},

@@ -51,7 +51,7 @@ class Views(ctypes.Structure):
 
 class Settings(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("sort_digit_bits", ctypes.c_int32), ("pointmap_frame", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("near_z", ctypes.c_float), ("alpha_min", ctypes.c_float),
+                ("pixels_per_lane", ctypes.c_int32), ("near_z", ctypes.c_float), ("alpha_min", ctypes.c_float),
                 ("alpha_max", ctypes.c_float), ("t_min", ctypes.c_float), ("eps2d", ctypes.c_float),
                 ("jac_clamp", ctypes.c_float), ("bg", ctypes.c_float * 3)]
 
@@ -136,6 +136,7 @@ class RasterConfig:
     tile: int = 16
     sort_digit_bits: int = 8
     pointmap_frame: int = 1
+    pixels_per_lane: int = 2
     near_z: float = 0.2
     alpha_min: float = 1.0 / 255.0
     alpha_max: float = 0.99
@@ -145,8 +146,16 @@ class RasterConfig:
     bg: tuple = (0.0, 0.0, 0.0)
 
     def c(self) -> Settings:
-        return Settings(self.tile, self.sort_digit_bits, self.pointmap_frame, 0, self.near_z, self.alpha_min,
+        return Settings(self.tile, self.sort_digit_bits, self.pointmap_frame, self.pixels_per_lane, self.near_z,
+                        self.alpha_min,
                         self.alpha_max, self.t_min, self.eps2d, self.jac_clamp, (ctypes.c_float * 3)(*self.bg))
+
+    # Supported (tile, pixels_per_lane) launch shapes of the raster kernels.
+    SHAPES = ((8, 1), (16, 1), (16, 2), (16, 4), (32, 4))
+
+    def with_shape(self, tile, ppl):
+        import dataclasses
+        return dataclasses.replace(self, tile=tile, pixels_per_lane=ppl)
 
 
 def make_intrinsics(cams):

@@ -157,6 +157,9 @@ gspm_status prepare(const gspm_gaussians *g, const gspm_views *views, const gspm
     if (!s) return fail(GSPM_ERR_INVALID_ARG, "settings is NULL");
     if (s->tile != 8 && s->tile != 16 && s->tile != 32)
         return fail(GSPM_ERR_INVALID_ARG, "tile = %d, expected 8, 16 or 32", s->tile);
+    if (!raster_config_supported(s->tile, s->pixels_per_lane))
+        return fail(GSPM_ERR_INVALID_ARG, "(tile, pixels_per_lane) = (%d, %d) is not a supported configuration",
+                    s->tile, s->pixels_per_lane);
     if (s->sort_digit_bits < 4 || s->sort_digit_bits > 8)
         return fail(GSPM_ERR_INVALID_ARG, "sort_digit_bits = %d outside [4, 8]", s->sort_digit_bits);
     if (s->pointmap_frame < 0 || s->pointmap_frame > 2)
@@ -171,6 +174,7 @@ gspm_status prepare(const gspm_gaussians *g, const gspm_views *views, const gspm
         if (!isfinite(s->bg[c])) return fail(GSPM_ERR_INVALID_ARG, "bg must be finite");
     st = build_views(views, s->tile, P.vt, P.n_tiles, P.n_pixels);
     if (st) return st;
+    P.vt.ppt = s->pixels_per_lane;
     P.n_records = g->n * views->n_views;
     if (P.n_records >= (1ll << 31)) return fail(GSPM_ERR_INVALID_ARG, "n * n_views must be < 2^31");
     P.rs.near_z = s->near_z;

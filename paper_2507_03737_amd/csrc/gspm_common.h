@@ -17,6 +17,7 @@ constexpr int kWave = 64;
 struct ViewTable {
     int32_t n_views;
     int32_t tile;
+    int32_t ppt;  // pixels per lane in the raster kernels
     int32_t width[kMaxViews];
     int32_t height[kMaxViews];
     int32_t tiles_x[kMaxViews];
@@ -220,6 +221,8 @@ hipError_t launch_sum_u64(const uint32_t *x, int64_t n, unsigned long long *out,
 
 hipError_t launch_ranges(const uint32_t *sorted_keys, const FrameHeader *hdr, uint2 *ranges,
                          int64_t n_tiles, int64_t n_max, hipStream_t s);
+
+bool raster_config_supported(int tile, int ppt);
 
 hipError_t launch_raster_forward(const ViewTable &vt, const RasterSettings &rs, const uint2 *ranges,
                                  const uint32_t *pair_vals, const float *records, float *rgb,

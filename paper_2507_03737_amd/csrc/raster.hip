@@ -1,20 +1,22 @@
 // Tile rasterizer: front-to-back compositing (Sec. 3.1, Eq. 2; Sec. 3.2.1, Eq. 3-5) and
 // its backward.
 //
-// One workgroup per tile of T x T pixels (T = 8, 16 or 32), one lane per pixel.  The
-// tile's depth-ordered record list is streamed through LDS in batches of T*T records
-// (one 64-byte record per lane, converted to tile-local coordinates on load); every
-// lane walks the batch, and the workgroup stops as soon as all its pixels have reached
-// the transmittance floor.
+// One workgroup per tile of T x T pixels (T = 8, 16 or 32) with T*T/PPT lanes; each lane
+// owns PPT pixels of one column, PPT rows apart (for T = 16, PPT = 4 a single wave covers
+// the tile).  The tile's depth-ordered record list is streamed through LDS in batches of
+// one record per lane (a 64-byte record, converted to tile-local coordinates on load);
+// every lane walks the batch for all its pixels, and the workgroup stops as soon as every
+// pixel has reached the transmittance floor.  Several pixels per lane amortise the LDS
+// broadcast reads and the loop control over more fragments.
 //
-// The backward walks the same list front to back and recomputes alpha and
-// transmittance exactly as the forward did (same instructions), so no per-fragment
-// state is stored: only the per-pixel count of list entries up to the last contributing
-// fragment.  The suffix sums that the alpha derivative needs are recovered as
-// (sum over all fragments) - (prefix sum), the total coming from the forward's outputs.
-// Per-record gradients (13 values) are summed across the 64 lanes of a wave with one
-// reduce-scatter (cross-half lane swaps and DPP), after which 13 lanes each hold one
-// total and issue one float atomic.
+// The backward walks the same list front to back and recomputes alpha and transmittance
+// with the same instructions as the forward, so no per-fragment state is stored: only the
+// per-pixel count of list entries up to the last contributing fragment.  The suffix sums
+// that the alpha derivative needs are recovered as (sum over all fragments) - (prefix
+// sum), the total coming from the forward's outputs.  Each lane adds its pixels'
+// contributions to the 13 per-record gradient values, the wave sums them with one
+// reduce-scatter (cross-half lane swaps and DPP), and 13 lanes each issue one float
+// atomic, so the reduction and the atomics are paid once per wave and list entry.
 #include "gspm_common.h"
 
 namespace gspm {
@@ -25,10 +27,8 @@ constexpr float kLn2 = 0.69314718055994530942f;
 
 struct TilePos {
     int v, W, H;
-    int i, j;         // pixel coordinates
-    bool inside;
+    int tx, ty;
     float x0, y0;     // tile origin
-    int64_t pix;      // packed pixel index
     int64_t plane;    // W * H of the view
     int64_t pix_off;  // packed offset of the view
 };
@@ -39,17 +39,14 @@ __device__ inline TilePos tile_pos(const ViewTable &vt) {
     const int gt = blockIdx.x;
     p.v = find_view(vt, gt);
     const int lt = gt - vt.tile_off[p.v];
-    const int tx = lt % vt.tiles_x[p.v], ty = lt / vt.tiles_x[p.v];
+    p.tx = lt % vt.tiles_x[p.v];
+    p.ty = lt / vt.tiles_x[p.v];
     p.W = vt.width[p.v];
     p.H = vt.height[p.v];
-    p.i = tx * TILE + (int)(threadIdx.x % TILE);
-    p.j = ty * TILE + (int)(threadIdx.x / TILE);
-    p.inside = p.i < p.W && p.j < p.H;
-    p.x0 = (float)(tx * TILE);
-    p.y0 = (float)(ty * TILE);
+    p.x0 = (float)(p.tx * TILE);
+    p.y0 = (float)(p.ty * TILE);
     p.plane = (int64_t)p.W * p.H;
     p.pix_off = vt.pix_off[p.v];
-    p.pix = p.pix_off + (int64_t)p.j * p.W + p.i;
     return p;
 }
 
@@ -66,179 +63,233 @@ __device__ inline void stage(const float4 *__restrict__ rec, uint32_t r, float x
     s3[q] = make_float4(d.z, __uint_as_float(r), 0.f, 0.f);
 }
 
-template <int TILE>
-__global__ void __launch_bounds__(TILE *TILE)
+template <int TILE, int PPT>
+__global__ void __launch_bounds__(TILE *TILE / PPT)
 k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
              const float4 *__restrict__ rec, float *__restrict__ out_rgb, float *__restrict__ out_depth,
              float *__restrict__ out_alpha, float *__restrict__ out_pm, float *__restrict__ t_final,
              uint32_t *__restrict__ last, uint32_t *__restrict__ contrib) {
-    constexpr int NT = TILE * TILE;
+    constexpr int NT = TILE * TILE / PPT;
+    constexpr int RS = NT / TILE;  // row stride between a lane's pixels
     __shared__ float4 s0[NT], s1[NT], s2[NT], s3[NT];
     const TilePos tp = tile_pos<TILE>(vt);
     const uint2 rg = ranges[blockIdx.x];
-    const float px = (float)(threadIdx.x % TILE), py = (float)(threadIdx.x / TILE);
+    const int lx = threadIdx.x % TILE, ly = threadIdx.x / TILE;
+    const float px = (float)lx;
     const float amin = rs.alpha_min, amax = rs.alpha_max, tmin = rs.t_min;
+    const int i = tp.tx * TILE + lx;
 
-    float T = 1.0f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f, X0 = 0.f, X1 = 0.f, X2 = 0.f;
-    uint32_t n_last = 0, n_contrib = 0;
-    bool done = !tp.inside;
+    float T[PPT], C0[PPT], C1[PPT], C2[PPT], D[PPT], X0[PPT], X1[PPT], X2[PPT];
+    uint32_t n_last[PPT], n_contrib[PPT];
+    bool done[PPT];
+    int live = 0;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        T[k] = 1.0f;
+        C0[k] = C1[k] = C2[k] = D[k] = X0[k] = X1[k] = X2[k] = 0.f;
+        n_last[k] = n_contrib[k] = 0u;
+        const int j = tp.ty * TILE + ly + k * RS;
+        done[k] = !(i < tp.W && j < tp.H);
+        live += done[k] ? 0 : 1;
+    }
     for (uint32_t base = rg.x; base < rg.y; base += NT) {
-        const uint32_t k = base + threadIdx.x;
-        if (k < rg.y) stage(rec, vals[k], tp.x0, tp.y0, s0, s1, s2, s3, threadIdx.x);
+        const uint32_t kk = base + threadIdx.x;
+        if (kk < rg.y) stage(rec, vals[kk], tp.x0, tp.y0, s0, s1, s2, s3, threadIdx.x);
         __syncthreads();
         const int cnt = (int)min((uint32_t)NT, rg.y - base);
-        if (!done) {
-            for (int q = 0; q < cnt; ++q) {
-                const float4 a = s0[q], b = s1[q];
-                float g2;
-                const float al = frag_alpha(px - a.x, py - a.y, a.z, a.w, b.x, b.y, amax, g2);
-                if (al < amin) continue;
-                const float Tn = __fmul_rn(T, __fsub_rn(1.0f, al));
+        for (int q = 0; q < cnt && live > 0; ++q) {
+            const float4 a = s0[q], b = s1[q];
+            const float dx = px - a.x;
+            float al[PPT], g2[PPT];
+            bool pass = false;
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                al[k] = frag_alpha(dx, (float)(ly + k * RS) - a.y, a.z, a.w, b.x, b.y, amax, g2[k]);
+                pass |= !done[k] && !(al[k] < amin);
+            }
+            if (!pass) continue;
+            const float4 c = s2[q];
+            const float pz = s3[q].x;
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                if (done[k] || al[k] < amin) continue;
+                const float Tn = __fmul_rn(T[k], __fsub_rn(1.0f, al[k]));
                 if (Tn < tmin) {
-                    done = true;
-                    break;
+                    done[k] = true;
+                    --live;
+                    continue;
                 }
-                const float w = __fmul_rn(al, T);
-                const float4 c = s2[q];
-                C0 = fmaf(w, b.w, C0);
-                C1 = fmaf(w, c.x, C1);
-                C2 = fmaf(w, c.y, C2);
-                D = fmaf(w, b.z, D);
-                X0 = fmaf(w, c.z, X0);
-                X1 = fmaf(w, c.w, X1);
-                X2 = fmaf(w, s3[q].x, X2);
-                T = Tn;
-                n_last = base - rg.x + (uint32_t)q + 1u;
-                ++n_contrib;
+                const float w = __fmul_rn(al[k], T[k]);
+                C0[k] = fmaf(w, b.w, C0[k]);
+                C1[k] = fmaf(w, c.x, C1[k]);
+                C2[k] = fmaf(w, c.y, C2[k]);
+                D[k] = fmaf(w, b.z, D[k]);
+                X0[k] = fmaf(w, c.z, X0[k]);
+                X1[k] = fmaf(w, c.w, X1[k]);
+                X2[k] = fmaf(w, pz, X2[k]);
+                T[k] = Tn;
+                n_last[k] = base - rg.x + (uint32_t)q + 1u;
+                ++n_contrib[k];
             }
         }
-        if (!__syncthreads_or(done ? 0 : 1)) break;
+        if (!__syncthreads_or(live > 0 ? 1 : 0)) break;
     }
-    if (!tp.inside) return;
-    const int64_t pix = tp.pix, plane = tp.plane, o3 = 3 * tp.pix_off + (int64_t)tp.j * tp.W + tp.i;
-    out_rgb[o3] = fmaf(T, rs.bg[0], C0);
-    out_rgb[o3 + plane] = fmaf(T, rs.bg[1], C1);
-    out_rgb[o3 + 2 * plane] = fmaf(T, rs.bg[2], C2);
-    out_depth[pix] = D;
-    out_alpha[pix] = 1.0f - T;
-    if (rs.frame == 2) {
-        const float rx = ((float)tp.i - vt.cx[tp.v]) / vt.fx[tp.v];
-        const float ry = ((float)tp.j - vt.cy[tp.v]) / vt.fy[tp.v];
-        X0 = D * rx;
-        X1 = D * ry;
-        X2 = D;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int j = tp.ty * TILE + ly + k * RS;
+        if (!(i < tp.W && j < tp.H)) continue;
+        const int64_t e = (int64_t)j * tp.W + i;
+        const int64_t pix = tp.pix_off + e, o3 = 3 * tp.pix_off + e, plane = tp.plane;
+        out_rgb[o3] = fmaf(T[k], rs.bg[0], C0[k]);
+        out_rgb[o3 + plane] = fmaf(T[k], rs.bg[1], C1[k]);
+        out_rgb[o3 + 2 * plane] = fmaf(T[k], rs.bg[2], C2[k]);
+        out_depth[pix] = D[k];
+        out_alpha[pix] = 1.0f - T[k];
+        float x0 = X0[k], x1 = X1[k], x2 = X2[k];
+        if (rs.frame == 2) {
+            const float rx = ((float)i - vt.cx[tp.v]) / vt.fx[tp.v];
+            const float ry = ((float)j - vt.cy[tp.v]) / vt.fy[tp.v];
+            x0 = D[k] * rx;
+            x1 = D[k] * ry;
+            x2 = D[k];
+        }
+        out_pm[o3] = x0;
+        out_pm[o3 + plane] = x1;
+        out_pm[o3 + 2 * plane] = x2;
+        t_final[pix] = T[k];
+        last[pix] = n_last[k];
+        contrib[pix] = n_contrib[k];
     }
-    out_pm[o3] = X0;
-    out_pm[o3 + plane] = X1;
-    out_pm[o3 + 2 * plane] = X2;
-    t_final[pix] = T;
-    last[pix] = n_last;
-    contrib[pix] = n_contrib;
 }
 
 __device__ inline float load_or0(const float *p, int64_t i) { return p ? p[i] : 0.0f; }
 
-template <int TILE, bool POSE_ONLY>
-__global__ void __launch_bounds__(TILE *TILE)
+template <int TILE, int PPT, bool POSE_ONLY>
+__global__ void __launch_bounds__(TILE *TILE / PPT)
 k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
              const float4 *__restrict__ rec, const uint32_t *__restrict__ last, const float *__restrict__ t_final,
              gspm_const_images fwd, gspm_const_images up, float *__restrict__ grad2d) {
-    constexpr int NT = TILE * TILE;
+    constexpr int NT = TILE * TILE / PPT;
+    constexpr int RS = NT / TILE;
     __shared__ float4 s0[NT], s1[NT], s2[NT], s3[NT];
     __shared__ uint32_t block_last;
     const TilePos tp = tile_pos<TILE>(vt);
     const uint2 rg = ranges[blockIdx.x];
-    const float px = (float)(threadIdx.x % TILE), py = (float)(threadIdx.x / TILE);
+    const int lx = threadIdx.x % TILE, ly = threadIdx.x / TILE;
+    const float px = (float)lx;
     const float amin = rs.alpha_min, amax = rs.alpha_max;
     const int lane = lane_id();
+    const int i = tp.tx * TILE + lx;
 
     // Per-pixel upstream gradient and the total sum_k w_k (g . e_k) from the forward outputs.
-    uint32_t my_last = 0;
-    float gC0 = 0.f, gC1 = 0.f, gC2 = 0.f, gD = 0.f, gA = 0.f, gX0 = 0.f, gX1 = 0.f, gX2 = 0.f;
-    float Gtot = 0.f, bgterm = 0.f;
-    if (tp.inside) {
-        const int64_t pix = tp.pix, plane = tp.plane, o3 = 3 * tp.pix_off + (int64_t)tp.j * tp.W + tp.i;
-        my_last = last[pix];
-        gC0 = load_or0(up.rgb, o3);
-        gC1 = load_or0(up.rgb, o3 + plane);
-        gC2 = load_or0(up.rgb, o3 + 2 * plane);
-        gD = load_or0(up.depth, pix);
-        gA = load_or0(up.alpha, pix);
-        gX0 = load_or0(up.pointmap, o3);
-        gX1 = load_or0(up.pointmap, o3 + plane);
-        gX2 = load_or0(up.pointmap, o3 + 2 * plane);
+    uint32_t my_last[PPT];
+    float gC0[PPT], gC1[PPT], gC2[PPT], gD[PPT], gA[PPT], gX0[PPT], gX1[PPT], gX2[PPT], Gtot[PPT], bgterm[PPT];
+    float T[PPT], Pfx[PPT];
+    uint32_t thread_last = 0;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        my_last[k] = 0;
+        gC0[k] = gC1[k] = gC2[k] = gD[k] = gA[k] = gX0[k] = gX1[k] = gX2[k] = Gtot[k] = bgterm[k] = 0.f;
+        T[k] = 1.0f;
+        Pfx[k] = 0.0f;
+        const int j = tp.ty * TILE + ly + k * RS;
+        if (!(i < tp.W && j < tp.H)) continue;
+        const int64_t e = (int64_t)j * tp.W + i;
+        const int64_t pix = tp.pix_off + e, o3 = 3 * tp.pix_off + e, plane = tp.plane;
+        my_last[k] = last[pix];
+        gC0[k] = load_or0(up.rgb, o3);
+        gC1[k] = load_or0(up.rgb, o3 + plane);
+        gC2[k] = load_or0(up.rgb, o3 + 2 * plane);
+        gD[k] = load_or0(up.depth, pix);
+        gA[k] = load_or0(up.alpha, pix);
+        gX0[k] = load_or0(up.pointmap, o3);
+        gX1[k] = load_or0(up.pointmap, o3 + plane);
+        gX2[k] = load_or0(up.pointmap, o3 + 2 * plane);
         const float Tf = t_final[pix];
         if (rs.frame == 2) {
             // Eq. 5: the pointmap is D K^-1 [i, j, 1]^T, a function of the depth only.
-            const float rx = ((float)tp.i - vt.cx[tp.v]) / vt.fx[tp.v];
-            const float ry = ((float)tp.j - vt.cy[tp.v]) / vt.fy[tp.v];
-            gD += gX0 * rx + gX1 * ry + gX2;
-            gX0 = gX1 = gX2 = 0.f;
+            const float rx = ((float)i - vt.cx[tp.v]) / vt.fx[tp.v];
+            const float ry = ((float)j - vt.cy[tp.v]) / vt.fy[tp.v];
+            gD[k] += gX0[k] * rx + gX1[k] * ry + gX2[k];
+            gX0[k] = gX1[k] = gX2[k] = 0.f;
         }
-        bgterm = Tf * (gC0 * rs.bg[0] + gC1 * rs.bg[1] + gC2 * rs.bg[2]);
-        Gtot = gC0 * fwd.rgb[o3] + gC1 * fwd.rgb[o3 + plane] + gC2 * fwd.rgb[o3 + 2 * plane] - bgterm +
-               gD * fwd.depth[pix] + gA * (1.0f - Tf);
+        bgterm[k] = Tf * (gC0[k] * rs.bg[0] + gC1[k] * rs.bg[1] + gC2[k] * rs.bg[2]);
+        Gtot[k] = gC0[k] * fwd.rgb[o3] + gC1[k] * fwd.rgb[o3 + plane] + gC2[k] * fwd.rgb[o3 + 2 * plane] -
+                  bgterm[k] + gD[k] * fwd.depth[pix] + gA[k] * (1.0f - Tf);
         if (rs.frame != 2)
-            Gtot += gX0 * fwd.pointmap[o3] + gX1 * fwd.pointmap[o3 + plane] + gX2 * fwd.pointmap[o3 + 2 * plane];
-        if (gC0 == 0.f && gC1 == 0.f && gC2 == 0.f && gD == 0.f && gA == 0.f && gX0 == 0.f && gX1 == 0.f &&
-            gX2 == 0.f)
-            my_last = 0;  // nothing flows back from this pixel
+            Gtot[k] += gX0[k] * fwd.pointmap[o3] + gX1[k] * fwd.pointmap[o3 + plane] +
+                       gX2[k] * fwd.pointmap[o3 + 2 * plane];
+        if (gC0[k] == 0.f && gC1[k] == 0.f && gC2[k] == 0.f && gD[k] == 0.f && gA[k] == 0.f && gX0[k] == 0.f &&
+            gX1[k] == 0.f && gX2[k] == 0.f)
+            my_last[k] = 0;  // nothing flows back from this pixel
+        thread_last = max(thread_last, my_last[k]);
     }
     if (threadIdx.x == 0) block_last = 0;
     __syncthreads();
-    // Wave-level bound first, then the block bound.
-    uint32_t wave_last = my_last;
+    uint32_t wave_last = thread_last;
     for (int off = 32; off > 0; off >>= 1) wave_last = max(wave_last, (uint32_t)__shfl_xor((int)wave_last, off, 64));
     if (lane == 0) atomicMax(&block_last, wave_last);
     __syncthreads();
     const uint32_t end = rg.x + block_last;
 
-    float T = 1.0f, Pfx = 0.0f;
     for (uint32_t base = rg.x; base < end; base += NT) {
-        const uint32_t k = base + threadIdx.x;
-        if (k < end) stage(rec, vals[k], tp.x0, tp.y0, s0, s1, s2, s3, threadIdx.x);
+        const uint32_t kk = base + threadIdx.x;
+        if (kk < end) stage(rec, vals[kk], tp.x0, tp.y0, s0, s1, s2, s3, threadIdx.x);
         __syncthreads();
         const int cnt = (int)min((uint32_t)NT, end - base);
         const uint32_t rel0 = base - rg.x;
         for (int q = 0; q < cnt; ++q) {
-            if (rel0 + (uint32_t)q >= wave_last) break;  // wave-uniform
+            const uint32_t rel = rel0 + (uint32_t)q;
+            if (rel >= wave_last) break;  // wave-uniform
             const float4 a = s0[q], b = s1[q];
-            const float dx = px - a.x, dy = py - a.y;
-            float g2;
-            const float al = frag_alpha(dx, dy, a.z, a.w, b.x, b.y, amax, g2);
-            const bool valid = (rel0 + (uint32_t)q < my_last) && !(al < amin);
+            const float dx = px - a.x;
+            float al[PPT], g2[PPT];
+            bool valid[PPT];
+            bool any = false;
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                al[k] = frag_alpha(dx, (float)(ly + k * RS) - a.y, a.z, a.w, b.x, b.y, amax, g2[k]);
+                valid[k] = rel < my_last[k] && !(al[k] < amin);
+                any |= valid[k];
+            }
+            if (__ballot(any) == 0ull) continue;
             float v[16];
 #pragma unroll
             for (int t = 0; t < 16; ++t) v[t] = 0.f;
-            if (valid) {
+            if (any) {
                 const float4 c = s2[q];
                 const float pz = s3[q].x;
-                const float w = __fmul_rn(al, T);
-                const float s = gC0 * b.w + gC1 * c.x + gC2 * c.y + gD * b.z + gA + gX0 * c.z + gX1 * c.w + gX2 * pz;
-                Pfx = fmaf(w, s, Pfx);
-                const float one_m = __fsub_rn(1.0f, al);
-                const float dLda = T * s - (Gtot - Pfx + bgterm) * __builtin_amdgcn_rcpf(one_m);
-                if (!(b.y * g2 > amax)) {
-                    const float Gl = dLda * al * kLn2;
-                    v[0] = -Gl * (2.0f * a.z * dx + a.w * dy);
-                    v[1] = -Gl * (a.w * dx + 2.0f * b.x * dy);
-                    v[2] = Gl * dx * dx;
-                    v[3] = Gl * dx * dy;
-                    v[4] = Gl * dy * dy;
-                    if (!POSE_ONLY) v[5] = dLda * g2;
+#pragma unroll
+                for (int k = 0; k < PPT; ++k) {
+                    if (!valid[k]) continue;
+                    const float dy = (float)(ly + k * RS) - a.y;
+                    const float w = __fmul_rn(al[k], T[k]);
+                    const float s = gC0[k] * b.w + gC1[k] * c.x + gC2[k] * c.y + gD[k] * b.z + gA[k] +
+                                    gX0[k] * c.z + gX1[k] * c.w + gX2[k] * pz;
+                    Pfx[k] = fmaf(w, s, Pfx[k]);
+                    const float one_m = __fsub_rn(1.0f, al[k]);
+                    const float dLda = T[k] * s - (Gtot[k] - Pfx[k] + bgterm[k]) * __builtin_amdgcn_rcpf(one_m);
+                    if (!(b.y * g2[k] > amax)) {
+                        const float Gl = dLda * al[k] * kLn2;
+                        v[0] -= Gl * (2.0f * a.z * dx + a.w * dy);
+                        v[1] -= Gl * (a.w * dx + 2.0f * b.x * dy);
+                        v[2] += Gl * dx * dx;
+                        v[3] += Gl * dx * dy;
+                        v[4] += Gl * dy * dy;
+                        if (!POSE_ONLY) v[5] += dLda * g2[k];
+                    }
+                    v[6] += w * gD[k];
+                    if (!POSE_ONLY) {
+                        v[7] += w * gC0[k];
+                        v[8] += w * gC1[k];
+                        v[9] += w * gC2[k];
+                    }
+                    v[10] += w * gX0[k];
+                    v[11] += w * gX1[k];
+                    v[12] += w * gX2[k];
+                    T[k] = __fmul_rn(T[k], one_m);
                 }
-                v[6] = w * gD;
-                if (!POSE_ONLY) {
-                    v[7] = w * gC0;
-                    v[8] = w * gC1;
-                    v[9] = w * gC2;
-                }
-                v[10] = w * gX0;
-                v[11] = w * gX1;
-                v[12] = w * gX2;
-                T = __fmul_rn(T, one_m);
             }
-            if (__ballot(valid) == 0ull) continue;
             const float tot = wave_reduce_scatter16(v);
             const int idx = (lane >> 2) & 15;
             if ((lane & 3) == 0 && idx < kG2Used && tot != 0.f) {
@@ -252,50 +303,53 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
 
 }  // namespace
 
-template <int TILE>
-static void fwd_launch(const ViewTable &vt, const RasterSettings &rs, const uint2 *ranges, const uint32_t *vals,
-                       const float *records, float *rgb, float *depth, float *alpha, float *pm, float *t_final,
-                       uint32_t *last, uint32_t *contrib, hipStream_t s) {
-    const int n_tiles = vt.tile_off[vt.n_views];
-    hipLaunchKernelGGL((k_raster_fwd<TILE>), dim3(n_tiles), dim3(TILE * TILE), 0, s, vt, rs, ranges, vals,
-                       reinterpret_cast<const float4 *>(records), rgb, depth, alpha, pm, t_final, last, contrib);
+// Launch configurations: (tile, pixels per lane).
+#define GSPM_RASTER_CONFIGS(X) X(8, 1) X(16, 1) X(16, 2) X(16, 4) X(32, 4)
+
+bool raster_config_supported(int tile, int ppt) {
+#define GSPM_CHECK(T_, P_) \
+    if (tile == T_ && ppt == P_) return true;
+    GSPM_RASTER_CONFIGS(GSPM_CHECK)
+#undef GSPM_CHECK
+    return false;
 }
 
 hipError_t launch_raster_forward(const ViewTable &vt, const RasterSettings &rs, const uint2 *ranges,
                                  const uint32_t *pair_vals, const float *records, float *rgb, float *depth,
                                  float *alpha, float *pointmap, float *t_final, uint32_t *last, uint32_t *contrib,
                                  hipStream_t s) {
-    switch (vt.tile) {
-        case 8: fwd_launch<8>(vt, rs, ranges, pair_vals, records, rgb, depth, alpha, pointmap, t_final, last, contrib, s); break;
-        case 32: fwd_launch<32>(vt, rs, ranges, pair_vals, records, rgb, depth, alpha, pointmap, t_final, last, contrib, s); break;
-        default: fwd_launch<16>(vt, rs, ranges, pair_vals, records, rgb, depth, alpha, pointmap, t_final, last, contrib, s); break;
-    }
-    return hipGetLastError();
-}
-
-template <int TILE, bool POSE_ONLY>
-static void bwd_launch(const ViewTable &vt, const RasterSettings &rs, const uint2 *ranges, const uint32_t *vals,
-                       const float *records, const uint32_t *last, const float *t_final, const gspm_const_images &fwd,
-                       const gspm_const_images &up, float *grad2d, hipStream_t s) {
     const int n_tiles = vt.tile_off[vt.n_views];
-    hipLaunchKernelGGL((k_raster_bwd<TILE, POSE_ONLY>), dim3(n_tiles), dim3(TILE * TILE), 0, s, vt, rs, ranges, vals,
-                       reinterpret_cast<const float4 *>(records), last, t_final, fwd, up, grad2d);
+    const float4 *rec = reinterpret_cast<const float4 *>(records);
+#define GSPM_FWD(T_, P_)                                                                                    \
+    if (vt.tile == T_ && vt.ppt == P_) {                                                                    \
+        hipLaunchKernelGGL((k_raster_fwd<T_, P_>), dim3(n_tiles), dim3(T_ * T_ / P_), 0, s, vt, rs, ranges, \
+                           pair_vals, rec, rgb, depth, alpha, pointmap, t_final, last, contrib);            \
+        return hipGetLastError();                                                                           \
+    }
+    GSPM_RASTER_CONFIGS(GSPM_FWD)
+#undef GSPM_FWD
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_raster_backward(const ViewTable &vt, const RasterSettings &rs, const uint2 *ranges,
                                   const uint32_t *pair_vals, const float *records, const uint32_t *last,
                                   const float *t_final, const gspm_const_images &fwd, const gspm_const_images &up,
                                   float *grad2d, bool pose_only, hipStream_t s) {
-#define GSPM_BWD(T)                                                                                         \
-    (pose_only ? bwd_launch<T, true>(vt, rs, ranges, pair_vals, records, last, t_final, fwd, up, grad2d, s) \
-               : bwd_launch<T, false>(vt, rs, ranges, pair_vals, records, last, t_final, fwd, up, grad2d, s))
-    switch (vt.tile) {
-        case 8: GSPM_BWD(8); break;
-        case 32: GSPM_BWD(32); break;
-        default: GSPM_BWD(16); break;
+    const int n_tiles = vt.tile_off[vt.n_views];
+    const float4 *rec = reinterpret_cast<const float4 *>(records);
+#define GSPM_BWD(T_, P_)                                                                                      \
+    if (vt.tile == T_ && vt.ppt == P_) {                                                                      \
+        if (pose_only)                                                                                        \
+            hipLaunchKernelGGL((k_raster_bwd<T_, P_, true>), dim3(n_tiles), dim3(T_ * T_ / P_), 0, s, vt, rs, \
+                               ranges, pair_vals, rec, last, t_final, fwd, up, grad2d);                       \
+        else                                                                                                  \
+            hipLaunchKernelGGL((k_raster_bwd<T_, P_, false>), dim3(n_tiles), dim3(T_ * T_ / P_), 0, s, vt,    \
+                               rs, ranges, pair_vals, rec, last, t_final, fwd, up, grad2d);                   \
+        return hipGetLastError();                                                                             \
     }
+    GSPM_RASTER_CONFIGS(GSPM_BWD)
 #undef GSPM_BWD
-    return hipGetLastError();
+    return hipErrorInvalidValue;
 }
 
 }  // namespace gspm

@@ -73,7 +73,7 @@ def test_forward_argument_errors_before_any_launch(L):
     assert fwd(o_=B.Images(1, 0, 1, 1)) == B.GSPM_ERR_INVALID_ARG
     assert fwd(fs=None) == B.GSPM_ERR_INVALID_ARG
     assert fwd(nbytes=16) == B.GSPM_ERR_INVALID_ARG and "frame_state_bytes" in B.last_error()
-    for field, val in (("tile", 12), ("sort_digit_bits", 9), ("pointmap_frame", 3), ("alpha_min", 0.0),
+    for field, val in (("tile", 12), ("pixels_per_lane", 3), ("sort_digit_bits", 9), ("pointmap_frame", 3), ("alpha_min", 0.0),
                        ("alpha_max", 1.0), ("t_min", 0.0), ("near_z", -1.0), ("eps2d", -0.1), ("jac_clamp", 0.0)):
         s = B.RasterConfig().c()
         setattr(s, field, val)

@@ -72,16 +72,23 @@ def test_forward_c0(lib, oracle, frame):
     assert (ref["ambiguous"] != 0).mean() < 0.01
 
 
-@pytest.mark.parametrize("tile", [8, 16, 32])
-def test_forward_tiles_and_ragged(lib, oracle, tile):
-    """Tile sizes 8/16/32 on a view whose size is not a multiple of any of them."""
-    U.log(f"[gpu] forward ragged tile={tile}")
+@pytest.mark.parametrize("tile,ppl", [(8, 1), (16, 1), (16, 2), (16, 4), (32, 4)])
+def test_forward_tiles_and_ragged(lib, oracle, tile, ppl):
+    """Every launch shape on a view whose size is not a multiple of any tile size."""
+    U.log(f"[gpu] forward ragged tile={tile} ppl={ppl}")
     sc = scenes.make_scene("c0", seed=7, n=1500)
     cam = sc.cams[0]
     sc.cams = [scenes.Camera(157, 93, cam.fx, cam.fy, 78.5, 46.5)]
-    cfg = lib.RasterConfig(tile=tile, pointmap_frame=1)
+    cfg = lib.RasterConfig(tile=tile, pixels_per_lane=ppl, pointmap_frame=1)
     rast, params, out, fs = _render_gpu(lib, sc, cfg)
-    _check_view_forward(oracle, sc, 0, out, 0, cfg, tag=f"ragged/t{tile}")
+    _check_view_forward(oracle, sc, 0, out, 0, cfg, tag=f"ragged/t{tile}x{ppl}")
+    ref = oracle.render_image(oracle.Params.from_scene(sc), sc.cams[0], sc.T_cw[0], _oracle_settings(oracle, cfg))
+    up = _upstream(sc, 9, [ref["ambiguous"] == 0])
+    g = _gpu_backward(lib, rast, params, out, fs, up)
+    r = _oracle_backward(oracle, sc, cfg, up)
+    for k in ("means", "log_scales", "quats", "opacity_logit", "rgb"):
+        U.check_grad(f"ragged/t{tile}x{ppl} {k}", g[k], r[k])
+    U.check_grad(f"ragged/t{tile}x{ppl} pose", g["pose"], r["pose"], frac=1.0)
 
 
 def test_tile_lists_exact(lib, oracle):
