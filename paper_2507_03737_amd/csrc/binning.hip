@@ -100,77 +100,132 @@ k_scan_apply(const uint32_t *__restrict__ counts, const uint32_t *__restrict__ i
 }
 
 // ------------------------------- radix sort -------------------------------------------
+//
+// LSD passes over fixed tiles of 4096 keys (4 waves x 16 steps of 64).  The upsweep
+// writes a digit histogram per tile (digit-major, so one exclusive scan yields every
+// tile's output offsets).  The downsweep ranks each tile's keys stably (wave-level match
+// of equal digits by ballots, then per-digit offsets across the four waves), stages the
+// tile in LDS in sorted order and writes it out so that consecutive lanes write
+// consecutive addresses inside each digit's run.  Grids are fixed; the key count may be
+// read from device memory.
 
 constexpr int kSortBlock = 256;
 constexpr int kSortWaves = kSortBlock / kWave;
+constexpr int kSortSteps = 16;
+constexpr int kSortTile = kSortBlock * kSortSteps;  // 4096 keys
 
-__device__ inline void wave_range(int64_t n, int64_t nw, int64_t w, int64_t &b, int64_t &e) {
-    int64_t chunk = (n + nw - 1) / nw;
-    chunk = (chunk + kWave - 1) / kWave * kWave;
-    b = w * chunk;
-    e = b + chunk < n ? b + chunk : n;
+__device__ inline int64_t sort_count(const uint32_t *n_dev, int64_t n_max) {
+    if (!n_dev) return n_max;
+    const int64_t n = (int64_t)*n_dev;
+    return n < n_max ? n : n_max;
 }
 
 template <int DB>
 __global__ void __launch_bounds__(kSortBlock)
 k_radix_upsweep(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ n_dev, int64_t n_max, int shift,
-                uint32_t *__restrict__ hist, int64_t nw) {
+                uint32_t *__restrict__ hist, int64_t n_tiles) {
     constexpr int R = 1 << DB;
     __shared__ uint32_t cnt[kSortWaves][R];
     const int wid = threadIdx.x / kWave, lane = lane_id();
-    for (int d = lane; d < R; d += kWave) cnt[wid][d] = 0u;
-    __syncthreads();
-    int64_t n = n_max;
-    if (n_dev) n = (int64_t)*n_dev < n_max ? (int64_t)*n_dev : n_max;
-    const int64_t w = (int64_t)blockIdx.x * kSortWaves + wid;
-    int64_t b, e;
-    wave_range(n, nw, w, b, e);
-    for (int64_t i = b + lane; i < e; i += kWave) {
-        const uint32_t d = (keys[i] >> shift) & (R - 1);
-        atomicAdd(&cnt[wid][d], 1u);
+    const int64_t n = sort_count(n_dev, n_max);
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        for (int d = lane; d < R; d += kWave) cnt[wid][d] = 0u;
+        __syncthreads();
+        const int64_t b = tile * kSortTile + (int64_t)wid * (kSortTile / kSortWaves);
+#pragma unroll 4
+        for (int st = 0; st < kSortSteps; ++st) {
+            const int64_t i = b + st * kWave + lane;
+            if (i < n) atomicAdd(&cnt[wid][(keys[i] >> shift) & (R - 1)], 1u);
+        }
+        __syncthreads();
+        for (int d = threadIdx.x; d < R; d += kSortBlock)
+            hist[(int64_t)d * n_tiles + tile] = cnt[0][d] + cnt[1][d] + cnt[2][d] + cnt[3][d];
+        __syncthreads();
     }
-    __syncthreads();
-    for (int d = lane; d < R; d += kWave) hist[(int64_t)d * nw + w] = cnt[wid][d];
 }
 
 template <int DB>
 __global__ void __launch_bounds__(kSortBlock)
 k_radix_downsweep(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
                   uint32_t *__restrict__ vout, const uint32_t *__restrict__ n_dev, int64_t n_max, int shift,
-                  const uint32_t *__restrict__ hist, int64_t nw) {
+                  const uint32_t *__restrict__ hist, int64_t n_tiles) {
     constexpr int R = 1 << DB;
-    __shared__ uint32_t cnt[kSortWaves][R];
+    __shared__ uint32_t wcnt[kSortWaves][R];
+    __shared__ uint32_t dstart[R];
+    __shared__ uint32_t gbase[R];
+    __shared__ uint32_t scan_lds[kSortWaves];
+    __shared__ uint32_t lk[kSortTile];
+    __shared__ uint32_t lv[kSortTile];
     const int wid = threadIdx.x / kWave, lane = lane_id();
-    const int64_t w = (int64_t)blockIdx.x * kSortWaves + wid;
-    for (int d = lane; d < R; d += kWave) cnt[wid][d] = hist[(int64_t)d * nw + w];
-    __syncthreads();
-    int64_t n = n_max;
-    if (n_dev) n = (int64_t)*n_dev < n_max ? (int64_t)*n_dev : n_max;
-    int64_t b, e;
-    wave_range(n, nw, w, b, e);
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    for (int64_t base = b; base < e; base += kWave) {
-        const int64_t i = base + lane;
-        const bool act = i < e;
-        const uint32_t k = act ? kin[i] : 0u;
-        const uint32_t val = act ? vin[i] : 0u;
-        const uint32_t d = (k >> shift) & (R - 1);
-        uint64_t m = __ballot(act);
-#pragma unroll
-        for (int bit = 0; bit < DB; ++bit) {
-            const bool set = (d >> bit) & 1u;
-            const uint64_t bb = __ballot(set);
-            m &= set ? bb : ~bb;
-        }
-        if (act) {
-            const uint32_t rank = (uint32_t)__popcll(m & lt);
-            const uint32_t base_d = cnt[wid][d];
-            const uint32_t pos = base_d + rank;
-            kout[pos] = k;
-            vout[pos] = val;
-            if (rank == 0) cnt[wid][d] = base_d + (uint32_t)__popcll(m);
-        }
+    const int64_t n = sort_count(n_dev, n_max);
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const int64_t tile_begin = tile * kSortTile;
+        if (tile_begin >= n) break;  // block-uniform; later tiles of this block are empty too
+        for (int d = lane; d < R; d += kWave) wcnt[wid][d] = 0u;
         __builtin_amdgcn_wave_barrier();
+        const int64_t b = tile_begin + (int64_t)wid * (kSortTile / kSortWaves);
+        uint32_t key[kSortSteps], val[kSortSteps], rank[kSortSteps];
+#pragma unroll
+        for (int st = 0; st < kSortSteps; ++st) {
+            const int64_t i = b + st * kWave + lane;
+            const bool act = i < n;
+            key[st] = act ? kin[i] : 0u;
+            val[st] = act ? vin[i] : 0u;
+            const uint32_t d = (key[st] >> shift) & (R - 1);
+            uint64_t m = __ballot(act);
+#pragma unroll
+            for (int bit = 0; bit < DB; ++bit) {
+                const bool set = (d >> bit) & 1u;
+                const uint64_t bb = __ballot(set);
+                m &= set ? bb : ~bb;
+            }
+            rank[st] = 0xffffffffu;
+            if (act) {
+                const uint32_t r = (uint32_t)__popcll(m & lt);
+                const uint32_t base_d = wcnt[wid][d];
+                rank[st] = base_d + r;
+                if (r == 0) wcnt[wid][d] = base_d + (uint32_t)__popcll(m);
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        __syncthreads();
+        // Per digit: offsets of the four waves, then the block-local start of the digit.
+        uint32_t tot = 0;
+        if (threadIdx.x < R) {
+            const int d = threadIdx.x;
+            uint32_t acc = 0;
+#pragma unroll
+            for (int w = 0; w < kSortWaves; ++w) {
+                const uint32_t c = wcnt[w][d];
+                wcnt[w][d] = acc;
+                acc += c;
+            }
+            tot = acc;
+            gbase[d] = hist[(int64_t)d * n_tiles + tile];
+        }
+        uint32_t all;
+        const uint32_t pre = block_exclusive_scan(tot, scan_lds, all);
+        if (threadIdx.x < R) dstart[threadIdx.x] = pre;
+        __syncthreads();
+#pragma unroll
+        for (int st = 0; st < kSortSteps; ++st) {
+            if (rank[st] == 0xffffffffu) continue;
+            const uint32_t d = (key[st] >> shift) & (R - 1);
+            const uint32_t lp = dstart[d] + wcnt[wid][d] + rank[st];
+            lk[lp] = key[st];
+            lv[lp] = val[st];
+        }
+        __syncthreads();
+        const int cnt = (int)(n - tile_begin < kSortTile ? n - tile_begin : kSortTile);
+        for (int j = threadIdx.x; j < cnt; j += kSortBlock) {
+            const uint32_t k = lk[j];
+            const uint32_t d = (k >> shift) & (R - 1);
+            const uint32_t pos = gbase[d] + ((uint32_t)j - dstart[d]);
+            kout[pos] = k;
+            vout[pos] = lv[j];
+        }
+        __syncthreads();
     }
 }
 
@@ -260,28 +315,30 @@ hipError_t launch_scan_indirect(const uint32_t *counts, const uint32_t *idx, int
     return hipGetLastError();
 }
 
+static int64_t sort_tiles(int64_t n_max) { return (n_max + kSortTile - 1) / kSortTile; }
+
 static int64_t sort_blocks(int64_t n_max) {
-    // About 16 steps of 64 keys per wave at capacity, between 1 and 1024 blocks.
-    int64_t nb = (n_max + kSortBlock * 16 - 1) / (kSortBlock * 16);
+    int64_t nb = sort_tiles(n_max);
     if (nb > 1024) nb = 1024;
     return nb < 1 ? 1 : nb;
 }
 
 int64_t radix_hist_words(int64_t n_max, int digit_bits) {
-    return ((int64_t)1 << digit_bits) * sort_blocks(n_max) * kSortWaves;
+    const int64_t t = sort_tiles(n_max);
+    return ((int64_t)1 << digit_bits) * (t > 0 ? t : 1);
 }
 
 template <int DB>
 static void sort_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, int64_t n_max,
                       const uint32_t *n_dev, int shift, uint32_t *hist, uint32_t *scan_part, hipStream_t s) {
     const int64_t nb = sort_blocks(n_max);
-    const int64_t nw = nb * kSortWaves;
+    const int64_t nt = sort_tiles(n_max);
     hipLaunchKernelGGL(k_radix_upsweep<DB>, dim3((unsigned)nb), dim3(kSortBlock), 0, s, kin, n_dev, n_max, shift,
-                       hist, nw);
-    const int64_t hw = ((int64_t)1 << DB) * nw;
+                       hist, nt);
+    const int64_t hw = ((int64_t)1 << DB) * nt;
     (void)launch_scan_indirect(hist, nullptr, hw, hist, hist + hw, scan_part, s);
     hipLaunchKernelGGL(k_radix_downsweep<DB>, dim3((unsigned)nb), dim3(kSortBlock), 0, s, kin, vin, kout, vout,
-                       n_dev, n_max, shift, hist, nw);
+                       n_dev, n_max, shift, hist, nt);
 }
 
 hipError_t radix_sort(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_tmp, uint32_t *vals_tmp,

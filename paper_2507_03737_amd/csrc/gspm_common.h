@@ -108,17 +108,15 @@ __device__ inline float wave_total(float x) {
     __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, (x)), \
                                                           (ctrl), 0xf, 0xf, true))
 
-// gfx950 cross-half lane swaps.  After permlane32_swap(a, b): a = (a[0:32], b[0:32]) and
-// b = (a[32:64], b[32:64]); after permlane16_swap(a, b) the odd 16-lane rows of a and
-// the even rows of b are exchanged.  (Written as single instructions: this compiler's
-// two-result builtins return the first result twice.)  The s_nop pairs give the wait
-// states a VALU result needs before and after a lane-permute instruction.
-__device__ inline void permlane32_swap(float &a, float &b) {
-    asm volatile("s_nop 1\n\tv_permlane32_swap_b32 %0, %1\n\ts_nop 1" : "+v"(a), "+v"(b));
-}
-__device__ inline void permlane16_swap(float &a, float &b) {
-    asm volatile("s_nop 1\n\tv_permlane16_swap_b32 %0, %1\n\ts_nop 1" : "+v"(a), "+v"(b));
-}
+// gfx950 cross-half lane swaps, written as single instructions because this compiler's
+// two-result builtins return the first result twice.  After v_permlane32_swap a, b:
+// a = (a[0:32], b[0:32]) and b = (a[32:64], b[32:64]); after v_permlane16_swap a, b the
+// odd 16-lane rows of a and the even rows of b are exchanged.  One s_nop 1 gives the
+// wait states a VALU result needs before a lane-permute reads it; the swaps of a group
+// read only registers written before the group.
+#define GSPM_SWAP4(op, a0, b0, a1, b1, a2, b2, a3, b3)                                     \
+    asm volatile("s_nop 1\n\t" op " %0, %4\n\t" op " %1, %5\n\t" op " %2, %6\n\t" op " %3, %7" \
+                 : "+v"(a0), "+v"(a1), "+v"(a2), "+v"(a3), "+v"(b0), "+v"(b1), "+v"(b2), "+v"(b3))
 
 // Reduce-scatter of 16 per-lane values over a wave of 64 lanes.  On return, every lane
 // of quad q (lanes 4q .. 4q+3) holds the wave-wide sum of v[q & 15].  Lane bits 5 and 4
@@ -127,20 +125,18 @@ __device__ inline void permlane16_swap(float &a, float &b) {
 // values, so the whole reduction costs 15 exchanges instead of 6 per value.
 __device__ inline float wave_reduce_scatter16(const float (&v)[16]) {
     const int lane = lane_id();
+    float x[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) x[k] = v[k];
+    GSPM_SWAP4("v_permlane32_swap_b32", x[0], x[8], x[1], x[9], x[2], x[10], x[3], x[11]);
+    GSPM_SWAP4("v_permlane32_swap_b32", x[4], x[12], x[5], x[13], x[6], x[14], x[7], x[15]);
     float a[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        float x = v[k], y = v[k + 8];
-        permlane32_swap(x, y);
-        a[k] = x + y;  // lanes 0-31: total of v[k]; lanes 32-63: total of v[k + 8]
-    }
+    for (int k = 0; k < 8; ++k) a[k] = x[k] + x[k + 8];  // lanes 0-31: v[k]; lanes 32-63: v[k + 8]
+    GSPM_SWAP4("v_permlane16_swap_b32", a[0], a[4], a[1], a[5], a[2], a[6], a[3], a[7]);
     float b[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        float x = a[k], y = a[k + 4];
-        permlane16_swap(x, y);
-        b[k] = x + y;  // even rows keep a[k], odd rows a[k + 4]
-    }
+    for (int k = 0; k < 4; ++k) b[k] = a[k] + a[k + 4];  // even rows keep a[k], odd rows a[k + 4]
     const bool b3 = (lane >> 3) & 1, b2 = (lane >> 2) & 1;
     float c[2];
 #pragma unroll
@@ -176,14 +172,6 @@ __device__ inline int find_view(const ViewTable &vt, int32_t global_tile) {
     for (int k = 1; k < vt.n_views; ++k)
         if (global_tile >= vt.tile_off[k]) v = k;
     return v;
-}
-
-// Alpha of a fragment exactly as the forward and backward kernels evaluate it.
-__device__ inline float frag_alpha(float dx, float dy, float A, float B, float C, float opac,
-                                   float alpha_max, float &g2) {
-    const float e = fmaf(dx, fmaf(A, dx, B * dy), C * dy * dy);
-    g2 = __builtin_amdgcn_exp2f(e);
-    return fminf(alpha_max, opac * g2);
 }
 
 // ---------------------------------------------------------------------------------------

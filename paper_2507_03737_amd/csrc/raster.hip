@@ -2,8 +2,9 @@
 // its backward.
 //
 // One workgroup per tile of T x T pixels (T = 8, 16 or 32) with T*T/PPT lanes; each lane
-// owns PPT pixels of one column, PPT rows apart (for T = 16, PPT = 4 a single wave covers
-// the tile).  The tile's depth-ordered record list is streamed through LDS in batches of
+// owns PPT vertically adjacent pixels of one column (for T = 16, PPT = 4 a single wave
+// covers the tile).  A fragment is rejected on its base-2 exponent against a per-record
+// threshold, so the exponential is only evaluated for pixels that composite it.  The tile's depth-ordered record list is streamed through LDS in batches of
 // one record per lane (a 64-byte record, converted to tile-local coordinates on load);
 // every lane walks the batch for all its pixels, and the workgroup stops as soon as every
 // pixel has reached the transmittance floor.  Several pixels per lane amortise the LDS
@@ -50,17 +51,27 @@ __device__ inline TilePos tile_pos(const ViewTable &vt) {
     return p;
 }
 
-// Stage record r into LDS slot q, in tile-local pixel coordinates.
-__device__ inline void stage(const float4 *__restrict__ rec, uint32_t r, float x0, float y0, float4 *s0,
-                             float4 *s1, float4 *s2, float4 *s3, int q) {
+// Stage record r into LDS slot q, in tile-local pixel coordinates, with the exponent
+// threshold e_min = log2(alpha_min / opacity): alpha >= alpha_min exactly when the
+// base-2 exponent e >= e_min, so rejected pixels never evaluate the exponential.
+//   s0 = (u, v, A, B), s1 = (C, e_min, opacity, record index), s2 = (colour, z), s3 = point
+// The acceptance test reads s0 and s1 only.
+__device__ inline void stage(const float4 *__restrict__ rec, uint32_t r, float x0, float y0, float alpha_min,
+                             float4 *s0, float4 *s1, float4 *s2, float4 *s3, int q) {
     const float4 *src = rec + 4 * (int64_t)r;
     const float4 a = src[0], b = src[1], c = src[2], d = src[3];
     const float ul = (a.x - x0) + a.z;
     const float vl = (a.y - y0) + a.w;
     s0[q] = make_float4(ul, vl, b.x, b.y);
-    s1[q] = make_float4(b.z, b.w, c.w, c.x);
-    s2[q] = make_float4(c.y, c.z, d.x, d.y);
-    s3[q] = make_float4(d.z, __uint_as_float(r), 0.f, 0.f);
+    s1[q] = make_float4(b.z, __log2f(alpha_min / b.w), b.w, __uint_as_float(r));
+    s2[q] = c;
+    s3[q] = d;
+}
+
+// Base-2 exponent of a Gaussian at a pixel, from the per-column terms A dx^2 and B dx:
+// e = A dx^2 + B dx dy + C dy^2.
+__device__ inline float quad_e(float Adx2, float Bdx, float C, float dy) {
+    return fmaf(fmaf(C, dy, Bdx), dy, Adx2);
 }
 
 template <int TILE, int PPT>
@@ -70,16 +81,16 @@ k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
              float *__restrict__ out_alpha, float *__restrict__ out_pm, float *__restrict__ t_final,
              uint32_t *__restrict__ last, uint32_t *__restrict__ contrib) {
     constexpr int NT = TILE * TILE / PPT;
-    constexpr int RS = NT / TILE;  // row stride between a lane's pixels
     __shared__ float4 s0[NT], s1[NT], s2[NT], s3[NT];
     const TilePos tp = tile_pos<TILE>(vt);
     const uint2 rg = ranges[blockIdx.x];
-    const int lx = threadIdx.x % TILE, ly = threadIdx.x / TILE;
+    // Lane (lx, ly) owns pixels (lx, ly * PPT + k): a wave covers a compact band of rows.
+    const int lx = threadIdx.x % TILE, ly = (threadIdx.x / TILE) * PPT;
     const float px = (float)lx;
     const float amin = rs.alpha_min, amax = rs.alpha_max, tmin = rs.t_min;
     const int i = tp.tx * TILE + lx;
 
-    float T[PPT], C0[PPT], C1[PPT], C2[PPT], D[PPT], X0[PPT], X1[PPT], X2[PPT];
+    float T[PPT], C0[PPT], C1[PPT], C2[PPT], D[PPT], X0[PPT], X1[PPT], X2[PPT], py[PPT];
     uint32_t n_last[PPT], n_contrib[PPT];
     bool done[PPT];
     int live = 0;
@@ -88,55 +99,62 @@ k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
         T[k] = 1.0f;
         C0[k] = C1[k] = C2[k] = D[k] = X0[k] = X1[k] = X2[k] = 0.f;
         n_last[k] = n_contrib[k] = 0u;
-        const int j = tp.ty * TILE + ly + k * RS;
+        py[k] = (float)(ly + k);
+        const int j = tp.ty * TILE + ly + k;
         done[k] = !(i < tp.W && j < tp.H);
         live += done[k] ? 0 : 1;
     }
     for (uint32_t base = rg.x; base < rg.y; base += NT) {
         const uint32_t kk = base + threadIdx.x;
-        if (kk < rg.y) stage(rec, vals[kk], tp.x0, tp.y0, s0, s1, s2, s3, threadIdx.x);
+        if (kk < rg.y) stage(rec, vals[kk], tp.x0, tp.y0, amin, s0, s1, s2, s3, threadIdx.x);
         __syncthreads();
         const int cnt = (int)min((uint32_t)NT, rg.y - base);
-        for (int q = 0; q < cnt && live > 0; ++q) {
-            const float4 a = s0[q], b = s1[q];
+        bool wave_live = __ballot(live > 0) != 0ull;
+        for (int q = 0; q < cnt && wave_live; ++q) {
+            const float4 a = s0[q];
+            const float4 b = s1[q];
             const float dx = px - a.x;
-            float al[PPT], g2[PPT];
+            const float Adx2 = a.z * dx * dx, Bdx = a.w * dx;
+            float e[PPT];
+            bool ok[PPT];
             bool pass = false;
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
-                al[k] = frag_alpha(dx, (float)(ly + k * RS) - a.y, a.z, a.w, b.x, b.y, amax, g2[k]);
-                pass |= !done[k] && !(al[k] < amin);
+                e[k] = quad_e(Adx2, Bdx, b.x, py[k] - a.y);
+                ok[k] = !done[k] && e[k] >= b.y;
+                pass |= ok[k];
             }
-            if (!pass) continue;
+            if (__ballot(pass) == 0ull) continue;  // wave-uniform: nothing composites this entry
             const float4 c = s2[q];
-            const float pz = s3[q].x;
+            const float4 d = s3[q];
+            const uint32_t rel = base - rg.x + (uint32_t)q + 1u;
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
-                if (done[k] || al[k] < amin) continue;
-                const float Tn = __fmul_rn(T[k], __fsub_rn(1.0f, al[k]));
-                if (Tn < tmin) {
-                    done[k] = true;
-                    --live;
-                    continue;
-                }
-                const float w = __fmul_rn(al[k], T[k]);
-                C0[k] = fmaf(w, b.w, C0[k]);
-                C1[k] = fmaf(w, c.x, C1[k]);
-                C2[k] = fmaf(w, c.y, C2[k]);
-                D[k] = fmaf(w, b.z, D[k]);
-                X0[k] = fmaf(w, c.z, X0[k]);
-                X1[k] = fmaf(w, c.w, X1[k]);
-                X2[k] = fmaf(w, pz, X2[k]);
-                T[k] = Tn;
-                n_last[k] = base - rg.x + (uint32_t)q + 1u;
-                ++n_contrib[k];
+                const float al = fminf(amax, b.z * __builtin_amdgcn_exp2f(e[k]));
+                const float Tn = __fmul_rn(T[k], __fsub_rn(1.0f, al));
+                const bool stop = ok[k] && Tn < tmin;
+                const bool add = ok[k] && !stop;
+                const float w = add ? __fmul_rn(al, T[k]) : 0.0f;
+                C0[k] = fmaf(w, c.x, C0[k]);
+                C1[k] = fmaf(w, c.y, C1[k]);
+                C2[k] = fmaf(w, c.z, C2[k]);
+                D[k] = fmaf(w, c.w, D[k]);
+                X0[k] = fmaf(w, d.x, X0[k]);
+                X1[k] = fmaf(w, d.y, X1[k]);
+                X2[k] = fmaf(w, d.z, X2[k]);
+                T[k] = add ? Tn : T[k];
+                n_last[k] = add ? rel : n_last[k];
+                n_contrib[k] += add ? 1u : 0u;
+                done[k] = done[k] || stop;
+                live -= stop ? 1 : 0;
             }
+            wave_live = __ballot(live > 0) != 0ull;
         }
         if (!__syncthreads_or(live > 0 ? 1 : 0)) break;
     }
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
-        const int j = tp.ty * TILE + ly + k * RS;
+        const int j = tp.ty * TILE + ly + k;
         if (!(i < tp.W && j < tp.H)) continue;
         const int64_t e = (int64_t)j * tp.W + i;
         const int64_t pix = tp.pix_off + e, o3 = 3 * tp.pix_off + e, plane = tp.plane;
@@ -170,29 +188,30 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
              const float4 *__restrict__ rec, const uint32_t *__restrict__ last, const float *__restrict__ t_final,
              gspm_const_images fwd, gspm_const_images up, float *__restrict__ grad2d) {
     constexpr int NT = TILE * TILE / PPT;
-    constexpr int RS = NT / TILE;
     __shared__ float4 s0[NT], s1[NT], s2[NT], s3[NT];
     __shared__ uint32_t block_last;
     const TilePos tp = tile_pos<TILE>(vt);
     const uint2 rg = ranges[blockIdx.x];
-    const int lx = threadIdx.x % TILE, ly = threadIdx.x / TILE;
+    const int lx = threadIdx.x % TILE, ly = (threadIdx.x / TILE) * PPT;
     const float px = (float)lx;
     const float amin = rs.alpha_min, amax = rs.alpha_max;
     const int lane = lane_id();
     const int i = tp.tx * TILE + lx;
 
-    // Per-pixel upstream gradient and the total sum_k w_k (g . e_k) from the forward outputs.
+    // Per-pixel upstream gradient and G = sum_k w_k (g . e_k) + T_final (g_C . bg), the
+    // total that the forward's outputs give.
     uint32_t my_last[PPT];
-    float gC0[PPT], gC1[PPT], gC2[PPT], gD[PPT], gA[PPT], gX0[PPT], gX1[PPT], gX2[PPT], Gtot[PPT], bgterm[PPT];
+    float gC0[PPT], gC1[PPT], gC2[PPT], gD[PPT], gA[PPT], gX0[PPT], gX1[PPT], gX2[PPT], Gb[PPT], py[PPT];
     float T[PPT], Pfx[PPT];
     uint32_t thread_last = 0;
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
         my_last[k] = 0;
-        gC0[k] = gC1[k] = gC2[k] = gD[k] = gA[k] = gX0[k] = gX1[k] = gX2[k] = Gtot[k] = bgterm[k] = 0.f;
+        gC0[k] = gC1[k] = gC2[k] = gD[k] = gA[k] = gX0[k] = gX1[k] = gX2[k] = Gb[k] = 0.f;
         T[k] = 1.0f;
         Pfx[k] = 0.0f;
-        const int j = tp.ty * TILE + ly + k * RS;
+        py[k] = (float)(ly + k);
+        const int j = tp.ty * TILE + ly + k;
         if (!(i < tp.W && j < tp.H)) continue;
         const int64_t e = (int64_t)j * tp.W + i;
         const int64_t pix = tp.pix_off + e, o3 = 3 * tp.pix_off + e, plane = tp.plane;
@@ -213,12 +232,12 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
             gD[k] += gX0[k] * rx + gX1[k] * ry + gX2[k];
             gX0[k] = gX1[k] = gX2[k] = 0.f;
         }
-        bgterm[k] = Tf * (gC0[k] * rs.bg[0] + gC1[k] * rs.bg[1] + gC2[k] * rs.bg[2]);
-        Gtot[k] = gC0[k] * fwd.rgb[o3] + gC1[k] * fwd.rgb[o3 + plane] + gC2[k] * fwd.rgb[o3 + 2 * plane] -
-                  bgterm[k] + gD[k] * fwd.depth[pix] + gA[k] * (1.0f - Tf);
+        // The rgb output holds sum_k w_k c_k + T_final bg, which is exactly what G needs.
+        Gb[k] = gC0[k] * fwd.rgb[o3] + gC1[k] * fwd.rgb[o3 + plane] + gC2[k] * fwd.rgb[o3 + 2 * plane] +
+                gD[k] * fwd.depth[pix] + gA[k] * (1.0f - Tf);
         if (rs.frame != 2)
-            Gtot[k] += gX0[k] * fwd.pointmap[o3] + gX1[k] * fwd.pointmap[o3 + plane] +
-                       gX2[k] * fwd.pointmap[o3 + 2 * plane];
+            Gb[k] += gX0[k] * fwd.pointmap[o3] + gX1[k] * fwd.pointmap[o3 + plane] +
+                     gX2[k] * fwd.pointmap[o3 + 2 * plane];
         if (gC0[k] == 0.f && gC1[k] == 0.f && gC2[k] == 0.f && gD[k] == 0.f && gA[k] == 0.f && gX0[k] == 0.f &&
             gX1[k] == 0.f && gX2[k] == 0.f)
             my_last[k] = 0;  // nothing flows back from this pixel
@@ -234,66 +253,71 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
 
     for (uint32_t base = rg.x; base < end; base += NT) {
         const uint32_t kk = base + threadIdx.x;
-        if (kk < end) stage(rec, vals[kk], tp.x0, tp.y0, s0, s1, s2, s3, threadIdx.x);
+        if (kk < end) stage(rec, vals[kk], tp.x0, tp.y0, amin, s0, s1, s2, s3, threadIdx.x);
         __syncthreads();
         const int cnt = (int)min((uint32_t)NT, end - base);
         const uint32_t rel0 = base - rg.x;
         for (int q = 0; q < cnt; ++q) {
             const uint32_t rel = rel0 + (uint32_t)q;
             if (rel >= wave_last) break;  // wave-uniform
-            const float4 a = s0[q], b = s1[q];
+            const float4 a = s0[q];
+            const float4 b = s1[q];
             const float dx = px - a.x;
-            float al[PPT], g2[PPT];
+            const float Adx = a.z * dx, Bdx = a.w * dx;
+            const float Adx2 = Adx * dx;
+            float e[PPT];
             bool valid[PPT];
             bool any = false;
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
-                al[k] = frag_alpha(dx, (float)(ly + k * RS) - a.y, a.z, a.w, b.x, b.y, amax, g2[k]);
-                valid[k] = rel < my_last[k] && !(al[k] < amin);
+                e[k] = quad_e(Adx2, Bdx, b.x, py[k] - a.y);
+                valid[k] = rel < my_last[k] && e[k] >= b.y;
                 any |= valid[k];
             }
-            if (__ballot(any) == 0ull) continue;
+            if (__ballot(any) == 0ull) continue;  // wave-uniform
+            const float4 c = s2[q];
+            const float4 d = s3[q];
+            const float dx2 = dx * dx, twoAdx = 2.0f * Adx, twoC = 2.0f * b.x;
             float v[16];
 #pragma unroll
             for (int t = 0; t < 16; ++t) v[t] = 0.f;
-            if (any) {
-                const float4 c = s2[q];
-                const float pz = s3[q].x;
 #pragma unroll
-                for (int k = 0; k < PPT; ++k) {
-                    if (!valid[k]) continue;
-                    const float dy = (float)(ly + k * RS) - a.y;
-                    const float w = __fmul_rn(al[k], T[k]);
-                    const float s = gC0[k] * b.w + gC1[k] * c.x + gC2[k] * c.y + gD[k] * b.z + gA[k] +
-                                    gX0[k] * c.z + gX1[k] * c.w + gX2[k] * pz;
-                    Pfx[k] = fmaf(w, s, Pfx[k]);
-                    const float one_m = __fsub_rn(1.0f, al[k]);
-                    const float dLda = T[k] * s - (Gtot[k] - Pfx[k] + bgterm[k]) * __builtin_amdgcn_rcpf(one_m);
-                    if (!(b.y * g2[k] > amax)) {
-                        const float Gl = dLda * al[k] * kLn2;
-                        v[0] -= Gl * (2.0f * a.z * dx + a.w * dy);
-                        v[1] -= Gl * (a.w * dx + 2.0f * b.x * dy);
-                        v[2] += Gl * dx * dx;
-                        v[3] += Gl * dx * dy;
-                        v[4] += Gl * dy * dy;
-                        if (!POSE_ONLY) v[5] += dLda * g2[k];
-                    }
-                    v[6] += w * gD[k];
-                    if (!POSE_ONLY) {
-                        v[7] += w * gC0[k];
-                        v[8] += w * gC1[k];
-                        v[9] += w * gC2[k];
-                    }
-                    v[10] += w * gX0[k];
-                    v[11] += w * gX1[k];
-                    v[12] += w * gX2[k];
-                    T[k] = __fmul_rn(T[k], one_m);
+            for (int k = 0; k < PPT; ++k) {
+                // Branch-free: an invalid pixel gets zero weight and leaves T unchanged
+                // (e <= 0, so alpha lies in [0, alpha_max] and 1 - alpha >= 1 - alpha_max).
+                const float dy = py[k] - a.y;
+                const float g2 = __builtin_amdgcn_exp2f(e[k]);
+                const float al = fminf(amax, b.z * g2);
+                const float w = valid[k] ? __fmul_rn(al, T[k]) : 0.0f;
+                const float s = gC0[k] * c.x + gC1[k] * c.y + gC2[k] * c.z + gD[k] * c.w + gA[k] +
+                                gX0[k] * d.x + gX1[k] * d.y + gX2[k] * d.z;
+                Pfx[k] = fmaf(w, s, Pfx[k]);
+                const float one_m = __fsub_rn(1.0f, al);
+                const float dLda = T[k] * s - (Gb[k] - Pfx[k]) * __builtin_amdgcn_rcpf(one_m);
+                const bool unclamped = valid[k] && al < amax;
+                const float Gl = unclamped ? dLda * al * kLn2 : 0.0f;
+                const float Gldy = Gl * dy;
+                v[0] = fmaf(-Gl, fmaf(a.w, dy, twoAdx), v[0]);
+                v[1] = fmaf(-Gl, fmaf(twoC, dy, Bdx), v[1]);
+                v[2] = fmaf(Gl, dx2, v[2]);
+                v[3] = fmaf(Gldy, dx, v[3]);
+                v[4] = fmaf(Gldy, dy, v[4]);
+                if (!POSE_ONLY) v[5] = fmaf(unclamped ? dLda : 0.0f, g2, v[5]);
+                v[6] = fmaf(w, gD[k], v[6]);
+                if (!POSE_ONLY) {
+                    v[7] = fmaf(w, gC0[k], v[7]);
+                    v[8] = fmaf(w, gC1[k], v[8]);
+                    v[9] = fmaf(w, gC2[k], v[9]);
                 }
+                v[10] = fmaf(w, gX0[k], v[10]);
+                v[11] = fmaf(w, gX1[k], v[11]);
+                v[12] = fmaf(w, gX2[k], v[12]);
+                T[k] = valid[k] ? __fmul_rn(T[k], one_m) : T[k];
             }
             const float tot = wave_reduce_scatter16(v);
             const int idx = (lane >> 2) & 15;
             if ((lane & 3) == 0 && idx < kG2Used && tot != 0.f) {
-                const uint32_t r = __float_as_uint(s3[q].y);
+                const uint32_t r = __float_as_uint(b.w);
                 unsafeAtomicAdd(grad2d + (int64_t)r * kG2 + idx, tot);
             }
         }
