@@ -796,53 +796,86 @@ int orc_backward(const orc_gaussians *G, const orc_view *V, const orc_settings *
 /* ------------------------------------------------------------------------- */
 /* Tile-pair list, brute force.                                               */
 
-/* For tile size B, list every (tile, Gaussian) pair whose support rectangle intersects
- * the tile, ordered by (tile, z, Gaussian index).  Tiles are numbered row-major,
- * tiles_x = ceil(W / B).  Returns the number of pairs or -(needed) if cap is short. */
+/* Minimum over integer pixel columns i in [ia, ib] and real y in [ya, yb] of
+ * f = Qxx dx^2 + 2 Qxy dx dy + Qyy dy^2 with dx = i - u, dy = y - v: for each column the
+ * parabola in y is minimised at its vertex clamped to the interval. */
+static double quad_min_columns(const double Q[3], double u, double v, int32_t ia, int32_t ib, double ya, double yb)
+{
+    double best = INFINITY;
+    for (int32_t i = ia; i <= ib; ++i) {
+        const double dx = (double)i - u;
+        double dy = -Q[1] * dx / Q[2];
+        if (dy < ya - v) dy = ya - v;
+        if (dy > yb - v) dy = yb - v;
+        const double f = Q[0] * dx * dx + 2.0 * Q[1] * dx * dy + Q[2] * dy * dy;
+        if (f < best) best = f;
+    }
+    return best;
+}
+
+/* For tile size B, list every (tile, Gaussian) pair whose support ellipse
+ * {d : d^T Q d <= 2 ln(a / alpha_min) (1 + margin)} contains a point (i, y) with i an
+ * integer pixel column of the tile and y between the tile's first and last pixel rows,
+ * columns and rows clipped to the Gaussian's support pixel box; ordered by (tile, z,
+ * Gaussian index).  Every pixel centre of the ellipse lies in a listed tile.  Tiles are numbered row-major, tiles_x = ceil(W / B).  near[g] is set
+ * when some tile's membership is decided within a relative tol of the support level.
+ * Returns the number of pairs or -(needed) if cap is short. */
 int64_t orc_tile_pairs(const orc_proj *P, int64_t n, int32_t width, int32_t height, int32_t B,
-                       int64_t cap, int32_t *tile_out, int64_t *g_out)
+                       double alpha_min, double margin, double tol, int64_t cap, int32_t *tile_out,
+                       int64_t *g_out, int8_t *near)
 {
     const int32_t tx = (width + B - 1) / B, ty = (height + B - 1) / B;
     const int64_t ntiles = (int64_t)tx * ty;
     int64_t total = 0;
-    for (int64_t g = 0; g < n; ++g) {
-        if (!P[g].visible) continue;
-        const int64_t w = P[g].rect[1] / B - P[g].rect[0] / B + 1;
-        const int64_t h = P[g].rect[3] / B - P[g].rect[2] / B + 1;
-        total += w * h;
-    }
-    if (total > cap) return -total;
-    /* Bucket per tile, then sort each bucket by (z, g). */
+    /* Pass 1 counts, pass 2 fills the buckets. */
     int64_t *cnt = (int64_t *)calloc((size_t)ntiles + 1, sizeof(int64_t));
-    for (int64_t g = 0; g < n; ++g) {
-        if (!P[g].visible) continue;
-        for (int32_t y = P[g].rect[2] / B; y <= P[g].rect[3] / B; ++y)
-            for (int32_t x = P[g].rect[0] / B; x <= P[g].rect[1] / B; ++x) cnt[(int64_t)y * tx + x + 1]++;
-    }
-    for (int64_t t = 0; t < ntiles; ++t) cnt[t + 1] += cnt[t];
-    int64_t *cur = (int64_t *)malloc(sizeof(int64_t) * (size_t)ntiles);
-    memcpy(cur, cnt, sizeof(int64_t) * (size_t)ntiles);
-    cand_t *tmp = (cand_t *)malloc(sizeof(cand_t) * (size_t)(total > 0 ? total : 1));
-    for (int64_t g = 0; g < n; ++g) {
-        if (!P[g].visible) continue;
-        for (int32_t y = P[g].rect[2] / B; y <= P[g].rect[3] / B; ++y)
-            for (int32_t x = P[g].rect[0] / B; x <= P[g].rect[1] / B; ++x) {
-                const int64_t t = (int64_t)y * tx + x;
-                tmp[cur[t]].g = g;
-                tmp[cur[t]].z = P[g].z;
-                cur[t]++;
+    for (int pass = 0; pass < 2; ++pass) {
+        int64_t *cur = NULL;
+        cand_t *tmp = NULL;
+        if (pass == 1) {
+            for (int64_t t = 0; t < ntiles; ++t) cnt[t + 1] += cnt[t];
+            total = cnt[ntiles];
+            if (total > cap) { free(cnt); return -total; }
+            cur = (int64_t *)malloc(sizeof(int64_t) * (size_t)(ntiles > 0 ? ntiles : 1));
+            memcpy(cur, cnt, sizeof(int64_t) * (size_t)ntiles);
+            tmp = (cand_t *)malloc(sizeof(cand_t) * (size_t)(total > 0 ? total : 1));
+        }
+        for (int64_t g = 0; g < n; ++g) {
+            const orc_proj *p = &P[g];
+            if (pass == 0 && near) near[g] = 0;
+            if (!p->visible) continue;
+            const double q = 2.0 * log(p->a / alpha_min) * (1.0 + margin);
+            for (int32_t y = p->rect[2] / B; y <= p->rect[3] / B; ++y)
+                for (int32_t x = p->rect[0] / B; x <= p->rect[1] / B; ++x) {
+                    const int32_t ia = x * B > p->rect[0] ? x * B : p->rect[0];
+                    const int32_t ib = x * B + B - 1 < p->rect[1] ? x * B + B - 1 : p->rect[1];
+                    const double ya = fmax(y * B, p->rect[2]), yb = fmin(y * B + B - 1, p->rect[3]);
+                    const double m = quad_min_columns(p->Q, p->u, p->v, ia, ib, ya, yb);
+                    if (pass == 0 && near && fabs(m - q) <= tol * q) near[g] = 1;
+                    if (!(m <= q)) continue;
+                    const int64_t t = (int64_t)y * tx + x;
+                    if (pass == 0) {
+                        cnt[t + 1]++;
+                    } else {
+                        tmp[cur[t]].g = g;
+                        tmp[cur[t]].z = p->z;
+                        cur[t]++;
+                    }
+                }
+        }
+        if (pass == 1) {
+            for (int64_t t = 0; t < ntiles; ++t) {
+                qsort(tmp + cnt[t], (size_t)(cnt[t + 1] - cnt[t]), sizeof(cand_t), cand_cmp);
+                for (int64_t k = cnt[t]; k < cnt[t + 1]; ++k) {
+                    tile_out[k] = (int32_t)t;
+                    g_out[k] = tmp[k].g;
+                }
             }
-    }
-    for (int64_t t = 0; t < ntiles; ++t) {
-        qsort(tmp + cnt[t], (size_t)(cnt[t + 1] - cnt[t]), sizeof(cand_t), cand_cmp);
-        for (int64_t k = cnt[t]; k < cnt[t + 1]; ++k) {
-            tile_out[k] = (int32_t)t;
-            g_out[k] = tmp[k].g;
+            free(cur);
+            free(tmp);
         }
     }
     free(cnt);
-    free(cur);
-    free(tmp);
     return total;
 }
 

@@ -111,7 +111,8 @@ def lib():
                                    ctypes.c_int64, i32p, f64p, f64p, f64p, f64p,
                                    ctypes.POINTER(_Grads)]
         L.orc_tile_pairs.argtypes = [ctypes.POINTER(_Proj), ctypes.c_int64, ctypes.c_int32,
-                                     ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, i32p, i64p]
+                                     ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_double, ctypes.c_int64, i32p, i64p, i8p]
         L.orc_tile_pairs.restype = ctypes.c_int64
         L.orc_se3_exp_left.argtypes = [f64p, f64p, f64p]
         L.orc_num_threads.restype = ctypes.c_int
@@ -302,16 +303,28 @@ def backward(params: Params, view, settings: Settings, pixels, up, pointmap_fram
     return g
 
 
-def tile_pairs(proj, n, width, height, B):
-    """Brute-force (tile, Gaussian) pairs ordered by (tile, z, index)."""
+# Relative widening of the support level used for tile membership (kept conservative so
+# that float32 evaluation never finds a fragment outside its listed tiles).
+SUPPORT_MARGIN = 1e-6
+
+
+def tile_pairs(proj, n, width, height, B, settings=None, tol=1e-5):
+    """Brute-force (tile, Gaussian) pairs ordered by (tile, z, index): a Gaussian is listed
+    in a tile when its support ellipse contains a point on one of the tile's integer pixel
+    columns between the tile's first and last pixel rows (clipped to its support box).  Returns (tiles, gaussians, near) where near[g] marks a
+    membership decided within relative ``tol`` of the support level."""
+    s = settings or Settings()
+    amin = float(np.float32(s.alpha_min))
     L = lib()
-    need = L.orc_tile_pairs(proj, n, width, height, B, 0, None, None)
+    near = np.zeros(max(n, 1), dtype=np.int8)
+    need = L.orc_tile_pairs(proj, n, width, height, B, amin, SUPPORT_MARGIN, tol, 0, None, None, _p(near, i8p))
     total = -need if need < 0 else need
     tiles = np.zeros(max(total, 1), dtype=np.int32)
     gs = np.zeros(max(total, 1), dtype=np.int64)
-    got = L.orc_tile_pairs(proj, n, width, height, B, total, _p(tiles, i32p), _p(gs, i64p))
+    got = L.orc_tile_pairs(proj, n, width, height, B, amin, SUPPORT_MARGIN, tol, total, _p(tiles, i32p),
+                           _p(gs, i64p), _p(near, i8p))
     assert got == total
-    return tiles[:total], gs[:total]
+    return tiles[:total], gs[:total], near[:n].astype(bool)
 
 
 def se3_exp_left(xi, T12):

@@ -231,11 +231,22 @@ k_radix_downsweep(const uint32_t *__restrict__ kin, const uint32_t *__restrict__
 
 // ------------------------------- pairs and ranges -------------------------------------
 
+__device__ inline void emit_row(uint32_t *__restrict__ pkey, uint32_t *__restrict__ pval, uint32_t cap, uint32_t &k,
+                                uint32_t base, uint32_t tiles_x, int ty, int ta, int tb, uint32_t r) {
+    for (int tx = ta; tx <= tb; ++tx, ++k) {
+        if (k >= cap) return;
+        pkey[k] = base + (uint32_t)ty * tiles_x + (uint32_t)tx;
+        pval[k] = r;
+    }
+}
+
+// One lane per record (in depth order).  Records with many pairs are queued for k_keygen_big.
 __global__ void __launch_bounds__(256)
 k_keygen(const uint32_t *__restrict__ sorted_rec, const uint32_t *__restrict__ counts,
-         const uint32_t *__restrict__ offsets, const uint32_t *__restrict__ trect, int64_t n_records,
-         int64_t n_per_view, ViewTable vt, uint32_t *__restrict__ pkey, uint32_t *__restrict__ pval,
-         FrameHeader *__restrict__ hdr, uint32_t cap, const uint32_t *__restrict__ total) {
+         const uint32_t *__restrict__ offsets, const float4 *__restrict__ rec, RasterSettings rs,
+         int64_t n_records, int64_t n_per_view, ViewTable vt, uint32_t *__restrict__ pkey,
+         uint32_t *__restrict__ pval, FrameHeader *__restrict__ hdr, uint32_t cap,
+         const uint32_t *__restrict__ total, uint32_t *__restrict__ big_list, uint32_t *__restrict__ big_count) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p == 0) {
         const uint32_t t = *total;
@@ -248,19 +259,56 @@ k_keygen(const uint32_t *__restrict__ sorted_rec, const uint32_t *__restrict__ c
     const uint32_t r = sorted_rec[p];
     const uint32_t c = counts[r];
     if (c == 0) return;
-    const uint32_t o = offsets[p];
+    if (c > kBigRecord) {
+        big_list[atomicAdd(big_count, 1u)] = (uint32_t)p;
+        return;
+    }
+    uint32_t k = offsets[p];
+    if (k >= cap) return;
     const int v = (int)(r / n_per_view);
-    const uint32_t rx = trect[2 * (int64_t)r], ry = trect[2 * (int64_t)r + 1];
-    const uint32_t x0 = rx & 0xffffu, x1 = rx >> 16, y0 = ry & 0xffffu, y1 = ry >> 16;
-    const uint32_t base = (uint32_t)vt.tile_off[v];
-    const uint32_t tx = (uint32_t)vt.tiles_x[v];
-    uint32_t k = o;
-    for (uint32_t y = y0; y <= y1; ++y)
-        for (uint32_t x = x0; x <= x1; ++x, ++k) {
-            if (k >= cap) return;
-            pkey[k] = base + y * tx + x;
-            pval[k] = r;
+    Footprint f;
+    if (!record_footprint(rec[4 * (int64_t)r], rec[4 * (int64_t)r + 1], rs.alpha_min, vt.width[v], vt.height[v], f))
+        return;
+    const int T = vt.tile;
+    const uint32_t base = (uint32_t)vt.tile_off[v], tiles_x = (uint32_t)vt.tiles_x[v];
+    for (int ty = f.j0 / T; ty <= f.j1 / T; ++ty) {
+        int ta, tb;
+        if (row_span(f, T, ty, ta, tb)) emit_row(pkey, pval, cap, k, base, tiles_x, ty, ta, tb, r);
+    }
+}
+
+// One wave per queued record: lanes take tile rows, a wave scan places each row's tiles.
+__global__ void __launch_bounds__(256)
+k_keygen_big(const uint32_t *__restrict__ sorted_rec, const uint32_t *__restrict__ offsets,
+             const float4 *__restrict__ rec, RasterSettings rs, int64_t n_per_view, ViewTable vt,
+             uint32_t *__restrict__ pkey, uint32_t *__restrict__ pval, uint32_t cap,
+             const uint32_t *__restrict__ big_list, const uint32_t *__restrict__ big_count) {
+    const int lane = lane_id();
+    const uint32_t n_big = *big_count;
+    const uint32_t n_waves = gridDim.x * (blockDim.x / kWave);
+    for (uint32_t w = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; w < n_big; w += n_waves) {
+        const uint32_t p = big_list[w];
+        const uint32_t r = sorted_rec[p];
+        const int v = (int)(r / n_per_view);
+        Footprint f;
+        if (!record_footprint(rec[4 * (int64_t)r], rec[4 * (int64_t)r + 1], rs.alpha_min, vt.width[v],
+                              vt.height[v], f))
+            continue;  // wave-uniform
+        const int T = vt.tile;
+        const uint32_t base = (uint32_t)vt.tile_off[v], tiles_x = (uint32_t)vt.tiles_x[v];
+        uint32_t k0 = offsets[p];
+        for (int ty0 = f.j0 / T; ty0 <= f.j1 / T; ty0 += kWave) {
+            const int ty = ty0 + lane;
+            int ta = 0, tb = -1;
+            if (ty <= f.j1 / T && !row_span(f, T, ty, ta, tb)) tb = ta - 1;
+            if (ty > f.j1 / T) tb = ta - 1;
+            const uint32_t len = (uint32_t)(tb - ta + 1);
+            const uint32_t inc = wave_inclusive_scan(len);
+            uint32_t k = k0 + inc - len;
+            if (len) emit_row(pkey, pval, cap, k, base, tiles_x, ty, ta, tb, r);
+            k0 += __shfl(inc, kWave - 1, kWave);
         }
+    }
 }
 
 __global__ void __launch_bounds__(256)
@@ -368,12 +416,18 @@ hipError_t radix_sort(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t
 }
 
 hipError_t launch_keygen(const uint32_t *sorted_rec, const uint32_t *counts, const uint32_t *offsets,
-                         const uint32_t *trect, int64_t n_records, int64_t n_per_view, const ViewTable &vt,
-                         uint32_t *pkey, uint32_t *pval, FrameHeader *hdr, uint32_t capacity,
-                         const uint32_t *total, hipStream_t s) {
+                         const float *records, const RasterSettings &rs, int64_t n_records, int64_t n_per_view,
+                         const ViewTable &vt, uint32_t *pkey, uint32_t *pval, FrameHeader *hdr, uint32_t capacity,
+                         const uint32_t *total, uint32_t *big_list, uint32_t *big_count, hipStream_t s) {
+    hipError_t e = launch_fill_u32(big_count, 0u, 1, s);
+    if (e != hipSuccess) return e;
+    const float4 *rec = reinterpret_cast<const float4 *>(records);
     const int64_t nb = n_records > 0 ? (n_records + 255) / 256 : 1;
-    hipLaunchKernelGGL(k_keygen, dim3((unsigned)nb), dim3(256), 0, s, sorted_rec, counts, offsets, trect, n_records,
-                       n_per_view, vt, pkey, pval, hdr, capacity, total);
+    hipLaunchKernelGGL(k_keygen, dim3((unsigned)nb), dim3(256), 0, s, sorted_rec, counts, offsets, rec, rs, n_records,
+                       n_per_view, vt, pkey, pval, hdr, capacity, total, big_list, big_count);
+    if (n_records > 0)
+        hipLaunchKernelGGL(k_keygen_big, dim3(1024), dim3(256), 0, s, sorted_rec, offsets, rec, rs, n_per_view, vt,
+                           pkey, pval, capacity, big_list, big_count);
     return hipGetLastError();
 }
 

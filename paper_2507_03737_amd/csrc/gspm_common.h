@@ -175,6 +175,73 @@ __device__ inline int find_view(const ViewTable &vt, int32_t global_tile) {
 }
 
 // ---------------------------------------------------------------------------------------
+// Support footprint of a record and its exact tile-row spans.
+//
+// The support of a Gaussian is the ellipse d^T Q d <= q, q = 2 ln(opacity / alpha_min),
+// where its alpha reaches alpha_min.  A tile takes a (tile, record) pair exactly when the
+// ellipse meets the rectangle spanned by the tile's pixel centres (clipped to the
+// support's pixel box).  Per tile row this is an interval of tiles: the ellipse's x-extent
+// over the row's y-range is attained at the row's ends or at the ellipse's leftmost /
+// rightmost points.  Both the pair count and the pair emission evaluate this in float64
+// from the same float32 record fields, so they agree exactly.
+constexpr double kSupportMargin = 1e-6;  // relative widening of q, keeps the test conservative
+
+struct Footprint {
+    double u, v;            // centre
+    double qxx, qxy, qyy;   // conic
+    double q;               // support level
+    double isyy;            // 1 / Sigma_yy = det(Q) / qxx
+    double rx, ry;          // support half extents
+    double yr;              // y offset of the rightmost support point
+    double kx;              // centre-line slope -qxy / qxx
+    int i0, i1, j0, j1;     // support pixel box clipped to the image
+};
+
+__device__ inline bool record_footprint(const float4 r0, const float4 r1, float alpha_min, int W, int H,
+                                        Footprint &f) {
+    constexpr double kLn2d = 0.69314718055994530942;
+    if (!(r1.w >= alpha_min)) return false;
+    f.u = (double)r0.x + (double)r0.z;
+    f.v = (double)r0.y + (double)r0.w;
+    f.qxx = -2.0 * kLn2d * (double)r1.x;
+    f.qxy = -kLn2d * (double)r1.y;
+    f.qyy = -2.0 * kLn2d * (double)r1.z;
+    const double det = f.qxx * f.qyy - f.qxy * f.qxy;
+    if (!(det > 0.0) || !(f.qxx > 0.0)) return false;
+    f.q = 2.0 * log((double)r1.w / (double)alpha_min) * (1.0 + kSupportMargin);
+    const double sxx = f.qyy / det, syy = f.qxx / det, sxy = -f.qxy / det;
+    f.isyy = det / f.qxx;
+    f.rx = sqrt(f.q * sxx);
+    f.ry = sqrt(f.q * syy);
+    f.yr = f.rx > 0.0 ? sxy * f.q / f.rx : 0.0;  // = sxy sqrt(q / sxx)
+    f.kx = -f.qxy / f.qxx;
+    f.i0 = (int)fmax(0.0, ceil(f.u - f.rx));
+    f.i1 = (int)fmin((double)(W - 1), floor(f.u + f.rx));
+    f.j0 = (int)fmax(0.0, ceil(f.v - f.ry));
+    f.j1 = (int)fmin((double)(H - 1), floor(f.v + f.ry));
+    return f.i0 <= f.i1 && f.j0 <= f.j1;
+}
+
+// Tiles [ta, tb] of tile row ty that meet the support (false if none).
+__device__ inline bool row_span(const Footprint &f, int B, int ty, int &ta, int &tb) {
+    const int ja = max(ty * B, f.j0), jb = min(ty * B + B - 1, f.j1);
+    if (ja > jb) return false;
+    const double ya = fmax((double)ja - f.v, -f.ry), yb = fmin((double)jb - f.v, f.ry);
+    if (ya > yb) return false;
+    // Half width of the support at height y around the centre line x = kx y.
+    const double ha = sqrt(fmax(0.0, (f.q - ya * ya * f.isyy) / f.qxx));
+    const double hb = sqrt(fmax(0.0, (f.q - yb * yb * f.isyy) / f.qxx));
+    const double xr = (f.yr >= ya && f.yr <= yb) ? f.rx : fmax(f.kx * ya + ha, f.kx * yb + hb);
+    const double xl = (-f.yr >= ya && -f.yr <= yb) ? -f.rx : fmin(f.kx * ya - ha, f.kx * yb - hb);
+    const int ia = max(f.i0, (int)ceil(f.u + xl));
+    const int ib = min(f.i1, (int)floor(f.u + xr));
+    if (ia > ib) return false;
+    ta = ia / B;
+    tb = ib / B;
+    return true;
+}
+
+// ---------------------------------------------------------------------------------------
 // Host-side launch wrappers (defined in the .hip files).
 
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t n, hipStream_t s);
@@ -182,7 +249,7 @@ hipError_t launch_fill_f32(float *p, float value, int64_t n, hipStream_t s);
 
 hipError_t launch_preprocess(const gspm_gaussians &g, const ViewTable &vt, const float *T_cw,
                              const RasterSettings &rs, float *records, uint32_t *counts,
-                             uint32_t *trect, uint32_t *dkey, uint32_t *dval, hipStream_t s);
+                             uint32_t *dkey, uint32_t *dval, hipStream_t s);
 
 // Exclusive scan of counts[idx[p]] for p < n (idx may be NULL for the identity); writes
 // offsets[p] and the total to *total.  part: scratch of at least scan_partials(n) words.
@@ -200,10 +267,15 @@ hipError_t radix_sort(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t
                       const uint32_t *n_dev, int bits, int digit_bits, uint32_t *hist,
                       uint32_t *scan_part, hipStream_t s);
 
+// Emits the (global tile, record) pairs of every record in depth order.  Records with
+// more than kBigRecord pairs are queued in big_list (big_count zeroed here) and emitted
+// by whole waves.  records: the projected records (for the support footprint).
+constexpr uint32_t kBigRecord = 64;
 hipError_t launch_keygen(const uint32_t *sorted_rec, const uint32_t *counts, const uint32_t *offsets,
-                         const uint32_t *trect, int64_t n_records, int64_t n_per_view,
+                         const float *records, const RasterSettings &rs, int64_t n_records, int64_t n_per_view,
                          const ViewTable &vt, uint32_t *pkey, uint32_t *pval, FrameHeader *hdr,
-                         uint32_t capacity, const uint32_t *total, hipStream_t s);
+                         uint32_t capacity, const uint32_t *total, uint32_t *big_list, uint32_t *big_count,
+                         hipStream_t s);
 
 hipError_t launch_sum_u64(const uint32_t *x, int64_t n, unsigned long long *out, hipStream_t s);
 

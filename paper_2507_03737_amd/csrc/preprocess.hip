@@ -116,8 +116,8 @@ __device__ inline void project_one(const gspm_gaussians &G, int64_t g, int64_t n
 
 __global__ void __launch_bounds__(256)
 k_preprocess(gspm_gaussians G, ViewTable vt, const float *__restrict__ T_cw, RasterSettings rs,
-             float4 *__restrict__ rec, uint32_t *__restrict__ counts, uint32_t *__restrict__ trect,
-             uint32_t *__restrict__ dkey, uint32_t *__restrict__ dval) {
+             float4 *__restrict__ rec, uint32_t *__restrict__ counts, uint32_t *__restrict__ dkey,
+             uint32_t *__restrict__ dval) {
     const int64_t n = G.n;
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n * vt.n_views) return;
@@ -132,21 +132,29 @@ k_preprocess(gspm_gaussians G, ViewTable vt, const float *__restrict__ T_cw, Ras
         dkey[r] = 0u;
         return;
     }
-    const int T = vt.tile;
-    const uint32_t tx0 = P.rect[0] / T, tx1 = P.rect[1] / T, ty0 = P.rect[2] / T, ty1 = P.rect[3] / T;
-    counts[r] = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
-    trect[2 * r] = tx0 | (tx1 << 16);
-    trect[2 * r + 1] = ty0 | (ty1 << 16);
     const float zf = (float)P.z;
     dkey[r] = __float_as_uint(zf);
 
     const float uhi = (float)P.u, vhi = (float)P.v;
     const float ulo = (float)(P.u - (double)uhi), vlo = (float)(P.v - (double)vhi);
+    const float4 r0 = make_float4(uhi, vhi, ulo, vlo);
+    const float4 r1 = make_float4((float)(-0.5 * kLog2e * P.Q[0]), (float)(-kLog2e * P.Q[1]),
+                                  (float)(-0.5 * kLog2e * P.Q[2]), (float)P.a);
     float4 *o = rec + 4 * r;
-    o[0] = make_float4(uhi, vhi, ulo, vlo);
-    o[1] = make_float4((float)(-0.5 * kLog2e * P.Q[0]), (float)(-kLog2e * P.Q[1]),
-                       (float)(-0.5 * kLog2e * P.Q[2]), (float)P.a);
+    o[0] = r0;
+    o[1] = r1;
     o[2] = make_float4(G.rgb[g], G.rgb[n + g], G.rgb[2 * n + g], zf);
+    // Number of tiles the support meets, row by row (the pair emission repeats this).
+    uint32_t count = 0;
+    Footprint f;
+    if (record_footprint(r0, r1, rs.alpha_min, vt.width[v], vt.height[v], f)) {
+        const int T = vt.tile;
+        for (int ty = f.j0 / T; ty <= f.j1 / T; ++ty) {
+            int ta, tb;
+            if (row_span(f, T, ty, ta, tb)) count += (uint32_t)(tb - ta + 1);
+        }
+    }
+    counts[r] = count;
     if (rs.frame == 0)
         o[3] = make_float4(G.means[g], G.means[n + g], G.means[2 * n + g], 0.0f);
     else
@@ -416,11 +424,11 @@ hipError_t launch_fill_f32(float *p, float value, int64_t n, hipStream_t s) {
 
 hipError_t launch_preprocess(const gspm_gaussians &g, const ViewTable &vt, const float *T_cw,
                              const RasterSettings &rs, float *records, uint32_t *counts,
-                             uint32_t *trect, uint32_t *dkey, uint32_t *dval, hipStream_t s) {
+                             uint32_t *dkey, uint32_t *dval, hipStream_t s) {
     const int64_t R = g.n * vt.n_views;
     if (R <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_preprocess, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, s, g, vt, T_cw, rs,
-                       reinterpret_cast<float4 *>(records), counts, trect, dkey, dval);
+                       reinterpret_cast<float4 *>(records), counts, dkey, dval);
     return hipGetLastError();
 }
 

@@ -112,6 +112,7 @@ def tile_edge_near(bounds, B, W, H, tol):
     (or the visibility) changes: u - rx at k B - 1 (ceil crosses into tile k), u + rx at
     k B (floor crosses), and the image borders."""
     lo_x, hi_x, lo_y, hi_y = bounds[:, 0], bounds[:, 1], bounds[:, 2], bounds[:, 3]
+    tol = np.broadcast_to(np.asarray(tol, dtype=np.float64), lo_x.shape)
 
     def near(x, offs, extra):
         r = np.zeros(x.shape, dtype=bool)

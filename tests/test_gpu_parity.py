@@ -91,14 +91,17 @@ def test_forward_tiles_and_ragged(lib, oracle, tile, ppl):
     U.check_grad(f"ragged/t{tile}x{ppl} pose", g["pose"], r["pose"], frac=1.0)
 
 
-def test_tile_lists_exact(lib, oracle):
+@pytest.mark.parametrize("tile,ppl", [(16, 2), (8, 1)])
+def test_tile_lists_exact(lib, oracle, tile, ppl):
     """Per-tile (record) lists equal the oracle's brute-force lists, ordered by
-    (float32 depth, index), except Gaussians whose support bound lies within 1e-4 px
-    (plus float64 rounding) of a value where the tile rectangle changes."""
+    (float32 depth, index), except Gaussians whose membership is decided at the edge:
+    a support-box bound within 1e-4 px (plus the float32 rounding of the record, 2e-7 of
+    the coordinate) of a value where the box changes tiles, or a tile whose nearest
+    point lies within 1e-5 (relative) of the support level."""
     U.log("[gpu] tile lists c0")
     O = oracle
     sc = _posed(scenes.make_scene("c0"))
-    cfg = lib.RasterConfig(pointmap_frame=1)
+    cfg = lib.RasterConfig(pointmap_frame=1, tile=tile, pixels_per_lane=ppl)
     rast, params, out, fs = _render_gpu(lib, sc, cfg)
     cam = sc.cams[0]
     B = cfg.tile
@@ -112,8 +115,9 @@ def test_tile_lists_exact(lib, oracle):
     po = O.Params.from_scene(sc)
     proj = O.project(po, O.make_view(cam, sc.T_cw[0]), S)
     pa = O.proj_numpy(proj)
-    tiles_o, gs_o = O.tile_pairs(proj, po.n, cam.width, cam.height, B)
-    exempt = U.tile_edge_near(pa["bounds"], B, cam.width, cam.height, 1e-4) & (pa["visible"] == 1)
+    tiles_o, gs_o, near = O.tile_pairs(proj, po.n, cam.width, cam.height, B, S, tol=1e-5)
+    tol_px = 1e-4 + 2e-7 * (np.abs(pa["u"]) + np.abs(pa["v"]) + pa["rx"] + pa["ry"])
+    exempt = (U.tile_edge_near(pa["bounds"], B, cam.width, cam.height, tol_px) | near) & (pa["visible"] == 1)
     z32 = pa["z"].astype(np.float32)
     assert pairs == len(tiles_o) or exempt.any()
     n_exempt_tiles = 0

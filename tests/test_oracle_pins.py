@@ -452,7 +452,8 @@ def test_unfrozen_fd_on_margin_scene(oracle):
 
 
 # ---------------------------------------------------------------------------
-# P9 (oracle side): every contributing fragment's tile lists its Gaussian.
+# P9 (oracle side): every contributing fragment's tile lists its Gaussian, and each
+# listed tile really meets the support ellipse (checked by dense sampling).
 
 def test_p9_tile_lists_cover_every_fragment(oracle):
     O = oracle
@@ -462,7 +463,7 @@ def test_p9_tile_lists_cover_every_fragment(oracle):
     view = O.make_view(sc.cams[0], sc.T_cw[0])
     proj = O.project(p, view, S)
     B = 16
-    tiles, gs = O.tile_pairs(proj, p.n, sc.cams[0].width, sc.cams[0].height, B)
+    tiles, gs, _ = O.tile_pairs(proj, p.n, sc.cams[0].width, sc.cams[0].height, B)
     pairs = set(zip(tiles.tolist(), gs.tolist()))
     pix = O.full_pixels(sc.cams[0])
     tr = O.trace(p, view, S, pix)
@@ -472,6 +473,28 @@ def test_p9_tile_lists_cover_every_fragment(oracle):
         t = (j // B) * tx + i // B
         for k in range(tr.offsets[pi], tr.offsets[pi + 1]):
             assert (t, int(tr.frag_g[k])) in pairs
+    # Membership: the ellipse holds a point on one of the tile's pixel columns between its
+    # first and last pixel rows; compare with dense sampling along the columns.
+    pa = O.proj_numpy(proj)
+    amin = float(np.float32(1.0 / 255.0))
+    rng = np.random.default_rng(2)
+    listed = set(zip(tiles.tolist(), gs.tolist()))
+    for g in rng.choice(np.flatnonzero(pa["visible"] == 1), 60, replace=False):
+        pr = pa[g]
+        q = 2.0 * np.log(pr["a"] / amin)
+        Q = pr["Q"]
+        for ty in range(pr["rect"][2] // B, pr["rect"][3] // B + 1):
+            for tx_ in range(pr["rect"][0] // B, pr["rect"][1] // B + 1):
+                xs = np.arange(max(tx_ * B, pr["rect"][0]), min(tx_ * B + B - 1, pr["rect"][1]) + 1) - pr["u"]
+                ys = np.linspace(max(ty * B, pr["rect"][2]), min(ty * B + B - 1, pr["rect"][3]), 161) - pr["v"]
+                X, Y = np.meshgrid(xs, ys)
+                m = (Q[0] * X * X + 2 * Q[1] * X * Y + Q[2] * Y * Y).min()
+                t = ty * tx + tx_
+                if m < q * 0.999:
+                    assert (t, int(g)) in listed
+                elif m > q * 1.01:
+                    # Sampling overestimates the minimum by at most the grid step's effect.
+                    pass
     # Ordered by (tile, depth, index).
     z = O.proj_numpy(proj)["z"][gs]
     key = np.lexsort((gs, z, tiles))
