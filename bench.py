@@ -138,7 +138,7 @@ def main():
     ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4"])
     ap.add_argument("--seed", type=int, default=None)
     ap.add_argument("--tile", type=int, default=16)
-    ap.add_argument("--ppl", type=int, default=2, help="pixels per lane of the raster kernels")
+    ap.add_argument("--ppl", type=int, default=1, help="pixels per lane of the raster kernels")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-graph", action="store_true")

@@ -96,7 +96,8 @@ typedef struct {
     int32_t pointmap_frame;  /* 0 world-frame composited centres, 1 camera frame,
                                 2 depth back-projection D K^-1 [i, j, 1]^T (Eq. 5) [1] */
     int32_t pixels_per_lane; /* pixels each lane of the raster kernels owns; supported
-                                (tile, pixels_per_lane): (8,1) (16,1) (16,2) (16,4) (32,4) [2] */
+                                (tile, pixels_per_lane): (8,1) (16,1) (16,2) (16,4) (32,1)
+                                (32,2) (32,4) [1] */
     float near_z;            /* Gaussians with camera depth <= near_z are dropped [0.2] */
     float alpha_min;         /* fragments with alpha < alpha_min are skipped [1/255] */
     float alpha_max;         /* alpha is clamped to alpha_max [0.99] */

@@ -136,7 +136,7 @@ class RasterConfig:
     tile: int = 16
     sort_digit_bits: int = 8
     pointmap_frame: int = 1
-    pixels_per_lane: int = 2
+    pixels_per_lane: int = 1
     near_z: float = 0.2
     alpha_min: float = 1.0 / 255.0
     alpha_max: float = 0.99
@@ -151,7 +151,7 @@ class RasterConfig:
                         self.alpha_max, self.t_min, self.eps2d, self.jac_clamp, (ctypes.c_float * 3)(*self.bg))
 
     # Supported (tile, pixels_per_lane) launch shapes of the raster kernels.
-    SHAPES = ((8, 1), (16, 1), (16, 2), (16, 4), (32, 4))
+    SHAPES = ((8, 1), (16, 1), (16, 2), (16, 4), (32, 1), (32, 2), (32, 4))
 
     def with_shape(self, tile, ppl):
         import dataclasses

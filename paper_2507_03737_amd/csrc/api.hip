@@ -68,7 +68,7 @@ struct gspm_ctx {
     size_t used = 0;
     std::vector<int> phase_of;  // per recorded pair
     // Per record (n * V).
-    DevBuf counts, big, dkey, dval, dkey_tmp, dval_tmp, dkey_s, dval_s, offsets, grad2d;
+    DevBuf counts, big, live, dkey, dval, dkey_tmp, dval_tmp, dkey_s, dval_s, offsets, grad2d;
     // Per pair (capacity).
     DevBuf pkey, pval, pkey_tmp, pval_tmp, pkey_s;
     // Small scratch.
@@ -199,6 +199,7 @@ hipError_t ensure_records(gspm_ctx *c, int64_t R, int digit_bits) {
     hipError_t e;
     if ((e = grow(c->counts, 4 * w))) return e;
     if ((e = grow(c->big, 4 * w))) return e;
+    if ((e = grow(c->live, 4 * w))) return e;
     if ((e = grow(c->dkey, 4 * w))) return e;
     if ((e = grow(c->dval, 4 * w))) return e;
     if ((e = grow(c->dkey_tmp, 4 * w))) return e;
@@ -282,7 +283,7 @@ gspm_status gspm_create(gspm_ctx **out) {
 
 void gspm_destroy(gspm_ctx *ctx) {
     if (!ctx) return;
-    DevBuf *bufs[] = {&ctx->counts, &ctx->big, &ctx->dkey, &ctx->dval, &ctx->dkey_tmp, &ctx->dval_tmp,
+    DevBuf *bufs[] = {&ctx->counts, &ctx->big, &ctx->live, &ctx->dkey, &ctx->dval, &ctx->dkey_tmp, &ctx->dval_tmp,
                       &ctx->dkey_s, &ctx->dval_s, &ctx->offsets, &ctx->grad2d, &ctx->pkey, &ctx->pval,
                       &ctx->pkey_tmp, &ctx->pval_tmp, &ctx->pkey_s, &ctx->hist, &ctx->scan_part, &ctx->misc,
                       &ctx->pose_part, &ctx->loss_part};
@@ -353,31 +354,39 @@ gspm_status gspm_render_forward(gspm_ctx *ctx, const gspm_gaussians *g, const gs
     // 1. Project every (Gaussian, view) record.
     PhaseTimer t_pre(ctx, hs, GSPM_PHASE_PREPROCESS);
     GSPM_HIP(launch_preprocess(*g, P.vt, views->T_cw, P.rs, records, counts, static_cast<uint32_t *>(ctx->dkey.p),
-                               static_cast<uint32_t *>(ctx->dval.p), hs));
+                               static_cast<uint32_t *>(ctx->dval.p), static_cast<uint32_t *>(ctx->big.p), total + 1,
+                               hs));
     t_pre.stop();
+    // Device-side counts: total[0] tile pairs, total[1] queued large records, total[2] live records.
+    uint32_t *n_live = total + 2;
     if (R > 0) {
-        // 2. Order records by float32 depth (stable: ties keep record order).
+        // 2. Keep the records that have tile pairs (in record order) and sort them by float32
+        //    depth (stable, so ties keep record order).
         PhaseTimer t_ds(ctx, hs, GSPM_PHASE_DEPTH_SORT);
-        GSPM_HIP(radix_sort(static_cast<uint32_t *>(ctx->dkey.p), static_cast<uint32_t *>(ctx->dval.p),
+        GSPM_HIP(launch_scan_indirect(counts, nullptr, R, static_cast<uint32_t *>(ctx->offsets.p), n_live, part, hs,
+                                      nullptr, 1));
+        GSPM_HIP(launch_compact(counts, static_cast<uint32_t *>(ctx->offsets.p), static_cast<uint32_t *>(ctx->dkey.p), R,
+                                static_cast<uint32_t *>(ctx->dval.p), static_cast<uint32_t *>(ctx->live.p), hs));
+        GSPM_HIP(radix_sort(static_cast<uint32_t *>(ctx->dval.p), static_cast<uint32_t *>(ctx->live.p),
                             static_cast<uint32_t *>(ctx->dkey_tmp.p), static_cast<uint32_t *>(ctx->dval_tmp.p),
-                            static_cast<uint32_t *>(ctx->dkey_s.p), static_cast<uint32_t *>(ctx->dval_s.p), R, nullptr,
+                            static_cast<uint32_t *>(ctx->dkey_s.p), static_cast<uint32_t *>(ctx->dval_s.p), R, n_live,
                             32, db, hist, part, hs));
         t_ds.stop();
     }
     PhaseTimer t_bin(ctx, hs, GSPM_PHASE_BINNING);
     if (R > 0) {
-        // 3. Offsets of each record's tile pairs, in depth order.
+        // 3. Offsets of each live record's tile pairs, in depth order.
         GSPM_HIP(launch_scan_indirect(counts, static_cast<uint32_t *>(ctx->dval_s.p), R,
-                                      static_cast<uint32_t *>(ctx->offsets.p), total, part, hs));
+                                      static_cast<uint32_t *>(ctx->offsets.p), total, part, hs, n_live, 0));
     } else {
-        GSPM_HIP(launch_fill_u32(total, 0u, 1, hs));
+        GSPM_HIP(launch_fill_u32(total, 0u, 3, hs));
     }
     // 4. Emit (tile, record) pairs; the header gets the pair count and overflow flag.
     GSPM_HIP(launch_fill_u32(reinterpret_cast<uint32_t *>(ranges), 0u, 2 * P.n_tiles, hs));
     GSPM_HIP(launch_keygen(static_cast<uint32_t *>(ctx->dval_s.p), counts, static_cast<uint32_t *>(ctx->offsets.p),
                            records, P.rs, R, g->n > 0 ? g->n : 1, P.vt, static_cast<uint32_t *>(ctx->pkey.p),
                            static_cast<uint32_t *>(ctx->pval.p), hdr, (uint32_t)cap, total,
-                           static_cast<uint32_t *>(ctx->big.p), total + 1, hs));
+                           static_cast<uint32_t *>(ctx->big.p), total + 1, n_live, hs));
     t_bin.stop();
     // 5. Stable sort by tile id; 6. per-tile ranges.
     if (cap > 0) {

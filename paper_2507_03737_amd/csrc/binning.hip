@@ -19,8 +19,15 @@ constexpr int kScanBlock = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kScanBlock * kScanItems;
 
-__device__ inline uint32_t load_count(const uint32_t *counts, const uint32_t *idx, int64_t p) {
-    return idx ? counts[idx[p]] : counts[p];
+__device__ inline uint32_t load_count(const uint32_t *counts, const uint32_t *idx, int64_t p, int flag) {
+    const uint32_t c = idx ? counts[idx[p]] : counts[p];
+    return flag ? (c != 0u ? 1u : 0u) : c;
+}
+
+__device__ inline int64_t scan_n(const uint32_t *n_dev, int64_t n_max) {
+    if (!n_dev) return n_max;
+    const int64_t n = (int64_t)*n_dev;
+    return n < n_max ? n : n_max;
 }
 
 // Block-wide exclusive scan of one value per thread; returns the prefix, *total the sum.
@@ -41,13 +48,15 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t x, uint32_t *lds, uint3
 }
 
 __global__ void __launch_bounds__(kScanBlock)
-k_scan_reduce(const uint32_t *__restrict__ counts, const uint32_t *__restrict__ idx, int64_t n, int64_t chunk,
-              uint32_t *__restrict__ part) {
+k_scan_reduce(const uint32_t *__restrict__ counts, const uint32_t *__restrict__ idx, const uint32_t *__restrict__ n_dev,
+              int64_t n_max, int flag, uint32_t *__restrict__ part) {
     __shared__ uint32_t lds[kScanBlock / kWave];
+    const int64_t n = scan_n(n_dev, n_max);
+    const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
     const int64_t b0 = (int64_t)blockIdx.x * chunk;
     const int64_t b1 = b0 + chunk < n ? b0 + chunk : n;
     uint32_t acc = 0;
-    for (int64_t p = b0 + threadIdx.x; p < b1; p += kScanBlock) acc += load_count(counts, idx, p);
+    for (int64_t p = b0 + threadIdx.x; p < b1; p += kScanBlock) acc += load_count(counts, idx, p, flag);
     uint32_t tot;
     block_exclusive_scan(acc, lds, tot);
     if (threadIdx.x == 0) part[blockIdx.x] = tot;
@@ -71,9 +80,11 @@ __global__ void __launch_bounds__(1024) k_scan_partials(uint32_t *part, int nb, 
 }
 
 __global__ void __launch_bounds__(kScanBlock)
-k_scan_apply(const uint32_t *__restrict__ counts, const uint32_t *__restrict__ idx, int64_t n, int64_t chunk,
-             const uint32_t *__restrict__ part, uint32_t *__restrict__ out) {
+k_scan_apply(const uint32_t *__restrict__ counts, const uint32_t *__restrict__ idx, const uint32_t *__restrict__ n_dev,
+             int64_t n_max, int flag, const uint32_t *__restrict__ part, uint32_t *__restrict__ out) {
     __shared__ uint32_t lds[kScanBlock / kWave];
+    const int64_t n = scan_n(n_dev, n_max);
+    const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
     const int64_t b0 = (int64_t)blockIdx.x * chunk;
     const int64_t b1 = b0 + chunk < n ? b0 + chunk : n;
     uint32_t running = part[blockIdx.x];
@@ -84,7 +95,7 @@ k_scan_apply(const uint32_t *__restrict__ counts, const uint32_t *__restrict__ i
 #pragma unroll
         for (int k = 0; k < kScanItems; ++k) {
             const int64_t p = p0 + k;
-            v[k] = p < b1 ? load_count(counts, idx, p) : 0u;
+            v[k] = p < b1 ? load_count(counts, idx, p, flag) : 0u;
             sum += v[k];
         }
         uint32_t tot;
@@ -246,8 +257,10 @@ k_keygen(const uint32_t *__restrict__ sorted_rec, const uint32_t *__restrict__ c
          const uint32_t *__restrict__ offsets, const float4 *__restrict__ rec, RasterSettings rs,
          int64_t n_records, int64_t n_per_view, ViewTable vt, uint32_t *__restrict__ pkey,
          uint32_t *__restrict__ pval, FrameHeader *__restrict__ hdr, uint32_t cap,
-         const uint32_t *__restrict__ total, uint32_t *__restrict__ big_list, uint32_t *__restrict__ big_count) {
+         const uint32_t *__restrict__ total, uint32_t *__restrict__ big_list, uint32_t *__restrict__ big_count,
+         const uint32_t *__restrict__ n_dev) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    n_records = scan_n(n_dev, n_records);
     if (p == 0) {
         const uint32_t t = *total;
         hdr->pairs = t;
@@ -255,14 +268,15 @@ k_keygen(const uint32_t *__restrict__ sorted_rec, const uint32_t *__restrict__ c
         hdr->capacity = cap;
         hdr->magic = kFrameMagic;
     }
-    if (p >= n_records) return;
-    const uint32_t r = sorted_rec[p];
-    const uint32_t c = counts[r];
-    if (c == 0) return;
-    if (c > kBigRecord) {
-        big_list[atomicAdd(big_count, 1u)] = (uint32_t)p;
-        return;
+    uint32_t r = 0, c = 0;
+    if (p < n_records) {
+        r = sorted_rec[p];
+        c = counts[r];
     }
+    const bool big = c > kBigRecord;
+    const uint32_t slot = wave_append(big_count, big);
+    if (big) big_list[slot] = (uint32_t)p;
+    if (c == 0 || big) return;
     uint32_t k = offsets[p];
     if (k >= cap) return;
     const int v = (int)(r / n_per_view);
@@ -353,13 +367,32 @@ static int64_t scan_blocks(int64_t n) {
 int64_t scan_partials(int64_t n) { return scan_blocks(n); }
 
 hipError_t launch_scan_indirect(const uint32_t *counts, const uint32_t *idx, int64_t n, uint32_t *offsets,
-                                uint32_t *total, uint32_t *part, hipStream_t s) {
+                                uint32_t *total, uint32_t *part, hipStream_t s, const uint32_t *n_dev, int flag) {
     const int64_t nb = scan_blocks(n);
-    const int64_t chunk = (n + nb - 1) / nb;
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanBlock), 0, s, counts, idx, n, chunk, part);
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanBlock), 0, s, counts, idx, n_dev, n, flag, part);
     hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, part, (int)nb, total);
-    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kScanBlock), 0, s, counts, idx, n, chunk, part,
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kScanBlock), 0, s, counts, idx, n_dev, n, flag, part,
                        offsets);
+    return hipGetLastError();
+}
+
+// Records with at least one tile pair, compacted in record order: ckey/cval get the depth
+// key and record index at position flag_scan[r].
+__global__ void __launch_bounds__(256)
+k_compact(const uint32_t *__restrict__ counts, const uint32_t *__restrict__ flag_scan, const uint32_t *__restrict__ dkey,
+          int64_t n, uint32_t *__restrict__ ckey, uint32_t *__restrict__ cval) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n || counts[r] == 0u) return;
+    const uint32_t pos = flag_scan[r];
+    ckey[pos] = dkey[r];
+    cval[pos] = (uint32_t)r;
+}
+
+hipError_t launch_compact(const uint32_t *counts, const uint32_t *flag_scan, const uint32_t *dkey, int64_t n,
+                          uint32_t *ckey, uint32_t *cval, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_compact, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, counts, flag_scan, dkey, n, ckey,
+                       cval);
     return hipGetLastError();
 }
 
@@ -384,7 +417,7 @@ static void sort_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, 
     hipLaunchKernelGGL(k_radix_upsweep<DB>, dim3((unsigned)nb), dim3(kSortBlock), 0, s, kin, n_dev, n_max, shift,
                        hist, nt);
     const int64_t hw = ((int64_t)1 << DB) * nt;
-    (void)launch_scan_indirect(hist, nullptr, hw, hist, hist + hw, scan_part, s);
+    (void)launch_scan_indirect(hist, nullptr, hw, hist, hist + hw, scan_part, s, nullptr, 0);
     hipLaunchKernelGGL(k_radix_downsweep<DB>, dim3((unsigned)nb), dim3(kSortBlock), 0, s, kin, vin, kout, vout,
                        n_dev, n_max, shift, hist, nt);
 }
@@ -418,13 +451,14 @@ hipError_t radix_sort(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t
 hipError_t launch_keygen(const uint32_t *sorted_rec, const uint32_t *counts, const uint32_t *offsets,
                          const float *records, const RasterSettings &rs, int64_t n_records, int64_t n_per_view,
                          const ViewTable &vt, uint32_t *pkey, uint32_t *pval, FrameHeader *hdr, uint32_t capacity,
-                         const uint32_t *total, uint32_t *big_list, uint32_t *big_count, hipStream_t s) {
+                         const uint32_t *total, uint32_t *big_list, uint32_t *big_count, const uint32_t *n_dev,
+                         hipStream_t s) {
     hipError_t e = launch_fill_u32(big_count, 0u, 1, s);
     if (e != hipSuccess) return e;
     const float4 *rec = reinterpret_cast<const float4 *>(records);
     const int64_t nb = n_records > 0 ? (n_records + 255) / 256 : 1;
     hipLaunchKernelGGL(k_keygen, dim3((unsigned)nb), dim3(256), 0, s, sorted_rec, counts, offsets, rec, rs, n_records,
-                       n_per_view, vt, pkey, pval, hdr, capacity, total, big_list, big_count);
+                       n_per_view, vt, pkey, pval, hdr, capacity, total, big_list, big_count, n_dev);
     if (n_records > 0)
         hipLaunchKernelGGL(k_keygen_big, dim3(1024), dim3(256), 0, s, sorted_rec, offsets, rec, rs, n_per_view, vt,
                            pkey, pval, capacity, big_list, big_count);

@@ -45,6 +45,9 @@ constexpr int kRecFloats = 16;
 constexpr int kG2 = 16;
 constexpr int kG2Used = 13;
 
+// Records with more tile pairs than this are counted and emitted by whole waves.
+constexpr uint32_t kBigRecord = 64;
+
 // Frame-state layout (caller-owned device buffer).
 struct FrameHeader {
     uint32_t pairs;     // tile pairs produced (or needed, on overflow)
@@ -166,6 +169,20 @@ __device__ inline uint32_t wave_inclusive_scan(uint32_t x) {
     return x;
 }
 
+// Appends the lanes with pred set to a global queue with one atomic per wave; returns
+// each such lane's slot.  Must be reached by every active lane of the wave.
+__device__ inline uint32_t wave_append(uint32_t *counter, bool pred) {
+    const uint64_t m = __ballot(pred);
+    if (m == 0ull) return 0u;
+    const int lane = lane_id();
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    uint32_t base = 0u;
+    if (lane == leader) base = atomicAdd(counter, (uint32_t)__popcll(m));
+    base = (uint32_t)__shfl((int)base, leader, kWave);
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    return base + (uint32_t)__popcll(m & lt);
+}
+
 __device__ inline int find_view(const ViewTable &vt, int32_t global_tile) {
     int v = 0;
 #pragma unroll 1
@@ -247,15 +264,25 @@ __device__ inline bool row_span(const Footprint &f, int B, int ty, int &ta, int 
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t n, hipStream_t s);
 hipError_t launch_fill_f32(float *p, float value, int64_t n, hipStream_t s);
 
+// Projects every record and counts its tile pairs; big_list / big_count are scratch for
+// the records counted by whole waves (big_count is zeroed here).
 hipError_t launch_preprocess(const gspm_gaussians &g, const ViewTable &vt, const float *T_cw,
                              const RasterSettings &rs, float *records, uint32_t *counts,
-                             uint32_t *dkey, uint32_t *dval, hipStream_t s);
+                             uint32_t *dkey, uint32_t *dval, uint32_t *big_list, uint32_t *big_count,
+                             hipStream_t s);
 
-// Exclusive scan of counts[idx[p]] for p < n (idx may be NULL for the identity); writes
+// Exclusive scan of counts[idx[p]] (or of counts[idx[p]] != 0 when flag is set) for
+// p < n, idx NULL meaning the identity; n is min(*n_dev, n) when n_dev is given.  Writes
 // offsets[p] and the total to *total.  part: scratch of at least scan_partials(n) words.
 int64_t scan_partials(int64_t n);
 hipError_t launch_scan_indirect(const uint32_t *counts, const uint32_t *idx, int64_t n,
-                                uint32_t *offsets, uint32_t *total, uint32_t *part, hipStream_t s);
+                                uint32_t *offsets, uint32_t *total, uint32_t *part, hipStream_t s,
+                                const uint32_t *n_dev = nullptr, int flag = 0);
+
+// Compacts (depth key, record index) of the records with counts[r] != 0 to the positions
+// given by the flag scan.
+hipError_t launch_compact(const uint32_t *counts, const uint32_t *flag_scan, const uint32_t *dkey, int64_t n,
+                          uint32_t *ckey, uint32_t *cval, hipStream_t s);
 
 // Stable LSD radix sort of (key, value) uint32 pairs over the low `bits` key bits.
 // n_dev: device count (may be NULL: n_max is then exact).  Buffers: keys/vals in,
@@ -270,12 +297,11 @@ hipError_t radix_sort(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t
 // Emits the (global tile, record) pairs of every record in depth order.  Records with
 // more than kBigRecord pairs are queued in big_list (big_count zeroed here) and emitted
 // by whole waves.  records: the projected records (for the support footprint).
-constexpr uint32_t kBigRecord = 64;
 hipError_t launch_keygen(const uint32_t *sorted_rec, const uint32_t *counts, const uint32_t *offsets,
                          const float *records, const RasterSettings &rs, int64_t n_records, int64_t n_per_view,
                          const ViewTable &vt, uint32_t *pkey, uint32_t *pval, FrameHeader *hdr,
                          uint32_t capacity, const uint32_t *total, uint32_t *big_list, uint32_t *big_count,
-                         hipStream_t s);
+                         const uint32_t *n_dev, hipStream_t s);
 
 hipError_t launch_sum_u64(const uint32_t *x, int64_t n, unsigned long long *out, hipStream_t s);
 

@@ -117,48 +117,79 @@ __device__ inline void project_one(const gspm_gaussians &G, int64_t g, int64_t n
 __global__ void __launch_bounds__(256)
 k_preprocess(gspm_gaussians G, ViewTable vt, const float *__restrict__ T_cw, RasterSettings rs,
              float4 *__restrict__ rec, uint32_t *__restrict__ counts, uint32_t *__restrict__ dkey,
-             uint32_t *__restrict__ dval) {
+             uint32_t *__restrict__ big_list, uint32_t *__restrict__ big_count) {
     const int64_t n = G.n;
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n * vt.n_views) return;
-    const int v = (int)(r / n);
-    const int64_t g = r - (int64_t)v * n;
-    Proj P;
-    project_one(G, g, n, T_cw + 12 * v, vt.fx[v], vt.fy[v], vt.cx[v], vt.cy[v], vt.width[v],
-                vt.height[v], rs, P);
-    dval[r] = (uint32_t)r;
-    if (!P.visible) {
-        counts[r] = 0u;
-        dkey[r] = 0u;
-        return;
-    }
-    const float zf = (float)P.z;
-    dkey[r] = __float_as_uint(zf);
-
-    const float uhi = (float)P.u, vhi = (float)P.v;
-    const float ulo = (float)(P.u - (double)uhi), vlo = (float)(P.v - (double)vhi);
-    const float4 r0 = make_float4(uhi, vhi, ulo, vlo);
-    const float4 r1 = make_float4((float)(-0.5 * kLog2e * P.Q[0]), (float)(-kLog2e * P.Q[1]),
-                                  (float)(-0.5 * kLog2e * P.Q[2]), (float)P.a);
-    float4 *o = rec + 4 * r;
-    o[0] = r0;
-    o[1] = r1;
-    o[2] = make_float4(G.rgb[g], G.rgb[n + g], G.rgb[2 * n + g], zf);
-    // Number of tiles the support meets, row by row (the pair emission repeats this).
-    uint32_t count = 0;
-    Footprint f;
-    if (record_footprint(r0, r1, rs.alpha_min, vt.width[v], vt.height[v], f)) {
-        const int T = vt.tile;
-        for (int ty = f.j0 / T; ty <= f.j1 / T; ++ty) {
-            int ta, tb;
-            if (row_span(f, T, ty, ta, tb)) count += (uint32_t)(tb - ta + 1);
+    bool big = false;
+    if (r < n * vt.n_views) {
+        const int v = (int)(r / n);
+        const int64_t g = r - (int64_t)v * n;
+        Proj P;
+        project_one(G, g, n, T_cw + 12 * v, vt.fx[v], vt.fy[v], vt.cx[v], vt.cy[v], vt.width[v],
+                    vt.height[v], rs, P);
+        uint32_t count = 0;
+        if (P.visible) {
+            const float zf = (float)P.z;
+            dkey[r] = __float_as_uint(zf);
+            const float uhi = (float)P.u, vhi = (float)P.v;
+            const float ulo = (float)(P.u - (double)uhi), vlo = (float)(P.v - (double)vhi);
+            const float4 r0 = make_float4(uhi, vhi, ulo, vlo);
+            const float4 r1 = make_float4((float)(-0.5 * kLog2e * P.Q[0]), (float)(-kLog2e * P.Q[1]),
+                                          (float)(-0.5 * kLog2e * P.Q[2]), (float)P.a);
+            float4 *o = rec + 4 * r;
+            o[0] = r0;
+            o[1] = r1;
+            o[2] = make_float4(G.rgb[g], G.rgb[n + g], G.rgb[2 * n + g], zf);
+            if (rs.frame == 0)
+                o[3] = make_float4(G.means[g], G.means[n + g], G.means[2 * n + g], 0.0f);
+            else
+                o[3] = make_float4((float)P.m[0], (float)P.m[1], (float)P.m[2], 0.0f);
+            // Number of tiles the support meets, row by row (the pair emission repeats this).
+            // Records whose support box covers many tiles are counted by whole waves instead.
+            Footprint f;
+            if (record_footprint(r0, r1, rs.alpha_min, vt.width[v], vt.height[v], f)) {
+                const int T = vt.tile;
+                const int rows = f.j1 / T - f.j0 / T + 1, cols = f.i1 / T - f.i0 / T + 1;
+                if ((uint32_t)(rows * cols) > kBigRecord) {
+                    big = true;
+                } else {
+                    for (int ty = f.j0 / T; ty <= f.j1 / T; ++ty) {
+                        int ta, tb;
+                        if (row_span(f, T, ty, ta, tb)) count += (uint32_t)(tb - ta + 1);
+                    }
+                }
+            }
         }
+        counts[r] = count;
     }
-    counts[r] = count;
-    if (rs.frame == 0)
-        o[3] = make_float4(G.means[g], G.means[n + g], G.means[2 * n + g], 0.0f);
-    else
-        o[3] = make_float4((float)P.m[0], (float)P.m[1], (float)P.m[2], 0.0f);
+    const uint32_t slot = wave_append(big_count, big);
+    if (big) big_list[slot] = (uint32_t)r;
+}
+
+// Exact pair count of the queued large records: one wave per record, one lane per tile row.
+__global__ void __launch_bounds__(256)
+k_count_big(const float4 *__restrict__ rec, ViewTable vt, RasterSettings rs, int64_t n_per_view,
+            uint32_t *__restrict__ counts, const uint32_t *__restrict__ big_list,
+            const uint32_t *__restrict__ big_count) {
+    const int lane = lane_id();
+    const uint32_t n_big = *big_count;
+    const uint32_t n_waves = gridDim.x * (blockDim.x / kWave);
+    for (uint32_t w = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; w < n_big; w += n_waves) {
+        const uint32_t r = big_list[w];
+        const int v = (int)(r / n_per_view);
+        Footprint f;
+        uint32_t count = 0;
+        if (record_footprint(rec[4 * (int64_t)r], rec[4 * (int64_t)r + 1], rs.alpha_min, vt.width[v],
+                             vt.height[v], f)) {
+            const int T = vt.tile;
+            for (int ty = f.j0 / T + lane; ty <= f.j1 / T; ty += kWave) {
+                int ta, tb;
+                if (row_span(f, T, ty, ta, tb)) count += (uint32_t)(tb - ta + 1);
+            }
+        }
+        for (int off = 32; off > 0; off >>= 1) count += __shfl_xor(count, off, 64);
+        if (lane == 0) counts[r] = count;
+    }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -424,11 +455,17 @@ hipError_t launch_fill_f32(float *p, float value, int64_t n, hipStream_t s) {
 
 hipError_t launch_preprocess(const gspm_gaussians &g, const ViewTable &vt, const float *T_cw,
                              const RasterSettings &rs, float *records, uint32_t *counts,
-                             uint32_t *dkey, uint32_t *dval, hipStream_t s) {
+                             uint32_t *dkey, uint32_t *dval, uint32_t *big_list, uint32_t *big_count,
+                             hipStream_t s) {
     const int64_t R = g.n * vt.n_views;
     if (R <= 0) return hipSuccess;
+    hipError_t e = launch_fill_u32(big_count, 0u, 1, s);
+    if (e != hipSuccess) return e;
+    (void)dval;
     hipLaunchKernelGGL(k_preprocess, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, s, g, vt, T_cw, rs,
-                       reinterpret_cast<float4 *>(records), counts, dkey, dval);
+                       reinterpret_cast<float4 *>(records), counts, dkey, big_list, big_count);
+    hipLaunchKernelGGL(k_count_big, dim3(1024), dim3(256), 0, s, reinterpret_cast<const float4 *>(records), vt, rs,
+                       g.n, counts, big_list, big_count);
     return hipGetLastError();
 }
 

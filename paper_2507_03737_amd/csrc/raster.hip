@@ -1,14 +1,19 @@
 // Tile rasterizer: front-to-back compositing (Sec. 3.1, Eq. 2; Sec. 3.2.1, Eq. 3-5) and
 // its backward.
 //
-// One workgroup per tile of T x T pixels (T = 8, 16 or 32) with T*T/PPT lanes; each lane
-// owns PPT vertically adjacent pixels of one column (for T = 16, PPT = 4 a single wave
-// covers the tile).  A fragment is rejected on its base-2 exponent against a per-record
-// threshold, so the exponential is only evaluated for pixels that composite it.  The tile's depth-ordered record list is streamed through LDS in batches of
-// one record per lane (a 64-byte record, converted to tile-local coordinates on load);
-// every lane walks the batch for all its pixels, and the workgroup stops as soon as every
-// pixel has reached the transmittance floor.  Several pixels per lane amortise the LDS
-// broadcast reads and the loop control over more fragments.
+// One workgroup per tile of T x T pixels (T = 8, 16 or 32) with T*T/PPT lanes.  Each wave
+// owns a compact rectangle of the tile (8 x 8 pixels for PPT = 1, 8 x 16 for PPT = 2, ...)
+// and each lane PPT vertically adjacent pixels of one of its columns.  The tile's
+// depth-ordered record list is streamed through LDS in batches of one record per lane (a
+// 64-byte record, converted to tile-local coordinates on load).  When a tile holds several
+// waves, each wave first tests the whole batch against its own rectangle (one record per
+// lane: the maximum of the concave base-2 exponent over the rectangle, against the
+// record's threshold, with a rounding margin so that no record a pixel would accept is
+// dropped) and then walks only the records that meet it, taken from the ballot mask with
+// scalar bit scans.  Binning stays at tile granularity while the per-pixel work is that of
+// 8-pixel-wide tiles.  A fragment is rejected on its base-2 exponent against a per-record
+// threshold, so the exponential is only evaluated for pixels that composite it; the
+// workgroup stops as soon as every pixel has reached the transmittance floor.
 //
 // The backward walks the same list front to back and recomputes alpha and transmittance
 // with the same instructions as the forward, so no per-fragment state is stored: only the
@@ -74,18 +79,76 @@ __device__ inline float quad_e(float Adx2, float Bdx, float C, float dy) {
     return fmaf(fmaf(C, dy, Bdx), dy, Adx2);
 }
 
+// Lane layout of a (TILE, PPT) workgroup: wave w owns a WW x WH pixel rectangle.
+template <int TILE, int PPT>
+struct Layout {
+    static constexpr int NT = TILE * TILE / PPT;  // lanes per workgroup = records per batch
+    static constexpr int NW = NT / kWave;         // waves per workgroup
+    static constexpr int WH = TILE < 8 * PPT ? TILE : 8 * PPT;
+    static constexpr int WW = kWave * PPT / WH;
+    static constexpr bool CULL = NW > 1;  // a single wave owns the whole tile: binning culled already
+    static_assert(WW * WH == kWave * PPT && TILE % WW == 0 && TILE % WH == 0, "unsupported raster shape");
+    int lx, ly;                  // tile-local column and first row of this lane
+    float rx0, rx1, ry0, ry1;    // this wave's rectangle of pixel centres, tile-local
+    __device__ Layout() {
+        const int w = threadIdx.x / kWave, lane = lane_id();
+        const int wx = (w % (TILE / WW)) * WW, wy = (w / (TILE / WW)) * WH;
+        lx = wx + lane % WW;
+        ly = wy + (lane / WW) * PPT;
+        rx0 = (float)wx;
+        rx1 = (float)(wx + WW - 1);
+        ry0 = (float)wy;
+        ry1 = (float)(wy + WH - 1);
+    }
+};
+
+// Largest value of P d^2 + Q d t + R t^2 (R < 0) over t in [lo, hi], for fixed d.
+__device__ inline float edge_max(float P, float Q, float R, float d, float lo, float hi) {
+    const float t = fminf(hi, fmaxf(lo, -0.5f * Q * d * __builtin_amdgcn_rcpf(R)));
+    return fmaf(fmaf(R, t, Q * d), t, P * d * d);
+}
+
+// Whether a staged record (s0 = (u, v, A, B), s1 = (C, e_min, ...)) can reach its threshold
+// at a pixel centre of the rectangle [x0, x1] x [y0, y1].  The exponent is concave, so its
+// maximum over the rectangle is 0 when the mean lies inside and otherwise lies on an edge,
+// where it is a one-dimensional concave quadratic.  The margin exceeds the float rounding
+// of this evaluation plus that of the per-pixel evaluation (a few units in the last place
+// of the sum of the terms' magnitudes), so the test never drops a record that a pixel
+// accepts; it may keep a few that none does.
+__device__ inline bool meets_rect(const float4 a, const float4 b, float x0, float x1, float y0, float y1) {
+    const float A = a.z, B = a.w, C = b.x;
+    const float ax = x0 - a.x, bx = x1 - a.x, ay = y0 - a.y, by = y1 - a.y;
+    if (ax <= 0.f && bx >= 0.f && ay <= 0.f && by >= 0.f) return b.y <= 0x1p-10f;
+    float m = fmaxf(edge_max(A, B, C, ax, ay, by), edge_max(A, B, C, bx, ay, by));
+    m = fmaxf(m, fmaxf(edge_max(C, B, A, ay, ax, bx), edge_max(C, B, A, by, ax, bx)));
+    const float DX = fmaxf(fabsf(ax), fabsf(bx)), DY = fmaxf(fabsf(ay), fabsf(by));
+    const float S = fmaf(fabsf(A) * DX, DX, fmaf(fabsf(B) * DX, DY, fabsf(C) * DY * DY));
+    return m >= b.y - fmaf(0x1p-16f, S, 0x1p-10f);
+}
+
+// Ballot mask of the batch entries [c, c + 64) that this wave must walk.
+template <bool CULL>
+__device__ inline uint64_t batch_mask(const float4 *s0, const float4 *s1, int c, int cnt, float x0, float x1,
+                                      float y0, float y1) {
+    const int n = cnt - c;
+    if (!CULL) return n >= kWave ? ~0ull : ((1ull << n) - 1ull);
+    const int q = c + lane_id();
+    return __ballot(q < cnt && meets_rect(s0[q], s1[q], x0, x1, y0, y1));
+}
+
 template <int TILE, int PPT>
 __global__ void __launch_bounds__(TILE *TILE / PPT)
 k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
              const float4 *__restrict__ rec, float *__restrict__ out_rgb, float *__restrict__ out_depth,
              float *__restrict__ out_alpha, float *__restrict__ out_pm, float *__restrict__ t_final,
              uint32_t *__restrict__ last, uint32_t *__restrict__ contrib) {
-    constexpr int NT = TILE * TILE / PPT;
+    using L = Layout<TILE, PPT>;
+    constexpr int NT = L::NT;
     __shared__ float4 s0[NT], s1[NT], s2[NT], s3[NT];
     const TilePos tp = tile_pos<TILE>(vt);
     const uint2 rg = ranges[blockIdx.x];
-    // Lane (lx, ly) owns pixels (lx, ly * PPT + k): a wave covers a compact band of rows.
-    const int lx = threadIdx.x % TILE, ly = (threadIdx.x / TILE) * PPT;
+    const L lay;
+    const int lx = lay.lx, ly = lay.ly;
     const float px = (float)lx;
     const float amin = rs.alpha_min, amax = rs.alpha_max, tmin = rs.t_min;
     const int i = tp.tx * TILE + lx;
@@ -104,51 +167,56 @@ k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
         done[k] = !(i < tp.W && j < tp.H);
         live += done[k] ? 0 : 1;
     }
+    bool wave_live = __ballot(live > 0) != 0ull;
     for (uint32_t base = rg.x; base < rg.y; base += NT) {
         const uint32_t kk = base + threadIdx.x;
         if (kk < rg.y) stage(rec, vals[kk], tp.x0, tp.y0, amin, s0, s1, s2, s3, threadIdx.x);
         __syncthreads();
         const int cnt = (int)min((uint32_t)NT, rg.y - base);
-        bool wave_live = __ballot(live > 0) != 0ull;
-        for (int q = 0; q < cnt && wave_live; ++q) {
-            const float4 a = s0[q];
-            const float4 b = s1[q];
-            const float dx = px - a.x;
-            const float Adx2 = a.z * dx * dx, Bdx = a.w * dx;
-            float e[PPT];
-            bool ok[PPT];
-            bool pass = false;
+        for (int c = 0; c < cnt && wave_live; c += kWave) {
+            uint64_t m = batch_mask<L::CULL>(s0, s1, c, cnt, lay.rx0, lay.rx1, lay.ry0, lay.ry1);
+            while (m != 0ull && wave_live) {
+                const int q = c + (int)__builtin_ctzll(m);
+                m &= m - 1ull;
+                const float4 a = s0[q];
+                const float4 b = s1[q];
+                const float dx = px - a.x;
+                const float Adx2 = a.z * dx * dx, Bdx = a.w * dx;
+                float e[PPT];
+                bool ok[PPT];
+                bool pass = false;
 #pragma unroll
-            for (int k = 0; k < PPT; ++k) {
-                e[k] = quad_e(Adx2, Bdx, b.x, py[k] - a.y);
-                ok[k] = !done[k] && e[k] >= b.y;
-                pass |= ok[k];
-            }
-            if (__ballot(pass) == 0ull) continue;  // wave-uniform: nothing composites this entry
-            const float4 c = s2[q];
-            const float4 d = s3[q];
-            const uint32_t rel = base - rg.x + (uint32_t)q + 1u;
+                for (int k = 0; k < PPT; ++k) {
+                    e[k] = quad_e(Adx2, Bdx, b.x, py[k] - a.y);
+                    ok[k] = !done[k] && e[k] >= b.y;
+                    pass |= ok[k];
+                }
+                if (__ballot(pass) == 0ull) continue;  // wave-uniform: nothing composites this entry
+                const float4 cc = s2[q];
+                const float4 d = s3[q];
+                const uint32_t rel = base - rg.x + (uint32_t)q + 1u;
 #pragma unroll
-            for (int k = 0; k < PPT; ++k) {
-                const float al = fminf(amax, b.z * __builtin_amdgcn_exp2f(e[k]));
-                const float Tn = __fmul_rn(T[k], __fsub_rn(1.0f, al));
-                const bool stop = ok[k] && Tn < tmin;
-                const bool add = ok[k] && !stop;
-                const float w = add ? __fmul_rn(al, T[k]) : 0.0f;
-                C0[k] = fmaf(w, c.x, C0[k]);
-                C1[k] = fmaf(w, c.y, C1[k]);
-                C2[k] = fmaf(w, c.z, C2[k]);
-                D[k] = fmaf(w, c.w, D[k]);
-                X0[k] = fmaf(w, d.x, X0[k]);
-                X1[k] = fmaf(w, d.y, X1[k]);
-                X2[k] = fmaf(w, d.z, X2[k]);
-                T[k] = add ? Tn : T[k];
-                n_last[k] = add ? rel : n_last[k];
-                n_contrib[k] += add ? 1u : 0u;
-                done[k] = done[k] || stop;
-                live -= stop ? 1 : 0;
+                for (int k = 0; k < PPT; ++k) {
+                    const float al = fminf(amax, b.z * __builtin_amdgcn_exp2f(e[k]));
+                    const float Tn = __fmul_rn(T[k], __fsub_rn(1.0f, al));
+                    const bool stop = ok[k] && Tn < tmin;
+                    const bool add = ok[k] && !stop;
+                    const float w = add ? __fmul_rn(al, T[k]) : 0.0f;
+                    C0[k] = fmaf(w, cc.x, C0[k]);
+                    C1[k] = fmaf(w, cc.y, C1[k]);
+                    C2[k] = fmaf(w, cc.z, C2[k]);
+                    D[k] = fmaf(w, cc.w, D[k]);
+                    X0[k] = fmaf(w, d.x, X0[k]);
+                    X1[k] = fmaf(w, d.y, X1[k]);
+                    X2[k] = fmaf(w, d.z, X2[k]);
+                    T[k] = add ? Tn : T[k];
+                    n_last[k] = add ? rel : n_last[k];
+                    n_contrib[k] += add ? 1u : 0u;
+                    done[k] = done[k] || stop;
+                    live -= stop ? 1 : 0;
+                }
+                wave_live = __ballot(live > 0) != 0ull;
             }
-            wave_live = __ballot(live > 0) != 0ull;
         }
         if (!__syncthreads_or(live > 0 ? 1 : 0)) break;
     }
@@ -187,17 +255,18 @@ __global__ void __launch_bounds__(TILE *TILE / PPT)
 k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
              const float4 *__restrict__ rec, const uint32_t *__restrict__ last, const float *__restrict__ t_final,
              gspm_const_images fwd, gspm_const_images up, float *__restrict__ grad2d) {
-    constexpr int NT = TILE * TILE / PPT;
+    using L = Layout<TILE, PPT>;
+    constexpr int NT = L::NT;
     __shared__ float4 s0[NT], s1[NT], s2[NT], s3[NT];
     __shared__ uint32_t block_last;
     const TilePos tp = tile_pos<TILE>(vt);
     const uint2 rg = ranges[blockIdx.x];
-    const int lx = threadIdx.x % TILE, ly = (threadIdx.x / TILE) * PPT;
+    const L lay;
+    const int lx = lay.lx, ly = lay.ly;
     const float px = (float)lx;
     const float amin = rs.alpha_min, amax = rs.alpha_max;
     const int lane = lane_id();
     const int i = tp.tx * TILE + lx;
-
     // Per-pixel upstream gradient and G = sum_k w_k (g . e_k) + T_final (g_C . bg), the
     // total that the forward's outputs give.
     uint32_t my_last[PPT];
@@ -247,6 +316,7 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
     __syncthreads();
     uint32_t wave_last = thread_last;
     for (int off = 32; off > 0; off >>= 1) wave_last = max(wave_last, (uint32_t)__shfl_xor((int)wave_last, off, 64));
+    wave_last = (uint32_t)__builtin_amdgcn_readfirstlane((int)wave_last);  // uniform: keep it scalar
     if (lane == 0) atomicMax(&block_last, wave_last);
     __syncthreads();
     const uint32_t end = rg.x + block_last;
@@ -257,68 +327,73 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
         __syncthreads();
         const int cnt = (int)min((uint32_t)NT, end - base);
         const uint32_t rel0 = base - rg.x;
-        for (int q = 0; q < cnt; ++q) {
-            const uint32_t rel = rel0 + (uint32_t)q;
-            if (rel >= wave_last) break;  // wave-uniform
-            const float4 a = s0[q];
-            const float4 b = s1[q];
-            const float dx = px - a.x;
-            const float Adx = a.z * dx, Bdx = a.w * dx;
-            const float Adx2 = Adx * dx;
-            float e[PPT];
-            bool valid[PPT];
-            bool any = false;
+        for (int c = 0; c < cnt && rel0 + (uint32_t)c < wave_last; c += kWave) {
+            uint64_t m = batch_mask<L::CULL>(s0, s1, c, cnt, lay.rx0, lay.rx1, lay.ry0, lay.ry1);
+            while (m != 0ull) {
+                const int q = c + (int)__builtin_ctzll(m);
+                m &= m - 1ull;
+                const uint32_t rel = rel0 + (uint32_t)q;
+                if (rel >= wave_last) break;  // wave-uniform
+                const float4 a = s0[q];
+                const float4 b = s1[q];
+                const float dx = px - a.x;
+                const float Adx = a.z * dx, Bdx = a.w * dx;
+                const float Adx2 = Adx * dx;
+                float e[PPT];
+                bool valid[PPT];
+                bool any = false;
 #pragma unroll
-            for (int k = 0; k < PPT; ++k) {
-                e[k] = quad_e(Adx2, Bdx, b.x, py[k] - a.y);
-                valid[k] = rel < my_last[k] && e[k] >= b.y;
-                any |= valid[k];
-            }
-            if (__ballot(any) == 0ull) continue;  // wave-uniform
-            const float4 c = s2[q];
-            const float4 d = s3[q];
-            const float dx2 = dx * dx, twoAdx = 2.0f * Adx, twoC = 2.0f * b.x;
-            float v[16];
-#pragma unroll
-            for (int t = 0; t < 16; ++t) v[t] = 0.f;
-#pragma unroll
-            for (int k = 0; k < PPT; ++k) {
-                // Branch-free: an invalid pixel gets zero weight and leaves T unchanged
-                // (e <= 0, so alpha lies in [0, alpha_max] and 1 - alpha >= 1 - alpha_max).
-                const float dy = py[k] - a.y;
-                const float g2 = __builtin_amdgcn_exp2f(e[k]);
-                const float al = fminf(amax, b.z * g2);
-                const float w = valid[k] ? __fmul_rn(al, T[k]) : 0.0f;
-                const float s = gC0[k] * c.x + gC1[k] * c.y + gC2[k] * c.z + gD[k] * c.w + gA[k] +
-                                gX0[k] * d.x + gX1[k] * d.y + gX2[k] * d.z;
-                Pfx[k] = fmaf(w, s, Pfx[k]);
-                const float one_m = __fsub_rn(1.0f, al);
-                const float dLda = T[k] * s - (Gb[k] - Pfx[k]) * __builtin_amdgcn_rcpf(one_m);
-                const bool unclamped = valid[k] && al < amax;
-                const float Gl = unclamped ? dLda * al * kLn2 : 0.0f;
-                const float Gldy = Gl * dy;
-                v[0] = fmaf(-Gl, fmaf(a.w, dy, twoAdx), v[0]);
-                v[1] = fmaf(-Gl, fmaf(twoC, dy, Bdx), v[1]);
-                v[2] = fmaf(Gl, dx2, v[2]);
-                v[3] = fmaf(Gldy, dx, v[3]);
-                v[4] = fmaf(Gldy, dy, v[4]);
-                if (!POSE_ONLY) v[5] = fmaf(unclamped ? dLda : 0.0f, g2, v[5]);
-                v[6] = fmaf(w, gD[k], v[6]);
-                if (!POSE_ONLY) {
-                    v[7] = fmaf(w, gC0[k], v[7]);
-                    v[8] = fmaf(w, gC1[k], v[8]);
-                    v[9] = fmaf(w, gC2[k], v[9]);
+                for (int k = 0; k < PPT; ++k) {
+                    e[k] = quad_e(Adx2, Bdx, b.x, py[k] - a.y);
+                    valid[k] = rel < my_last[k] && e[k] >= b.y;
+                    any |= valid[k];
                 }
-                v[10] = fmaf(w, gX0[k], v[10]);
-                v[11] = fmaf(w, gX1[k], v[11]);
-                v[12] = fmaf(w, gX2[k], v[12]);
-                T[k] = valid[k] ? __fmul_rn(T[k], one_m) : T[k];
-            }
-            const float tot = wave_reduce_scatter16(v);
-            const int idx = (lane >> 2) & 15;
-            if ((lane & 3) == 0 && idx < kG2Used && tot != 0.f) {
-                const uint32_t r = __float_as_uint(b.w);
-                unsafeAtomicAdd(grad2d + (int64_t)r * kG2 + idx, tot);
+                if (__ballot(any) == 0ull) continue;  // wave-uniform
+                const float4 cc = s2[q];
+                const float4 d = s3[q];
+                const float dx2 = dx * dx, twoAdx = 2.0f * Adx, twoC = 2.0f * b.x;
+                float v[16];
+#pragma unroll
+                for (int t = 0; t < 16; ++t) v[t] = 0.f;
+#pragma unroll
+                for (int k = 0; k < PPT; ++k) {
+                    // Branch-free: an invalid pixel gets zero weight and leaves T unchanged
+                    // (e <= 0, so alpha lies in [0, alpha_max] and 1 - alpha >= 1 - alpha_max).
+                    const float dy = py[k] - a.y;
+                    const float g2 = __builtin_amdgcn_exp2f(e[k]);
+                    const float al = fminf(amax, b.z * g2);
+                    const float w = valid[k] ? __fmul_rn(al, T[k]) : 0.0f;
+                    const float sv = gC0[k] * cc.x + gC1[k] * cc.y + gC2[k] * cc.z + gD[k] * cc.w + gA[k] +
+                                     gX0[k] * d.x + gX1[k] * d.y + gX2[k] * d.z;
+                    Pfx[k] = fmaf(w, sv, Pfx[k]);
+                    const float one_m = __fsub_rn(1.0f, al);
+                    const float dLda = T[k] * sv - (Gb[k] - Pfx[k]) * __builtin_amdgcn_rcpf(one_m);
+                    const bool unclamped = valid[k] && al < amax;
+                    const float Gl = unclamped ? dLda * al * kLn2 : 0.0f;
+                    const float Gldy = Gl * dy;
+                    v[0] = fmaf(-Gl, fmaf(a.w, dy, twoAdx), v[0]);
+                    v[1] = fmaf(-Gl, fmaf(twoC, dy, Bdx), v[1]);
+                    v[2] = fmaf(Gl, dx2, v[2]);
+                    v[3] = fmaf(Gldy, dx, v[3]);
+                    v[4] = fmaf(Gldy, dy, v[4]);
+                    if (!POSE_ONLY) v[5] = fmaf(unclamped ? dLda : 0.0f, g2, v[5]);
+                    v[6] = fmaf(w, gD[k], v[6]);
+                    if (!POSE_ONLY) {
+                        v[7] = fmaf(w, gC0[k], v[7]);
+                        v[8] = fmaf(w, gC1[k], v[8]);
+                        v[9] = fmaf(w, gC2[k], v[9]);
+                    }
+                    v[10] = fmaf(w, gX0[k], v[10]);
+                    v[11] = fmaf(w, gX1[k], v[11]);
+                    v[12] = fmaf(w, gX2[k], v[12]);
+                    T[k] = valid[k] ? __fmul_rn(T[k], one_m) : T[k];
+                }
+                const float tot = wave_reduce_scatter16(v);
+                const int idx = (lane >> 2) & 15;
+                if ((lane & 3) == 0 && idx < kG2Used && tot != 0.f) {
+                    const uint32_t r = __float_as_uint(b.w);
+                    unsafeAtomicAdd(grad2d + (int64_t)r * kG2 + idx, tot);
+                }
             }
         }
         __syncthreads();
@@ -328,7 +403,7 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
 }  // namespace
 
 // Launch configurations: (tile, pixels per lane).
-#define GSPM_RASTER_CONFIGS(X) X(8, 1) X(16, 1) X(16, 2) X(16, 4) X(32, 4)
+#define GSPM_RASTER_CONFIGS(X) X(8, 1) X(16, 1) X(16, 2) X(16, 4) X(32, 1) X(32, 2) X(32, 4)
 
 bool raster_config_supported(int tile, int ppt) {
 #define GSPM_CHECK(T_, P_) \
