@@ -40,6 +40,11 @@ FWD_FLOPS_PER_FRAG = 29
 BWD_FLOPS_PER_FRAG = 64
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0
+# Measured HBM traffic of the dominant kernel (rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by
+# the same counters on a copy of known size) and the hash of the sources it was taken on.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "raster_bwd_c3_traffic.txt")
+KERNEL_SOURCES = ("paper_2507_03737_amd/csrc/raster.hip", "paper_2507_03737_amd/csrc/gspm_common.h")
+COPY_BYTES = 1 << 29  # 512 MiB read + 512 MiB written by the calibration copy
 
 
 def log(msg):
@@ -77,6 +82,42 @@ def build_inputs(name, seed, torch, dev):
         prior[seg] = (pm * s[None] + 0.02 * torch.randn(3, h, w, device=dev, generator=g)).reshape(-1)
     del r_gt
     return sc, win, cfg, opt, target, prior
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def stored_traffic(kernel, workload, tile, ppl):
+    """HBM bytes per launch from the committed counter summary, if it was taken on the
+    current kernel sources and the same launch shape; else None."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.loads([ln for ln in fh.read().splitlines() if ln.startswith("{")][-1])
+    except (OSError, ValueError, IndexError):
+        return None
+    if (rec.get("kernel"), rec.get("workload"), rec.get("tile"), rec.get("ppl")) != (kernel, workload, tile, ppl):
+        return None
+    if rec.get("source_sha256") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def copy_calibration(torch, dev):
+    """A plain copy of known size, for scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    n = COPY_BYTES // 4
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    log(f"[bench] calibration copy: 3 launches, {COPY_BYTES} bytes read and {COPY_BYTES} written each")
+    del src, dst
 
 
 def time_steps(fn, steps, warmup, torch):
@@ -137,12 +178,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4"])
     ap.add_argument("--seed", type=int, default=None)
-    ap.add_argument("--tile", type=int, default=16)
-    ap.add_argument("--ppl", type=int, default=1, help="pixels per lane of the raster kernels")
+    ap.add_argument("--tile", type=int, default=None, help="raster tile edge (default: autotuned)")
+    ap.add_argument("--ppl", type=int, default=None, help="pixels per lane of the raster kernels (default: autotuned)")
+    ap.add_argument("--digit-bits", type=int, default=None, help="radix digit width (default: autotuned)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--cpu-px", type=int, default=2048, help="pixels in the CPU-baseline sample")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a copy of known size (for scaling HBM traffic counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -157,11 +201,20 @@ def main():
 
     dev = torch.device("cuda:0")
     B.load()
+    if args.calibrate_copy:
+        copy_calibration(torch, dev)
     seed = args.seed if args.seed is not None else ["c0", "c1", "c2", "c3", "c4"].index(args.workload)
     log(f"[bench] building {args.workload} inputs")
     sc, win, cfg, opt, target, prior = build_inputs(args.workload, seed, torch, dev)
-    cfg.tile = args.tile
-    cfg.pixels_per_lane = args.ppl
+    tuned = None
+    if args.tile is None and args.ppl is None and args.digit_bits is None:
+        from paper_2507_03737_amd.autotune import autotune
+        cfg, tuned = autotune(win, sc.n, opt, target, prior, base=cfg, log=log)
+        log(f"[bench] autotuned: tile={cfg.tile} ppl={cfg.pixels_per_lane} digit_bits={cfg.sort_digit_bits}")
+    else:
+        cfg.tile = args.tile if args.tile is not None else 16
+        cfg.pixels_per_lane = args.ppl if args.ppl is not None else 1
+        cfg.sort_digit_bits = args.digit_bits if args.digit_bits is not None else 8
 
     # ---- batched window -------------------------------------------------------------------
     rast = Rasterizer(win, sc.n, cfg)
@@ -228,7 +281,8 @@ def main():
         flops = frags * (FWD_FLOPS_PER_FRAG if dominant == "raster_fwd" else BWD_FLOPS_PER_FRAG)
         achieved = flops / (ph_ms[dominant] * 1e-3) / 1e12
         roof = {"kernel": dominant, "bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
+                "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
+                "traffic": stored_traffic(dominant, args.workload, cfg.tile, cfg.pixels_per_lane),
                 "algorithmic": f"{frags} contributing fragments x "
                                f"{FWD_FLOPS_PER_FRAG if dominant == 'raster_fwd' else BWD_FLOPS_PER_FRAG} flop"}
     else:
@@ -268,13 +322,16 @@ def main():
                                "2x640x480), render + patch-scale L1 loss + backward to all params and poses",
                          "c4": "c4 16 keyframes 1920x1080, 3M Gaussians"}[args.workload],
             "n_gaussians": sc.n, "views": [[c.width, c.height] for c in sc.cams], "tile": cfg.tile,
-            "pixels_per_lane": cfg.pixels_per_lane,
+            "pixels_per_lane": cfg.pixels_per_lane, "sort_digit_bits": cfg.sort_digit_bits,
+            "autotuned": tuned is not None,
             "patch": 8, "loss_alpha": 0.98, "pointmap_frame": "camera",
         },
         "fwd_bwd_ms_per_iter": {"batched_eager": ms_batched, "batched_graph": ms_graph, "per_view_eager": ms_per_view},
         "batched_speedup_vs_per_view": (ms_per_view / ms_batched) if ms_per_view else None,
         "work": {"tile_pairs": pairs, "contributing_fragments": frags, "evaluated_bound": evals_bound},
         "phase_ms": {k: round(v, 4) for k, v in ph_ms.items()},
+        "autotune_ms": ({f"{r['tile']}x{r['tile']}/ppl{r['pixels_per_lane']}/bits{r['sort_digit_bits']}": round(r["ms"], 3)
+                         for r in tuned} if tuned else None),
         "roofline": roof,
         "cpu_baseline": cpu,
         "wall_s_timed": wall,

@@ -32,6 +32,7 @@ namespace {
 constexpr float kLn2 = 0.69314718055994530942f;
 
 struct TilePos {
+    int gt;  // global tile index
     int v, W, H;
     int tx, ty;
     float x0, y0;     // tile origin
@@ -42,7 +43,8 @@ struct TilePos {
 template <int TILE>
 __device__ inline TilePos tile_pos(const ViewTable &vt) {
     TilePos p;
-    const int gt = blockIdx.x;
+    const int gt = (int)blockIdx.x;
+    p.gt = gt;
     p.v = find_view(vt, gt);
     const int lt = gt - vt.tile_off[p.v];
     p.tx = lt % vt.tiles_x[p.v];
@@ -146,7 +148,7 @@ k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
     constexpr int NT = L::NT;
     __shared__ float4 s0[NT], s1[NT], s2[NT], s3[NT];
     const TilePos tp = tile_pos<TILE>(vt);
-    const uint2 rg = ranges[blockIdx.x];
+    const uint2 rg = ranges[tp.gt];
     const L lay;
     const int lx = lay.lx, ly = lay.ly;
     const float px = (float)lx;
@@ -260,7 +262,7 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
     __shared__ float4 s0[NT], s1[NT], s2[NT], s3[NT];
     __shared__ uint32_t block_last;
     const TilePos tp = tile_pos<TILE>(vt);
-    const uint2 rg = ranges[blockIdx.x];
+    const uint2 rg = ranges[tp.gt];
     const L lay;
     const int lx = lay.lx, ly = lay.ly;
     const float px = (float)lx;

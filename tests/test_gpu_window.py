@@ -168,6 +168,34 @@ def test_graph_replay_matches_eager(lib):
     assert not torch.equal(step.out["rgb"], out["rgb"])
 
 
+def test_autotune_picks_fastest_and_caches(lib, tmp_path):
+    """The autotuner times each candidate on the caller's window, returns the fastest,
+    and a second call with the same cache file returns the stored choice untimed."""
+    U.log("[gpu] autotune")
+    from paper_2507_03737_amd.autotune import autotune
+    from paper_2507_03737_amd.render import Rasterizer, Window
+    sc = _window_scene(seed=15)
+    params, T = U.to_dev(sc, torch)
+    win = Window(sc.cams, T)
+    base = lib.RasterConfig(pointmap_frame=1)
+    out, _ = Rasterizer(win, sc.n, base).forward(params)
+    target = (out["rgb"] + 0.05 * torch.randn_like(out["rgb"])).contiguous()
+    prior = (out["pointmap"] * 1.1).contiguous()
+    cands = [(8, 1, 8), (16, 1, 6), (16, 2, 8), (32, 2, 8)]
+    cache = str(tmp_path / "tune.json")
+    cfg, res = autotune(win, sc.n, params, target, prior, base=base, candidates=cands, steps=2, warmup=1,
+                        cache_path=cache)
+    assert len(res) == len(cands)
+    best = min(res, key=lambda r: r["ms"])
+    assert (cfg.tile, cfg.pixels_per_lane, cfg.sort_digit_bits) == (best["tile"], best["pixels_per_lane"],
+                                                                     best["sort_digit_bits"])
+    assert cfg.pointmap_frame == 1 and cfg.alpha_min == base.alpha_min
+    cfg2, res2 = autotune(win, sc.n, params, target, prior, base=base, candidates=[(8, 1, 4)], cache_path=cache)
+    assert (cfg2.tile, cfg2.pixels_per_lane, cfg2.sort_digit_bits) == (cfg.tile, cfg.pixels_per_lane,
+                                                                       cfg.sort_digit_bits)
+    assert res2 == res
+
+
 def test_autograd_function(lib):
     U.log("[gpu] autograd function")
     from paper_2507_03737_amd.render import Rasterizer, Window, rasterize
