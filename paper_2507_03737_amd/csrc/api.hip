@@ -376,14 +376,18 @@ gspm_status gspm_render_forward(gspm_ctx *ctx, const gspm_gaussians *g, const gs
     PhaseTimer t_bin(ctx, hs, GSPM_PHASE_BINNING);
     if (R > 0) {
         // 3. Offsets of each live record's tile pairs, in depth order.
+        // The sorted depth keys are no longer needed: their buffer receives the pair counts
+        // in depth order, gathered once by the scan.
         GSPM_HIP(launch_scan_indirect(counts, static_cast<uint32_t *>(ctx->dval_s.p), R,
-                                      static_cast<uint32_t *>(ctx->offsets.p), total, part, hs, n_live, 0));
+                                      static_cast<uint32_t *>(ctx->offsets.p), total, part, hs, n_live, 0,
+                                      static_cast<uint32_t *>(ctx->dkey_s.p)));
     } else {
         GSPM_HIP(launch_fill_u32(total, 0u, 3, hs));
     }
     // 4. Emit (tile, record) pairs; the header gets the pair count and overflow flag.
     GSPM_HIP(launch_fill_u32(reinterpret_cast<uint32_t *>(ranges), 0u, 2 * P.n_tiles, hs));
-    GSPM_HIP(launch_keygen(static_cast<uint32_t *>(ctx->dval_s.p), counts, static_cast<uint32_t *>(ctx->offsets.p),
+    GSPM_HIP(launch_keygen(static_cast<uint32_t *>(ctx->dval_s.p), static_cast<uint32_t *>(ctx->dkey_s.p),
+                           static_cast<uint32_t *>(ctx->offsets.p),
                            records, P.rs, R, g->n > 0 ? g->n : 1, P.vt, static_cast<uint32_t *>(ctx->pkey.p),
                            static_cast<uint32_t *>(ctx->pval.p), hdr, (uint32_t)cap, total,
                            static_cast<uint32_t *>(ctx->big.p), total + 1, n_live, hs));

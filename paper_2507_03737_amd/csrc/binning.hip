@@ -49,14 +49,18 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t x, uint32_t *lds, uint3
 
 __global__ void __launch_bounds__(kScanBlock)
 k_scan_reduce(const uint32_t *__restrict__ counts, const uint32_t *__restrict__ idx, const uint32_t *__restrict__ n_dev,
-              int64_t n_max, int flag, uint32_t *__restrict__ part) {
+              int64_t n_max, int flag, uint32_t *__restrict__ part, uint32_t *__restrict__ gathered) {
     __shared__ uint32_t lds[kScanBlock / kWave];
     const int64_t n = scan_n(n_dev, n_max);
     const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
     const int64_t b0 = (int64_t)blockIdx.x * chunk;
     const int64_t b1 = b0 + chunk < n ? b0 + chunk : n;
     uint32_t acc = 0;
-    for (int64_t p = b0 + threadIdx.x; p < b1; p += kScanBlock) acc += load_count(counts, idx, p, flag);
+    for (int64_t p = b0 + threadIdx.x; p < b1; p += kScanBlock) {
+        const uint32_t c = load_count(counts, idx, p, flag);
+        if (gathered) gathered[p] = c;
+        acc += c;
+    }
     uint32_t tot;
     block_exclusive_scan(acc, lds, tot);
     if (threadIdx.x == 0) part[blockIdx.x] = tot;
@@ -251,9 +255,10 @@ __device__ inline void emit_row(uint32_t *__restrict__ pkey, uint32_t *__restric
     }
 }
 
-// One lane per record (in depth order).  Records with many pairs are queued for k_keygen_big.
+// One lane per record (in depth order; sorted_counts[p] is the pair count of sorted_rec[p]).
+// Records with many pairs are queued for k_keygen_big.
 __global__ void __launch_bounds__(256)
-k_keygen(const uint32_t *__restrict__ sorted_rec, const uint32_t *__restrict__ counts,
+k_keygen(const uint32_t *__restrict__ sorted_rec, const uint32_t *__restrict__ sorted_counts,
          const uint32_t *__restrict__ offsets, const float4 *__restrict__ rec, RasterSettings rs,
          int64_t n_records, int64_t n_per_view, ViewTable vt, uint32_t *__restrict__ pkey,
          uint32_t *__restrict__ pval, FrameHeader *__restrict__ hdr, uint32_t cap,
@@ -271,7 +276,7 @@ k_keygen(const uint32_t *__restrict__ sorted_rec, const uint32_t *__restrict__ c
     uint32_t r = 0, c = 0;
     if (p < n_records) {
         r = sorted_rec[p];
-        c = counts[r];
+        c = sorted_counts[p];
     }
     const bool big = c > kBigRecord;
     const uint32_t slot = wave_append(big_count, big);
@@ -367,12 +372,21 @@ static int64_t scan_blocks(int64_t n) {
 int64_t scan_partials(int64_t n) { return scan_blocks(n); }
 
 hipError_t launch_scan_indirect(const uint32_t *counts, const uint32_t *idx, int64_t n, uint32_t *offsets,
-                                uint32_t *total, uint32_t *part, hipStream_t s, const uint32_t *n_dev, int flag) {
+                                uint32_t *total, uint32_t *part, hipStream_t s, const uint32_t *n_dev, int flag,
+                                uint32_t *gathered) {
     const int64_t nb = scan_blocks(n);
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanBlock), 0, s, counts, idx, n_dev, n, flag, part);
+    // With `gathered`, the reduce pass stores counts[idx[p]] (or its flag) there and the
+    // apply pass reads it back contiguously instead of gathering a second time.
+    if (!idx) gathered = nullptr;
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanBlock), 0, s, counts, idx, n_dev, n, flag, part,
+                       gathered);
     hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, part, (int)nb, total);
-    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kScanBlock), 0, s, counts, idx, n_dev, n, flag, part,
-                       offsets);
+    if (gathered)
+        hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kScanBlock), 0, s, gathered, nullptr, n_dev, n, 0,
+                           part, offsets);
+    else
+        hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kScanBlock), 0, s, counts, idx, n_dev, n, flag,
+                           part, offsets);
     return hipGetLastError();
 }
 
@@ -448,7 +462,7 @@ hipError_t radix_sort(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t
     return hipGetLastError();
 }
 
-hipError_t launch_keygen(const uint32_t *sorted_rec, const uint32_t *counts, const uint32_t *offsets,
+hipError_t launch_keygen(const uint32_t *sorted_rec, const uint32_t *sorted_counts, const uint32_t *offsets,
                          const float *records, const RasterSettings &rs, int64_t n_records, int64_t n_per_view,
                          const ViewTable &vt, uint32_t *pkey, uint32_t *pval, FrameHeader *hdr, uint32_t capacity,
                          const uint32_t *total, uint32_t *big_list, uint32_t *big_count, const uint32_t *n_dev,
@@ -457,7 +471,7 @@ hipError_t launch_keygen(const uint32_t *sorted_rec, const uint32_t *counts, con
     if (e != hipSuccess) return e;
     const float4 *rec = reinterpret_cast<const float4 *>(records);
     const int64_t nb = n_records > 0 ? (n_records + 255) / 256 : 1;
-    hipLaunchKernelGGL(k_keygen, dim3((unsigned)nb), dim3(256), 0, s, sorted_rec, counts, offsets, rec, rs, n_records,
+    hipLaunchKernelGGL(k_keygen, dim3((unsigned)nb), dim3(256), 0, s, sorted_rec, sorted_counts, offsets, rec, rs, n_records,
                        n_per_view, vt, pkey, pval, hdr, capacity, total, big_list, big_count, n_dev);
     if (n_records > 0)
         hipLaunchKernelGGL(k_keygen_big, dim3(1024), dim3(256), 0, s, sorted_rec, offsets, rec, rs, n_per_view, vt,

@@ -208,6 +208,7 @@ struct Footprint {
     double qxx, qxy, qyy;   // conic
     double q;               // support level
     double isyy;            // 1 / Sigma_yy = det(Q) / qxx
+    double iqxx;            // 1 / qxx
     double rx, ry;          // support half extents
     double yr;              // y offset of the rightmost support point
     double kx;              // centre-line slope -qxy / qxx
@@ -226,12 +227,14 @@ __device__ inline bool record_footprint(const float4 r0, const float4 r1, float 
     const double det = f.qxx * f.qyy - f.qxy * f.qxy;
     if (!(det > 0.0) || !(f.qxx > 0.0)) return false;
     f.q = 2.0 * log((double)r1.w / (double)alpha_min) * (1.0 + kSupportMargin);
-    const double sxx = f.qyy / det, syy = f.qxx / det, sxy = -f.qxy / det;
-    f.isyy = det / f.qxx;
+    const double idet = 1.0 / det;
+    const double sxx = f.qyy * idet, syy = f.qxx * idet, sxy = -f.qxy * idet;
+    f.iqxx = 1.0 / f.qxx;
+    f.isyy = det * f.iqxx;
     f.rx = sqrt(f.q * sxx);
     f.ry = sqrt(f.q * syy);
     f.yr = f.rx > 0.0 ? sxy * f.q / f.rx : 0.0;  // = sxy sqrt(q / sxx)
-    f.kx = -f.qxy / f.qxx;
+    f.kx = -f.qxy * f.iqxx;
     f.i0 = (int)fmax(0.0, ceil(f.u - f.rx));
     f.i1 = (int)fmin((double)(W - 1), floor(f.u + f.rx));
     f.j0 = (int)fmax(0.0, ceil(f.v - f.ry));
@@ -246,8 +249,8 @@ __device__ inline bool row_span(const Footprint &f, int B, int ty, int &ta, int 
     const double ya = fmax((double)ja - f.v, -f.ry), yb = fmin((double)jb - f.v, f.ry);
     if (ya > yb) return false;
     // Half width of the support at height y around the centre line x = kx y.
-    const double ha = sqrt(fmax(0.0, (f.q - ya * ya * f.isyy) / f.qxx));
-    const double hb = sqrt(fmax(0.0, (f.q - yb * yb * f.isyy) / f.qxx));
+    const double ha = sqrt(fmax(0.0, (f.q - ya * ya * f.isyy) * f.iqxx));
+    const double hb = sqrt(fmax(0.0, (f.q - yb * yb * f.isyy) * f.iqxx));
     const double xr = (f.yr >= ya && f.yr <= yb) ? f.rx : fmax(f.kx * ya + ha, f.kx * yb + hb);
     const double xl = (-f.yr >= ya && -f.yr <= yb) ? -f.rx : fmin(f.kx * ya - ha, f.kx * yb - hb);
     const int ia = max(f.i0, (int)ceil(f.u + xl));
@@ -277,7 +280,7 @@ hipError_t launch_preprocess(const gspm_gaussians &g, const ViewTable &vt, const
 int64_t scan_partials(int64_t n);
 hipError_t launch_scan_indirect(const uint32_t *counts, const uint32_t *idx, int64_t n,
                                 uint32_t *offsets, uint32_t *total, uint32_t *part, hipStream_t s,
-                                const uint32_t *n_dev = nullptr, int flag = 0);
+                                const uint32_t *n_dev = nullptr, int flag = 0, uint32_t *gathered = nullptr);
 
 // Compacts (depth key, record index) of the records with counts[r] != 0 to the positions
 // given by the flag scan.
@@ -297,7 +300,7 @@ hipError_t radix_sort(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t
 // Emits the (global tile, record) pairs of every record in depth order.  Records with
 // more than kBigRecord pairs are queued in big_list (big_count zeroed here) and emitted
 // by whole waves.  records: the projected records (for the support footprint).
-hipError_t launch_keygen(const uint32_t *sorted_rec, const uint32_t *counts, const uint32_t *offsets,
+hipError_t launch_keygen(const uint32_t *sorted_rec, const uint32_t *sorted_counts, const uint32_t *offsets,
                          const float *records, const RasterSettings &rs, int64_t n_records, int64_t n_per_view,
                          const ViewTable &vt, uint32_t *pkey, uint32_t *pval, FrameHeader *hdr,
                          uint32_t capacity, const uint32_t *total, uint32_t *big_list, uint32_t *big_count,

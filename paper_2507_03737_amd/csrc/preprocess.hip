@@ -197,45 +197,52 @@ k_count_big(const float4 *__restrict__ rec, ViewTable vt, RasterSettings rs, int
 
 constexpr int kBwdBlock = 256;
 
-__device__ inline double block_sum(double x, double *lds) {
-    // Fixed-order block reduction (deterministic for a fixed launch shape).
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+// Fixed-order block reduction of 6 values (deterministic for a fixed launch shape); the
+// sums are valid in thread 0.
+__device__ inline void block_sum6(double x[6], double *lds) {
     const int wid = threadIdx.x / 64;
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+        for (int off = 32; off > 0; off >>= 1) x[k] += __shfl_xor(x[k], off, 64);
+    if (lane_id() == 0)
+        for (int k = 0; k < 6; ++k) lds[wid * 6 + k] = x[k];
     __syncthreads();
-    if (lane_id() == 0) lds[wid] = x;
-    __syncthreads();
-    double t = 0.0;
-    for (int k = 0; k < kBwdBlock / 64; ++k) t += lds[k];
-    return t;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 6; ++k) {
+            double t = 0.0;
+            for (int w = 0; w < kBwdBlock / 64; ++w) t += lds[w * 6 + k];
+            x[k] = t;
+        }
 }
 
 __global__ void __launch_bounds__(kBwdBlock)
 k_preprocess_backward(gspm_gaussians G, ViewTable vt, const float *__restrict__ T_cw, RasterSettings rs,
                       const float4 *__restrict__ grad2d, gspm_gaussian_grads out, int want_pose,
                       double *__restrict__ pose_part) {
-    __shared__ double lds[kBwdBlock / 64];
+    // One thread per (Gaussian, view) record: blockIdx.y is the view.  Parameter gradients
+    // of the views are summed with float atomics; pose partials per block in FP64.
+    __shared__ double lds[6 * (kBwdBlock / 64)];
     const int64_t n = G.n;
+    const int v = blockIdx.y;
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool live = g < n;
     double gmu[3] = {0, 0, 0}, gls[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go = 0.0, gc[3] = {0, 0, 0};
-
-    for (int v = 0; v < vt.n_views; ++v) {
-        double pose[6] = {0, 0, 0, 0, 0, 0};
-        bool any = false;
-        float4 q0 = make_float4(0, 0, 0, 0), q1 = q0, q2 = q0, q3 = q0;
-        if (live) {
-            const float4 *src = grad2d + 4 * ((int64_t)v * n + g);
-            q0 = src[0]; q1 = src[1]; q2 = src[2]; q3 = src[3];
-            any = q0.x != 0.f || q0.y != 0.f || q0.z != 0.f || q0.w != 0.f || q1.x != 0.f || q1.y != 0.f ||
-                  q1.z != 0.f || q1.w != 0.f || q2.x != 0.f || q2.y != 0.f || q2.z != 0.f || q2.w != 0.f ||
-                  q3.x != 0.f;
-        }
-        Proj P;
-        if (any) {
-            project_one(G, g, n, T_cw + 12 * v, vt.fx[v], vt.fy[v], vt.cx[v], vt.cy[v], vt.width[v],
-                        vt.height[v], rs, P);
-            any = P.visible;
-        }
+    double pose[6] = {0, 0, 0, 0, 0, 0};
+    bool any = false;
+    float4 q0 = make_float4(0, 0, 0, 0), q1 = q0, q2 = q0, q3 = q0;
+    if (g < n) {
+        const float4 *src = grad2d + 4 * ((int64_t)v * n + g);
+        q0 = src[0]; q1 = src[1]; q2 = src[2]; q3 = src[3];
+        any = q0.x != 0.f || q0.y != 0.f || q0.z != 0.f || q0.w != 0.f || q1.x != 0.f || q1.y != 0.f ||
+              q1.z != 0.f || q1.w != 0.f || q2.x != 0.f || q2.y != 0.f || q2.z != 0.f || q2.w != 0.f ||
+              q3.x != 0.f;
+    }
+    Proj P;
+    if (any) {
+        project_one(G, g, n, T_cw + 12 * v, vt.fx[v], vt.fy[v], vt.cx[v], vt.cy[v], vt.width[v], vt.height[v],
+                    rs, P);
+        any = P.visible;
+    }
+    {
         if (any) {
             const double gu = q0.x, gv = q0.y, gA = q0.z, gB = q0.w, gC = q1.x, gop = q1.y, gz = q1.z;
             gc[0] += q1.w; gc[1] += q2.x; gc[2] += q2.y;
@@ -349,24 +356,23 @@ k_preprocess_backward(gspm_gaussians G, ViewTable vt, const float *__restrict__ 
             for (int k = 0; k < 4; ++k) gq[k] += (gqn[k] - P.qn[k] * dot) * iq;
             go += gop * P.a * (1.0 - P.a);
         }
-        if (want_pose) {
-            // Every thread of the block takes part (uniform branch).
-            for (int k = 0; k < 6; ++k) {
-                const double t = block_sum(pose[k], lds);
-                if (threadIdx.x == 0) pose_part[((int64_t)v * gridDim.x + blockIdx.x) * 6 + k] = t;
-            }
-        }
     }
-    if (!live) return;
+    if (want_pose) {
+        // Every thread of the block takes part (uniform branch).
+        block_sum6(pose, lds);
+        if (threadIdx.x == 0)
+            for (int k = 0; k < 6; ++k) pose_part[((int64_t)v * gridDim.x + blockIdx.x) * 6 + k] = pose[k];
+    }
+    if (!any) return;
     if (out.means)
-        for (int c = 0; c < 3; ++c) out.means[c * n + g] += (float)gmu[c];
+        for (int c = 0; c < 3; ++c) unsafeAtomicAdd(out.means + c * n + g, (float)gmu[c]);
     if (out.log_scales)
-        for (int c = 0; c < 3; ++c) out.log_scales[c * n + g] += (float)gls[c];
+        for (int c = 0; c < 3; ++c) unsafeAtomicAdd(out.log_scales + c * n + g, (float)gls[c]);
     if (out.quats)
-        for (int c = 0; c < 4; ++c) out.quats[c * n + g] += (float)gq[c];
-    if (out.opacity_logit) out.opacity_logit[g] += (float)go;
+        for (int c = 0; c < 4; ++c) unsafeAtomicAdd(out.quats + c * n + g, (float)gq[c]);
+    if (out.opacity_logit) unsafeAtomicAdd(out.opacity_logit + g, (float)go);
     if (out.rgb)
-        for (int c = 0; c < 3; ++c) out.rgb[c * n + g] += (float)gc[c];
+        for (int c = 0; c < 3; ++c) unsafeAtomicAdd(out.rgb + c * n + g, (float)gc[c]);
 }
 
 __global__ void __launch_bounds__(256)
@@ -476,7 +482,8 @@ hipError_t launch_preprocess_backward(const gspm_gaussians &g, const ViewTable &
                                       const gspm_gaussian_grads &out, bool want_pose,
                                       double *pose_partials, hipStream_t s) {
     if (g.n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_preprocess_backward, dim3((unsigned)pose_partial_blocks(g.n)), dim3(kBwdBlock), 0, s,
+    hipLaunchKernelGGL(k_preprocess_backward, dim3((unsigned)pose_partial_blocks(g.n), (unsigned)vt.n_views),
+                       dim3(kBwdBlock), 0, s,
                        g, vt, T_cw, rs, reinterpret_cast<const float4 *>(grad2d), out, want_pose ? 1 : 0,
                        pose_partials);
     return hipGetLastError();
