@@ -158,7 +158,6 @@ k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
     float T[PPT], C0[PPT], C1[PPT], C2[PPT], D[PPT], X0[PPT], X1[PPT], X2[PPT], py[PPT];
     uint32_t n_last[PPT], n_contrib[PPT];
     bool done[PPT];
-    int live = 0;
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
         T[k] = 1.0f;
@@ -167,9 +166,16 @@ k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
         py[k] = (float)(ly + k);
         const int j = tp.ty * TILE + ly + k;
         done[k] = !(i < tp.W && j < tp.H);
-        live += done[k] ? 0 : 1;
     }
-    bool wave_live = __ballot(live > 0) != 0ull;
+    // Whether any pixel of this lane is still compositing.  Re-evaluated once per 64
+    // entries: a wave whose pixels have all stopped walks at most the rest of one mask.
+    auto lane_live = [&]() {
+        bool l = false;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) l |= !done[k];
+        return l;
+    };
+    bool wave_live = __ballot(lane_live()) != 0ull;
     for (uint32_t base = rg.x; base < rg.y; base += NT) {
         const uint32_t kk = base + threadIdx.x;
         if (kk < rg.y) stage(rec, vals[kk], tp.x0, tp.y0, amin, s0, s1, s2, s3, threadIdx.x);
@@ -177,7 +183,7 @@ k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
         const int cnt = (int)min((uint32_t)NT, rg.y - base);
         for (int c = 0; c < cnt && wave_live; c += kWave) {
             uint64_t m = batch_mask<L::CULL>(s0, s1, c, cnt, lay.rx0, lay.rx1, lay.ry0, lay.ry1);
-            while (m != 0ull && wave_live) {
+            while (m != 0ull) {
                 const int q = c + (int)__builtin_ctzll(m);
                 m &= m - 1ull;
                 const float4 a = s0[q];
@@ -215,12 +221,11 @@ k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
                     n_last[k] = add ? rel : n_last[k];
                     n_contrib[k] += add ? 1u : 0u;
                     done[k] = done[k] || stop;
-                    live -= stop ? 1 : 0;
                 }
-                wave_live = __ballot(live > 0) != 0ull;
             }
+            wave_live = __ballot(lane_live()) != 0ull;
         }
-        if (!__syncthreads_or(live > 0 ? 1 : 0)) break;
+        if (!__syncthreads_or(lane_live() ? 1 : 0)) break;
     }
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
