@@ -201,6 +201,7 @@ def main():
 
     dev = torch.device("cuda:0")
     B.load()
+    free0, total_mem = torch.cuda.mem_get_info(dev)
     if args.calibrate_copy:
         copy_calibration(torch, dev)
     seed = args.seed if args.seed is not None else ["c0", "c1", "c2", "c3", "c4"].index(args.workload)
@@ -301,6 +302,9 @@ def main():
         opt_host = [t.cpu().numpy() for t in opt]
         cpu = cpu_baseline(sc, opt_host, sc.cams, sc.T_cw, 7, args.cpu_px)
 
+    free1, _ = torch.cuda.mem_get_info(dev)
+    memory = {"device_used_bytes": int(free0 - free1), "torch_peak_bytes": int(torch.cuda.max_memory_allocated(dev)),
+              "device_total_bytes": int(total_mem)}
     fps_evals = 2.0 * frags / (ms_batched * 1e-3)
     res = {
         "metric": METRIC,
@@ -333,6 +337,7 @@ def main():
         "autotune_ms": ({f"{r['tile']}x{r['tile']}/ppl{r['pixels_per_lane']}/bits{r['sort_digit_bits']}": round(r["ms"], 3)
                          for r in tuned} if tuned else None),
         "roofline": roof,
+        "memory": memory,
         "cpu_baseline": cpu,
         "wall_s_timed": wall,
     }
