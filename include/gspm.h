@@ -216,6 +216,48 @@ GSPM_API gspm_status gspm_window_loss(gspm_ctx *ctx, const gspm_views *views, co
                              float *scale_out, float *loss_out, float *grad_rgb, float *grad_pm,
                              void *stream);
 
+/* ---- scale alignment and pointmap replacement (supplementary Alg. 1; Sec. 3.3.2, Eq. 14) */
+
+/* Parameters of the patch-based scale alignment (the supplementary parameter table gives
+ * P = 10, delta_mu = delta_sigma = 0.3, eps_r = 0.1, max_iter = 3, tau = 0.01). */
+typedef struct {
+    int32_t patch;      /* P in [2, 64] */
+    float delta_mu;     /* patch test |mu_r - mu_p| < delta_mu mu_p */
+    float delta_sigma;  /* patch test |sd_r - sd_p| < delta_sigma sd_p */
+    float eps_r;        /* correct point |Xr_N - Xp_N| < eps_r */
+    int32_t max_iter;   /* iterations, >= 1 */
+    float tau;          /* too few correct points: |CP| < tau N_p */
+} gspm_align_params;
+
+/* Result per view (device memory). */
+typedef struct {
+    double scale;          /* sigma': the aligned prior is scale * Xp */
+    int32_t cp;            /* correct points of the last iteration */
+    int32_t n_valid;       /* N_p: pixels with mask != 0 */
+    int32_t insufficient;  /* 1 if cp < tau n_valid (the caller's remedy applies) */
+    int32_t pad;
+} gspm_align_result;
+
+/* Alg. 1 for every view of the window.  The per-pixel scalar is the norm |X(x)|; patch
+ * means and standard deviations (population) are over pixels with mask != 0 (mask NULL =
+ * all; border patches partial); correct points are collected afresh in every iteration
+ * over the candidate patches, and sigma' = mean|Xr[CP]| / mean|Xp[CP]| measures the
+ * original Xp (an empty CP keeps the previous sigma', initially 1).  Xr, Xp: packed
+ * camera-frame pointmaps [3][H][W] per view; mask: packed [H][W] or NULL; result: device
+ * [V], overwritten.  The context provides scratch (56 bytes per patch).  Returns
+ * GSPM_ERR_INVALID_ARG for NULL arrays or parameters out of range, before any launch. */
+GSPM_API gspm_status gspm_align_scale(gspm_ctx *ctx, const gspm_views *views, const float *Xr, const float *Xp,
+                                      const float *mask, const gspm_align_params *params,
+                                      gspm_align_result *result, void *stream);
+
+/* Eq. 14 for every pixel: Xr_hat = Xr where |Xr - s Xp| <= eps_m |s Xp| (s = result[v].scale),
+ * else s Xp (products and norms in float64, outputs rounded to float).  Xr_hat may not
+ * alias Xr or Xp.  replaced_out: device int32 [V], overwritten with the replaced-pixel
+ * count of each view. */
+GSPM_API gspm_status gspm_replace_pointmap(const gspm_views *views, const float *Xr, const float *Xp,
+                                           const gspm_align_result *result, float eps_m, float *Xr_hat,
+                                           int32_t *replaced_out, void *stream);
+
 /* T_cw[v] <- Exp(xi[v]) T_cw[v] for every view (device arrays [V][12], [V][6]). */
 GSPM_API gspm_status gspm_pose_retract(int32_t n_views, float *T_cw, const float *xi, void *stream);
 

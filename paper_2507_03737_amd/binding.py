@@ -64,11 +64,36 @@ class GaussianGrads(ctypes.Structure):
     _fields_ = [("means", vp), ("log_scales", vp), ("quats", vp), ("opacity_logit", vp), ("rgb", vp)]
 
 
+class AlignParams(ctypes.Structure):
+    _fields_ = [("patch", ctypes.c_int32), ("delta_mu", ctypes.c_float), ("delta_sigma", ctypes.c_float),
+                ("eps_r", ctypes.c_float), ("max_iter", ctypes.c_int32), ("tau", ctypes.c_float)]
+
+
+# gspm_align_result as stored in device memory (24 bytes per view).
+ALIGN_RESULT_DTYPE = np.dtype([("scale", "<f8"), ("cp", "<i4"), ("n_valid", "<i4"), ("insufficient", "<i4"),
+                               ("pad", "<i4")])
+
+
+@dataclass
+class AlignConfig:
+    """Parameters of the patch-based scale alignment (the paper's values by default)."""
+    patch: int = 10
+    delta_mu: float = 0.3
+    delta_sigma: float = 0.3
+    eps_r: float = 0.1
+    max_iter: int = 3
+    tau: float = 0.01
+    eps_m: float = 0.15  # pointmap replacement threshold (Eq. 14)
+
+    def c(self) -> AlignParams:
+        return AlignParams(self.patch, self.delta_mu, self.delta_sigma, self.eps_r, self.max_iter, self.tau)
+
+
 EXPORTS = (
     "gspm_create", "gspm_destroy", "gspm_reserve", "gspm_frame_state_bytes", "gspm_render_forward",
     "gspm_frame_status", "gspm_render_backward", "gspm_pose_backward", "gspm_patch_scale_align",
     "gspm_window_loss", "gspm_pose_retract", "gspm_timing_enable", "gspm_timing_collect", "gspm_frame_work",
-    "gspm_last_error", "gspm_version",
+    "gspm_last_error", "gspm_version", "gspm_align_scale", "gspm_replace_pointmap",
 )
 
 PHASES = ("preprocess", "depth_sort", "binning", "tile_sort", "raster_fwd", "raster_bwd", "param_bwd")
@@ -99,6 +124,8 @@ def load(path: str = LIB_PATH):
     L.gspm_patch_scale_align.argtypes = [P(Views), vp, vp, vp, ctypes.c_int32, vp, vp, vp]
     L.gspm_window_loss.argtypes = [vp, P(Views), vp, vp, vp, vp, ctypes.c_int32, ctypes.c_float, vp, vp, vp, vp, vp]
     L.gspm_pose_retract.argtypes = [ctypes.c_int32, vp, vp, vp]
+    L.gspm_align_scale.argtypes = [vp, P(Views), vp, vp, vp, P(AlignParams), vp, vp]
+    L.gspm_replace_pointmap.argtypes = [P(Views), vp, vp, vp, ctypes.c_float, vp, vp, vp]
     L.gspm_frame_work.argtypes = [vp, P(Views), ctypes.c_int64, ctypes.c_int32, vp, vp, P(ctypes.c_int64)]
     L.gspm_timing_enable.argtypes = [vp, ctypes.c_int32]
     L.gspm_timing_collect.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
@@ -256,6 +283,17 @@ def window_loss(ctx: Context, views: Views, rgb, rgb_target, pm, Xp, patch, alph
                 grad_pm, stream):
     check(load().gspm_window_loss(ctx.h, ctypes.byref(views), ptr(rgb), ptr(rgb_target), ptr(pm), ptr(Xp), int(patch),
                                   float(alpha), ptr(scale_out), ptr(loss_out), ptr(grad_rgb), ptr(grad_pm), stream))
+
+
+def align_scale(ctx: Context, views: Views, Xr, Xp, mask, params: AlignParams, result, stream):
+    """result: device buffer of 24 * n_views bytes (gspm_align_result per view)."""
+    check(load().gspm_align_scale(ctx.h, ctypes.byref(views), ptr(Xr), ptr(Xp), ptr(mask), ctypes.byref(params),
+                                  ptr(result), stream))
+
+
+def replace_pointmap(views: Views, Xr, Xp, result, eps_m, Xr_hat, replaced_out, stream):
+    check(load().gspm_replace_pointmap(ctypes.byref(views), ptr(Xr), ptr(Xp), ptr(result), float(eps_m), ptr(Xr_hat),
+                                       ptr(replaced_out), stream))
 
 
 def pose_retract(n_views, T_cw, xi, stream):

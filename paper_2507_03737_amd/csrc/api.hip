@@ -72,7 +72,7 @@ struct gspm_ctx {
     // Per pair (capacity).
     DevBuf pkey, pval, pkey_tmp, pval_tmp, pkey_s;
     // Small scratch.
-    DevBuf hist, scan_part, misc, pose_part, loss_part;
+    DevBuf hist, scan_part, misc, pose_part, loss_part, align;
 };
 
 namespace {
@@ -286,7 +286,7 @@ void gspm_destroy(gspm_ctx *ctx) {
     DevBuf *bufs[] = {&ctx->counts, &ctx->big, &ctx->live, &ctx->dkey, &ctx->dval, &ctx->dkey_tmp, &ctx->dval_tmp,
                       &ctx->dkey_s, &ctx->dval_s, &ctx->offsets, &ctx->grad2d, &ctx->pkey, &ctx->pval,
                       &ctx->pkey_tmp, &ctx->pval_tmp, &ctx->pkey_s, &ctx->hist, &ctx->scan_part, &ctx->misc,
-                      &ctx->pose_part, &ctx->loss_part};
+                      &ctx->pose_part, &ctx->loss_part, &ctx->align};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
@@ -500,6 +500,41 @@ gspm_status gspm_window_loss(gspm_ctx *ctx, const gspm_views *views, const float
     if (!(alpha >= 0.0f && alpha <= 1.0f)) return fail(GSPM_ERR_INVALID_ARG, "alpha must lie in [0, 1]");
     return patch_common(ctx, views, pm, Xp, nullptr, patch, rgb, rgb_target, alpha, scale_out, nullptr, loss_out,
                         grad_rgb, grad_pm, stream);
+}
+
+gspm_status gspm_align_scale(gspm_ctx *ctx, const gspm_views *views, const float *Xr, const float *Xp,
+                             const float *mask, const gspm_align_params *prm, gspm_align_result *result,
+                             void *stream) {
+    if (!ctx) return fail(GSPM_ERR_INVALID_ARG, "ctx is NULL");
+    if (!Xr || !Xp || !prm || !result) return fail(GSPM_ERR_INVALID_ARG, "Xr, Xp, params and result are required");
+    if (prm->patch < 2 || prm->patch > 64) return fail(GSPM_ERR_INVALID_ARG, "patch = %d outside [2, 64]", prm->patch);
+    if (prm->max_iter < 1) return fail(GSPM_ERR_INVALID_ARG, "max_iter must be >= 1");
+    if (!(prm->delta_mu > 0.0f) || !(prm->delta_sigma > 0.0f) || !(prm->eps_r > 0.0f) || !(prm->tau >= 0.0f))
+        return fail(GSPM_ERR_INVALID_ARG, "delta_mu, delta_sigma, eps_r must be > 0 and tau >= 0");
+    ViewTable vt;
+    int64_t nt, np;
+    gspm_status st = build_views(views, 16, vt, nt, np);
+    if (st) return st;
+    GSPM_HIP(grow(ctx->align, (int64_t)sizeof(AlignPatch) * (align_patches(vt, prm->patch) + 1)));
+    GSPM_HIP(launch_align_scale(vt, Xr, Xp, mask, *prm, static_cast<AlignPatch *>(ctx->align.p), result,
+                                reinterpret_cast<hipStream_t>(stream)));
+    return GSPM_OK;
+}
+
+gspm_status gspm_replace_pointmap(const gspm_views *views, const float *Xr, const float *Xp,
+                                  const gspm_align_result *result, float eps_m, float *Xr_hat,
+                                  int32_t *replaced_out, void *stream) {
+    if (!Xr || !Xp || !result || !Xr_hat || !replaced_out)
+        return fail(GSPM_ERR_INVALID_ARG, "Xr, Xp, result, Xr_hat and replaced_out are required");
+    if (Xr_hat == Xr || Xr_hat == Xp) return fail(GSPM_ERR_INVALID_ARG, "Xr_hat may not alias Xr or Xp");
+    if (!(eps_m >= 0.0f)) return fail(GSPM_ERR_INVALID_ARG, "eps_m must be >= 0");
+    ViewTable vt;
+    int64_t nt, np;
+    gspm_status st = build_views(views, 16, vt, nt, np);
+    if (st) return st;
+    GSPM_HIP(launch_replace(vt, Xr, Xp, result, eps_m, Xr_hat, reinterpret_cast<uint32_t *>(replaced_out),
+                            reinterpret_cast<hipStream_t>(stream)));
+    return GSPM_OK;
 }
 
 gspm_status gspm_pose_retract(int32_t n_views, float *T_cw, const float *xi, void *stream) {

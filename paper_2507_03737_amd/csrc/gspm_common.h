@@ -308,6 +308,19 @@ hipError_t launch_keygen(const uint32_t *sorted_rec, const uint32_t *sorted_coun
 
 hipError_t launch_sum_u64(const uint32_t *x, int64_t n, unsigned long long *out, hipStream_t s);
 
+// Scale alignment (align.hip).  Per patch: statistics of |X^r| and |X^p| and the sums
+// over the pixels that pass the normalised correct-point test.
+struct AlignPatch {
+    double mu_r, sd_r, mu_p, sd_p, cp_sr, cp_sp;
+    int32_t n, cp_n;
+};
+int64_t align_patches(const ViewTable &vt, int patch);
+hipError_t launch_align_scale(const ViewTable &vt, const float *Xr, const float *Xp, const float *mask,
+                              const gspm_align_params &prm, AlignPatch *patches, gspm_align_result *result,
+                              hipStream_t s);
+hipError_t launch_replace(const ViewTable &vt, const float *Xr, const float *Xp, const gspm_align_result *result,
+                          float eps_m, float *out, uint32_t *replaced, hipStream_t s);
+
 hipError_t launch_ranges(const uint32_t *sorted_keys, const FrameHeader *hdr, uint2 *ranges,
                          int64_t n_tiles, int64_t n_max, hipStream_t s);
 

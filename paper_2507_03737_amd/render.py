@@ -13,7 +13,7 @@ import torch
 
 from . import binding as B
 
-__all__ = ["Window", "Rasterizer", "RasterizePointmap", "rasterize", "MappingStep", "split_views"]
+__all__ = ["Window", "Rasterizer", "RasterizePointmap", "rasterize", "MappingStep", "split_views", "align_results"]
 
 
 class Window:
@@ -152,6 +152,25 @@ class Rasterizer:
     def window_loss_into(self, rgb, target, pm, Xp, patch, alpha, scale, loss, grad_rgb, grad_pm, stream=None):
         B.window_loss(self.ctx, self.win.c(), rgb, target, pm, Xp, patch, alpha, scale, loss, grad_rgb, grad_pm,
                       B.stream_handle(stream))
+
+    # -- scale alignment and pointmap replacement -----------------------------------------
+    def new_align_result(self):
+        return torch.empty(B.ALIGN_RESULT_DTYPE.itemsize * self.win.n_views, dtype=torch.uint8,
+                           device=self.win.T_cw.device)
+
+    def align_scale_into(self, Xr, Xp, result, mask=None, cfg: B.AlignConfig | None = None, stream=None):
+        """Patch-based scale alignment of the prior Xp to the rendered Xr, every view."""
+        cfg = cfg or B.AlignConfig()
+        B.align_scale(self.ctx, self.win.c(), Xr, Xp, mask, cfg.c(), result, B.stream_handle(stream))
+
+    def replace_pointmap_into(self, Xr, Xp, result, Xr_hat, replaced, eps_m=0.15, stream=None):
+        """Eq. 14 with the aligned prior result[v].scale * Xp."""
+        B.replace_pointmap(self.win.c(), Xr, Xp, result, eps_m, Xr_hat, replaced, B.stream_handle(stream))
+
+
+def align_results(result: torch.Tensor):
+    """Host view of a device gspm_align_result array (synchronises)."""
+    return result.cpu().numpy().view(B.ALIGN_RESULT_DTYPE)
 
 
 class RasterizePointmap(torch.autograd.Function):

@@ -30,7 +30,7 @@ import numpy as np
 
 __all__ = [
     "Camera", "Scene", "make_scene", "upstream_grads", "perturb_pose",
-    "rotation_about_axis", "CONFIG_NAMES",
+    "rotation_about_axis", "CONFIG_NAMES", "street_pointmap", "noisy_prior",
 ]
 
 CONFIG_NAMES = ("c0", "c1", "c2", "c3", "c4")
@@ -268,3 +268,38 @@ def perturb_pose(T_row: np.ndarray, deg: float, meters: float, seed: int) -> np.
     R = R_d @ T[:, :3]
     t = R_d @ T[:, 3] + meters * d
     return _f32(np.concatenate([R, t[:, None]], axis=1).reshape(-1))
+
+
+def street_pointmap(cam: Camera, seed: int) -> np.ndarray:
+    """Camera-frame pointmap [3][H][W] (float32) of a synthetic street view: a ground plane
+    1.6 m below the camera up to 80 m, walls 6-10 m to either side and a far backdrop,
+    with centimetre-scale surface roughness.  Stands in for a rendered pointmap."""
+    rng = np.random.default_rng(seed)
+    H, W = cam.height, cam.width
+    jj, ii = np.mgrid[0:H, 0:W].astype(np.float64)
+    rx, ry = (ii - cam.cx) / cam.fx, (jj - cam.cy) / cam.fy
+    z = np.full((H, W), 80.0)
+    ground = ry > 1e-3
+    z[ground] = np.minimum(80.0, 1.6 / ry[ground])
+    for side, off in ((-1.0, rng.uniform(6.0, 10.0)), (1.0, rng.uniform(6.0, 10.0))):
+        hit = side * rx > 1e-3
+        zw = off / np.abs(rx[hit])
+        z[hit] = np.minimum(z[hit], zw)
+    z *= 1.0 + rng.normal(0.0, 0.003, (H, W))
+    return _f32(np.stack([rx * z, ry * z, z]))
+
+
+def noisy_prior(Xr: np.ndarray, scale: float, seed: int, noise: float = 0.01, patch: int = 10,
+                outlier_patches: float = 0.1, outlier_pixels: float = 0.01) -> np.ndarray:
+    """A prior pointmap at another scale: Xr / scale with relative noise, a fraction of whole
+    patches at an unrelated scale and a fraction of isolated pixels pushed far off."""
+    rng = np.random.default_rng(seed)
+    _, H, W = Xr.shape
+    Xp = Xr.astype(np.float64) / scale * (1.0 + rng.normal(0.0, noise, (1, H, W)))
+    nph, npw = -(-H // patch), -(-W // patch)
+    bad = rng.random((nph, npw)) < outlier_patches
+    f = np.repeat(np.repeat(np.where(bad, rng.uniform(0.3, 3.0, (nph, npw)), 1.0), patch, 0), patch, 1)[:H, :W]
+    Xp *= f[None]
+    px = rng.random((H, W)) < outlier_pixels
+    Xp[:, px] *= rng.uniform(2.0, 5.0, px.sum())[None]
+    return _f32(Xp)
