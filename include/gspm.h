@@ -105,6 +105,8 @@ typedef struct {
     float eps2d;             /* low-pass added to the 2D covariance, px^2 [0.3] */
     float jac_clamp;         /* x/z, y/z clamped to jac_clamp * half FOV in the Jacobian [1.3] */
     float bg[3];             /* background colour added as T_final * bg [0] */
+    int32_t mark_visible;    /* nonzero: the forward records which (Gaussian, view) records
+                                contribute to at least one pixel, for gspm_covisibility [0] */
 } gspm_settings;
 
 /* Per-view packed output planes (device): rgb [3][H][W], depth [H][W] (Eq. 3, not
@@ -257,6 +259,32 @@ GSPM_API gspm_status gspm_align_scale(gspm_ctx *ctx, const gspm_views *views, co
 GSPM_API gspm_status gspm_replace_pointmap(const gspm_views *views, const float *Xr, const float *Xp,
                                            const gspm_align_result *result, float eps_m, float *Xr_hat,
                                            int32_t *replaced_out, void *stream);
+
+/* ---- regulariser and keyframe window (Sec. 3.3.3 Eq. 16; supplementary Eq. S1-S2) -- */
+
+/* Isotropic regulariser of Eq. 16: loss = weight * sum_i sum_k |s_ik - mean_k s_ik| with
+ * s = exp(log_scales) (float64 inside; sign(0) = 0).  loss_out: device float [1],
+ * overwritten; grad_log_scales: device [3][n], accumulated (+=), may be NULL.  The
+ * context provides scratch for the partial sums. */
+GSPM_API gspm_status gspm_iso_loss(gspm_ctx *ctx, const gspm_gaussians *g, float weight, float *loss_out,
+                                   float *grad_log_scales, void *stream);
+
+/* Covisibility of the views of one forward (supplementary Eq. S1-S2): with G_i the
+ * Gaussians that contribute to at least one pixel of view i, iou_out[i][j] =
+ * |G_i & G_j| / |G_i | G_j| and oc_out[i][j] = |G_i & G_j| / min(|G_i|, |G_j|) (0 for an
+ * empty denominator); count_out[i] = |G_i| (may be NULL).  Device float64 [V][V] and
+ * int64 [V], overwritten.  The forward must have run with settings.mark_visible != 0;
+ * otherwise the outputs are NaN and count_out is -1.  frame_state and views are those of
+ * that forward (n_gaussians its Gaussian count). */
+GSPM_API gspm_status gspm_covisibility(gspm_ctx *ctx, const gspm_views *views, int64_t n_gaussians,
+                                       const void *frame_state, double *iou_out, double *oc_out,
+                                       int64_t *count_out, void *stream);
+
+/* Median of the positive values of each view's depth image (the lower middle value for
+ * an even count, 0 for a view without positive depth): the median pointmap depth of the
+ * keyframe rule.  depth: packed [H][W] per view; median_out: device float [V]. */
+GSPM_API gspm_status gspm_median_depth(gspm_ctx *ctx, const gspm_views *views, const float *depth,
+                                       float *median_out, void *stream);
 
 /* T_cw[v] <- Exp(xi[v]) T_cw[v] for every view (device arrays [V][12], [V][6]). */
 GSPM_API gspm_status gspm_pose_retract(int32_t n_views, float *T_cw, const float *xi, void *stream);

@@ -53,7 +53,7 @@ class Settings(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("sort_digit_bits", ctypes.c_int32), ("pointmap_frame", ctypes.c_int32),
                 ("pixels_per_lane", ctypes.c_int32), ("near_z", ctypes.c_float), ("alpha_min", ctypes.c_float),
                 ("alpha_max", ctypes.c_float), ("t_min", ctypes.c_float), ("eps2d", ctypes.c_float),
-                ("jac_clamp", ctypes.c_float), ("bg", ctypes.c_float * 3)]
+                ("jac_clamp", ctypes.c_float), ("bg", ctypes.c_float * 3), ("mark_visible", ctypes.c_int32)]
 
 
 class Images(ctypes.Structure):
@@ -93,7 +93,8 @@ EXPORTS = (
     "gspm_create", "gspm_destroy", "gspm_reserve", "gspm_frame_state_bytes", "gspm_render_forward",
     "gspm_frame_status", "gspm_render_backward", "gspm_pose_backward", "gspm_patch_scale_align",
     "gspm_window_loss", "gspm_pose_retract", "gspm_timing_enable", "gspm_timing_collect", "gspm_frame_work",
-    "gspm_last_error", "gspm_version", "gspm_align_scale", "gspm_replace_pointmap",
+    "gspm_last_error", "gspm_version", "gspm_align_scale", "gspm_replace_pointmap", "gspm_iso_loss",
+    "gspm_covisibility", "gspm_median_depth",
 )
 
 PHASES = ("preprocess", "depth_sort", "binning", "tile_sort", "raster_fwd", "raster_bwd", "param_bwd")
@@ -126,6 +127,9 @@ def load(path: str = LIB_PATH):
     L.gspm_pose_retract.argtypes = [ctypes.c_int32, vp, vp, vp]
     L.gspm_align_scale.argtypes = [vp, P(Views), vp, vp, vp, P(AlignParams), vp, vp]
     L.gspm_replace_pointmap.argtypes = [P(Views), vp, vp, vp, ctypes.c_float, vp, vp, vp]
+    L.gspm_iso_loss.argtypes = [vp, P(Gaussians), ctypes.c_float, vp, vp, vp]
+    L.gspm_covisibility.argtypes = [vp, P(Views), ctypes.c_int64, vp, vp, vp, vp, vp]
+    L.gspm_median_depth.argtypes = [vp, P(Views), vp, vp, vp]
     L.gspm_frame_work.argtypes = [vp, P(Views), ctypes.c_int64, ctypes.c_int32, vp, vp, P(ctypes.c_int64)]
     L.gspm_timing_enable.argtypes = [vp, ctypes.c_int32]
     L.gspm_timing_collect.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
@@ -171,11 +175,13 @@ class RasterConfig:
     eps2d: float = 0.3
     jac_clamp: float = 1.3
     bg: tuple = (0.0, 0.0, 0.0)
+    mark_visible: int = 0
 
     def c(self) -> Settings:
         return Settings(self.tile, self.sort_digit_bits, self.pointmap_frame, self.pixels_per_lane, self.near_z,
                         self.alpha_min,
-                        self.alpha_max, self.t_min, self.eps2d, self.jac_clamp, (ctypes.c_float * 3)(*self.bg))
+                        self.alpha_max, self.t_min, self.eps2d, self.jac_clamp, (ctypes.c_float * 3)(*self.bg),
+                        int(self.mark_visible))
 
     # Supported (tile, pixels_per_lane) launch shapes of the raster kernels.
     SHAPES = ((8, 1), (16, 1), (16, 2), (16, 4), (32, 1), (32, 2), (32, 4))
@@ -294,6 +300,19 @@ def align_scale(ctx: Context, views: Views, Xr, Xp, mask, params: AlignParams, r
 def replace_pointmap(views: Views, Xr, Xp, result, eps_m, Xr_hat, replaced_out, stream):
     check(load().gspm_replace_pointmap(ctypes.byref(views), ptr(Xr), ptr(Xp), ptr(result), float(eps_m), ptr(Xr_hat),
                                        ptr(replaced_out), stream))
+
+
+def iso_loss(ctx: Context, g: Gaussians, weight, loss_out, grad_log_scales, stream):
+    check(load().gspm_iso_loss(ctx.h, ctypes.byref(g), float(weight), ptr(loss_out), ptr(grad_log_scales), stream))
+
+
+def covisibility(ctx: Context, views: Views, n, frame_state, iou_out, oc_out, count_out, stream):
+    check(load().gspm_covisibility(ctx.h, ctypes.byref(views), int(n), ptr(frame_state), ptr(iou_out), ptr(oc_out),
+                                   ptr(count_out), stream))
+
+
+def median_depth(ctx: Context, views: Views, depth, median_out, stream):
+    check(load().gspm_median_depth(ctx.h, ctypes.byref(views), ptr(depth), ptr(median_out), stream))
 
 
 def pose_retract(n_views, T_cw, xi, stream):

@@ -72,7 +72,7 @@ struct gspm_ctx {
     // Per pair (capacity).
     DevBuf pkey, pval, pkey_tmp, pval_tmp, pkey_s;
     // Small scratch.
-    DevBuf hist, scan_part, misc, pose_part, loss_part, align;
+    DevBuf hist, scan_part, misc, pose_part, loss_part, align, aux;
 };
 
 namespace {
@@ -185,6 +185,7 @@ gspm_status prepare(const gspm_gaussians *g, const gspm_views *views, const gspm
     P.rs.jac_clamp = s->jac_clamp;
     P.rs.bg[0] = s->bg[0]; P.rs.bg[1] = s->bg[1]; P.rs.bg[2] = s->bg[2];
     P.rs.frame = s->pointmap_frame;
+    P.rs.mark_visible = s->mark_visible != 0 ? 1 : 0;
     return GSPM_OK;
 }
 
@@ -286,7 +287,7 @@ void gspm_destroy(gspm_ctx *ctx) {
     DevBuf *bufs[] = {&ctx->counts, &ctx->big, &ctx->live, &ctx->dkey, &ctx->dval, &ctx->dkey_tmp, &ctx->dval_tmp,
                       &ctx->dkey_s, &ctx->dval_s, &ctx->offsets, &ctx->grad2d, &ctx->pkey, &ctx->pval,
                       &ctx->pkey_tmp, &ctx->pval_tmp, &ctx->pkey_s, &ctx->hist, &ctx->scan_part, &ctx->misc,
-                      &ctx->pose_part, &ctx->loss_part, &ctx->align};
+                      &ctx->pose_part, &ctx->loss_part, &ctx->align, &ctx->aux};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
@@ -403,11 +404,16 @@ gspm_status gspm_render_forward(gspm_ctx *ctx, const gspm_gaussians *g, const gs
         PhaseTimer t_rg(ctx, hs, GSPM_PHASE_BINNING);
         GSPM_HIP(launch_ranges(static_cast<uint32_t *>(ctx->pkey_s.p), hdr, ranges, P.n_tiles, cap, hs));
     }
-    // 7. Composite.
+    // 7. Composite (optionally marking the records that contribute to a pixel).
+    uint8_t *visible = nullptr;
+    if (P.rs.mark_visible) {
+        visible = at<uint8_t>(frame_state, L0.visible);
+        GSPM_HIP(launch_fill_u32(reinterpret_cast<uint32_t *>(visible), 0u, (R + 3) / 4, hs));
+    }
     PhaseTimer t_fwd(ctx, hs, GSPM_PHASE_RASTER_FWD);
     GSPM_HIP(launch_raster_forward(P.vt, P.rs, ranges, pair_vals, records, out->rgb, out->depth, out->alpha,
                                    out->pointmap, at<float>(frame_state, L0.t_final), at<uint32_t>(frame_state, L0.last),
-                                   at<uint32_t>(frame_state, L0.contrib), hs));
+                                   at<uint32_t>(frame_state, L0.contrib), visible, hs));
     return GSPM_OK;
 }
 
@@ -534,6 +540,51 @@ gspm_status gspm_replace_pointmap(const gspm_views *views, const float *Xr, cons
     if (st) return st;
     GSPM_HIP(launch_replace(vt, Xr, Xp, result, eps_m, Xr_hat, reinterpret_cast<uint32_t *>(replaced_out),
                             reinterpret_cast<hipStream_t>(stream)));
+    return GSPM_OK;
+}
+
+gspm_status gspm_iso_loss(gspm_ctx *ctx, const gspm_gaussians *g, float weight, float *loss_out,
+                          float *grad_log_scales, void *stream) {
+    if (!ctx) return fail(GSPM_ERR_INVALID_ARG, "ctx is NULL");
+    if (!g || g->n < 0 || (g->n > 0 && !g->log_scales)) return fail(GSPM_ERR_INVALID_ARG, "Gaussians are invalid");
+    if (!loss_out) return fail(GSPM_ERR_INVALID_ARG, "loss_out is required");
+    if (!std::isfinite(weight)) return fail(GSPM_ERR_INVALID_ARG, "weight must be finite");
+    GSPM_HIP(grow(ctx->aux, 8 * iso_partials()));
+    GSPM_HIP(launch_iso_loss(g->log_scales, g->n, weight, static_cast<double *>(ctx->aux.p), loss_out,
+                             grad_log_scales, reinterpret_cast<hipStream_t>(stream)));
+    return GSPM_OK;
+}
+
+gspm_status gspm_covisibility(gspm_ctx *ctx, const gspm_views *views, int64_t n_gaussians, const void *frame_state,
+                              double *iou_out, double *oc_out, int64_t *count_out, void *stream) {
+    if (!ctx) return fail(GSPM_ERR_INVALID_ARG, "ctx is NULL");
+    if (!frame_state || !iou_out || !oc_out) return fail(GSPM_ERR_INVALID_ARG, "frame_state, iou_out, oc_out required");
+    if (n_gaussians < 0) return fail(GSPM_ERR_INVALID_ARG, "n_gaussians < 0");
+    ViewTable vt;
+    int64_t nt, np;
+    gspm_status st = build_views(views, 16, vt, nt, np);
+    if (st) return st;
+    const FrameLayout L = frame_layout(0, 0, n_gaussians * vt.n_views, 0);
+    const int V = vt.n_views;
+    GSPM_HIP(grow(ctx->aux, 8 * (int64_t)V * V));
+    GSPM_HIP(launch_covisibility(at<uint8_t>(frame_state, L.visible), n_gaussians, V,
+                                 at<FrameHeader>(frame_state, L.header),
+                                 static_cast<unsigned long long *>(ctx->aux.p), iou_out, oc_out, count_out,
+                                 reinterpret_cast<hipStream_t>(stream)));
+    return GSPM_OK;
+}
+
+gspm_status gspm_median_depth(gspm_ctx *ctx, const gspm_views *views, const float *depth, float *median_out,
+                              void *stream) {
+    if (!ctx) return fail(GSPM_ERR_INVALID_ARG, "ctx is NULL");
+    if (!depth || !median_out) return fail(GSPM_ERR_INVALID_ARG, "depth and median_out are required");
+    ViewTable vt;
+    int64_t nt, np;
+    gspm_status st = build_views(views, 16, vt, nt, np);
+    if (st) return st;
+    GSPM_HIP(grow(ctx->aux, 4 * median_scratch_words(vt.n_views)));
+    GSPM_HIP(launch_median_depth(vt, depth, static_cast<uint32_t *>(ctx->aux.p), median_out,
+                                 reinterpret_cast<hipStream_t>(stream)));
     return GSPM_OK;
 }
 

@@ -272,6 +272,7 @@ k_keygen(const uint32_t *__restrict__ sorted_rec, const uint32_t *__restrict__ s
         hdr->overflow = t > cap ? 1u : 0u;
         hdr->capacity = cap;
         hdr->magic = kFrameMagic;
+        hdr->visible = (uint32_t)rs.mark_visible;
     }
     uint32_t r = 0, c = 0;
     if (p < n_records) {

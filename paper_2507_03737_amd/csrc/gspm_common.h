@@ -30,6 +30,7 @@ struct RasterSettings {
     float near_z, alpha_min, alpha_max, t_min, eps2d, jac_clamp;
     float bg[3];
     int32_t frame;  // 0 world, 1 camera, 2 depth back-projection
+    int32_t mark_visible;
 };
 
 // Projected record of one (Gaussian, view) pair: 64 bytes, 4 x float4.
@@ -59,12 +60,13 @@ struct FrameHeader {
     uint64_t n_pixels;
     uint64_t n_records;
     uint32_t magic;
-    uint32_t pad[5];
+    uint32_t visible;  // nonzero if the forward marked contributing records
+    uint32_t pad[4];
 };
 constexpr uint32_t kFrameMagic = 0x47535046u;  // "GSPF"
 
 struct FrameLayout {
-    int64_t header, ranges, t_final, last, contrib, records, pair_vals, total;
+    int64_t header, visible, ranges, t_final, last, contrib, records, pair_vals, total;
 };
 
 inline int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
@@ -73,6 +75,7 @@ inline FrameLayout frame_layout(int64_t n_tiles, int64_t n_pixels, int64_t n_rec
     FrameLayout L;
     int64_t o = 0;
     L.header = o;    o += align256(sizeof(FrameHeader));
+    L.visible = o;   o += align256(n_records);  // one byte per record (offset independent of the tile)
     L.ranges = o;    o += align256(n_tiles * 8);
     L.t_final = o;   o += align256(n_pixels * 4);
     L.last = o;      o += align256(n_pixels * 4);
@@ -321,6 +324,17 @@ hipError_t launch_align_scale(const ViewTable &vt, const float *Xr, const float 
 hipError_t launch_replace(const ViewTable &vt, const float *Xr, const float *Xp, const gspm_align_result *result,
                           float eps_m, float *out, uint32_t *replaced, hipStream_t s);
 
+// Regulariser and window management (window.hip).
+int64_t iso_partials();
+hipError_t launch_iso_loss(const float *log_scales, int64_t n, float weight, double *part, float *loss_out,
+                           float *grad, hipStream_t s);
+hipError_t launch_covisibility(const uint8_t *visible, int64_t n, int V, const FrameHeader *hdr,
+                               unsigned long long *counts, double *iou, double *oc, int64_t *count_out,
+                               hipStream_t s);
+int64_t median_scratch_words(int V);
+hipError_t launch_median_depth(const ViewTable &vt, const float *depth, uint32_t *scratch, float *out,
+                               hipStream_t s);
+
 hipError_t launch_ranges(const uint32_t *sorted_keys, const FrameHeader *hdr, uint2 *ranges,
                          int64_t n_tiles, int64_t n_max, hipStream_t s);
 
@@ -329,7 +343,7 @@ bool raster_config_supported(int tile, int ppt);
 hipError_t launch_raster_forward(const ViewTable &vt, const RasterSettings &rs, const uint2 *ranges,
                                  const uint32_t *pair_vals, const float *records, float *rgb,
                                  float *depth, float *alpha, float *pointmap, float *t_final,
-                                 uint32_t *last, uint32_t *contrib, hipStream_t s);
+                                 uint32_t *last, uint32_t *contrib, uint8_t *visible, hipStream_t s);
 
 hipError_t launch_raster_backward(const ViewTable &vt, const RasterSettings &rs, const uint2 *ranges,
                                   const uint32_t *pair_vals, const float *records, const uint32_t *last,

@@ -143,7 +143,7 @@ __global__ void __launch_bounds__(TILE *TILE / PPT)
 k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
              const float4 *__restrict__ rec, float *__restrict__ out_rgb, float *__restrict__ out_depth,
              float *__restrict__ out_alpha, float *__restrict__ out_pm, float *__restrict__ t_final,
-             uint32_t *__restrict__ last, uint32_t *__restrict__ contrib) {
+             uint32_t *__restrict__ last, uint32_t *__restrict__ contrib, uint8_t *__restrict__ visible) {
     using L = Layout<TILE, PPT>;
     constexpr int NT = L::NT;
     __shared__ float4 s0[NT], s1[NT], s2[NT], s3[NT];
@@ -203,6 +203,7 @@ k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
                 const float4 cc = s2[q];
                 const float4 d = s3[q];
                 const uint32_t rel = base - rg.x + (uint32_t)q + 1u;
+                bool added = false;
 #pragma unroll
                 for (int k = 0; k < PPT; ++k) {
                     const float al = fminf(amax, b.z * __builtin_amdgcn_exp2f(e[k]));
@@ -221,6 +222,10 @@ k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
                     n_last[k] = add ? rel : n_last[k];
                     n_contrib[k] += add ? 1u : 0u;
                     done[k] = done[k] || stop;
+                    added |= add;
+                }
+                if (visible) {  // uniform: marking requested
+                    if (__ballot(added) != 0ull && lane_id() == 0) visible[__float_as_uint(b.w)] = 1;
                 }
             }
             wave_live = __ballot(lane_live()) != 0ull;
@@ -423,13 +428,13 @@ bool raster_config_supported(int tile, int ppt) {
 hipError_t launch_raster_forward(const ViewTable &vt, const RasterSettings &rs, const uint2 *ranges,
                                  const uint32_t *pair_vals, const float *records, float *rgb, float *depth,
                                  float *alpha, float *pointmap, float *t_final, uint32_t *last, uint32_t *contrib,
-                                 hipStream_t s) {
+                                 uint8_t *visible, hipStream_t s) {
     const int n_tiles = vt.tile_off[vt.n_views];
     const float4 *rec = reinterpret_cast<const float4 *>(records);
 #define GSPM_FWD(T_, P_)                                                                                    \
     if (vt.tile == T_ && vt.ppt == P_) {                                                                    \
         hipLaunchKernelGGL((k_raster_fwd<T_, P_>), dim3(n_tiles), dim3(T_ * T_ / P_), 0, s, vt, rs, ranges, \
-                           pair_vals, rec, rgb, depth, alpha, pointmap, t_final, last, contrib);            \
+                           pair_vals, rec, rgb, depth, alpha, pointmap, t_final, last, contrib, visible);            \
         return hipGetLastError();                                                                           \
     }
     GSPM_RASTER_CONFIGS(GSPM_FWD)

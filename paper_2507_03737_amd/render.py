@@ -168,6 +168,28 @@ class Rasterizer:
         B.replace_pointmap(self.win.c(), Xr, Xp, result, eps_m, Xr_hat, replaced, B.stream_handle(stream))
 
 
+    # -- regulariser and keyframe window ---------------------------------------------------
+    def iso_loss_into(self, params, weight, loss, grad_log_scales=None, stream=None):
+        """Eq. 16 times weight into loss [1]; its gradient is added to grad_log_scales."""
+        B.iso_loss(self.ctx, _params(params), weight, loss, grad_log_scales, B.stream_handle(stream))
+
+    def covisibility(self, frame_state, stream=None):
+        """(iou [V][V], oc [V][V], visible counts [V]) of a forward run with mark_visible."""
+        V = self.win.n_views
+        dev = self.win.T_cw.device
+        iou = torch.empty(V, V, dtype=torch.float64, device=dev)
+        oc = torch.empty_like(iou)
+        cnt = torch.empty(V, dtype=torch.int64, device=dev)
+        B.covisibility(self.ctx, self.win.c(), self.n, frame_state, iou, oc, cnt, B.stream_handle(stream))
+        return iou, oc, cnt
+
+    def median_depth(self, depth, stream=None):
+        """Median positive depth of each view (packed depth planes) -> float32 [V]."""
+        out = torch.empty(self.win.n_views, device=self.win.T_cw.device)
+        B.median_depth(self.ctx, self.win.c(), depth, out, B.stream_handle(stream))
+        return out
+
+
 def align_results(result: torch.Tensor):
     """Host view of a device gspm_align_result array (synchronises)."""
     return result.cpu().numpy().view(B.ALIGN_RESULT_DTYPE)

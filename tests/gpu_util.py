@@ -98,6 +98,7 @@ def frame_layout(n_tiles, n_pixels, n_records):
     o = 0
     lay = {}
     lay["header"] = o; o += a(64)
+    lay["visible"] = o; o += a(n_records)
     lay["ranges"] = o; o += a(n_tiles * 8)
     lay["t_final"] = o; o += a(n_pixels * 4)
     lay["last"] = o; o += a(n_pixels * 4)
