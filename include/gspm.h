@@ -260,6 +260,37 @@ GSPM_API gspm_status gspm_replace_pointmap(const gspm_views *views, const float 
                                            const gspm_align_result *result, float eps_m, float *Xr_hat,
                                            int32_t *replaced_out, void *stream);
 
+/* ---- pose initialisation (Sec. 3.2.1, Eq. 6-9) ------------------------------------- */
+
+/* RANSAC + PnP parameters. */
+typedef struct {
+    int32_t n_hypotheses; /* H: rows of the sample array, >= 1 */
+    float threshold;      /* inlier reprojection error in pixels, > 0 */
+    int32_t iterations;   /* Gauss-Newton steps per refinement round, >= 0 */
+    int32_t rounds;       /* refinement rounds; the inliers are re-selected after each, >= 0 */
+} gspm_pnp_params;
+
+/* Relative pose T (frame A -> camera frame B, T_n = T T_ak) from n 2D-3D correspondences:
+ * X [3][n] points in frame A (the rendered pointmap of the adjacent keyframe), uv [2][n]
+ * pixels of frame B with intrinsics K (host).  samples: device int32 [H][6] indices drawn
+ * by the caller (out-of-range rows give invalid hypotheses).  Each hypothesis is the
+ * linear six-point PnP on its sample (points centred and scaled, eigenvector of least
+ * eigenvalue, det > 0, nearest rotation, mean singular value as the scale); it scores the
+ * correspondences with positive depth and reprojection error < threshold; the best (ties
+ * to the lowest index) is refined by Gauss-Newton on the squared reprojection errors of its
+ * inliers, with T <- Exp(xi) T and damping 1e-9 trace(J^T J) / 6, inliers re-selected
+ * after each round.  Outputs (device): T_out float64 [12] row-major [R | t], n_inliers
+ * int32 [1], inlier_mask uint8 [n] (may be NULL), scores int32 [H] (may be NULL; -1 for an
+ * invalid hypothesis).  With T_ak (device float [12], the adjacent keyframe's world->camera
+ * pose) and T_n_out (device float [12]) both non-NULL, the new frame's pose T_n = T T_ak
+ * (Eq. 9) is written too.  All arithmetic after the float32 loads is float64.  The context
+ * provides scratch (104 bytes per hypothesis). */
+GSPM_API gspm_status gspm_pnp_ransac(gspm_ctx *ctx, const float *X, const float *uv, int64_t n,
+                                     const gspm_intrinsics *K, const int32_t *samples,
+                                     const gspm_pnp_params *params, double *T_out, int32_t *n_inliers,
+                                     uint8_t *inlier_mask, int32_t *scores, const float *T_ak, float *T_n_out,
+                                     void *stream);
+
 /* ---- regulariser and keyframe window (Sec. 3.3.3 Eq. 16; supplementary Eq. S1-S2) -- */
 
 /* Isotropic regulariser of Eq. 16: loss = weight * sum_i sum_k |s_ik - mean_k s_ik| with

@@ -64,6 +64,11 @@ class GaussianGrads(ctypes.Structure):
     _fields_ = [("means", vp), ("log_scales", vp), ("quats", vp), ("opacity_logit", vp), ("rgb", vp)]
 
 
+class PnpParams(ctypes.Structure):
+    _fields_ = [("n_hypotheses", ctypes.c_int32), ("threshold", ctypes.c_float), ("iterations", ctypes.c_int32),
+                ("rounds", ctypes.c_int32)]
+
+
 class AlignParams(ctypes.Structure):
     _fields_ = [("patch", ctypes.c_int32), ("delta_mu", ctypes.c_float), ("delta_sigma", ctypes.c_float),
                 ("eps_r", ctypes.c_float), ("max_iter", ctypes.c_int32), ("tau", ctypes.c_float)]
@@ -94,7 +99,7 @@ EXPORTS = (
     "gspm_frame_status", "gspm_render_backward", "gspm_pose_backward", "gspm_patch_scale_align",
     "gspm_window_loss", "gspm_pose_retract", "gspm_timing_enable", "gspm_timing_collect", "gspm_frame_work",
     "gspm_last_error", "gspm_version", "gspm_align_scale", "gspm_replace_pointmap", "gspm_iso_loss",
-    "gspm_covisibility", "gspm_median_depth",
+    "gspm_covisibility", "gspm_median_depth", "gspm_pnp_ransac",
 )
 
 PHASES = ("preprocess", "depth_sort", "binning", "tile_sort", "raster_fwd", "raster_bwd", "param_bwd")
@@ -130,6 +135,8 @@ def load(path: str = LIB_PATH):
     L.gspm_iso_loss.argtypes = [vp, P(Gaussians), ctypes.c_float, vp, vp, vp]
     L.gspm_covisibility.argtypes = [vp, P(Views), ctypes.c_int64, vp, vp, vp, vp, vp]
     L.gspm_median_depth.argtypes = [vp, P(Views), vp, vp, vp]
+    L.gspm_pnp_ransac.argtypes = [vp, vp, vp, ctypes.c_int64, P(Intrinsics), vp, P(PnpParams), vp, vp, vp, vp, vp,
+                                  vp, vp]
     L.gspm_frame_work.argtypes = [vp, P(Views), ctypes.c_int64, ctypes.c_int32, vp, vp, P(ctypes.c_int64)]
     L.gspm_timing_enable.argtypes = [vp, ctypes.c_int32]
     L.gspm_timing_collect.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
@@ -313,6 +320,13 @@ def covisibility(ctx: Context, views: Views, n, frame_state, iou_out, oc_out, co
 
 def median_depth(ctx: Context, views: Views, depth, median_out, stream):
     check(load().gspm_median_depth(ctx.h, ctypes.byref(views), ptr(depth), ptr(median_out), stream))
+
+
+def pnp_ransac(ctx: Context, X, uv, K: Intrinsics, samples, params: PnpParams, T_out, n_inliers, mask, scores,
+               T_ak, T_n_out, stream):
+    check(load().gspm_pnp_ransac(ctx.h, ptr(X), ptr(uv), int(X.shape[-1]), ctypes.byref(K), ptr(samples),
+                                 ctypes.byref(params), ptr(T_out), ptr(n_inliers), ptr(mask), ptr(scores),
+                                 ptr(T_ak), ptr(T_n_out), stream))
 
 
 def pose_retract(n_views, T_cw, xi, stream):

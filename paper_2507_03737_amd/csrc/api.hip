@@ -72,7 +72,7 @@ struct gspm_ctx {
     // Per pair (capacity).
     DevBuf pkey, pval, pkey_tmp, pval_tmp, pkey_s;
     // Small scratch.
-    DevBuf hist, scan_part, misc, pose_part, loss_part, align, aux;
+    DevBuf hist, scan_part, misc, pose_part, loss_part, align, aux, pnp;
 };
 
 namespace {
@@ -287,7 +287,7 @@ void gspm_destroy(gspm_ctx *ctx) {
     DevBuf *bufs[] = {&ctx->counts, &ctx->big, &ctx->live, &ctx->dkey, &ctx->dval, &ctx->dkey_tmp, &ctx->dval_tmp,
                       &ctx->dkey_s, &ctx->dval_s, &ctx->offsets, &ctx->grad2d, &ctx->pkey, &ctx->pval,
                       &ctx->pkey_tmp, &ctx->pval_tmp, &ctx->pkey_s, &ctx->hist, &ctx->scan_part, &ctx->misc,
-                      &ctx->pose_part, &ctx->loss_part, &ctx->align, &ctx->aux};
+                      &ctx->pose_part, &ctx->loss_part, &ctx->align, &ctx->aux, &ctx->pnp};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
@@ -540,6 +540,28 @@ gspm_status gspm_replace_pointmap(const gspm_views *views, const float *Xr, cons
     if (st) return st;
     GSPM_HIP(launch_replace(vt, Xr, Xp, result, eps_m, Xr_hat, reinterpret_cast<uint32_t *>(replaced_out),
                             reinterpret_cast<hipStream_t>(stream)));
+    return GSPM_OK;
+}
+
+gspm_status gspm_pnp_ransac(gspm_ctx *ctx, const float *X, const float *uv, int64_t n, const gspm_intrinsics *K,
+                            const int32_t *samples, const gspm_pnp_params *prm, double *T_out, int32_t *n_inliers,
+                            uint8_t *inlier_mask, int32_t *scores, const float *T_ak, float *T_n_out,
+                            void *stream) {
+    if (!ctx) return fail(GSPM_ERR_INVALID_ARG, "ctx is NULL");
+    if (!X || !uv || !K || !samples || !prm || !T_out || !n_inliers)
+        return fail(GSPM_ERR_INVALID_ARG, "X, uv, K, samples, params, T_out and n_inliers are required");
+    if (n < 6 || n > (1ll << 31)) return fail(GSPM_ERR_INVALID_ARG, "n = %lld outside [6, 2^31]", (long long)n);
+    if (prm->n_hypotheses < 1 || prm->n_hypotheses > (1 << 20))
+        return fail(GSPM_ERR_INVALID_ARG, "n_hypotheses = %d outside [1, 2^20]", prm->n_hypotheses);
+    if (!(prm->threshold > 0.0f) || !std::isfinite(prm->threshold) || prm->iterations < 0 || prm->rounds < 0)
+        return fail(GSPM_ERR_INVALID_ARG, "threshold must be > 0, iterations and rounds >= 0");
+    if (!finite_pos(K->fx) || !finite_pos(K->fy) || !std::isfinite(K->cx) || !std::isfinite(K->cy))
+        return fail(GSPM_ERR_INVALID_ARG, "invalid intrinsics");
+    GSPM_HIP(grow(ctx->pnp, pnp_scratch_bytes(prm->n_hypotheses)));
+    GSPM_HIP(launch_pnp(X, uv, n, *K, samples, prm->n_hypotheses, (double)prm->threshold, prm->iterations,
+                        prm->rounds, ctx->pnp.p, T_out, n_inliers, inlier_mask, scores,
+                        (T_ak && T_n_out) ? T_ak : nullptr, (T_ak && T_n_out) ? T_n_out : nullptr,
+                        reinterpret_cast<hipStream_t>(stream)));
     return GSPM_OK;
 }
 
