@@ -120,6 +120,85 @@ def copy_calibration(torch, dev):
     del src, dst
 
 
+def time_ms(fn, reps, torch):
+    """Average milliseconds of fn over reps launches on the current stream (after 2 warm-ups)."""
+    for _ in range(2):
+        fn()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        fn()
+    t1.record()
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1) / reps
+
+
+def time_mapping_ops(rast, step, win, sc, opt, cfg, torch, dev, reps=20):
+    """Milliseconds and HBM rates of the mapping-side operations on the same window: scale
+    alignment and pointmap replacement of the prior against the rendered pointmap, the
+    isotropic regulariser, keyframe covisibility, median depth, and RANSAC + PnP between two
+    views of the window (20k correspondences from the rendered pointmap, 20% outliers)."""
+    import dataclasses
+    from paper_2507_03737_amd import binding as B
+    from paper_2507_03737_amd.render import Rasterizer
+    from paper_2507_03737_amd.tracking import PnpConfig, draw_samples, pnp_ransac
+
+    P = win.n_pixels
+    R = sc.n * win.n_views
+    out = {}
+    pm, prior = step.out["pointmap"], step.prior
+    res = rast.new_align_result()
+    ms = time_ms(lambda: rast.align_scale_into(pm, prior, res), reps, torch)
+    out["align_scale"] = {"ms": ms, "GB/s": 24 * P / (ms * 1e-3) / 1e9, "bytes": "24 B/px (Xr, Xp read once)"}
+    hat = torch.empty_like(pm)
+    rep = torch.empty(win.n_views, dtype=torch.int32, device=dev)
+    ms = time_ms(lambda: rast.replace_pointmap_into(pm, prior, res, hat, rep), reps, torch)
+    out["replace_pointmap"] = {"ms": ms, "GB/s": 36 * P / (ms * 1e-3) / 1e9, "bytes": "24 B/px read + 12 B/px written"}
+    loss = torch.empty(1, device=dev)
+    g = torch.zeros(3, sc.n, device=dev)
+    ms = time_ms(lambda: rast.iso_loss_into(opt, 10.0, loss, g), reps, torch)
+    out["iso_loss"] = {"ms": ms, "GB/s": 36 * sc.n / (ms * 1e-3) / 1e9,
+                       "bytes": "12 B/Gaussian read + 12 B/Gaussian gradient read and written"}
+    rv = Rasterizer(win, sc.n, dataclasses.replace(cfg, mark_visible=1))
+    rv.max_pairs = rast.max_pairs
+    o, fs = rv.forward(opt)
+    ms = time_ms(lambda: rv.covisibility(fs), reps, torch)
+    out["covisibility"] = {"ms": ms, "GB/s": R / (ms * 1e-3) / 1e9, "bytes": "1 B/record"}
+    del rv, o, fs
+    ms = time_ms(lambda: rast.median_depth(step.out["depth"]), reps, torch)
+    out["median_depth"] = {"ms": ms, "GB/s": 4 * P / (ms * 1e-3) / 1e9, "bytes": "4 B/px"}
+    # PnP: view 0's rendered points seen from view 1 (true relative pose), 1 px noise, 20% outliers.
+    h0, w0 = win.sizes[0]
+    X0 = step.out["pointmap"][:3 * h0 * w0].view(3, -1)
+    A = step.out["alpha"][:h0 * w0]
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(77)
+    idx = torch.nonzero(A > 0.5).flatten()
+    idx = idx[torch.randperm(idx.numel(), device=dev, generator=gen)[:20000]]
+    X = X0[:, idx].contiguous()
+    T0 = win.T_cw[0].double().view(3, 4)
+    T1 = win.T_cw[1].double().view(3, 4)
+    Rr = T1[:, :3] @ T0[:, :3].T
+    tr = T1[:, 3] - Rr @ T0[:, 3]
+    Y = Rr @ X.double() + tr[:, None]
+    c1 = win.cams[1]
+    uv = torch.stack([c1.fx * Y[0] / Y[2] + c1.cx, c1.fy * Y[1] / Y[2] + c1.cy])
+    uv = uv + torch.randn(uv.shape, device=dev, generator=gen, dtype=torch.float64)
+    bad = torch.rand(uv.shape[1], device=dev, generator=gen) < 0.2
+    uv[:, bad] += 50.0 + 100.0 * torch.rand((2, int(bad.sum())), device=dev, generator=gen, dtype=torch.float64)
+    uv = uv.float().contiguous()
+    pcfg = PnpConfig(n_hypotheses=1024, threshold=3.0)
+    samples = draw_samples(X.shape[1], pcfg.n_hypotheses, generator=gen, device=dev)
+    ctx = B.Context()
+    ms = time_ms(lambda: pnp_ransac(X, uv, c1, samples, pcfg, ctx=ctx), 5, torch)
+    T, cnt, _, _, _ = pnp_ransac(X, uv, c1, samples, pcfg, ctx=ctx)
+    err_t = float(torch.linalg.norm(T[:, 3] - tr).item())
+    out["pnp_ransac"] = {"ms": ms, "correspondences": int(X.shape[1]), "hypotheses": pcfg.n_hypotheses,
+                         "inliers": int(cnt.item()), "translation_error_m": err_t}
+    return out
+
+
 def time_steps(fn, steps, warmup, torch):
     for _ in range(warmup):
         fn()
@@ -185,6 +264,7 @@ def main():
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--cpu-px", type=int, default=2048, help="pixels in the CPU-baseline sample")
+    ap.add_argument("--no-extras", action="store_true", help="skip timing the mapping-side operations")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a copy of known size (for scaling HBM traffic counters)")
     args = ap.parse_args()
@@ -296,6 +376,11 @@ def main():
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None, "algorithmic": f"{nbytes} bytes"}
     roof["kernel_ms"] = ph_ms[dominant]
 
+    mapping_ops = None
+    if not args.no_extras:
+        log("[bench] mapping-side operations")
+        mapping_ops = time_mapping_ops(rast, step, win, sc, opt, cfg, torch, dev)
+
     cpu = None
     if not args.no_cpu:
         log("[bench] CPU oracle baseline")
@@ -339,6 +424,7 @@ def main():
         "roofline": roof,
         "memory": memory,
         "cpu_baseline": cpu,
+        "mapping_ops": mapping_ops,
         "wall_s_timed": wall,
     }
     print(json.dumps(res), flush=True)

@@ -284,7 +284,7 @@ typedef struct {
  * invalid hypothesis).  With T_ak (device float [12], the adjacent keyframe's world->camera
  * pose) and T_n_out (device float [12]) both non-NULL, the new frame's pose T_n = T T_ak
  * (Eq. 9) is written too.  All arithmetic after the float32 loads is float64.  The context
- * provides scratch (104 bytes per hypothesis). */
+ * provides scratch (104 bytes per hypothesis and 1 byte per correspondence). */
 GSPM_API gspm_status gspm_pnp_ransac(gspm_ctx *ctx, const float *X, const float *uv, int64_t n,
                                      const gspm_intrinsics *K, const int32_t *samples,
                                      const gspm_pnp_params *params, double *T_out, int32_t *n_inliers,

@@ -234,10 +234,11 @@ k_replace(ViewTable vt, const float *__restrict__ Xr, const float *__restrict__ 
     const int W = vt.width[v], H = vt.height[v];
     const int64_t plane = (int64_t)W * H, o3 = 3 * vt.pix_off[v];
     const double s = res[v].scale;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e - threadIdx.x < plane;
-         e += (int64_t)gridDim.x * blockDim.x) {
+    __shared__ uint32_t wave_cnt[256 / kWave];
+    uint32_t cnt = 0u;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < plane; e += (int64_t)gridDim.x * blockDim.x) {
         bool rep = false;
-        if (e < plane) {
+        {
             const int64_t a = o3 + e;
             const double r0 = Xr[a], r1 = Xr[a + plane], r2 = Xr[a + 2 * plane];
             const double h0 = s * (double)Xp[a], h1 = s * (double)Xp[a + plane], h2 = s * (double)Xp[a + 2 * plane];
@@ -248,8 +249,15 @@ k_replace(ViewTable vt, const float *__restrict__ Xr, const float *__restrict__ 
             out[a + plane] = rep ? (float)h1 : (float)r1;
             out[a + 2 * plane] = rep ? (float)h2 : (float)r2;
         }
-        const uint64_t m = __ballot(rep);
-        if (lane_id() == 0 && m) atomicAdd(replaced + v, (uint32_t)__popcll(m));
+        cnt += rep ? 1u : 0u;
+    }
+    // One atomic per workgroup: the per-view counter sees few updates.
+    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
+    if (lane_id() == 0) wave_cnt[threadIdx.x / kWave] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t t = wave_cnt[0] + wave_cnt[1] + wave_cnt[2] + wave_cnt[3];
+        if (t) atomicAdd(replaced + v, t);
     }
 }
 

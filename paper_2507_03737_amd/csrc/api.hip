@@ -557,7 +557,7 @@ gspm_status gspm_pnp_ransac(gspm_ctx *ctx, const float *X, const float *uv, int6
         return fail(GSPM_ERR_INVALID_ARG, "threshold must be > 0, iterations and rounds >= 0");
     if (!finite_pos(K->fx) || !finite_pos(K->fy) || !std::isfinite(K->cx) || !std::isfinite(K->cy))
         return fail(GSPM_ERR_INVALID_ARG, "invalid intrinsics");
-    GSPM_HIP(grow(ctx->pnp, pnp_scratch_bytes(prm->n_hypotheses)));
+    GSPM_HIP(grow(ctx->pnp, pnp_scratch_bytes(prm->n_hypotheses, n)));
     GSPM_HIP(launch_pnp(X, uv, n, *K, samples, prm->n_hypotheses, (double)prm->threshold, prm->iterations,
                         prm->rounds, ctx->pnp.p, T_out, n_inliers, inlier_mask, scores,
                         (T_ak && T_n_out) ? T_ak : nullptr, (T_ak && T_n_out) ? T_n_out : nullptr,

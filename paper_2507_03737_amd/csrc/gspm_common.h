@@ -325,7 +325,7 @@ hipError_t launch_replace(const ViewTable &vt, const float *Xr, const float *Xp,
                           float eps_m, float *out, uint32_t *replaced, hipStream_t s);
 
 // Pose initialisation (pnp.hip).
-int64_t pnp_scratch_bytes(int H);
+int64_t pnp_scratch_bytes(int H, int64_t n);
 hipError_t launch_pnp(const float *X, const float *uv, int64_t n, const gspm_intrinsics &K, const int32_t *samples,
                       int H, double thr, int iters, int rounds, void *scratch, double *T_out, int32_t *n_inliers,
                       uint8_t *mask, int32_t *scores_out, const float *T_ak, float *T_n_out, hipStream_t s);

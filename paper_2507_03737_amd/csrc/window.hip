@@ -113,12 +113,23 @@ k_median_hist(ViewTable vt, const float *__restrict__ depth, int round, const Me
     const uint32_t prefix = round ? st[v].prefix : 0u;
     const int64_t np = (int64_t)vt.width[v] * vt.height[v];
     const float *d = depth + vt.pix_off[v];
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < np; e += (int64_t)gridDim.x * blockDim.x) {
-        const float x = d[e];
-        if (!(x > 0.0f)) continue;
+    // Uniform trip count per wave, so the ballots below see every lane.
+    const int lane = lane_id();
+    for (int64_t e0 = (int64_t)blockIdx.x * blockDim.x; e0 < np; e0 += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t e = e0 + threadIdx.x;
+        const float x = e < np ? d[e] : 0.0f;
         const uint32_t b = __float_as_uint(x);
-        if (round && (b >> (shift + 8)) != prefix) continue;
-        atomicAdd(&h[(b >> shift) & 255u], 1u);
+        const bool valid = x > 0.0f && (round == 0 || (b >> (shift + 8)) == prefix);
+        const uint32_t bin = (b >> shift) & 255u;
+        // Depths cluster in few bins: one LDS atomic per distinct bin of the wave.
+        uint64_t active = __ballot(valid);
+        while (active) {
+            const int leader = __ffsll((unsigned long long)active) - 1;
+            const uint32_t lb = (uint32_t)__shfl((int)bin, leader, kWave);
+            const uint64_t same = __ballot(valid && bin == lb);
+            if (lane == leader) atomicAdd(&h[lb], (uint32_t)__popcll(same));
+            active &= ~same;
+        }
     }
     __syncthreads();
     if (h[threadIdx.x]) atomicAdd(hist + v * 256 + threadIdx.x, h[threadIdx.x]);
