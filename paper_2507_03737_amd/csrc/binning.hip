@@ -122,7 +122,8 @@ k_scan_apply(const uint32_t *__restrict__ counts, const uint32_t *__restrict__ i
 // of equal digits by ballots, then per-digit offsets across the four waves), stages the
 // tile in LDS in sorted order and writes it out so that consecutive lanes write
 // consecutive addresses inside each digit's run.  Grids are fixed; the key count may be
-// read from device memory.
+// read from device memory, and then only its ceil(n / 4096) tiles are histogrammed,
+// scanned and scattered (the histogram stride is that tile count).
 
 constexpr int kSortBlock = 256;
 constexpr int kSortWaves = kSortBlock / kWave;
@@ -135,14 +136,19 @@ __device__ inline int64_t sort_count(const uint32_t *n_dev, int64_t n_max) {
     return n < n_max ? n : n_max;
 }
 
+// Tiles holding the n live keys.
+__device__ inline int64_t sort_active_tiles(int64_t n) { return (n + kSortTile - 1) / kSortTile; }
+
 template <int DB>
 __global__ void __launch_bounds__(kSortBlock)
 k_radix_upsweep(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ n_dev, int64_t n_max, int shift,
-                uint32_t *__restrict__ hist, int64_t n_tiles) {
+                uint32_t *__restrict__ hist, uint32_t *__restrict__ hist_words) {
     constexpr int R = 1 << DB;
     __shared__ uint32_t cnt[kSortWaves][R];
     const int wid = threadIdx.x / kWave, lane = lane_id();
     const int64_t n = sort_count(n_dev, n_max);
+    const int64_t n_tiles = sort_active_tiles(n);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *hist_words = (uint32_t)(R * n_tiles);
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         for (int d = lane; d < R; d += kWave) cnt[wid][d] = 0u;
         __syncthreads();
@@ -163,7 +169,7 @@ template <int DB>
 __global__ void __launch_bounds__(kSortBlock)
 k_radix_downsweep(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
                   uint32_t *__restrict__ vout, const uint32_t *__restrict__ n_dev, int64_t n_max, int shift,
-                  const uint32_t *__restrict__ hist, int64_t n_tiles) {
+                  const uint32_t *__restrict__ hist) {
     constexpr int R = 1 << DB;
     __shared__ uint32_t wcnt[kSortWaves][R];
     __shared__ uint32_t dstart[R];
@@ -174,6 +180,7 @@ k_radix_downsweep(const uint32_t *__restrict__ kin, const uint32_t *__restrict__
     const int wid = threadIdx.x / kWave, lane = lane_id();
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int64_t n = sort_count(n_dev, n_max);
+    const int64_t n_tiles = sort_active_tiles(n);
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const int64_t tile_begin = tile * kSortTile;
         if (tile_begin >= n) break;  // block-uniform; later tiles of this block are empty too
@@ -428,13 +435,13 @@ template <int DB>
 static void sort_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, int64_t n_max,
                       const uint32_t *n_dev, int shift, uint32_t *hist, uint32_t *scan_part, hipStream_t s) {
     const int64_t nb = sort_blocks(n_max);
-    const int64_t nt = sort_tiles(n_max);
+    const int64_t hw = ((int64_t)1 << DB) * sort_tiles(n_max);
+    // hist[hw] receives the scan total, hist[hw + 1] the number of live histogram words.
     hipLaunchKernelGGL(k_radix_upsweep<DB>, dim3((unsigned)nb), dim3(kSortBlock), 0, s, kin, n_dev, n_max, shift,
-                       hist, nt);
-    const int64_t hw = ((int64_t)1 << DB) * nt;
-    (void)launch_scan_indirect(hist, nullptr, hw, hist, hist + hw, scan_part, s, nullptr, 0);
+                       hist, hist + hw + 1);
+    (void)launch_scan_indirect(hist, nullptr, hw, hist, hist + hw, scan_part, s, hist + hw + 1, 0);
     hipLaunchKernelGGL(k_radix_downsweep<DB>, dim3((unsigned)nb), dim3(kSortBlock), 0, s, kin, vin, kout, vout,
-                       n_dev, n_max, shift, hist, nt);
+                       n_dev, n_max, shift, hist);
 }
 
 hipError_t radix_sort(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_tmp, uint32_t *vals_tmp,
