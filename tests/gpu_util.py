@@ -3,7 +3,10 @@
 Tolerances (stated by the method's accuracy targets, applied per view and channel):
 
 * images: |x - r| <= 1e-4 (|r| + 1e-3 max|r|) on every pixel the oracle does not flag as
-  ambiguous (a float32 decision within rounding of a threshold);
+  ambiguous (a float32 decision within rounding of a threshold); for the pointmap, a
+  3-vector per pixel, |r| is the norm of the pixel's point (a coordinate that nearly
+  cancels, such as x on the principal column, carries the rounding of terms of the
+  point's own size);
 * gradients, per tensor: ||g - r||_2 / ||r||_2 <= 2e-3, and |g - r| <= 2e-3 (|r| + rms(r))
   for at least 99.99% of the elements.
 """
@@ -29,12 +32,15 @@ def to_dev(scene, torch):
     return params, T
 
 
-def check_image(name, got, ref, ok_mask):
-    """got, ref: [..., H, W] arrays; ok_mask: [H, W] bool of pixels to compare."""
+def check_image(name, got, ref, ok_mask, vector=False):
+    """got, ref: [..., H, W] arrays; ok_mask: [H, W] bool of pixels to compare.  With
+    vector=True the leading axis holds the components of one vector per pixel and the
+    relative part of the tolerance uses the vector's norm."""
     got = np.asarray(got, dtype=np.float64)
     ref = np.asarray(ref, dtype=np.float64)
     scale = np.abs(ref).max() if ref.size else 0.0
-    tol = IMG_RTOL * (np.abs(ref) + 1e-3 * scale)
+    mag = np.sqrt((ref ** 2).sum(axis=0, keepdims=True)) if vector else np.abs(ref)
+    tol = IMG_RTOL * (mag + 1e-3 * scale)
     bad = (np.abs(got - ref) > tol) & ok_mask
     if bad.any():
         idx = np.argwhere(bad)[:5]

@@ -58,7 +58,7 @@ def _check_view_forward(O, sc, v, out, off, cfg, pixels=None, tag=""):
     U.check_image(f"{tag} rgb", got_rgb.T, ref["rgb"].T, ok[None])
     U.check_image(f"{tag} depth", U.gpu_pixels(host["depth"], cam, off, 1, pix), ref["depth"], ok)
     U.check_image(f"{tag} alpha", U.gpu_pixels(host["alpha"], cam, off, 1, pix), ref["alpha"], ok)
-    U.check_image(f"{tag} pointmap", got_pm.T, ref[key].T, ok[None])
+    U.check_image(f"{tag} pointmap", got_pm.T, ref[key].T, ok[None], vector=True)
     return ref
 
 
