@@ -199,6 +199,41 @@ def time_mapping_ops(rast, step, win, sc, opt, cfg, torch, dev, reps=20):
     return out
 
 
+def time_tracking(torch, dev, iters=20):
+    """ms per tracking iteration on the tracking configuration (500k Gaussians, one 960x640
+    view, pose perturbed by 2 deg / 0.3 m): render, L1 RGB + L1 pointmap loss gradient,
+    pose-only backward (Sec. 3.2.2, Eq. 10-11)."""
+    from paper_2507_03737_amd import scenes
+    from paper_2507_03737_amd import binding as B
+    from paper_2507_03737_amd.render import Rasterizer, Window
+    sc = scenes.make_scene("c2")
+    params = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in sc.params()]
+    cfg = B.RasterConfig(pointmap_frame=1)
+    T_true = torch.from_numpy(np.ascontiguousarray(sc.T_cw)).to(dev)
+    out_t, _ = Rasterizer(Window(sc.cams, T_true), sc.n, cfg).forward(params)
+    T = torch.from_numpy(np.ascontiguousarray(scenes.perturb_pose(sc.T_cw[0], 2.0, 0.3, 2)[None])).to(dev)
+    win = Window(sc.cams, T)
+    rast = Rasterizer(win, sc.n, cfg)
+    rast.forward(params)
+    rast.max_pairs = int(rast.pairs * 1.5) + 4096
+    out, fs = rast.new_outputs(), rast.new_frame_state()
+    scale = torch.empty(win.n_patches(8), device=dev)
+    loss = torch.empty(1, device=dev)
+    g_rgb, g_pm = torch.empty_like(out["rgb"]), torch.empty_like(out["pointmap"])
+    pose = torch.zeros(1, 6, device=dev)
+    rast.reserve()
+
+    def it():
+        rast.forward_into(params, out, fs)
+        rast.window_loss_into(out["rgb"], out_t["rgb"], out["pointmap"], out_t["pointmap"], 8, 0.98, scale, loss,
+                              g_rgb, g_pm)
+        pose.zero_()
+        rast.pose_backward_into(params, out, {"rgb": g_rgb, "pointmap": g_pm}, fs, pose)
+    ms, _ = time_steps(it, iters, 3, torch)
+    B.frame_status(fs, B.stream_handle())
+    return {"workload": "500k Gaussians, one 960x640 view, pose-only backward", "ms_per_iter": ms}
+
+
 def time_steps(fn, steps, warmup, torch):
     for _ in range(warmup):
         fn()
@@ -377,9 +412,12 @@ def main():
     roof["kernel_ms"] = ph_ms[dominant]
 
     mapping_ops = None
+    tracking = None
     if not args.no_extras:
         log("[bench] mapping-side operations")
         mapping_ops = time_mapping_ops(rast, step, win, sc, opt, cfg, torch, dev)
+        log("[bench] tracking iteration")
+        tracking = time_tracking(torch, dev)
 
     cpu = None
     if not args.no_cpu:
@@ -425,6 +463,7 @@ def main():
         "memory": memory,
         "cpu_baseline": cpu,
         "mapping_ops": mapping_ops,
+        "tracking": tracking,
         "wall_s_timed": wall,
     }
     print(json.dumps(res), flush=True)
