@@ -92,7 +92,8 @@ typedef struct {
  * caller's choice.  Defaults used by the Python layer are given in brackets. */
 typedef struct {
     int32_t tile;            /* tile edge in pixels: 8, 16 or 32 [16] */
-    int32_t sort_digit_bits; /* radix-sort digit width, 4..8 [8] */
+    int32_t sort_digit_bits; /* largest radix-sort digit width, 4..8 [8]; each sort uses the
+                                fewest passes this allows, with the bits spread evenly */
     int32_t pointmap_frame;  /* 0 world-frame composited centres, 1 camera frame,
                                 2 depth back-projection D K^-1 [i, j, 1]^T (Eq. 5) [1] */
     int32_t pixels_per_lane; /* pixels each lane of the raster kernels owns; supported

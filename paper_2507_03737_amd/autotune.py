@@ -25,7 +25,7 @@ __all__ = ["Candidate", "default_candidates", "autotune", "cache_key"]
 Candidate = Tuple[int, int, int]  # (tile, pixels_per_lane, sort_digit_bits)
 
 
-def default_candidates(digit_bits: Sequence[int] = (6, 8)) -> List[Candidate]:
+def default_candidates(digit_bits: Sequence[int] = (6, 7, 8)) -> List[Candidate]:
     """Every supported raster shape with each digit width."""
     return [(t, p, d) for (t, p) in B.RasterConfig.SHAPES for d in digit_bits]
 

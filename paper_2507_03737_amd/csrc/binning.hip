@@ -449,7 +449,11 @@ hipError_t radix_sort(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t
                       int digit_bits, uint32_t *hist, uint32_t *scan_part, hipStream_t s) {
     if (n_max <= 0) return hipSuccess;
     if (bits < 1) bits = 1;
+    // As few passes as digit_bits allows, with the bits spread evenly over them (14 tile-id
+    // bits sort as 2 x 7: fewer buckets per pass than 8 + 6).
     const int passes = (bits + digit_bits - 1) / digit_bits;
+    digit_bits = (bits + passes - 1) / passes;
+    if (digit_bits < 4) digit_bits = 4;
     const uint32_t *kin = keys_in, *vin = vals_in;
     for (int p = 0; p < passes; ++p) {
         // The last pass writes to *_out; earlier passes alternate so that this holds.
