@@ -159,8 +159,11 @@ def test_graph_replay_matches_eager(lib):
             assert torch.equal(step.out[k], eager.out[k]), (it, k)
         assert torch.equal(step.loss, eager.loss)
         for k in step.grads:
-            torch.testing.assert_close(step.grads[k], eager.grads[k], rtol=1e-4, atol=1e-6)
-        torch.testing.assert_close(step.pose_grad, eager.pose_grad, rtol=1e-4, atol=1e-4)
+            # float atomics: the summation order differs between runs
+            torch.testing.assert_close(step.grads[k], eager.grads[k], rtol=1e-4,
+                                       atol=1e-5 * float(eager.grads[k].abs().max()))
+        torch.testing.assert_close(step.pose_grad, eager.pose_grad, rtol=1e-4,
+                                   atol=1e-5 * float(eager.pose_grad.abs().max()))
         # Move the cameras in place: the next replay must see it.
         xi.normal_(0.0, 0.01)
         lib.pose_retract(3, T, xi, lib.stream_handle())
@@ -215,8 +218,10 @@ def test_autograd_function(lib):
     pose = torch.zeros(3, 6, device="cuda")
     rast.backward_into(params, out, up, fs, grads, pose)
     torch.cuda.synchronize()
+    # Same kernels on the same inputs; float atomics make the summation order differ, so a
+    # cancelling element may differ by rounding relative to the tensor's scale.
     for leaf, k in zip(leaves, ("means", "log_scales", "quats", "opacity_logit", "rgb")):
-        torch.testing.assert_close(leaf.grad, grads[k], rtol=1e-4, atol=1e-5)
+        torch.testing.assert_close(leaf.grad, grads[k], rtol=1e-4, atol=1e-5 * float(grads[k].abs().max()))
     torch.testing.assert_close(xi.grad, pose, rtol=1e-4, atol=1e-3)
 
 
