@@ -41,10 +41,15 @@ struct RasterSettings {
 // A = -0.5 log2(e) Q_xx, B = -log2(e) Q_xy, C = -0.5 log2(e) Q_yy for the conic Q.
 constexpr int kRecFloats = 16;
 
-// Per-record image-plane gradient accumulator (16 floats, 13 used):
-//   0 u, 1 v, 2 A, 3 B, 4 C, 5 opacity, 6 z, 7..9 colour, 10..12 point.
+// Per-record image-plane gradient accumulator (16 floats, 13 used).  With
+// g = alpha dL/dalpha per composited fragment (0 where alpha is clamped) and (dx, dy) the
+// pixel centre minus the projected mean, the first six are the moments
+//   0 sum g, 1 sum g dx, 2 sum g dy, 3 sum g dx^2, 4 sum g dx dy, 5 sum g dy^2,
+// from which the mean, conic and opacity gradients follow (d e / d u = log2(e) (Q d)_x,
+// d e / d Q = -log2(e) d d^T / 2 for the base-2 exponent e, d alpha / d e = ln 2 alpha);
+// then 6 z, 7..9 colour, 10..12 point (sums of w dL/d output).  In the camera pointmap
+// frame the depth is the point's z, so its gradient is carried in column 12 and 6 stays 0.
 constexpr int kG2 = 16;
-constexpr int kG2Used = 13;
 
 // Records with more tile pairs than this are counted and emitted by whole waves.
 constexpr uint32_t kBigRecord = 64;
@@ -124,12 +129,29 @@ __device__ inline float wave_total(float x) {
     asm volatile("s_nop 1\n\t" op " %0, %4\n\t" op " %1, %5\n\t" op " %2, %6\n\t" op " %3, %7" \
                  : "+v"(a0), "+v"(a1), "+v"(a2), "+v"(a3), "+v"(b0), "+v"(b1), "+v"(b2), "+v"(b3))
 
-// Reduce-scatter of 16 per-lane values over a wave of 64 lanes.  On return, every lane
-// of quad q (lanes 4q .. 4q+3) holds the wave-wide sum of v[q & 15].  Lane bits 5 and 4
-// are folded with the cross-half swaps, bits 3 and 2 with DPP row rotations/shifts, and
-// bits 1 and 0 are fully reduced inside the quad.  Each fold halves the number of live
-// values, so the whole reduction costs 15 exchanges instead of 6 per value.
-__device__ inline float wave_reduce_scatter16(const float (&v)[16]) {
+#define GSPM_SWAP3(op, a0, b0, a1, b1, a2, b2)                                           \
+    asm volatile("s_nop 1\n\t" op " %0, %3\n\t" op " %1, %4\n\t" op " %2, %5"                \
+                 : "+v"(a0), "+v"(a1), "+v"(a2), "+v"(b0), "+v"(b1), "+v"(b2))
+#define GSPM_SWAP2(op, a0, b0, a1, b1) \
+    asm volatile("s_nop 1\n\t" op " %0, %2\n\t" op " %1, %3" : "+v"(a0), "+v"(a1), "+v"(b0), "+v"(b1))
+
+// Sum over the 16 lanes of each row; every lane of the row receives it.
+__device__ inline float row_sum16(float x) {
+    x += GSPM_DPP_MOV(x, 0x128);  // row_ror:8
+    x += GSPM_DPP_MOV(x, 0x124);  // row_ror:4
+    x += GSPM_DPP_MOV(x, 0x4e);   // quad_perm [2,3,0,1]
+    x += GSPM_DPP_MOV(x, 0xb1);   // quad_perm [1,0,3,2]
+    return x;
+}
+
+// Reduce-scatter of N per-lane values (N = 8, 12 or 16) over a wave of 64 lanes: returns
+// the wave-wide sum of v[idx] in the lanes where idx >= 0, one lane per value.  Lane bits
+// 5 and 4 are folded with the cross-half swaps, each fold halving the number of live
+// values, so a value costs about two instructions instead of six exchanges.
+//   N = 16: lane 4q holds v[q] (bits 3 and 2 are folded with DPP as well);
+//   N = 12: lane 16 rho + k (k < 3) holds v[3 rho + k];
+//   N = 8:  lane 16 rho + k (k < 2) holds v[2 rho + k].
+__device__ inline float wave_reduce_scatter(const float (&v)[16], int &idx) {
     const int lane = lane_id();
     float x[16];
 #pragma unroll
@@ -158,7 +180,49 @@ __device__ inline float wave_reduce_scatter16(const float (&v)[16]) {
     float d = keep + (b2 ? from_lo : from_hi);
     d += GSPM_DPP_MOV(d, 0x4e);  // quad_perm [2,3,0,1]
     d += GSPM_DPP_MOV(d, 0xb1);  // quad_perm [1,0,3,2]
+    idx = (lane & 3) == 0 ? (lane >> 2) & 15 : -1;
     return d;
+}
+
+__device__ inline float wave_reduce_scatter(const float (&v)[12], int &idx) {
+    const int lane = lane_id();
+    float x[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) x[k] = v[k];
+    GSPM_SWAP3("v_permlane32_swap_b32", x[0], x[6], x[1], x[7], x[2], x[8]);
+    GSPM_SWAP3("v_permlane32_swap_b32", x[3], x[9], x[4], x[10], x[5], x[11]);
+    float a[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) a[k] = x[k] + x[k + 6];  // lanes 0-31: v[k]; lanes 32-63: v[k + 6]
+    GSPM_SWAP3("v_permlane16_swap_b32", a[0], a[3], a[1], a[4], a[2], a[5]);
+    float b[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) b[k] = row_sum16(a[k] + a[k + 3]);  // row rho: v[3 rho + k]
+    // Keep the sums whole in every lane: otherwise the last adds are sunk into branches
+    // on the lane's index, which costs more than the two selects.
+    asm volatile("" : "+v"(b[0]), "+v"(b[1]), "+v"(b[2]));
+    const int r = lane & 15;
+    idx = r < 3 ? 3 * (lane >> 4) + r : -1;
+    return r == 0 ? b[0] : (r == 1 ? b[1] : b[2]);
+}
+
+__device__ inline float wave_reduce_scatter(const float (&v)[8], int &idx) {
+    const int lane = lane_id();
+    float x[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[k] = v[k];
+    GSPM_SWAP4("v_permlane32_swap_b32", x[0], x[4], x[1], x[5], x[2], x[6], x[3], x[7]);
+    float a[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) a[k] = x[k] + x[k + 4];  // lanes 0-31: v[k]; lanes 32-63: v[k + 4]
+    GSPM_SWAP2("v_permlane16_swap_b32", a[0], a[2], a[1], a[3]);
+    float b[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) b[k] = row_sum16(a[k] + a[k + 2]);  // row rho: v[2 rho + k]
+    asm volatile("" : "+v"(b[0]), "+v"(b[1]));
+    const int r = lane & 15;
+    idx = r < 2 ? 2 * (lane >> 4) + r : -1;
+    return r == 0 ? b[0] : b[1];
 }
 
 // Wave-wide inclusive prefix sum of a uint32 (Hillis-Steele over cross-lane reads).

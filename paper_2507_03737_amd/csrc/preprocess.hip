@@ -244,14 +244,18 @@ k_preprocess_backward(gspm_gaussians G, ViewTable vt, const float *__restrict__ 
     }
     {
         if (any) {
-            const double gu = q0.x, gv = q0.y, gA = q0.z, gB = q0.w, gC = q1.x, gop = q1.y, gz = q1.z;
+            // Moments of g = alpha dL/dalpha over the pixel offsets d = pixel - mean.  With
+            // alpha = o 2^e and e = -log2(e) d^T Q d / 2: dL/de = ln 2 g, so
+            //   dL/du = sum g (Q d)_x, dL/dv = sum g (Q d)_y, dL/dQ = -sum g d d^T / 2,
+            //   dL/do = sum g / o, so the logit's gradient is sum g (1 - o).
+            const double R0 = q0.x, Rx = q0.y, Ry = q0.z, Rxx = q0.w, Rxy = q1.x, Ryy = q1.y, gz = q1.z;
             gc[0] += q1.w; gc[1] += q2.x; gc[2] += q2.y;
             const double gp[3] = {q2.z, q2.w, q3.x};
-            // Conic entries from the exponent coefficients.
-            const double gQxx = -0.5 * kLog2e * gA, gQxy = -kLog2e * gB, gQyy = -0.5 * kLog2e * gC;
+            const double Qa = P.Q[0], Qb = P.Q[1], Qc = P.Q[2];
+            const double gu = Qa * Rx + Qb * Ry, gv = Qb * Rx + Qc * Ry;
+            const double gQxx = -0.5 * Rxx, gQxy = -Rxy, gQyy = -0.5 * Ryy;
             // d L / d cov2 = -Q Ghat Q with Ghat the symmetric gradient wrt Q.
             const double G00 = gQxx, G01 = 0.5 * gQxy, G11 = gQyy;
-            const double Qa = P.Q[0], Qb = P.Q[1], Qc = P.Q[2];
             // X = Ghat Q
             const double X00 = G00 * Qa + G01 * Qb, X01 = G00 * Qb + G01 * Qc;
             const double X10 = G01 * Qa + G11 * Qb, X11 = G01 * Qb + G11 * Qc;
@@ -354,7 +358,7 @@ k_preprocess_backward(gspm_gaussians G, ViewTable vt, const float *__restrict__ 
             const double dot = gqn[0] * w + gqn[1] * x + gqn[2] * y + gqn[3] * z;
             const double iq = 1.0 / P.qnorm;
             for (int k = 0; k < 4; ++k) gq[k] += (gqn[k] - P.qn[k] * dot) * iq;
-            go += gop * P.a * (1.0 - P.a);
+            go += R0 * (1.0 - P.a);
         }
     }
     if (want_pose) {

@@ -20,16 +20,17 @@
 // per-pixel count of list entries up to the last contributing fragment.  The suffix sums
 // that the alpha derivative needs are recovered as (sum over all fragments) - (prefix
 // sum), the total coming from the forward's outputs.  Each lane adds its pixels'
-// contributions to the 13 per-record gradient values, the wave sums them with one
-// reduce-scatter (cross-half lane swaps and DPP), and 13 lanes each issue one float
-// atomic, so the reduction and the atomics are paid once per wave and list entry.
+// contributions to the per-record sums (up to 13: the moments of alpha dL/dalpha over the
+// pixel offsets, from which the mean, conic and opacity gradients follow, and the colour,
+// depth and point sums), the wave adds them up with one reduce-scatter (cross-half lane
+// swaps and DPP) of 8, 12 or 16 values, and one lane per value issues a float atomic, so
+// the reduction and the atomics are paid once per wave and list entry.
 #include "gspm_common.h"
 
 namespace gspm {
 
 namespace {
 
-constexpr float kLn2 = 0.69314718055994530942f;
 
 struct TilePos {
     int gt;  // global tile index
@@ -138,7 +139,10 @@ __device__ inline uint64_t batch_mask(const float4 *s0, const float4 *s1, int c,
     return __ballot(q < cnt && meets_rect(s0[q], s1[q], x0, x1, y0, y1));
 }
 
-template <int TILE, int PPT>
+// FRAME is the pointmap frame (0 world, 1 camera, 2 from the depth, Eq. 5).  In the
+// camera frame the depth is the composited point's z and is not accumulated twice; in
+// frame 2 the point is not accumulated at all.
+template <int TILE, int PPT, int FRAME>
 __global__ void __launch_bounds__(TILE *TILE / PPT)
 k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
              const float4 *__restrict__ rec, float *__restrict__ out_rgb, float *__restrict__ out_depth,
@@ -214,10 +218,12 @@ k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
                     C0[k] = fmaf(w, cc.x, C0[k]);
                     C1[k] = fmaf(w, cc.y, C1[k]);
                     C2[k] = fmaf(w, cc.z, C2[k]);
-                    D[k] = fmaf(w, cc.w, D[k]);
-                    X0[k] = fmaf(w, d.x, X0[k]);
-                    X1[k] = fmaf(w, d.y, X1[k]);
-                    X2[k] = fmaf(w, d.z, X2[k]);
+                    if (FRAME != 1) D[k] = fmaf(w, cc.w, D[k]);
+                    if (FRAME != 2) {
+                        X0[k] = fmaf(w, d.x, X0[k]);
+                        X1[k] = fmaf(w, d.y, X1[k]);
+                        X2[k] = fmaf(w, d.z, X2[k]);
+                    }
                     T[k] = add ? Tn : T[k];
                     n_last[k] = add ? rel : n_last[k];
                     n_contrib[k] += add ? 1u : 0u;
@@ -241,15 +247,16 @@ k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
         out_rgb[o3] = fmaf(T[k], rs.bg[0], C0[k]);
         out_rgb[o3 + plane] = fmaf(T[k], rs.bg[1], C1[k]);
         out_rgb[o3 + 2 * plane] = fmaf(T[k], rs.bg[2], C2[k]);
-        out_depth[pix] = D[k];
+        const float depth = FRAME == 1 ? X2[k] : D[k];
+        out_depth[pix] = depth;
         out_alpha[pix] = 1.0f - T[k];
         float x0 = X0[k], x1 = X1[k], x2 = X2[k];
-        if (rs.frame == 2) {
+        if (FRAME == 2) {
             const float rx = ((float)i - vt.cx[tp.v]) / vt.fx[tp.v];
             const float ry = ((float)j - vt.cy[tp.v]) / vt.fy[tp.v];
-            x0 = D[k] * rx;
-            x1 = D[k] * ry;
-            x2 = D[k];
+            x0 = depth * rx;
+            x1 = depth * ry;
+            x2 = depth;
         }
         out_pm[o3] = x0;
         out_pm[o3 + plane] = x1;
@@ -262,12 +269,38 @@ k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
 
 __device__ inline float load_or0(const float *p, int64_t i) { return p ? p[i] : 0.0f; }
 
-template <int TILE, int PPT, bool POSE_ONLY>
+// Which per-record sums the backward forms, in value order, and the accumulator column
+// of each: [sum g] [moments of g: 5] [colour: 3] [depth] [point: 3].  A pose-only pass
+// (tracking) needs no opacity or colour gradient; the camera frame carries the depth
+// gradient in the point's z, and frame 2 has no point term.
+template <bool POSE_ONLY, int FRAME>
+struct BwdValues {
+    static constexpr bool kOpacity = !POSE_ONLY, kColour = !POSE_ONLY;
+    static constexpr bool kDepth = FRAME != 1, kPoint = FRAME != 2;
+    static constexpr int N = (kOpacity ? 1 : 0) + 5 + (kColour ? 3 : 0) + (kDepth ? 1 : 0) + (kPoint ? 3 : 0);
+    static constexpr int NR = N <= 8 ? 8 : (N <= 12 ? 12 : 16);  // reduce-scatter width
+    // Column of value k in bits [4k, 4k + 4).
+    static constexpr uint64_t columns() {
+        uint64_t c = 0;
+        int k = 0;
+        auto put = [&](int col) { c |= (uint64_t)col << (4 * k++); };
+        if (kOpacity) put(0);
+        for (int j = 1; j <= 5; ++j) put(j);
+        if (kColour) { put(7); put(8); put(9); }
+        if (kDepth) put(6);
+        if (kPoint) { put(10); put(11); put(12); }
+        return c;
+    }
+    static constexpr uint64_t kColumns = columns();
+};
+
+template <int TILE, int PPT, bool POSE_ONLY, int FRAME>
 __global__ void __launch_bounds__(TILE *TILE / PPT)
 k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
              const float4 *__restrict__ rec, const uint32_t *__restrict__ last, const float *__restrict__ t_final,
              gspm_const_images fwd, gspm_const_images up, float *__restrict__ grad2d) {
     using L = Layout<TILE, PPT>;
+    using V = BwdValues<POSE_ONLY, FRAME>;
     constexpr int NT = L::NT;
     __shared__ float4 s0[NT], s1[NT], s2[NT], s3[NT];
     __shared__ uint32_t block_last;
@@ -277,7 +310,6 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
     const int lx = lay.lx, ly = lay.ly;
     const float px = (float)lx;
     const float amin = rs.alpha_min, amax = rs.alpha_max;
-    const int lane = lane_id();
     const int i = tp.tx * TILE + lx;
     // Per-pixel upstream gradient and G = sum_k w_k (g . e_k) + T_final (g_C . bg), the
     // total that the forward's outputs give.
@@ -306,22 +338,29 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
         gX1[k] = load_or0(up.pointmap, o3 + plane);
         gX2[k] = load_or0(up.pointmap, o3 + 2 * plane);
         const float Tf = t_final[pix];
-        if (rs.frame == 2) {
-            // Eq. 5: the pointmap is D K^-1 [i, j, 1]^T, a function of the depth only.
-            const float rx = ((float)i - vt.cx[tp.v]) / vt.fx[tp.v];
-            const float ry = ((float)j - vt.cy[tp.v]) / vt.fy[tp.v];
-            gD[k] += gX0[k] * rx + gX1[k] * ry + gX2[k];
-            gX0[k] = gX1[k] = gX2[k] = 0.f;
-        }
+        const bool none = gC0[k] == 0.f && gC1[k] == 0.f && gC2[k] == 0.f && gD[k] == 0.f && gA[k] == 0.f &&
+                          gX0[k] == 0.f && gX1[k] == 0.f && gX2[k] == 0.f;
         // The rgb output holds sum_k w_k c_k + T_final bg, which is exactly what G needs.
         Gb[k] = gC0[k] * fwd.rgb[o3] + gC1[k] * fwd.rgb[o3 + plane] + gC2[k] * fwd.rgb[o3 + 2 * plane] +
                 gD[k] * fwd.depth[pix] + gA[k] * (1.0f - Tf);
-        if (rs.frame != 2)
+        if (FRAME == 2) {
+            // Eq. 5: the pointmap is D K^-1 [i, j, 1]^T, a function of the depth only.
+            const float rx = ((float)i - vt.cx[tp.v]) / vt.fx[tp.v];
+            const float ry = ((float)j - vt.cy[tp.v]) / vt.fy[tp.v];
+            const float gXD = gX0[k] * rx + gX1[k] * ry + gX2[k];
+            Gb[k] += gXD * fwd.depth[pix];
+            gD[k] += gXD;
+            gX0[k] = gX1[k] = gX2[k] = 0.f;
+        } else {
             Gb[k] += gX0[k] * fwd.pointmap[o3] + gX1[k] * fwd.pointmap[o3 + plane] +
                      gX2[k] * fwd.pointmap[o3 + 2 * plane];
-        if (gC0[k] == 0.f && gC1[k] == 0.f && gC2[k] == 0.f && gD[k] == 0.f && gA[k] == 0.f && gX0[k] == 0.f &&
-            gX1[k] == 0.f && gX2[k] == 0.f)
-            my_last[k] = 0;  // nothing flows back from this pixel
+        }
+        if (FRAME == 1) {
+            // The depth is the point's z: one gradient for both.
+            gX2[k] += gD[k];
+            gD[k] = 0.f;
+        }
+        if (none) my_last[k] = 0;  // nothing flows back from this pixel
         thread_last = max(thread_last, my_last[k]);
     }
     if (threadIdx.x == 0) block_last = 0;
@@ -329,7 +368,7 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
     uint32_t wave_last = thread_last;
     for (int off = 32; off > 0; off >>= 1) wave_last = max(wave_last, (uint32_t)__shfl_xor((int)wave_last, off, 64));
     wave_last = (uint32_t)__builtin_amdgcn_readfirstlane((int)wave_last);  // uniform: keep it scalar
-    if (lane == 0) atomicMax(&block_last, wave_last);
+    if (lane_id() == 0) atomicMax(&block_last, wave_last);
     __syncthreads();
     const uint32_t end = rg.x + block_last;
 
@@ -349,8 +388,7 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
                 const float4 a = s0[q];
                 const float4 b = s1[q];
                 const float dx = px - a.x;
-                const float Adx = a.z * dx, Bdx = a.w * dx;
-                const float Adx2 = Adx * dx;
+                const float Adx2 = a.z * dx * dx, Bdx = a.w * dx;
                 float e[PPT];
                 bool valid[PPT];
                 bool any = false;
@@ -363,48 +401,54 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
                 if (__ballot(any) == 0ull) continue;  // wave-uniform
                 const float4 cc = s2[q];
                 const float4 d = s3[q];
-                const float dx2 = dx * dx, twoAdx = 2.0f * Adx, twoC = 2.0f * b.x;
-                float v[16];
+                float v[V::NR];
 #pragma unroll
-                for (int t = 0; t < 16; ++t) v[t] = 0.f;
+                for (int t = V::N; t < V::NR; ++t) v[t] = 0.f;
 #pragma unroll
                 for (int k = 0; k < PPT; ++k) {
+                    // The first pixel assigns, later ones accumulate (x + 0 is not folded).
+                    auto add = [&](int t, float x) { v[t] = k == 0 ? x : v[t] + x; };
+                    auto mad = [&](int t, float x, float y) { v[t] = k == 0 ? x * y : fmaf(x, y, v[t]); };
                     // Branch-free: an invalid pixel gets zero weight and leaves T unchanged
                     // (e <= 0, so alpha lies in [0, alpha_max] and 1 - alpha >= 1 - alpha_max).
                     const float dy = py[k] - a.y;
-                    const float g2 = __builtin_amdgcn_exp2f(e[k]);
-                    const float al = fminf(amax, b.z * g2);
+                    const float al = fminf(amax, b.z * __builtin_amdgcn_exp2f(e[k]));
                     const float w = valid[k] ? __fmul_rn(al, T[k]) : 0.0f;
-                    const float sv = gC0[k] * cc.x + gC1[k] * cc.y + gC2[k] * cc.z + gD[k] * cc.w + gA[k] +
-                                     gX0[k] * d.x + gX1[k] * d.y + gX2[k] * d.z;
+                    float sv = fmaf(gC0[k], cc.x, fmaf(gC1[k], cc.y, fmaf(gC2[k], cc.z, gA[k])));
+                    if (V::kDepth) sv = fmaf(gD[k], cc.w, sv);
+                    if (V::kPoint) sv = fmaf(gX0[k], d.x, fmaf(gX1[k], d.y, fmaf(gX2[k], d.z, sv)));
                     Pfx[k] = fmaf(w, sv, Pfx[k]);
                     const float one_m = __fsub_rn(1.0f, al);
                     const float dLda = T[k] * sv - (Gb[k] - Pfx[k]) * __builtin_amdgcn_rcpf(one_m);
-                    const bool unclamped = valid[k] && al < amax;
-                    const float Gl = unclamped ? dLda * al * kLn2 : 0.0f;
-                    const float Gldy = Gl * dy;
-                    v[0] = fmaf(-Gl, fmaf(a.w, dy, twoAdx), v[0]);
-                    v[1] = fmaf(-Gl, fmaf(twoC, dy, Bdx), v[1]);
-                    v[2] = fmaf(Gl, dx2, v[2]);
-                    v[3] = fmaf(Gldy, dx, v[3]);
-                    v[4] = fmaf(Gldy, dy, v[4]);
-                    if (!POSE_ONLY) v[5] = fmaf(unclamped ? dLda : 0.0f, g2, v[5]);
-                    v[6] = fmaf(w, gD[k], v[6]);
-                    if (!POSE_ONLY) {
-                        v[7] = fmaf(w, gC0[k], v[7]);
-                        v[8] = fmaf(w, gC1[k], v[8]);
-                        v[9] = fmaf(w, gC2[k], v[9]);
+                    const float g = (valid[k] && al < amax) ? dLda * al : 0.0f;
+                    const float gdx = g * dx, gdy = g * dy;
+                    int t = 0;
+                    if (V::kOpacity) add(t++, g);
+                    add(t++, gdx);
+                    add(t++, gdy);
+                    mad(t++, gdx, dx);
+                    mad(t++, gdy, dx);
+                    mad(t++, gdy, dy);
+                    if (V::kColour) {
+                        mad(t++, w, gC0[k]);
+                        mad(t++, w, gC1[k]);
+                        mad(t++, w, gC2[k]);
                     }
-                    v[10] = fmaf(w, gX0[k], v[10]);
-                    v[11] = fmaf(w, gX1[k], v[11]);
-                    v[12] = fmaf(w, gX2[k], v[12]);
+                    if (V::kDepth) mad(t++, w, gD[k]);
+                    if (V::kPoint) {
+                        mad(t++, w, gX0[k]);
+                        mad(t++, w, gX1[k]);
+                        mad(t++, w, gX2[k]);
+                    }
                     T[k] = valid[k] ? __fmul_rn(T[k], one_m) : T[k];
                 }
-                const float tot = wave_reduce_scatter16(v);
-                const int idx = (lane >> 2) & 15;
-                if ((lane & 3) == 0 && idx < kG2Used && tot != 0.f) {
-                    const uint32_t r = __float_as_uint(b.w);
-                    unsafeAtomicAdd(grad2d + (int64_t)r * kG2 + idx, tot);
+                int idx;
+                const float tot = wave_reduce_scatter(v, idx);
+                if (idx >= 0 && idx < V::N && tot != 0.f) {
+                    // The record index is wave-uniform: a scalar row base plus the lane's column.
+                    const uint32_t r = (uint32_t)__builtin_amdgcn_readfirstlane((int)__float_as_uint(b.w));
+                    const uint32_t col = (uint32_t)((V::kColumns >> (4 * idx)) & 15u);
+                    unsafeAtomicAdd(grad2d + (int64_t)r * kG2 + col, tot);
                 }
             }
         }
@@ -431,14 +475,20 @@ hipError_t launch_raster_forward(const ViewTable &vt, const RasterSettings &rs, 
                                  uint8_t *visible, hipStream_t s) {
     const int n_tiles = vt.tile_off[vt.n_views];
     const float4 *rec = reinterpret_cast<const float4 *>(records);
-#define GSPM_FWD(T_, P_)                                                                                    \
-    if (vt.tile == T_ && vt.ppt == P_) {                                                                    \
-        hipLaunchKernelGGL((k_raster_fwd<T_, P_>), dim3(n_tiles), dim3(T_ * T_ / P_), 0, s, vt, rs, ranges, \
-                           pair_vals, rec, rgb, depth, alpha, pointmap, t_final, last, contrib, visible);            \
-        return hipGetLastError();                                                                           \
+    if (rs.frame < 0 || rs.frame > 2) return hipErrorInvalidValue;
+#define GSPM_FWD1(T_, P_, F_)                                                                        \
+    hipLaunchKernelGGL((k_raster_fwd<T_, P_, F_>), dim3(n_tiles), dim3(T_ * T_ / P_), 0, s, vt, rs, \
+                       ranges, pair_vals, rec, rgb, depth, alpha, pointmap, t_final, last, contrib, visible)
+#define GSPM_FWD(T_, P_)                                      \
+    if (vt.tile == T_ && vt.ppt == P_) {                      \
+        if (rs.frame == 0) GSPM_FWD1(T_, P_, 0);              \
+        else if (rs.frame == 1) GSPM_FWD1(T_, P_, 1);         \
+        else GSPM_FWD1(T_, P_, 2);                            \
+        return hipGetLastError();                             \
     }
     GSPM_RASTER_CONFIGS(GSPM_FWD)
 #undef GSPM_FWD
+#undef GSPM_FWD1
     return hipErrorInvalidValue;
 }
 
@@ -448,18 +498,27 @@ hipError_t launch_raster_backward(const ViewTable &vt, const RasterSettings &rs,
                                   float *grad2d, bool pose_only, hipStream_t s) {
     const int n_tiles = vt.tile_off[vt.n_views];
     const float4 *rec = reinterpret_cast<const float4 *>(records);
-#define GSPM_BWD(T_, P_)                                                                                      \
-    if (vt.tile == T_ && vt.ppt == P_) {                                                                      \
-        if (pose_only)                                                                                        \
-            hipLaunchKernelGGL((k_raster_bwd<T_, P_, true>), dim3(n_tiles), dim3(T_ * T_ / P_), 0, s, vt, rs, \
-                               ranges, pair_vals, rec, last, t_final, fwd, up, grad2d);                       \
-        else                                                                                                  \
-            hipLaunchKernelGGL((k_raster_bwd<T_, P_, false>), dim3(n_tiles), dim3(T_ * T_ / P_), 0, s, vt,    \
-                               rs, ranges, pair_vals, rec, last, t_final, fwd, up, grad2d);                   \
-        return hipGetLastError();                                                                             \
+    if (rs.frame < 0 || rs.frame > 2) return hipErrorInvalidValue;
+#define GSPM_BWD1(T_, P_, PO_, F_)                                                                         \
+    hipLaunchKernelGGL((k_raster_bwd<T_, P_, PO_, F_>), dim3(n_tiles), dim3(T_ * T_ / P_), 0, s, vt, rs, \
+                       ranges, pair_vals, rec, last, t_final, fwd, up, grad2d)
+#define GSPM_BWD2(T_, P_, PO_)                            \
+    if (rs.frame == 0) GSPM_BWD1(T_, P_, PO_, 0);         \
+    else if (rs.frame == 1) GSPM_BWD1(T_, P_, PO_, 1);    \
+    else GSPM_BWD1(T_, P_, PO_, 2);
+#define GSPM_BWD(T_, P_)                                  \
+    if (vt.tile == T_ && vt.ppt == P_) {                  \
+        if (pose_only) {                                  \
+            GSPM_BWD2(T_, P_, true)                       \
+        } else {                                          \
+            GSPM_BWD2(T_, P_, false)                      \
+        }                                                 \
+        return hipGetLastError();                         \
     }
     GSPM_RASTER_CONFIGS(GSPM_BWD)
 #undef GSPM_BWD
+#undef GSPM_BWD2
+#undef GSPM_BWD1
     return hipErrorInvalidValue;
 }
 
