@@ -352,6 +352,7 @@ gspm_status gspm_render_forward(gspm_ctx *ctx, const gspm_gaussians *g, const gs
     uint32_t *hist = static_cast<uint32_t *>(ctx->hist.p);
     uint32_t *part = static_cast<uint32_t *>(ctx->scan_part.p);
 
+    GSPM_HIP(launch_fill_u32(&hdr->sort_stall, 0u, 1, hs));
     // 1. Project every (Gaussian, view) record.
     PhaseTimer t_pre(ctx, hs, GSPM_PHASE_PREPROCESS);
     GSPM_HIP(launch_preprocess(*g, P.vt, views->T_cw, P.rs, records, counts, static_cast<uint32_t *>(ctx->dkey.p),
@@ -371,7 +372,7 @@ gspm_status gspm_render_forward(gspm_ctx *ctx, const gspm_gaussians *g, const gs
         GSPM_HIP(radix_sort(static_cast<uint32_t *>(ctx->dval.p), static_cast<uint32_t *>(ctx->live.p),
                             static_cast<uint32_t *>(ctx->dkey_tmp.p), static_cast<uint32_t *>(ctx->dval_tmp.p),
                             static_cast<uint32_t *>(ctx->dkey_s.p), static_cast<uint32_t *>(ctx->dval_s.p), R, n_live,
-                            32, db, hist, part, hs));
+                            32, db, hist, &hdr->sort_stall, hs));
         t_ds.stop();
     }
     PhaseTimer t_bin(ctx, hs, GSPM_PHASE_BINNING);
@@ -399,7 +400,7 @@ gspm_status gspm_render_forward(gspm_ctx *ctx, const gspm_gaussians *g, const gs
         GSPM_HIP(radix_sort(static_cast<uint32_t *>(ctx->pkey.p), static_cast<uint32_t *>(ctx->pval.p),
                             static_cast<uint32_t *>(ctx->pkey_tmp.p), static_cast<uint32_t *>(ctx->pval_tmp.p),
                             static_cast<uint32_t *>(ctx->pkey_s.p), pair_vals, cap, &hdr->pairs,
-                            tile_bits(P.n_tiles), db, hist, part, hs));
+                            tile_bits(P.n_tiles), db, hist, &hdr->sort_stall, hs));
         t_ts.stop();
         PhaseTimer t_rg(ctx, hs, GSPM_PHASE_BINNING);
         GSPM_HIP(launch_ranges(static_cast<uint32_t *>(ctx->pkey_s.p), hdr, ranges, P.n_tiles, cap, hs));
@@ -425,6 +426,7 @@ gspm_status gspm_frame_status(const void *frame_state, void *stream, int64_t *pa
     GSPM_HIP(hipMemcpy(&h, frame_state, sizeof(h), hipMemcpyDeviceToHost));
     if (h.magic != kFrameMagic) return fail(GSPM_ERR_INVALID_ARG, "frame_state was not written by a forward");
     if (pairs) *pairs = h.pairs;
+    if (h.sort_stall) return fail(GSPM_ERR_INTERNAL, "a radix sort pass stopped waiting for an earlier tile");
     if (h.overflow)
         return fail(GSPM_ERR_CAPACITY, "tile pairs %u exceed the frame state's capacity %u", h.pairs, h.capacity);
     return GSPM_OK;

@@ -116,19 +116,33 @@ k_scan_apply(const uint32_t *__restrict__ counts, const uint32_t *__restrict__ i
 
 // ------------------------------- radix sort -------------------------------------------
 //
-// LSD passes over fixed tiles of 4096 keys (4 waves x 16 steps of 64).  The upsweep
-// writes a digit histogram per tile (digit-major, so one exclusive scan yields every
-// tile's output offsets).  The downsweep ranks each tile's keys stably (wave-level match
-// of equal digits by ballots, then per-digit offsets across the four waves), stages the
-// tile in LDS in sorted order and writes it out so that consecutive lanes write
-// consecutive addresses inside each digit's run.  Grids are fixed; the key count may be
-// read from device memory, and then only its ceil(n / 4096) tiles are histogrammed,
-// scanned and scattered (the histogram stride is that tile count).
+// LSD radix sort with one histogram pass for every digit and one kernel per digit pass
+// (the single-sweep scheme with decoupled look-back of Merrill and Garland's scan and
+// Adinets and Merrill's Onesweep sort).  Keys are cut into tiles of 4096 (4 waves x 16
+// steps of 64).  Block b of a pass kernel ranks tile b's keys stably (wave-level match of
+// equal digits by ballots, then per-digit offsets across the four waves), publishes its
+// per-digit counts, and finds the count of each digit in all earlier tiles by walking
+// back over their published words until one carries an inclusive prefix; it then
+// publishes its own inclusive prefix.  Workgroups are dispatched in index order, so a
+// block only waits for blocks that are already running, which never wait for later ones:
+// the walk ends.  (Taking tile numbers from a global counter instead would serialise the
+// blocks on one atomic address, tens of nanoseconds each.)  A wait is still bounded (then
+// the sort is abandoned and the stall flag set) so that a broken ordering assumption or
+// a fault elsewhere cannot leave the kernel spinning.  The tile is staged in LDS in sorted order and
+// written so that consecutive lanes write consecutive addresses within each digit's run.
+// The key count may be read from device memory; only its ceil(n / 4096) tiles are used.
 
 constexpr int kSortBlock = 256;
 constexpr int kSortWaves = kSortBlock / kWave;
 constexpr int kSortSteps = 16;
 constexpr int kSortTile = kSortBlock * kSortSteps;  // 4096 keys
+constexpr int kSortMaxPasses = 8;
+// Published word per (tile, digit): flag in bits 31:30, count in bits 29:0.
+constexpr uint32_t kStatAgg = 1u << 30;  // the tile's own count
+constexpr uint32_t kStatInc = 2u << 30;  // count over this and every earlier tile
+constexpr uint32_t kStatCount = (1u << 30) - 1u;
+constexpr uint32_t kSortSpinLimit = 1u << 20;
+constexpr int kLookback = 16;  // earlier tiles read per look-back step
 
 __device__ inline int64_t sort_count(const uint32_t *n_dev, int64_t n_max) {
     if (!n_dev) return n_max;
@@ -139,37 +153,48 @@ __device__ inline int64_t sort_count(const uint32_t *n_dev, int64_t n_max) {
 // Tiles holding the n live keys.
 __device__ inline int64_t sort_active_tiles(int64_t n) { return (n + kSortTile - 1) / kSortTile; }
 
+// Digit histograms of every pass (ghist[p * R + d], zeroed by the caller); also clears the
+// first pass's published words of the live tiles.
 template <int DB>
 __global__ void __launch_bounds__(kSortBlock)
-k_radix_upsweep(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ n_dev, int64_t n_max, int shift,
-                uint32_t *__restrict__ hist, uint32_t *__restrict__ hist_words) {
+k_radix_hist(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ n_dev, int64_t n_max, int passes,
+             uint32_t *__restrict__ ghist, uint32_t *__restrict__ status0) {
     constexpr int R = 1 << DB;
-    __shared__ uint32_t cnt[kSortWaves][R];
-    const int wid = threadIdx.x / kWave, lane = lane_id();
+    __shared__ uint32_t h[kSortMaxPasses * R];
+    for (int i = threadIdx.x; i < passes * R; i += kSortBlock) h[i] = 0u;
+    __syncthreads();
     const int64_t n = sort_count(n_dev, n_max);
-    const int64_t n_tiles = sort_active_tiles(n);
-    if (blockIdx.x == 0 && threadIdx.x == 0) *hist_words = (uint32_t)(R * n_tiles);
-    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        for (int d = lane; d < R; d += kWave) cnt[wid][d] = 0u;
-        __syncthreads();
-        const int64_t b = tile * kSortTile + (int64_t)wid * (kSortTile / kSortWaves);
-#pragma unroll 4
-        for (int st = 0; st < kSortSteps; ++st) {
-            const int64_t i = b + st * kWave + lane;
-            if (i < n) atomicAdd(&cnt[wid][(keys[i] >> shift) & (R - 1)], 1u);
-        }
-        __syncthreads();
-        for (int d = threadIdx.x; d < R; d += kSortBlock)
-            hist[(int64_t)d * n_tiles + tile] = cnt[0][d] + cnt[1][d] + cnt[2][d] + cnt[3][d];
-        __syncthreads();
+    const int64_t stride = (int64_t)gridDim.x * kSortBlock;
+    constexpr int kItems = 8;  // keys loaded before any is counted
+    for (int64_t i0 = (int64_t)blockIdx.x * kSortBlock + threadIdx.x; i0 < n; i0 += kItems * stride) {
+        uint32_t k[kItems];
+#pragma unroll
+        for (int q = 0; q < kItems; ++q) k[q] = i0 + q * stride < n ? keys[i0 + q * stride] : 0u;
+#pragma unroll
+        for (int q = 0; q < kItems; ++q)
+            if (i0 + q * stride < n)
+                for (int p = 0; p < passes; ++p) atomicAdd(&h[p * R + ((k[q] >> (p * DB)) & (R - 1))], 1u);
     }
+    const int64_t words = sort_active_tiles(n) * R;
+    for (int64_t i = (int64_t)blockIdx.x * kSortBlock + threadIdx.x; i < words; i += stride) status0[i] = 0u;
+    __syncthreads();
+    for (int i = threadIdx.x; i < passes * R; i += kSortBlock)
+        if (h[i] != 0u) atomicAdd(&ghist[i], h[i]);
+}
+
+__device__ inline uint32_t load_status(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void store_status(uint32_t *p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <int DB>
 __global__ void __launch_bounds__(kSortBlock)
-k_radix_downsweep(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
-                  uint32_t *__restrict__ vout, const uint32_t *__restrict__ n_dev, int64_t n_max, int shift,
-                  const uint32_t *__restrict__ hist) {
+k_radix_pass(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
+             uint32_t *__restrict__ vout, const uint32_t *__restrict__ n_dev, int64_t n_max, int shift,
+             const uint32_t *__restrict__ ghist, uint32_t *__restrict__ status,
+             uint32_t *__restrict__ status_next, uint32_t *__restrict__ stall) {
     constexpr int R = 1 << DB;
     __shared__ uint32_t wcnt[kSortWaves][R];
     __shared__ uint32_t dstart[R];
@@ -180,74 +205,118 @@ k_radix_downsweep(const uint32_t *__restrict__ kin, const uint32_t *__restrict__
     const int wid = threadIdx.x / kWave, lane = lane_id();
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int64_t n = sort_count(n_dev, n_max);
-    const int64_t n_tiles = sort_active_tiles(n);
-    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        const int64_t tile_begin = tile * kSortTile;
-        if (tile_begin >= n) break;  // block-uniform; later tiles of this block are empty too
-        for (int d = lane; d < R; d += kWave) wcnt[wid][d] = 0u;
+    const int64_t tile = blockIdx.x;
+    if (tile >= sort_active_tiles(n)) return;  // block-uniform
+    const uint32_t gcount = threadIdx.x < R ? ghist[threadIdx.x] : 0u;
+    for (int d = lane; d < R; d += kWave) wcnt[wid][d] = 0u;
+    __builtin_amdgcn_wave_barrier();
+    const int64_t tile_begin = tile * kSortTile;
+    const int64_t b = tile_begin + (int64_t)wid * (kSortTile / kSortWaves);
+    uint32_t key[kSortSteps], val[kSortSteps], rank[kSortSteps];
+    // All loads first, so that the tile is in flight at once rather than one step at a time.
+#pragma unroll
+    for (int st = 0; st < kSortSteps; ++st) {
+        const int64_t i = b + st * kWave + lane;
+        key[st] = i < n ? kin[i] : 0u;
+        val[st] = i < n ? vin[i] : 0u;
+    }
+#pragma unroll
+    for (int st = 0; st < kSortSteps; ++st) {
+        const bool act = b + st * kWave + lane < n;
+        const uint32_t d = (key[st] >> shift) & (R - 1);
+        uint64_t m = __ballot(act);
+#pragma unroll
+        for (int bit = 0; bit < DB; ++bit) {
+            const bool set = (d >> bit) & 1u;
+            const uint64_t bb = __ballot(set);
+            m &= set ? bb : ~bb;
+        }
+        rank[st] = 0xffffffffu;
+        if (act) {
+            const uint32_t r = (uint32_t)__popcll(m & lt);
+            const uint32_t base_d = wcnt[wid][d];
+            rank[st] = base_d + r;
+            if (r == 0) wcnt[wid][d] = base_d + (uint32_t)__popcll(m);
+        }
         __builtin_amdgcn_wave_barrier();
-        const int64_t b = tile_begin + (int64_t)wid * (kSortTile / kSortWaves);
-        uint32_t key[kSortSteps], val[kSortSteps], rank[kSortSteps];
+    }
+    __syncthreads();
+    // Per digit: offsets of the four waves and the tile's count, published at once.
+    uint32_t tot = 0;
+    if (threadIdx.x < R) {
+        const int d = threadIdx.x;
+        uint32_t acc = 0;
 #pragma unroll
-        for (int st = 0; st < kSortSteps; ++st) {
-            const int64_t i = b + st * kWave + lane;
-            const bool act = i < n;
-            key[st] = act ? kin[i] : 0u;
-            val[st] = act ? vin[i] : 0u;
-            const uint32_t d = (key[st] >> shift) & (R - 1);
-            uint64_t m = __ballot(act);
+        for (int w = 0; w < kSortWaves; ++w) {
+            const uint32_t c = wcnt[w][d];
+            wcnt[w][d] = acc;
+            acc += c;
+        }
+        tot = acc;
+        store_status(status + tile * R + d, (tile == 0 ? kStatInc : kStatAgg) | tot);
+        status_next[tile * R + d] = 0u;  // the next pass's word for this tile
+    }
+    uint32_t all;
+    const uint32_t gpre = block_exclusive_scan(gcount, scan_lds, all);
+    const uint32_t pre = block_exclusive_scan(tot, scan_lds, all);
+    if (threadIdx.x < R) {
+        const int d = threadIdx.x;
+        dstart[d] = pre;
+        uint32_t prefix = 0;
+        if (tile > 0) {
+            // Words of kLookback earlier tiles are read at once (one memory latency per
+            // window instead of per tile), then taken nearest first.
+            int64_t j = tile - 1;
+            uint32_t spins = 0;
+            for (;;) {
+                uint32_t w[kLookback];
 #pragma unroll
-            for (int bit = 0; bit < DB; ++bit) {
-                const bool set = (d >> bit) & 1u;
-                const uint64_t bb = __ballot(set);
-                m &= set ? bb : ~bb;
+                for (int q = 0; q < kLookback; ++q)
+                    w[q] = j - q >= 0 ? load_status(status + (j - q) * R + d) : kStatInc;
+                int used = kLookback;
+                bool done = false;
+#pragma unroll
+                for (int q = 0; q < kLookback; ++q) {
+                    if (q < used && !done) {
+                        if ((w[q] & ~kStatCount) == 0u) {
+                            used = q;  // not yet published: read again from this tile
+                        } else {
+                            prefix += w[q] & kStatCount;
+                            done = (w[q] & kStatInc) != 0u;  // tile 0's word is inclusive
+                        }
+                    }
+                }
+                if (done) break;
+                j -= used;
+                if (used < kLookback) {
+                    if (++spins > kSortSpinLimit || load_status(stall) != 0u) {
+                        store_status(stall, 1u);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
             }
-            rank[st] = 0xffffffffu;
-            if (act) {
-                const uint32_t r = (uint32_t)__popcll(m & lt);
-                const uint32_t base_d = wcnt[wid][d];
-                rank[st] = base_d + r;
-                if (r == 0) wcnt[wid][d] = base_d + (uint32_t)__popcll(m);
-            }
-            __builtin_amdgcn_wave_barrier();
+            store_status(status + tile * R + d, kStatInc | (prefix + tot));
         }
-        __syncthreads();
-        // Per digit: offsets of the four waves, then the block-local start of the digit.
-        uint32_t tot = 0;
-        if (threadIdx.x < R) {
-            const int d = threadIdx.x;
-            uint32_t acc = 0;
+        gbase[d] = gpre + prefix;
+    }
+    __syncthreads();
 #pragma unroll
-            for (int w = 0; w < kSortWaves; ++w) {
-                const uint32_t c = wcnt[w][d];
-                wcnt[w][d] = acc;
-                acc += c;
-            }
-            tot = acc;
-            gbase[d] = hist[(int64_t)d * n_tiles + tile];
-        }
-        uint32_t all;
-        const uint32_t pre = block_exclusive_scan(tot, scan_lds, all);
-        if (threadIdx.x < R) dstart[threadIdx.x] = pre;
-        __syncthreads();
-#pragma unroll
-        for (int st = 0; st < kSortSteps; ++st) {
-            if (rank[st] == 0xffffffffu) continue;
-            const uint32_t d = (key[st] >> shift) & (R - 1);
-            const uint32_t lp = dstart[d] + wcnt[wid][d] + rank[st];
-            lk[lp] = key[st];
-            lv[lp] = val[st];
-        }
-        __syncthreads();
-        const int cnt = (int)(n - tile_begin < kSortTile ? n - tile_begin : kSortTile);
-        for (int j = threadIdx.x; j < cnt; j += kSortBlock) {
-            const uint32_t k = lk[j];
-            const uint32_t d = (k >> shift) & (R - 1);
-            const uint32_t pos = gbase[d] + ((uint32_t)j - dstart[d]);
-            kout[pos] = k;
-            vout[pos] = lv[j];
-        }
-        __syncthreads();
+    for (int st = 0; st < kSortSteps; ++st) {
+        if (rank[st] == 0xffffffffu) continue;
+        const uint32_t d = (key[st] >> shift) & (R - 1);
+        const uint32_t lp = dstart[d] + wcnt[wid][d] + rank[st];
+        lk[lp] = key[st];
+        lv[lp] = val[st];
+    }
+    __syncthreads();
+    const int cnt = (int)(n - tile_begin < kSortTile ? n - tile_begin : kSortTile);
+    for (int j = threadIdx.x; j < cnt; j += kSortBlock) {
+        const uint32_t k = lk[j];
+        const uint32_t d = (k >> shift) & (R - 1);
+        const uint32_t pos = gbase[d] + ((uint32_t)j - dstart[d]);
+        kout[pos] = k;
+        vout[pos] = lv[j];
     }
 }
 
@@ -420,56 +489,56 @@ hipError_t launch_compact(const uint32_t *counts, const uint32_t *flag_scan, con
 
 static int64_t sort_tiles(int64_t n_max) { return (n_max + kSortTile - 1) / kSortTile; }
 
-static int64_t sort_blocks(int64_t n_max) {
-    int64_t nb = sort_tiles(n_max);
-    if (nb > 1024) nb = 1024;
-    return nb < 1 ? 1 : nb;
-}
-
+// Scratch words: digit histograms [kSortMaxPasses << digit_bits], published words
+// [2][tiles << digit_bits] (alternating passes).
 int64_t radix_hist_words(int64_t n_max, int digit_bits) {
-    const int64_t t = sort_tiles(n_max);
-    return ((int64_t)1 << digit_bits) * (t > 0 ? t : 1);
+    const int64_t t = sort_tiles(n_max) > 0 ? sort_tiles(n_max) : 1;
+    return ((int64_t)kSortMaxPasses << digit_bits) + 2 * (t << digit_bits);
 }
 
 template <int DB>
-static void sort_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, int64_t n_max,
-                      const uint32_t *n_dev, int shift, uint32_t *hist, uint32_t *scan_part, hipStream_t s) {
-    const int64_t nb = sort_blocks(n_max);
-    const int64_t hw = ((int64_t)1 << DB) * sort_tiles(n_max);
-    // hist[hw] receives the scan total, hist[hw + 1] the number of live histogram words.
-    hipLaunchKernelGGL(k_radix_upsweep<DB>, dim3((unsigned)nb), dim3(kSortBlock), 0, s, kin, n_dev, n_max, shift,
-                       hist, hist + hw + 1);
-    (void)launch_scan_indirect(hist, nullptr, hw, hist, hist + hw, scan_part, s, hist + hw + 1, 0);
-    hipLaunchKernelGGL(k_radix_downsweep<DB>, dim3((unsigned)nb), dim3(kSortBlock), 0, s, kin, vin, kout, vout,
-                       n_dev, n_max, shift, hist);
-}
-
-hipError_t radix_sort(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_tmp, uint32_t *vals_tmp,
-                      uint32_t *keys_out, uint32_t *vals_out, int64_t n_max, const uint32_t *n_dev, int bits,
-                      int digit_bits, uint32_t *hist, uint32_t *scan_part, hipStream_t s) {
-    if (n_max <= 0) return hipSuccess;
-    if (bits < 1) bits = 1;
-    // As few passes as digit_bits allows, with the bits spread evenly over them (14 tile-id
-    // bits sort as 2 x 7: fewer buckets per pass than 8 + 6).
-    const int passes = (bits + digit_bits - 1) / digit_bits;
-    digit_bits = (bits + passes - 1) / passes;
-    if (digit_bits < 4) digit_bits = 4;
+static void sort_passes(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_tmp, uint32_t *vals_tmp,
+                        uint32_t *keys_out, uint32_t *vals_out, int64_t n_max, const uint32_t *n_dev, int passes,
+                        uint32_t *scratch, uint32_t *stall, hipStream_t s) {
+    constexpr int R = 1 << DB;
+    const int64_t tiles = sort_tiles(n_max);
+    uint32_t *ghist = scratch;
+    uint32_t *status[2] = {ghist + (int64_t)kSortMaxPasses * R, ghist + (int64_t)kSortMaxPasses * R + tiles * R};
+    (void)launch_fill_u32(ghist, 0u, (int64_t)kSortMaxPasses * R, s);
+    int64_t hb = tiles < 1024 ? tiles : 1024;
+    hipLaunchKernelGGL(k_radix_hist<DB>, dim3((unsigned)(hb > 0 ? hb : 1)), dim3(kSortBlock), 0, s, keys_in, n_dev,
+                       n_max, passes, ghist, status[0]);
     const uint32_t *kin = keys_in, *vin = vals_in;
     for (int p = 0; p < passes; ++p) {
         // The last pass writes to *_out; earlier passes alternate so that this holds.
         const bool to_out = ((passes - 1 - p) % 2) == 0;
         uint32_t *ko = to_out ? keys_out : keys_tmp;
         uint32_t *vo = to_out ? vals_out : vals_tmp;
-        const int shift = p * digit_bits;
-        switch (digit_bits) {
-            case 4: sort_pass<4>(kin, vin, ko, vo, n_max, n_dev, shift, hist, scan_part, s); break;
-            case 5: sort_pass<5>(kin, vin, ko, vo, n_max, n_dev, shift, hist, scan_part, s); break;
-            case 6: sort_pass<6>(kin, vin, ko, vo, n_max, n_dev, shift, hist, scan_part, s); break;
-            case 7: sort_pass<7>(kin, vin, ko, vo, n_max, n_dev, shift, hist, scan_part, s); break;
-            default: sort_pass<8>(kin, vin, ko, vo, n_max, n_dev, shift, hist, scan_part, s); break;
-        }
+        hipLaunchKernelGGL(k_radix_pass<DB>, dim3((unsigned)tiles), dim3(kSortBlock), 0, s, kin, vin, ko, vo, n_dev,
+                           n_max, p * DB, ghist + (int64_t)p * R, status[p & 1], status[(p + 1) & 1], stall);
         kin = ko;
         vin = vo;
+    }
+}
+
+hipError_t radix_sort(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_tmp, uint32_t *vals_tmp,
+                      uint32_t *keys_out, uint32_t *vals_out, int64_t n_max, const uint32_t *n_dev, int bits,
+                      int digit_bits, uint32_t *scratch, uint32_t *stall, hipStream_t s) {
+    if (n_max <= 0) return hipSuccess;
+    if (bits < 1) bits = 1;
+    if (digit_bits < 4 || digit_bits > 8) return hipErrorInvalidValue;
+    // As few passes as digit_bits allows, with the bits spread evenly over them (14 tile-id
+    // bits sort as 2 x 7: fewer buckets per pass than 8 + 6).
+    const int passes = (bits + digit_bits - 1) / digit_bits;
+    if (passes > kSortMaxPasses) return hipErrorInvalidValue;
+    int db = (bits + passes - 1) / passes;
+    if (db < 4) db = 4;
+    switch (db) {
+        case 4: sort_passes<4>(keys_in, vals_in, keys_tmp, vals_tmp, keys_out, vals_out, n_max, n_dev, passes, scratch, stall, s); break;
+        case 5: sort_passes<5>(keys_in, vals_in, keys_tmp, vals_tmp, keys_out, vals_out, n_max, n_dev, passes, scratch, stall, s); break;
+        case 6: sort_passes<6>(keys_in, vals_in, keys_tmp, vals_tmp, keys_out, vals_out, n_max, n_dev, passes, scratch, stall, s); break;
+        case 7: sort_passes<7>(keys_in, vals_in, keys_tmp, vals_tmp, keys_out, vals_out, n_max, n_dev, passes, scratch, stall, s); break;
+        default: sort_passes<8>(keys_in, vals_in, keys_tmp, vals_tmp, keys_out, vals_out, n_max, n_dev, passes, scratch, stall, s); break;
     }
     return hipGetLastError();
 }

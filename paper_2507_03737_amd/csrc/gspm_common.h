@@ -65,8 +65,9 @@ struct FrameHeader {
     uint64_t n_pixels;
     uint64_t n_records;
     uint32_t magic;
-    uint32_t visible;  // nonzero if the forward marked contributing records
-    uint32_t pad[4];
+    uint32_t visible;     // nonzero if the forward marked contributing records
+    uint32_t sort_stall;  // nonzero if a radix sort pass abandoned its look-back
+    uint32_t pad[3];
 };
 constexpr uint32_t kFrameMagic = 0x47535046u;  // "GSPF"
 
@@ -354,15 +355,17 @@ hipError_t launch_scan_indirect(const uint32_t *counts, const uint32_t *idx, int
 hipError_t launch_compact(const uint32_t *counts, const uint32_t *flag_scan, const uint32_t *dkey, int64_t n,
                           uint32_t *ckey, uint32_t *cval, hipStream_t s);
 
-// Stable LSD radix sort of (key, value) uint32 pairs over the low `bits` key bits.
-// n_dev: device count (may be NULL: n_max is then exact).  Buffers: keys/vals in,
-// tmp, out (the sorted result ends in keys_out/vals_out).  hist: scratch of
-// radix_hist_words(n_max, digit_bits) words.
+// Stable LSD radix sort of (key, value) uint32 pairs over the low `bits` key bits, in
+// ceil(bits / digit_bits) passes of equal width (digit_bits in [4, 8]).  n_dev: device
+// count (may be NULL: n_max is then exact).  Buffers: keys/vals in, tmp, out (the sorted
+// result ends in keys_out/vals_out).  scratch: radix_hist_words(n_max, digit_bits) words.
+// *stall (device) is set if a pass gave up waiting for an earlier tile (the result is
+// then invalid); the caller clears it.
 int64_t radix_hist_words(int64_t n_max, int digit_bits);
 hipError_t radix_sort(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_tmp,
                       uint32_t *vals_tmp, uint32_t *keys_out, uint32_t *vals_out, int64_t n_max,
-                      const uint32_t *n_dev, int bits, int digit_bits, uint32_t *hist,
-                      uint32_t *scan_part, hipStream_t s);
+                      const uint32_t *n_dev, int bits, int digit_bits, uint32_t *scratch, uint32_t *stall,
+                      hipStream_t s);
 
 // Emits the (global tile, record) pairs of every record in depth order.  Records with
 // more than kBigRecord pairs are queued in big_list (big_count zeroed here) and emitted
