@@ -343,8 +343,10 @@ def main():
     del probe
     rast.max_pairs = int(pairs * 1.3) + 4096
     step = MappingStep(rast, opt, target, prior)
+    rast.cfg.count_work = 1  # one forward that also counts its contributing fragments
     step.run()
     pairs, frags, evals_bound = rast.work(step.fs)
+    rast.cfg.count_work = 0
     log(f"[bench] pairs={pairs} contributing fragments={frags}")
 
     rast.ctx.timing(True)

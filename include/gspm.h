@@ -108,6 +108,8 @@ typedef struct {
     float bg[3];             /* background colour added as T_final * bg [0] */
     int32_t mark_visible;    /* nonzero: the forward records which (Gaussian, view) records
                                 contribute to at least one pixel, for gspm_covisibility [0] */
+    int32_t count_work;      /* nonzero: the forward also counts each pixel's contributing
+                                fragments, which gspm_frame_work reports [0] */
 } gspm_settings;
 
 /* Per-view packed output planes (device): rgb [3][H][W], depth [H][W] (Eq. 3, not
@@ -172,7 +174,8 @@ GSPM_API gspm_status gspm_frame_status(const void *frame_state, void *stream, in
  * out[1] = contributing fragments (Gaussian-pixel pairs composited with alpha >=
  * alpha_min before the transmittance floor), out[2] = sum over pixels of the list
  * entries evaluated up to each pixel's last contributing fragment.  The frame state must
- * come from a forward with the same views, n_gaussians and tile. */
+ * come from a forward with the same views, n_gaussians and tile, run with
+ * settings.count_work != 0 (GSPM_ERR_INVALID_ARG otherwise). */
 GSPM_API gspm_status gspm_frame_work(gspm_ctx *ctx, const gspm_views *views, int64_t n_gaussians, int32_t tile,
                                      const void *frame_state, void *stream, int64_t *out);
 

@@ -186,6 +186,7 @@ gspm_status prepare(const gspm_gaussians *g, const gspm_views *views, const gspm
     P.rs.bg[0] = s->bg[0]; P.rs.bg[1] = s->bg[1]; P.rs.bg[2] = s->bg[2];
     P.rs.frame = s->pointmap_frame;
     P.rs.mark_visible = s->mark_visible != 0 ? 1 : 0;
+    P.rs.count_work = s->count_work != 0 ? 1 : 0;
     return GSPM_OK;
 }
 
@@ -452,6 +453,8 @@ gspm_status gspm_frame_work(gspm_ctx *ctx, const gspm_views *views, int64_t n_ga
     GSPM_HIP(hipMemcpyAsync(host, acc, sizeof(host), hipMemcpyDeviceToHost, hs));
     GSPM_HIP(hipMemcpyAsync(&h, frame_state, sizeof(h), hipMemcpyDeviceToHost, hs));
     GSPM_HIP(hipStreamSynchronize(hs));
+    if (h.magic != kFrameMagic) return fail(GSPM_ERR_INVALID_ARG, "frame_state was not written by a forward");
+    if (!h.counted) return fail(GSPM_ERR_INVALID_ARG, "the forward did not count its work (settings.count_work = 0)");
     out[0] = h.pairs;
     out[1] = (int64_t)host[0];
     out[2] = (int64_t)host[1];

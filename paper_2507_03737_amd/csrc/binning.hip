@@ -224,11 +224,11 @@ k_radix_pass(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
     for (int st = 0; st < kSortSteps; ++st) {
         const bool act = b + st * kWave + lane < n;
         const uint32_t d = (key[st] >> shift) & (R - 1);
-        uint64_t m = __ballot(act);
+        uint64_t m = ballot(act);
 #pragma unroll
         for (int bit = 0; bit < DB; ++bit) {
             const bool set = (d >> bit) & 1u;
-            const uint64_t bb = __ballot(set);
+            const uint64_t bb = ballot(set);
             m &= set ? bb : ~bb;
         }
         rank[st] = 0xffffffffu;
@@ -349,6 +349,7 @@ k_keygen(const uint32_t *__restrict__ sorted_rec, const uint32_t *__restrict__ s
         hdr->capacity = cap;
         hdr->magic = kFrameMagic;
         hdr->visible = (uint32_t)rs.mark_visible;
+        hdr->counted = (uint32_t)rs.count_work;
     }
     uint32_t r = 0, c = 0;
     if (p < n_records) {

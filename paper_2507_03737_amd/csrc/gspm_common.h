@@ -31,6 +31,7 @@ struct RasterSettings {
     float bg[3];
     int32_t frame;  // 0 world, 1 camera, 2 depth back-projection
     int32_t mark_visible;
+    int32_t count_work;  // the forward writes each pixel's contributing-fragment count
 };
 
 // Projected record of one (Gaussian, view) pair: 64 bytes, 4 x float4.
@@ -67,7 +68,8 @@ struct FrameHeader {
     uint32_t magic;
     uint32_t visible;     // nonzero if the forward marked contributing records
     uint32_t sort_stall;  // nonzero if a radix sort pass abandoned its look-back
-    uint32_t pad[3];
+    uint32_t counted;     // nonzero if the forward wrote the contributing-fragment counts
+    uint32_t pad[2];
 };
 constexpr uint32_t kFrameMagic = 0x47535046u;  // "GSPF"
 
@@ -96,6 +98,10 @@ inline FrameLayout frame_layout(int64_t n_tiles, int64_t n_pixels, int64_t n_rec
 // Device helpers.
 
 __device__ inline int lane_id() { return __lane_id(); }
+
+// Lane mask of a predicate.  Takes a bool: HIP's __ballot(int) converts the predicate to
+// an int and back, which costs two vector instructions per call.
+__device__ inline uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
 // Sum over the 64 lanes of a wave using DPP row operations; the total lands in lane 63.
 #define GSPM_DPP(x, ctrl, rmask)                                                            \
@@ -240,7 +246,7 @@ __device__ inline uint32_t wave_inclusive_scan(uint32_t x) {
 // Appends the lanes with pred set to a global queue with one atomic per wave; returns
 // each such lane's slot.  Must be reached by every active lane of the wave.
 __device__ inline uint32_t wave_append(uint32_t *counter, bool pred) {
-    const uint64_t m = __ballot(pred);
+    const uint64_t m = ballot(pred);
     if (m == 0ull) return 0u;
     const int lane = lane_id();
     const int leader = __ffsll((unsigned long long)m) - 1;

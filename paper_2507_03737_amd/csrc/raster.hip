@@ -136,13 +136,14 @@ __device__ inline uint64_t batch_mask(const float4 *s0, const float4 *s1, int c,
     const int n = cnt - c;
     if (!CULL) return n >= kWave ? ~0ull : ((1ull << n) - 1ull);
     const int q = c + lane_id();
-    return __ballot(q < cnt && meets_rect(s0[q], s1[q], x0, x1, y0, y1));
+    return ballot(q < cnt && meets_rect(s0[q], s1[q], x0, x1, y0, y1));
 }
 
 // FRAME is the pointmap frame (0 world, 1 camera, 2 from the depth, Eq. 5).  In the
 // camera frame the depth is the composited point's z and is not accumulated twice; in
-// frame 2 the point is not accumulated at all.
-template <int TILE, int PPT, int FRAME>
+// frame 2 the point is not accumulated at all.  COUNT: also write each pixel's number of
+// contributing fragments (work statistics).
+template <int TILE, int PPT, int FRAME, bool COUNT>
 __global__ void __launch_bounds__(TILE *TILE / PPT)
 k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
              const float4 *__restrict__ rec, float *__restrict__ out_rgb, float *__restrict__ out_depth,
@@ -160,8 +161,11 @@ k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
     const int i = tp.tx * TILE + lx;
 
     float T[PPT], C0[PPT], C1[PPT], C2[PPT], D[PPT], X0[PPT], X1[PPT], X2[PPT], py[PPT];
+    // 0 while the pixel composites, -inf once it has stopped (or lies outside the view).
+    // Added to the exponent, it turns the acceptance test into one comparison, whose lane
+    // mask is the wave's ballot as it stands.
+    float bias[PPT];
     uint32_t n_last[PPT], n_contrib[PPT];
-    bool done[PPT];
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
         T[k] = 1.0f;
@@ -169,17 +173,17 @@ k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
         n_last[k] = n_contrib[k] = 0u;
         py[k] = (float)(ly + k);
         const int j = tp.ty * TILE + ly + k;
-        done[k] = !(i < tp.W && j < tp.H);
+        bias[k] = (i < tp.W && j < tp.H) ? 0.0f : -INFINITY;
     }
     // Whether any pixel of this lane is still compositing.  Re-evaluated once per 64
     // entries: a wave whose pixels have all stopped walks at most the rest of one mask.
     auto lane_live = [&]() {
         bool l = false;
 #pragma unroll
-        for (int k = 0; k < PPT; ++k) l |= !done[k];
+        for (int k = 0; k < PPT; ++k) l |= bias[k] == 0.0f;
         return l;
     };
-    bool wave_live = __ballot(lane_live()) != 0ull;
+    bool wave_live = ballot(lane_live()) != 0ull;
     for (uint32_t base = rg.x; base < rg.y; base += NT) {
         const uint32_t kk = base + threadIdx.x;
         if (kk < rg.y) stage(rec, vals[kk], tp.x0, tp.y0, amin, s0, s1, s2, s3, threadIdx.x);
@@ -196,14 +200,14 @@ k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
                 const float Adx2 = a.z * dx * dx, Bdx = a.w * dx;
                 float e[PPT];
                 bool ok[PPT];
-                bool pass = false;
+                uint64_t pass = 0ull;
 #pragma unroll
                 for (int k = 0; k < PPT; ++k) {
-                    e[k] = quad_e(Adx2, Bdx, b.x, py[k] - a.y);
-                    ok[k] = !done[k] && e[k] >= b.y;
-                    pass |= ok[k];
+                    e[k] = quad_e(Adx2, Bdx, b.x, py[k] - a.y) + bias[k];
+                    ok[k] = e[k] >= b.y;
+                    pass |= ballot(ok[k]);
                 }
-                if (__ballot(pass) == 0ull) continue;  // wave-uniform: nothing composites this entry
+                if (pass == 0ull) continue;  // wave-uniform: nothing composites this entry
                 const float4 cc = s2[q];
                 const float4 d = s3[q];
                 const uint32_t rel = base - rg.x + (uint32_t)q + 1u;
@@ -226,15 +230,15 @@ k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
                     }
                     T[k] = add ? Tn : T[k];
                     n_last[k] = add ? rel : n_last[k];
-                    n_contrib[k] += add ? 1u : 0u;
-                    done[k] = done[k] || stop;
+                    if (COUNT) n_contrib[k] += add ? 1u : 0u;
+                    bias[k] = stop ? -INFINITY : bias[k];
                     added |= add;
                 }
                 if (visible) {  // uniform: marking requested
-                    if (__ballot(added) != 0ull && lane_id() == 0) visible[__float_as_uint(b.w)] = 1;
+                    if (ballot(added) != 0ull && lane_id() == 0) visible[__float_as_uint(b.w)] = 1;
                 }
             }
-            wave_live = __ballot(lane_live()) != 0ull;
+            wave_live = ballot(lane_live()) != 0ull;
         }
         if (!__syncthreads_or(lane_live() ? 1 : 0)) break;
     }
@@ -263,7 +267,7 @@ k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
         out_pm[o3 + 2 * plane] = x2;
         t_final[pix] = T[k];
         last[pix] = n_last[k];
-        contrib[pix] = n_contrib[k];
+        if (COUNT) contrib[pix] = n_contrib[k];
     }
 }
 
@@ -391,14 +395,15 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
                 const float Adx2 = a.z * dx * dx, Bdx = a.w * dx;
                 float e[PPT];
                 bool valid[PPT];
-                bool any = false;
+                uint64_t any = 0ull;
 #pragma unroll
                 for (int k = 0; k < PPT; ++k) {
                     e[k] = quad_e(Adx2, Bdx, b.x, py[k] - a.y);
-                    valid[k] = rel < my_last[k] && e[k] >= b.y;
-                    any |= valid[k];
+                    // One comparison decides (its lane mask is the ballot as it stands).
+                    valid[k] = (rel < my_last[k] ? e[k] : -INFINITY) >= b.y;
+                    any |= ballot(valid[k]);
                 }
-                if (__ballot(any) == 0ull) continue;  // wave-uniform
+                if (any == 0ull) continue;  // wave-uniform
                 const float4 cc = s2[q];
                 const float4 d = s3[q];
                 float v[V::NR];
@@ -476,9 +481,14 @@ hipError_t launch_raster_forward(const ViewTable &vt, const RasterSettings &rs, 
     const int n_tiles = vt.tile_off[vt.n_views];
     const float4 *rec = reinterpret_cast<const float4 *>(records);
     if (rs.frame < 0 || rs.frame > 2) return hipErrorInvalidValue;
-#define GSPM_FWD1(T_, P_, F_)                                                                        \
-    hipLaunchKernelGGL((k_raster_fwd<T_, P_, F_>), dim3(n_tiles), dim3(T_ * T_ / P_), 0, s, vt, rs, \
+#define GSPM_FWD2(T_, P_, F_, C_)                                                                        \
+    hipLaunchKernelGGL((k_raster_fwd<T_, P_, F_, C_>), dim3(n_tiles), dim3(T_ * T_ / P_), 0, s, vt, rs, \
                        ranges, pair_vals, rec, rgb, depth, alpha, pointmap, t_final, last, contrib, visible)
+#define GSPM_FWD1(T_, P_, F_)                                                                  \
+    do {                                                                                       \
+        if (rs.count_work) GSPM_FWD2(T_, P_, F_, true);                                        \
+        else GSPM_FWD2(T_, P_, F_, false);                                                     \
+    } while (0)
 #define GSPM_FWD(T_, P_)                                      \
     if (vt.tile == T_ && vt.ppt == P_) {                      \
         if (rs.frame == 0) GSPM_FWD1(T_, P_, 0);              \
@@ -488,6 +498,7 @@ hipError_t launch_raster_forward(const ViewTable &vt, const RasterSettings &rs, 
     }
     GSPM_RASTER_CONFIGS(GSPM_FWD)
 #undef GSPM_FWD
+#undef GSPM_FWD2
 #undef GSPM_FWD1
     return hipErrorInvalidValue;
 }

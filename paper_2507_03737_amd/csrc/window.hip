@@ -122,11 +122,11 @@ k_median_hist(ViewTable vt, const float *__restrict__ depth, int round, const Me
         const bool valid = x > 0.0f && (round == 0 || (b >> (shift + 8)) == prefix);
         const uint32_t bin = (b >> shift) & 255u;
         // Depths cluster in few bins: one LDS atomic per distinct bin of the wave.
-        uint64_t active = __ballot(valid);
+        uint64_t active = ballot(valid);
         while (active) {
             const int leader = __ffsll((unsigned long long)active) - 1;
             const uint32_t lb = (uint32_t)__shfl((int)bin, leader, kWave);
-            const uint64_t same = __ballot(valid && bin == lb);
+            const uint64_t same = ballot(valid && bin == lb);
             if (lane == leader) atomicAdd(&h[lb], (uint32_t)__popcll(same));
             active &= ~same;
         }

@@ -109,6 +109,38 @@ def test_wave_cull_is_exact(lib):
             assert np.array_equal(outs[ppl][k], ref, equal_nan=True), f"(16,{ppl}) {k}"
 
 
+@pytest.mark.parametrize("tile,ppl", [(16, 1), (32, 2)])
+def test_contributing_counts_exact(lib, oracle, tile, ppl):
+    """Per-pixel counts of contributing fragments (alpha >= alpha_min before the
+    transmittance floor) equal the oracle's, bit for bit, wherever no decision lies within
+    rounding of its threshold; the work query reports their sum and refuses a frame state
+    whose forward did not count."""
+    U.log(f"[gpu] contributing counts c0 tile {tile} ppl {ppl}")
+    sc = _posed(scenes.make_scene("c0"))
+    cam = sc.cams[0]
+    cfg = lib.RasterConfig(pointmap_frame=1, tile=tile, pixels_per_lane=ppl)
+    rast, params, out, fs = _render_gpu(lib, sc, cfg)
+    with pytest.raises(lib.GspmError):
+        rast.work(fs)
+    cfg.count_work = 1
+    out, fs = rast.forward(params)
+    torch.cuda.synchronize()
+    pairs, frags, _ = rast.work(fs)
+    n_tiles = math.ceil(cam.width / tile) * math.ceil(cam.height / tile)
+    lay = U.frame_layout(n_tiles, cam.width * cam.height, sc.n)
+    raw = fs.cpu().numpy()
+    got = raw[lay["contrib"]:lay["contrib"] + 4 * cam.width * cam.height].view(np.uint32)
+    got = got.reshape(cam.height, cam.width)
+    S = _oracle_settings(oracle, cfg)
+    ref, _ = U.oracle_view_images(oracle, oracle.Params.from_scene(sc), cam, sc.T_cw[0], S, None)
+    ok = (ref["ambiguous"] == 0).reshape(cam.height, cam.width)
+    n_ref = ref["n_frag"].reshape(cam.height, cam.width)
+    bad = int((got[ok] != n_ref[ok]).sum())
+    U.log(f"  fragments {frags} (oracle {int(n_ref.sum())}), pixels checked {int(ok.sum())}, mismatches {bad}")
+    assert bad == 0
+    assert frags == int(got.astype(np.int64).sum())
+
+
 @pytest.mark.parametrize("tile,ppl", [(16, 2), (8, 1)])
 def test_tile_lists_exact(lib, oracle, tile, ppl):
     """Per-tile (record) lists equal the oracle's brute-force lists, ordered by
