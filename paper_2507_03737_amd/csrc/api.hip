@@ -72,7 +72,7 @@ struct gspm_ctx {
     // Per pair (capacity).
     DevBuf pkey, pval, pkey_tmp, pval_tmp, pkey_s;
     // Small scratch.
-    DevBuf hist, scan_part, misc, pose_part, loss_part, align, aux, pnp;
+    DevBuf hist, scan_part, misc, pose_part, loss_part, align, aux, pnp, twork;
 };
 
 namespace {
@@ -260,7 +260,8 @@ gspm_status backward_common(gspm_ctx *ctx, const gspm_gaussians *g, const gspm_v
     PhaseTimer t_rb(ctx, hs, GSPM_PHASE_RASTER_BWD);
     GSPM_HIP(launch_raster_backward(P.vt, P.rs, at<uint2>(frame_state, L.ranges), at<uint32_t>(frame_state, L.pair_vals),
                                     at<float>(frame_state, L.records), at<uint32_t>(frame_state, L.last),
-                                    at<float>(frame_state, L.t_final), *fwd_out, *grad_out, g2, pose_only, hs));
+                                    at<float>(frame_state, L.t_final), *fwd_out, *grad_out, g2, pose_only,
+                                    at<uint32_t>(frame_state, L.order) + P.n_tiles, hs));
     t_rb.stop();
     PhaseTimer t_pb(ctx, hs, GSPM_PHASE_PARAM_BWD);
     gspm_gaussian_grads none = {nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -288,7 +289,7 @@ void gspm_destroy(gspm_ctx *ctx) {
     DevBuf *bufs[] = {&ctx->counts, &ctx->big, &ctx->live, &ctx->dkey, &ctx->dval, &ctx->dkey_tmp, &ctx->dval_tmp,
                       &ctx->dkey_s, &ctx->dval_s, &ctx->offsets, &ctx->grad2d, &ctx->pkey, &ctx->pval,
                       &ctx->pkey_tmp, &ctx->pval_tmp, &ctx->pkey_s, &ctx->hist, &ctx->scan_part, &ctx->misc,
-                      &ctx->pose_part, &ctx->loss_part, &ctx->align, &ctx->aux, &ctx->pnp};
+                      &ctx->pose_part, &ctx->loss_part, &ctx->align, &ctx->aux, &ctx->pnp, &ctx->twork};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
@@ -406,6 +407,12 @@ gspm_status gspm_render_forward(gspm_ctx *ctx, const gspm_gaussians *g, const gs
         PhaseTimer t_rg(ctx, hs, GSPM_PHASE_BINNING);
         GSPM_HIP(launch_ranges(static_cast<uint32_t *>(ctx->pkey_s.p), hdr, ranges, P.n_tiles, cap, hs));
     }
+    // Heaviest tiles first: by list length for the forward; the forward measures each
+    // tile's contributing depth, which orders the backward.
+    uint32_t *order = at<uint32_t>(frame_state, L0.order);
+    GSPM_HIP(grow(ctx->twork, 4 * (P.n_tiles > 0 ? P.n_tiles : 1)));
+    uint32_t *twork = static_cast<uint32_t *>(ctx->twork.p);
+    GSPM_HIP(launch_order_tiles(ranges, nullptr, P.n_tiles, order, hs));
     // 7. Composite (optionally marking the records that contribute to a pixel).
     uint8_t *visible = nullptr;
     if (P.rs.mark_visible) {
@@ -415,7 +422,8 @@ gspm_status gspm_render_forward(gspm_ctx *ctx, const gspm_gaussians *g, const gs
     PhaseTimer t_fwd(ctx, hs, GSPM_PHASE_RASTER_FWD);
     GSPM_HIP(launch_raster_forward(P.vt, P.rs, ranges, pair_vals, records, out->rgb, out->depth, out->alpha,
                                    out->pointmap, at<float>(frame_state, L0.t_final), at<uint32_t>(frame_state, L0.last),
-                                   at<uint32_t>(frame_state, L0.contrib), visible, hs));
+                                   at<uint32_t>(frame_state, L0.contrib), visible, order, twork, hs));
+    GSPM_HIP(launch_order_tiles(nullptr, twork, P.n_tiles, order + P.n_tiles, hs));
     return GSPM_OK;
 }
 

@@ -561,6 +561,45 @@ hipError_t launch_keygen(const uint32_t *sorted_rec, const uint32_t *sorted_coun
     return hipGetLastError();
 }
 
+// One workgroup: counting sort of the tiles into 256 work classes (32 list entries each,
+// the last one open-ended), heaviest class first.  The order inside a class is that of
+// the atomics; any order is a valid launch order.
+constexpr int kOrderBlock = 1024;
+constexpr int kOrderClasses = 256;
+constexpr int kOrderShift = 5;
+
+__global__ void __launch_bounds__(kOrderBlock)
+k_order_tiles(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ work, int64_t n,
+              uint32_t *__restrict__ order) {
+    __shared__ uint32_t cnt[kOrderClasses];
+    for (int b = threadIdx.x; b < kOrderClasses; b += kOrderBlock) cnt[b] = 0u;
+    __syncthreads();
+    auto cls = [&](int64_t t) {
+        const uint32_t w = ranges ? ranges[t].y - ranges[t].x : work[t];
+        return (uint32_t)(kOrderClasses - 1) - min((uint32_t)(kOrderClasses - 1), w >> kOrderShift);
+    };
+    for (int64_t t = threadIdx.x; t < n; t += kOrderBlock) atomicAdd(&cnt[cls(t)], 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0;
+        for (int b = 0; b < kOrderClasses; ++b) {
+            const uint32_t c = cnt[b];
+            cnt[b] = acc;
+            acc += c;
+        }
+    }
+    __syncthreads();
+    for (int64_t t = threadIdx.x; t < n; t += kOrderBlock) order[atomicAdd(&cnt[cls(t)], 1u)] = (uint32_t)t;
+}
+
+hipError_t launch_order_tiles(const uint2 *ranges, const uint32_t *work, int64_t n_tiles, uint32_t *order,
+                              hipStream_t s) {
+    if (n_tiles <= 0) return hipSuccess;
+    if ((ranges == nullptr) == (work == nullptr)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_order_tiles, dim3(1), dim3(kOrderBlock), 0, s, ranges, work, n_tiles, order);
+    return hipGetLastError();
+}
+
 hipError_t launch_ranges(const uint32_t *sorted_keys, const FrameHeader *hdr, uint2 *ranges, int64_t n_tiles,
                          int64_t n_max, hipStream_t s) {
     (void)n_tiles;

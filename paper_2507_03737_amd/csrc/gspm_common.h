@@ -74,7 +74,7 @@ struct FrameHeader {
 constexpr uint32_t kFrameMagic = 0x47535046u;  // "GSPF"
 
 struct FrameLayout {
-    int64_t header, visible, ranges, t_final, last, contrib, records, pair_vals, total;
+    int64_t header, visible, ranges, t_final, last, contrib, order, records, pair_vals, total;
 };
 
 inline int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
@@ -88,6 +88,7 @@ inline FrameLayout frame_layout(int64_t n_tiles, int64_t n_pixels, int64_t n_rec
     L.t_final = o;   o += align256(n_pixels * 4);
     L.last = o;      o += align256(n_pixels * 4);
     L.contrib = o;   o += align256(n_pixels * 4);
+    L.order = o;     o += align256(2 * n_tiles * 4);  // launch orders of the forward and backward
     L.records = o;   o += align256(n_records * kRecFloats * 4);
     L.pair_vals = o; o += align256(cap * 4);
     L.total = o;
@@ -417,18 +418,26 @@ hipError_t launch_median_depth(const ViewTable &vt, const float *depth, uint32_t
 hipError_t launch_ranges(const uint32_t *sorted_keys, const FrameHeader *hdr, uint2 *ranges,
                          int64_t n_tiles, int64_t n_max, hipStream_t s);
 
+// Launch order of the raster workgroups, heaviest tiles first: the tiles' work is the list
+// length (ranges) or a per-tile estimate (work); exactly one of the two is given.
+hipError_t launch_order_tiles(const uint2 *ranges, const uint32_t *work, int64_t n_tiles, uint32_t *order,
+                              hipStream_t s);
+
 bool raster_config_supported(int tile, int ppt);
 
+// order: workgroup -> tile (NULL: identity).  tile_work (optional) receives each tile's
+// largest per-pixel list count up to the last contributing fragment.
 hipError_t launch_raster_forward(const ViewTable &vt, const RasterSettings &rs, const uint2 *ranges,
                                  const uint32_t *pair_vals, const float *records, float *rgb,
                                  float *depth, float *alpha, float *pointmap, float *t_final,
-                                 uint32_t *last, uint32_t *contrib, uint8_t *visible, hipStream_t s);
+                                 uint32_t *last, uint32_t *contrib, uint8_t *visible, const uint32_t *order,
+                                 uint32_t *tile_work, hipStream_t s);
 
 hipError_t launch_raster_backward(const ViewTable &vt, const RasterSettings &rs, const uint2 *ranges,
                                   const uint32_t *pair_vals, const float *records, const uint32_t *last,
                                   const float *t_final, const gspm_const_images &fwd,
                                   const gspm_const_images &up, float *grad2d, bool pose_only,
-                                  hipStream_t s);
+                                  const uint32_t *order, hipStream_t s);
 
 hipError_t launch_preprocess_backward(const gspm_gaussians &g, const ViewTable &vt, const float *T_cw,
                                       const RasterSettings &rs, const float *grad2d,

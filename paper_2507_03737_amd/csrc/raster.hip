@@ -41,10 +41,12 @@ struct TilePos {
     int64_t pix_off;  // packed offset of the view
 };
 
+// Workgroups run the tiles in the given order (heaviest first, so that the long lists do
+// not start last and leave the chip idle behind them).
 template <int TILE>
-__device__ inline TilePos tile_pos(const ViewTable &vt) {
+__device__ inline TilePos tile_pos(const ViewTable &vt, const uint32_t *order) {
     TilePos p;
-    const int gt = (int)blockIdx.x;
+    const int gt = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
     p.gt = gt;
     p.v = find_view(vt, gt);
     const int lt = gt - vt.tile_off[p.v];
@@ -148,11 +150,13 @@ __global__ void __launch_bounds__(TILE *TILE / PPT)
 k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
              const float4 *__restrict__ rec, float *__restrict__ out_rgb, float *__restrict__ out_depth,
              float *__restrict__ out_alpha, float *__restrict__ out_pm, float *__restrict__ t_final,
-             uint32_t *__restrict__ last, uint32_t *__restrict__ contrib, uint8_t *__restrict__ visible) {
+             uint32_t *__restrict__ last, uint32_t *__restrict__ contrib, uint8_t *__restrict__ visible,
+             const uint32_t *__restrict__ order, uint32_t *__restrict__ tile_work) {
     using L = Layout<TILE, PPT>;
     constexpr int NT = L::NT;
     __shared__ float4 s0[NT], s1[NT], s2[NT], s3[NT];
-    const TilePos tp = tile_pos<TILE>(vt);
+    __shared__ uint32_t block_work;
+    const TilePos tp = tile_pos<TILE>(vt, order);
     const uint2 rg = ranges[tp.gt];
     const L lay;
     const int lx = lay.lx, ly = lay.ly;
@@ -269,6 +273,17 @@ k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
         last[pix] = n_last[k];
         if (COUNT) contrib[pix] = n_contrib[k];
     }
+    if (tile_work) {  // uniform
+        if (threadIdx.x == 0) block_work = 0u;
+        __syncthreads();
+        uint32_t m = 0u;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) m = max(m, n_last[k]);
+        for (int off = 32; off > 0; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off, 64));
+        if (lane_id() == 0) atomicMax(&block_work, m);
+        __syncthreads();
+        if (threadIdx.x == 0) tile_work[tp.gt] = block_work;
+    }
 }
 
 __device__ inline float load_or0(const float *p, int64_t i) { return p ? p[i] : 0.0f; }
@@ -302,13 +317,14 @@ template <int TILE, int PPT, bool POSE_ONLY, int FRAME>
 __global__ void __launch_bounds__(TILE *TILE / PPT)
 k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
              const float4 *__restrict__ rec, const uint32_t *__restrict__ last, const float *__restrict__ t_final,
-             gspm_const_images fwd, gspm_const_images up, float *__restrict__ grad2d) {
+             gspm_const_images fwd, gspm_const_images up, float *__restrict__ grad2d,
+             const uint32_t *__restrict__ order) {
     using L = Layout<TILE, PPT>;
     using V = BwdValues<POSE_ONLY, FRAME>;
     constexpr int NT = L::NT;
     __shared__ float4 s0[NT], s1[NT], s2[NT], s3[NT];
     __shared__ uint32_t block_last;
-    const TilePos tp = tile_pos<TILE>(vt);
+    const TilePos tp = tile_pos<TILE>(vt, order);
     const uint2 rg = ranges[tp.gt];
     const L lay;
     const int lx = lay.lx, ly = lay.ly;
@@ -477,13 +493,14 @@ bool raster_config_supported(int tile, int ppt) {
 hipError_t launch_raster_forward(const ViewTable &vt, const RasterSettings &rs, const uint2 *ranges,
                                  const uint32_t *pair_vals, const float *records, float *rgb, float *depth,
                                  float *alpha, float *pointmap, float *t_final, uint32_t *last, uint32_t *contrib,
-                                 uint8_t *visible, hipStream_t s) {
+                                 uint8_t *visible, const uint32_t *order, uint32_t *tile_work, hipStream_t s) {
     const int n_tiles = vt.tile_off[vt.n_views];
     const float4 *rec = reinterpret_cast<const float4 *>(records);
     if (rs.frame < 0 || rs.frame > 2) return hipErrorInvalidValue;
 #define GSPM_FWD2(T_, P_, F_, C_)                                                                        \
     hipLaunchKernelGGL((k_raster_fwd<T_, P_, F_, C_>), dim3(n_tiles), dim3(T_ * T_ / P_), 0, s, vt, rs, \
-                       ranges, pair_vals, rec, rgb, depth, alpha, pointmap, t_final, last, contrib, visible)
+                       ranges, pair_vals, rec, rgb, depth, alpha, pointmap, t_final, last, contrib, visible,   \
+                       order, tile_work)
 #define GSPM_FWD1(T_, P_, F_)                                                                  \
     do {                                                                                       \
         if (rs.count_work) GSPM_FWD2(T_, P_, F_, true);                                        \
@@ -506,13 +523,13 @@ hipError_t launch_raster_forward(const ViewTable &vt, const RasterSettings &rs, 
 hipError_t launch_raster_backward(const ViewTable &vt, const RasterSettings &rs, const uint2 *ranges,
                                   const uint32_t *pair_vals, const float *records, const uint32_t *last,
                                   const float *t_final, const gspm_const_images &fwd, const gspm_const_images &up,
-                                  float *grad2d, bool pose_only, hipStream_t s) {
+                                  float *grad2d, bool pose_only, const uint32_t *order, hipStream_t s) {
     const int n_tiles = vt.tile_off[vt.n_views];
     const float4 *rec = reinterpret_cast<const float4 *>(records);
     if (rs.frame < 0 || rs.frame > 2) return hipErrorInvalidValue;
 #define GSPM_BWD1(T_, P_, PO_, F_)                                                                         \
     hipLaunchKernelGGL((k_raster_bwd<T_, P_, PO_, F_>), dim3(n_tiles), dim3(T_ * T_ / P_), 0, s, vt, rs, \
-                       ranges, pair_vals, rec, last, t_final, fwd, up, grad2d)
+                       ranges, pair_vals, rec, last, t_final, fwd, up, grad2d, order)
 #define GSPM_BWD2(T_, P_, PO_)                            \
     if (rs.frame == 0) GSPM_BWD1(T_, P_, PO_, 0);         \
     else if (rs.frame == 1) GSPM_BWD1(T_, P_, PO_, 1);    \

@@ -109,6 +109,7 @@ def frame_layout(n_tiles, n_pixels, n_records):
     lay["t_final"] = o; o += a(n_pixels * 4)
     lay["last"] = o; o += a(n_pixels * 4)
     lay["contrib"] = o; o += a(n_pixels * 4)
+    lay["order"] = o; o += a(2 * n_tiles * 4)
     lay["records"] = o; o += a(n_records * 64)
     lay["pair_vals"] = o
     return lay

@@ -141,6 +141,39 @@ def test_contributing_counts_exact(lib, oracle, tile, ppl):
     assert frags == int(got.astype(np.int64).sum())
 
 
+def test_launch_orders(lib):
+    """The forward and backward launch orders are permutations of the tiles, heaviest
+    first: non-increasing in list length (forward) and in the deepest contributing list
+    entry of the tile (backward), in classes of 32 entries."""
+    U.log("[gpu] launch orders c1")
+    sc = _posed(scenes.make_scene("c1"))
+    cfg = lib.RasterConfig(pointmap_frame=1, tile=16, pixels_per_lane=1)
+    rast, params, out, fs = _render_gpu(lib, sc, cfg)
+    cam = sc.cams[0]
+    n_tiles = math.ceil(cam.width / 16) * math.ceil(cam.height / 16) * len(sc.cams)
+    npix = sum(c.width * c.height for c in sc.cams)
+    assert all((c.width, c.height) == (cam.width, cam.height) for c in sc.cams)
+    lay = U.frame_layout(n_tiles, npix, sc.n * len(sc.cams))
+    raw = fs.cpu().numpy()
+    ranges = raw[lay["ranges"]:lay["ranges"] + 8 * n_tiles].view(np.uint32).reshape(n_tiles, 2)
+    order = raw[lay["order"]:lay["order"] + 8 * n_tiles].view(np.uint32).reshape(2, n_tiles)
+    last = raw[lay["last"]:lay["last"] + 4 * npix].view(np.uint32)
+    for o in order:
+        assert np.array_equal(np.sort(o), np.arange(n_tiles, dtype=np.uint32))
+    cls = lambda w: np.minimum(w.astype(np.int64) >> 5, 255)  # noqa: E731
+    assert np.all(np.diff(cls(ranges[order[0], 1] - ranges[order[0], 0])) <= 0)
+    # Deepest contributing entry per tile, from the per-pixel counts.
+    tx, ty = math.ceil(cam.width / 16), math.ceil(cam.height / 16)
+    deep = []
+    for v in range(len(sc.cams)):
+        img = last[v * cam.width * cam.height:(v + 1) * cam.width * cam.height].reshape(cam.height, cam.width)
+        pad = np.zeros((ty * 16, tx * 16), np.uint32)
+        pad[:cam.height, :cam.width] = img
+        deep.append(pad.reshape(ty, 16, tx, 16).max(axis=(1, 3)).reshape(-1))
+    deep = np.concatenate(deep)
+    assert np.all(np.diff(cls(deep[order[1]])) <= 0)
+
+
 @pytest.mark.parametrize("tile,ppl", [(16, 2), (8, 1)])
 def test_tile_lists_exact(lib, oracle, tile, ppl):
     """Per-tile (record) lists equal the oracle's brute-force lists, ordered by
