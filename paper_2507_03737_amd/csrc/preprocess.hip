@@ -118,12 +118,13 @@ __global__ void __launch_bounds__(256)
 k_preprocess(gspm_gaussians G, ViewTable vt, const float *__restrict__ T_cw, RasterSettings rs,
              float4 *__restrict__ rec, uint32_t *__restrict__ counts, uint32_t *__restrict__ dkey,
              uint32_t *__restrict__ big_list, uint32_t *__restrict__ big_count) {
+    // blockIdx.y is the view: no 64-bit division to split the record index.
     const int64_t n = G.n;
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = (int)blockIdx.y;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t r = (int64_t)v * n + g;
     bool big = false;
-    if (r < n * vt.n_views) {
-        const int v = (int)(r / n);
-        const int64_t g = r - (int64_t)v * n;
+    if (g < n) {
         Proj P;
         project_one(G, g, n, T_cw + 12 * v, vt.fx[v], vt.fy[v], vt.cx[v], vt.cy[v], vt.width[v],
                     vt.height[v], rs, P);
@@ -472,8 +473,8 @@ hipError_t launch_preprocess(const gspm_gaussians &g, const ViewTable &vt, const
     hipError_t e = launch_fill_u32(big_count, 0u, 1, s);
     if (e != hipSuccess) return e;
     (void)dval;
-    hipLaunchKernelGGL(k_preprocess, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, s, g, vt, T_cw, rs,
-                       reinterpret_cast<float4 *>(records), counts, dkey, big_list, big_count);
+    hipLaunchKernelGGL(k_preprocess, dim3((unsigned)((g.n + 255) / 256), (unsigned)vt.n_views), dim3(256), 0, s, g,
+                       vt, T_cw, rs, reinterpret_cast<float4 *>(records), counts, dkey, big_list, big_count);
     hipLaunchKernelGGL(k_count_big, dim3(1024), dim3(256), 0, s, reinterpret_cast<const float4 *>(records), vt, rs,
                        g.n, counts, big_list, big_count);
     return hipGetLastError();
