@@ -43,6 +43,7 @@ HBM_PEAK_GBS = 8000.0
 # Measured HBM traffic of the dominant kernel (rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by
 # the same counters on a copy of known size) and the hash of the sources it was taken on.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "raster_bwd_c3_traffic.txt")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "raster_c3_counters.md")
 KERNEL_SOURCES = ("paper_2507_03737_amd/csrc/raster.hip", "paper_2507_03737_amd/csrc/gspm_common.h")
 COPY_BYTES = 1 << 29  # 512 MiB read + 512 MiB written by the calibration copy
 
@@ -93,11 +94,11 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def stored_traffic(kernel, workload, tile, ppl):
-    """HBM bytes per launch from the committed counter summary, if it was taken on the
+def stored_record(path, kernel, workload, tile, ppl):
+    """The machine-readable line of a committed counter summary, if it was taken on the
     current kernel sources and the same launch shape; else None."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             rec = json.loads([ln for ln in fh.read().splitlines() if ln.startswith("{")][-1])
     except (OSError, ValueError, IndexError):
         return None
@@ -105,7 +106,13 @@ def stored_traffic(kernel, workload, tile, ppl):
         return None
     if rec.get("source_sha256") != kernel_source_hash():
         return None
-    return rec.get("hbm_bytes_per_launch")
+    return rec
+
+
+def stored_traffic(kernel, workload, tile, ppl):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy)."""
+    rec = stored_record(TRAFFIC_FILE, kernel, workload, tile, ppl)
+    return None if rec is None else rec.get("hbm_bytes_per_launch")
 
 
 def copy_calibration(torch, dev):
@@ -412,6 +419,11 @@ def main():
         roof = {"kernel": dominant, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None, "algorithmic": f"{nbytes} bytes"}
     roof["kernel_ms"] = ph_ms[dominant]
+    # Instruction issue: the counted wave-level VALU instructions per launch over this run's
+    # launch time, against 1024 SIMDs x 2.4 GHz / 4 cycles per wave64 instruction.
+    cnt = stored_record(COUNTERS_FILE, dominant, args.workload, cfg.tile, cfg.pixels_per_lane)
+    if cnt is not None and "valu_insts_per_launch" in cnt:
+        roof["valu_issue_frac"] = cnt["valu_insts_per_launch"] / (ph_ms[dominant] * 1e-3) / cnt["valu_issue_peak_per_s"]
 
     mapping_ops = None
     tracking = None
