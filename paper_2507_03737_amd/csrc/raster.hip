@@ -200,6 +200,8 @@ k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
                 m &= m - 1ull;
                 const float4 a = s0[q];
                 const float4 b = s1[q];
+                // One 16-byte read now rather than a second, split read after the test.
+                asm volatile("" ::"v"(b.z), "v"(b.w));
                 const float dx = px - a.x;
                 const float Adx2 = a.z * dx * dx, Bdx = a.w * dx;
                 float e[PPT];
@@ -407,6 +409,8 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
                 if (rel >= wave_last) break;  // wave-uniform
                 const float4 a = s0[q];
                 const float4 b = s1[q];
+                // One 16-byte read now rather than a second, split read after the test.
+                asm volatile("" ::"v"(b.z), "v"(b.w));
                 const float dx = px - a.x;
                 const float Adx2 = a.z * dx * dx, Bdx = a.w * dx;
                 float e[PPT];
