@@ -209,7 +209,7 @@ hipError_t ensure_records(gspm_ctx *c, int64_t R, int digit_bits) {
     if ((e = grow(c->dkey_s, 4 * w))) return e;
     if ((e = grow(c->dval_s, 4 * w))) return e;
     if ((e = grow(c->offsets, 4 * w))) return e;
-    if ((e = grow(c->hist, 4 * (radix_hist_words(w, digit_bits) + 2)))) return e;
+    if ((e = grow(c->hist, 4 * radix_hist_words(w, digit_bits)))) return e;
     if ((e = grow(c->scan_part, 4 * 1024))) return e;
     if ((e = grow(c->misc, 256))) return e;
     return hipSuccess;
@@ -223,7 +223,7 @@ hipError_t ensure_pairs(gspm_ctx *c, int64_t cap, int digit_bits) {
     if ((e = grow(c->pkey_tmp, 4 * w))) return e;
     if ((e = grow(c->pval_tmp, 4 * w))) return e;
     if ((e = grow(c->pkey_s, 4 * w))) return e;
-    if ((e = grow(c->hist, 4 * (radix_hist_words(w, digit_bits) + 2)))) return e;
+    if ((e = grow(c->hist, 4 * radix_hist_words(w, digit_bits)))) return e;
     return hipSuccess;
 }
 
