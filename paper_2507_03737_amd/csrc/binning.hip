@@ -362,13 +362,13 @@ k_keygen(const uint32_t *__restrict__ sorted_rec, const uint32_t *__restrict__ s
     if (c == 0 || big) return;
     uint32_t k = offsets[p];
     if (k >= cap) return;
-    const int v = (int)(r / n_per_view);
+    const int v = (int)(r / (uint32_t)n_per_view);  // 32-bit: record indices fit
     Footprint f;
     if (!record_footprint(rec[4 * (int64_t)r], rec[4 * (int64_t)r + 1], rs.alpha_min, vt.width[v], vt.height[v], f))
         return;
-    const int T = vt.tile;
+    const int T = vt.tile, sh = __builtin_ctz((unsigned)vt.tile);
     const uint32_t base = (uint32_t)vt.tile_off[v], tiles_x = (uint32_t)vt.tiles_x[v];
-    for (int ty = f.j0 / T; ty <= f.j1 / T; ++ty) {
+    for (int ty = f.j0 >> sh; ty <= f.j1 >> sh; ++ty) {
         int ta, tb;
         if (row_span(f, T, ty, ta, tb)) emit_row(pkey, pval, cap, k, base, tiles_x, ty, ta, tb, r);
     }
@@ -386,19 +386,19 @@ k_keygen_big(const uint32_t *__restrict__ sorted_rec, const uint32_t *__restrict
     for (uint32_t w = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; w < n_big; w += n_waves) {
         const uint32_t p = big_list[w];
         const uint32_t r = sorted_rec[p];
-        const int v = (int)(r / n_per_view);
+        const int v = (int)(r / (uint32_t)n_per_view);
         Footprint f;
         if (!record_footprint(rec[4 * (int64_t)r], rec[4 * (int64_t)r + 1], rs.alpha_min, vt.width[v],
                               vt.height[v], f))
             continue;  // wave-uniform
-        const int T = vt.tile;
+        const int T = vt.tile, sh = __builtin_ctz((unsigned)vt.tile);
         const uint32_t base = (uint32_t)vt.tile_off[v], tiles_x = (uint32_t)vt.tiles_x[v];
         uint32_t k0 = offsets[p];
-        for (int ty0 = f.j0 / T; ty0 <= f.j1 / T; ty0 += kWave) {
+        for (int ty0 = f.j0 >> sh; ty0 <= f.j1 >> sh; ty0 += kWave) {
             const int ty = ty0 + lane;
             int ta = 0, tb = -1;
-            if (ty <= f.j1 / T && !row_span(f, T, ty, ta, tb)) tb = ta - 1;
-            if (ty > f.j1 / T) tb = ta - 1;
+            if (ty <= f.j1 >> sh && !row_span(f, T, ty, ta, tb)) tb = ta - 1;
+            if (ty > f.j1 >> sh) tb = ta - 1;
             const uint32_t len = (uint32_t)(tb - ta + 1);
             const uint32_t inc = wave_inclusive_scan(len);
             uint32_t k = k0 + inc - len;

@@ -331,8 +331,9 @@ __device__ inline bool row_span(const Footprint &f, int B, int ty, int &ta, int 
     const int ia = max(f.i0, (int)ceil(f.u + xl));
     const int ib = min(f.i1, (int)floor(f.u + xr));
     if (ia > ib) return false;
-    ta = ia / B;
-    tb = ib / B;
+    const int sh = __builtin_ctz((unsigned)B);  // tile edges are powers of two
+    ta = ia >> sh;
+    tb = ib >> sh;
     return true;
 }
 

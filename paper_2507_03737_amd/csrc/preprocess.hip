@@ -149,12 +149,12 @@ k_preprocess(gspm_gaussians G, ViewTable vt, const float *__restrict__ T_cw, Ras
             // Records whose support box covers many tiles are counted by whole waves instead.
             Footprint f;
             if (record_footprint(r0, r1, rs.alpha_min, vt.width[v], vt.height[v], f)) {
-                const int T = vt.tile;
-                const int rows = f.j1 / T - f.j0 / T + 1, cols = f.i1 / T - f.i0 / T + 1;
+                const int T = vt.tile, sh = __builtin_ctz((unsigned)vt.tile);  // a power of two
+                const int rows = (f.j1 >> sh) - (f.j0 >> sh) + 1, cols = (f.i1 >> sh) - (f.i0 >> sh) + 1;
                 if ((uint32_t)(rows * cols) > kBigRecord) {
                     big = true;
                 } else {
-                    for (int ty = f.j0 / T; ty <= f.j1 / T; ++ty) {
+                    for (int ty = f.j0 >> sh; ty <= f.j1 >> sh; ++ty) {
                         int ta, tb;
                         if (row_span(f, T, ty, ta, tb)) count += (uint32_t)(tb - ta + 1);
                     }
@@ -177,13 +177,13 @@ k_count_big(const float4 *__restrict__ rec, ViewTable vt, RasterSettings rs, int
     const uint32_t n_waves = gridDim.x * (blockDim.x / kWave);
     for (uint32_t w = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; w < n_big; w += n_waves) {
         const uint32_t r = big_list[w];
-        const int v = (int)(r / n_per_view);
+        const int v = (int)(r / (uint32_t)n_per_view);
         Footprint f;
         uint32_t count = 0;
         if (record_footprint(rec[4 * (int64_t)r], rec[4 * (int64_t)r + 1], rs.alpha_min, vt.width[v],
                              vt.height[v], f)) {
-            const int T = vt.tile;
-            for (int ty = f.j0 / T + lane; ty <= f.j1 / T; ty += kWave) {
+            const int T = vt.tile, sh = __builtin_ctz((unsigned)vt.tile);
+            for (int ty = (f.j0 >> sh) + lane; ty <= f.j1 >> sh; ty += kWave) {
                 int ta, tb;
                 if (row_span(f, T, ty, ta, tb)) count += (uint32_t)(tb - ta + 1);
             }
