@@ -399,9 +399,12 @@ def main():
         del steps_v
 
     # ---- roofline of the dominant kernel ---------------------------------------------------
+    # Phase time per iteration (a phase may be timed in several segments per iteration, as
+    # binning is), and per timed segment for the dominant kernel's roofline.
+    n_iter = max(1, phases["raster_fwd"][1])
+    ph_iter = {k: v[0] / n_iter for k, v in phases.items()}
     ph_ms = {k: (v[0] / max(1, v[1])) for k, v in phases.items()}
-    n_launch = {k: v[1] for k, v in phases.items()}
-    dominant = max(ph_ms, key=lambda k: ph_ms[k] * max(1, n_launch[k]) / max(1, args.steps))
+    dominant = max(ph_iter, key=lambda k: ph_iter[k])
     if dominant in ("raster_fwd", "raster_bwd"):
         flops = frags * (FWD_FLOPS_PER_FRAG if dominant == "raster_fwd" else BWD_FLOPS_PER_FRAG)
         achieved = flops / (ph_ms[dominant] * 1e-3) / 1e12
@@ -415,7 +418,7 @@ def main():
         nbytes = {"tile_sort": 16 * pairs, "depth_sort": 16 * sc.n * win.n_views,
                   "preprocess": (56 + 64) * sc.n * win.n_views, "binning": 12 * pairs,
                   "param_bwd": (56 + 64 + 56) * sc.n * win.n_views}[dominant]
-        achieved = nbytes / (ph_ms[dominant] * 1e-3) / 1e9
+        achieved = nbytes / (ph_iter[dominant] * 1e-3) / 1e9
         roof = {"kernel": dominant, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None, "algorithmic": f"{nbytes} bytes"}
     roof["kernel_ms"] = ph_ms[dominant]
@@ -470,7 +473,7 @@ def main():
         "fwd_bwd_ms_per_iter": {"batched_eager": ms_batched, "batched_graph": ms_graph, "per_view_eager": ms_per_view},
         "batched_speedup_vs_per_view": (ms_per_view / ms_batched) if ms_per_view else None,
         "work": {"tile_pairs": pairs, "contributing_fragments": frags, "evaluated_bound": evals_bound},
-        "phase_ms": {k: round(v, 4) for k, v in ph_ms.items()},
+        "phase_ms": {k: round(v, 4) for k, v in ph_iter.items()},
         "autotune_ms": ({f"{r['tile']}x{r['tile']}/ppl{r['pixels_per_lane']}/bits{r['sort_digit_bits']}": round(r["ms"], 3)
                          for r in tuned} if tuned else None),
         "roofline": roof,
