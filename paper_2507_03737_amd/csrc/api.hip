@@ -68,7 +68,7 @@ struct gspm_ctx {
     size_t used = 0;
     std::vector<int> phase_of;  // per recorded pair
     // Per record (n * V).
-    DevBuf counts, big, live, dkey, dval, dkey_tmp, dval_tmp, dkey_s, dval_s, offsets, grad2d;
+    DevBuf counts, big, live, dkey, dval, dkey_tmp, dval_tmp, dkey_s, dval_s, offsets, grad2d, spans;
     // Per pair (capacity).
     DevBuf pkey, pval, pkey_tmp, pval_tmp, pkey_s;
     // Small scratch.
@@ -209,6 +209,7 @@ hipError_t ensure_records(gspm_ctx *c, int64_t R, int digit_bits) {
     if ((e = grow(c->dkey_s, 4 * w))) return e;
     if ((e = grow(c->dval_s, 4 * w))) return e;
     if ((e = grow(c->offsets, 4 * w))) return e;
+    if ((e = grow(c->spans, 16 * w))) return e;
     if ((e = grow(c->hist, 4 * radix_hist_words(w, digit_bits)))) return e;
     if ((e = grow(c->scan_part, 4 * 1024))) return e;
     if ((e = grow(c->misc, 256))) return e;
@@ -287,7 +288,7 @@ gspm_status gspm_create(gspm_ctx **out) {
 void gspm_destroy(gspm_ctx *ctx) {
     if (!ctx) return;
     DevBuf *bufs[] = {&ctx->counts, &ctx->big, &ctx->live, &ctx->dkey, &ctx->dval, &ctx->dkey_tmp, &ctx->dval_tmp,
-                      &ctx->dkey_s, &ctx->dval_s, &ctx->offsets, &ctx->grad2d, &ctx->pkey, &ctx->pval,
+                      &ctx->dkey_s, &ctx->dval_s, &ctx->offsets, &ctx->grad2d, &ctx->spans, &ctx->pkey, &ctx->pval,
                       &ctx->pkey_tmp, &ctx->pval_tmp, &ctx->pkey_s, &ctx->hist, &ctx->scan_part, &ctx->misc,
                       &ctx->pose_part, &ctx->loss_part, &ctx->align, &ctx->aux, &ctx->pnp, &ctx->twork};
     for (DevBuf *b : bufs)
@@ -358,7 +359,7 @@ gspm_status gspm_render_forward(gspm_ctx *ctx, const gspm_gaussians *g, const gs
     // 1. Project every (Gaussian, view) record.
     PhaseTimer t_pre(ctx, hs, GSPM_PHASE_PREPROCESS);
     GSPM_HIP(launch_preprocess(*g, P.vt, views->T_cw, P.rs, records, counts, static_cast<uint32_t *>(ctx->dkey.p),
-                               static_cast<uint32_t *>(ctx->dval.p), static_cast<uint32_t *>(ctx->big.p), total + 1,
+                               static_cast<uint4 *>(ctx->spans.p), static_cast<uint32_t *>(ctx->big.p), total + 1,
                                hs));
     t_pre.stop();
     // Device-side counts: total[0] tile pairs, total[1] queued large records, total[2] live records.
@@ -392,7 +393,8 @@ gspm_status gspm_render_forward(gspm_ctx *ctx, const gspm_gaussians *g, const gs
     GSPM_HIP(launch_fill_u32(reinterpret_cast<uint32_t *>(ranges), 0u, 2 * P.n_tiles, hs));
     GSPM_HIP(launch_keygen(static_cast<uint32_t *>(ctx->dval_s.p), static_cast<uint32_t *>(ctx->dkey_s.p),
                            static_cast<uint32_t *>(ctx->offsets.p),
-                           records, P.rs, R, g->n > 0 ? g->n : 1, P.vt, static_cast<uint32_t *>(ctx->pkey.p),
+                           records, static_cast<const uint4 *>(ctx->spans.p), P.rs, R, g->n > 0 ? g->n : 1, P.vt,
+                           static_cast<uint32_t *>(ctx->pkey.p),
                            static_cast<uint32_t *>(ctx->pval.p), hdr, (uint32_t)cap, total,
                            static_cast<uint32_t *>(ctx->big.p), total + 1, n_live, hs));
     t_bin.stop();

@@ -333,13 +333,26 @@ __device__ inline void emit_row(uint32_t *__restrict__ pkey, uint32_t *__restric
 
 // One lane per record (in depth order; sorted_counts[p] is the pair count of sorted_rec[p]).
 // Records with many pairs are queued for k_keygen_big.
-__global__ void __launch_bounds__(256)
+//
+// A wave's records are consecutive in depth order, so their pairs form one contiguous run
+// of the output.  Each lane puts its pairs into the wave's LDS window (the first
+// kStagePairs positions of the run) and the wave then copies the window out with
+// consecutive lanes on consecutive addresses, instead of 64 lanes storing 4 bytes at 64
+// scattered places; pairs past the window are stored directly.  The window positions of
+// queued large records are copied as they stand and rewritten by k_keygen_big, which
+// runs after this kernel.
+constexpr int kKeygenBlock = 256;
+constexpr uint32_t kStagePairs = 1024;
+
+__global__ void __launch_bounds__(kKeygenBlock)
 k_keygen(const uint32_t *__restrict__ sorted_rec, const uint32_t *__restrict__ sorted_counts,
-         const uint32_t *__restrict__ offsets, const float4 *__restrict__ rec, RasterSettings rs,
-         int64_t n_records, int64_t n_per_view, ViewTable vt, uint32_t *__restrict__ pkey,
+         const uint32_t *__restrict__ offsets, const float4 *__restrict__ rec, const uint4 *__restrict__ spans,
+         RasterSettings rs, int64_t n_records, int64_t n_per_view, ViewTable vt, uint32_t *__restrict__ pkey,
          uint32_t *__restrict__ pval, FrameHeader *__restrict__ hdr, uint32_t cap,
          const uint32_t *__restrict__ total, uint32_t *__restrict__ big_list, uint32_t *__restrict__ big_count,
          const uint32_t *__restrict__ n_dev) {
+    __shared__ uint2 stage[kKeygenBlock / kWave][kStagePairs];
+    const int wid = threadIdx.x / kWave, lane = lane_id();
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     n_records = scan_n(n_dev, n_records);
     if (p == 0) {
@@ -351,30 +364,73 @@ k_keygen(const uint32_t *__restrict__ sorted_rec, const uint32_t *__restrict__ s
         hdr->visible = (uint32_t)rs.mark_visible;
         hdr->counted = (uint32_t)rs.count_work;
     }
-    uint32_t r = 0, c = 0;
-    if (p < n_records) {
+    const bool act = p < n_records;
+    uint32_t r = 0, c = 0, k = 0;
+    if (act) {
         r = sorted_rec[p];
         c = sorted_counts[p];
+        k = offsets[p];
     }
     const bool big = c > kBigRecord;
     const uint32_t slot = wave_append(big_count, big);
     if (big) big_list[slot] = (uint32_t)p;
-    if (c == 0 || big) return;
-    uint32_t k = offsets[p];
-    if (k >= cap) return;
-    const int v = (int)(r / (uint32_t)n_per_view);  // 32-bit: record indices fit
-    Footprint f;
-    if (!record_footprint(rec[4 * (int64_t)r], rec[4 * (int64_t)r + 1], rs.alpha_min, vt.width[v], vt.height[v], f))
-        return;
-    const int T = vt.tile, sh = __builtin_ctz((unsigned)vt.tile);
-    const uint32_t base = (uint32_t)vt.tile_off[v], tiles_x = (uint32_t)vt.tiles_x[v];
-    for (int ty = f.j0 >> sh; ty <= f.j1 >> sh; ++ty) {
-        int ta, tb;
-        if (row_span(f, T, ty, ta, tb)) emit_row(pkey, pval, cap, k, base, tiles_x, ty, ta, tb, r);
+    // Lane 0 holds the wave's first record (if it has none, neither has any other lane).
+    const uint32_t run0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)k);
+    const uint64_t win_end = (uint64_t)run0 + kStagePairs;
+    uint2 *win = stage[wid];
+    auto put = [&](uint32_t pos, uint32_t key) {
+        if (pos >= cap) return;
+        if ((uint64_t)pos < win_end) {
+            win[pos - run0] = make_uint2(key, r);
+        } else {
+            pkey[pos] = key;
+            pval[pos] = r;
+        }
+    };
+    if (act && c != 0u && !big) {
+        const int v = (int)(r / (uint32_t)n_per_view);  // 32-bit: record indices fit
+        const uint32_t base = (uint32_t)vt.tile_off[v], tiles_x = (uint32_t)vt.tiles_x[v];
+        uint32_t pos = k;
+        auto row = [&](int ty, int ta, int tb) {
+            for (int tx = ta; tx <= tb; ++tx) put(pos++, base + (uint32_t)ty * tiles_x + (uint32_t)tx);
+        };
+        const uint4 sp = spans[r];
+        const uint32_t nr = sp.x >> 16;
+        if (nr <= kSpanRows) {  // the counting pass cached the rows
+            const int ty0 = (int)(sp.x & 0xffffu);
+#pragma unroll
+            for (uint32_t i = 0; i < kSpanRows; ++i) {
+                if (i >= nr) break;
+                const uint32_t w = i == 0 ? sp.y : (i == 1 ? sp.z : sp.w);
+                const int ta = (int)(w & 0xffffu), tb = (int)(w >> 16);
+                if (ta <= tb) row(ty0 + (int)i, ta, tb);
+            }
+        } else {
+            Footprint f;
+            if (record_footprint(rec[4 * (int64_t)r], rec[4 * (int64_t)r + 1], rs.alpha_min, vt.width[v],
+                                 vt.height[v], f)) {
+                const int T = vt.tile, sh = __builtin_ctz((unsigned)vt.tile);
+                for (int ty = f.j0 >> sh; ty <= f.j1 >> sh; ++ty) {
+                    int ta, tb;
+                    if (row_span(f, T, ty, ta, tb)) row(ty, ta, tb);
+                }
+            }
+        }
+    }
+    // The run ends at the largest end of the wave's records (queued ones included).
+    uint32_t end = act ? k + c : run0;
+    for (int off = 32; off > 0; off >>= 1) end = max(end, (uint32_t)__shfl_xor((int)end, off, 64));
+    uint64_t stop = end;
+    if (stop > win_end) stop = win_end;
+    if (stop > cap) stop = cap;
+    __builtin_amdgcn_wave_barrier();  // the window is complete (one wave's LDS accesses stay in order)
+    for (uint64_t j = run0 + (uint32_t)lane; j < stop; j += kWave) {
+        const uint2 e = win[j - run0];
+        pkey[j] = e.x;
+        pval[j] = e.y;
     }
 }
 
-// One wave per queued record: lanes take tile rows, a wave scan places each row's tiles.
 __global__ void __launch_bounds__(256)
 k_keygen_big(const uint32_t *__restrict__ sorted_rec, const uint32_t *__restrict__ offsets,
              const float4 *__restrict__ rec, RasterSettings rs, int64_t n_per_view, ViewTable vt,
@@ -545,7 +601,8 @@ hipError_t radix_sort(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t
 }
 
 hipError_t launch_keygen(const uint32_t *sorted_rec, const uint32_t *sorted_counts, const uint32_t *offsets,
-                         const float *records, const RasterSettings &rs, int64_t n_records, int64_t n_per_view,
+                         const float *records, const uint4 *spans, const RasterSettings &rs, int64_t n_records,
+                         int64_t n_per_view,
                          const ViewTable &vt, uint32_t *pkey, uint32_t *pval, FrameHeader *hdr, uint32_t capacity,
                          const uint32_t *total, uint32_t *big_list, uint32_t *big_count, const uint32_t *n_dev,
                          hipStream_t s) {
@@ -553,8 +610,8 @@ hipError_t launch_keygen(const uint32_t *sorted_rec, const uint32_t *sorted_coun
     if (e != hipSuccess) return e;
     const float4 *rec = reinterpret_cast<const float4 *>(records);
     const int64_t nb = n_records > 0 ? (n_records + 255) / 256 : 1;
-    hipLaunchKernelGGL(k_keygen, dim3((unsigned)nb), dim3(256), 0, s, sorted_rec, sorted_counts, offsets, rec, rs, n_records,
-                       n_per_view, vt, pkey, pval, hdr, capacity, total, big_list, big_count, n_dev);
+    hipLaunchKernelGGL(k_keygen, dim3((unsigned)nb), dim3(256), 0, s, sorted_rec, sorted_counts, offsets, rec, spans, rs,
+                       n_records, n_per_view, vt, pkey, pval, hdr, capacity, total, big_list, big_count, n_dev);
     if (n_records > 0)
         hipLaunchKernelGGL(k_keygen_big, dim3(1024), dim3(256), 0, s, sorted_rec, offsets, rec, rs, n_per_view, vt,
                            pkey, pval, capacity, big_list, big_count);

@@ -55,6 +55,13 @@ constexpr int kG2 = 16;
 // Records with more tile pairs than this are counted and emitted by whole waves.
 constexpr uint32_t kBigRecord = 64;
 
+// Tile-row spans of a record, cached by the counting pass for the emission pass: x = first
+// tile row | rows << 16, then one row per word (first | last tile << 16; first > last
+// when the row is empty).  Records with more than kSpanRows rows are not cached
+// (rows = kSpanNone) and the emission evaluates them again.
+constexpr uint32_t kSpanRows = 3;
+constexpr uint32_t kSpanNone = 0xffffu;
+
 // Frame-state layout (caller-owned device buffer).
 struct FrameHeader {
     uint32_t pairs;     // tile pairs produced (or needed, on overflow)
@@ -343,11 +350,12 @@ __device__ inline bool row_span(const Footprint &f, int B, int ty, int &ta, int 
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t n, hipStream_t s);
 hipError_t launch_fill_f32(float *p, float value, int64_t n, hipStream_t s);
 
-// Projects every record and counts its tile pairs; big_list / big_count are scratch for
-// the records counted by whole waves (big_count is zeroed here).
+// Projects every record and counts its tile pairs, caching the tile-row spans of records
+// with pairs in spans [N V]; big_list / big_count are scratch for the records counted by
+// whole waves (big_count is zeroed here).
 hipError_t launch_preprocess(const gspm_gaussians &g, const ViewTable &vt, const float *T_cw,
                              const RasterSettings &rs, float *records, uint32_t *counts,
-                             uint32_t *dkey, uint32_t *dval, uint32_t *big_list, uint32_t *big_count,
+                             uint32_t *dkey, uint4 *spans, uint32_t *big_list, uint32_t *big_count,
                              hipStream_t s);
 
 // Exclusive scan of counts[idx[p]] (or of counts[idx[p]] != 0 when flag is set) for
@@ -377,9 +385,11 @@ hipError_t radix_sort(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t
 
 // Emits the (global tile, record) pairs of every record in depth order.  Records with
 // more than kBigRecord pairs are queued in big_list (big_count zeroed here) and emitted
-// by whole waves.  records: the projected records (for the support footprint).
+// by whole waves.  records: the projected records (for the support footprint of records
+// whose spans are not cached in spans).
 hipError_t launch_keygen(const uint32_t *sorted_rec, const uint32_t *sorted_counts, const uint32_t *offsets,
-                         const float *records, const RasterSettings &rs, int64_t n_records, int64_t n_per_view,
+                         const float *records, const uint4 *spans, const RasterSettings &rs, int64_t n_records,
+                         int64_t n_per_view,
                          const ViewTable &vt, uint32_t *pkey, uint32_t *pval, FrameHeader *hdr,
                          uint32_t capacity, const uint32_t *total, uint32_t *big_list, uint32_t *big_count,
                          const uint32_t *n_dev, hipStream_t s);

@@ -117,7 +117,7 @@ __device__ inline void project_one(const gspm_gaussians &G, int64_t g, int64_t n
 __global__ void __launch_bounds__(256)
 k_preprocess(gspm_gaussians G, ViewTable vt, const float *__restrict__ T_cw, RasterSettings rs,
              float4 *__restrict__ rec, uint32_t *__restrict__ counts, uint32_t *__restrict__ dkey,
-             uint32_t *__restrict__ big_list, uint32_t *__restrict__ big_count) {
+             uint4 *__restrict__ spans, uint32_t *__restrict__ big_list, uint32_t *__restrict__ big_count) {
     // blockIdx.y is the view: no 64-bit division to split the record index.
     const int64_t n = G.n;
     const int v = (int)blockIdx.y;
@@ -152,12 +152,19 @@ k_preprocess(gspm_gaussians G, ViewTable vt, const float *__restrict__ T_cw, Ras
                 const int T = vt.tile, sh = __builtin_ctz((unsigned)vt.tile);  // a power of two
                 const int rows = (f.j1 >> sh) - (f.j0 >> sh) + 1, cols = (f.i1 >> sh) - (f.i0 >> sh) + 1;
                 if ((uint32_t)(rows * cols) > kBigRecord) {
-                    big = true;
+                    big = true;  // its count may still come out at most kBigRecord: not cached
+                    spans[r] = make_uint4(kSpanNone << 16, 0u, 0u, 0u);
                 } else {
-                    for (int ty = f.j0 >> sh; ty <= f.j1 >> sh; ++ty) {
+                    uint32_t w[kSpanRows] = {1u, 1u, 1u};  // empty rows: first > last
+                    for (int ty = f.j0 >> sh, k = 0; ty <= f.j1 >> sh; ++ty, ++k) {
                         int ta, tb;
-                        if (row_span(f, T, ty, ta, tb)) count += (uint32_t)(tb - ta + 1);
+                        if (row_span(f, T, ty, ta, tb)) {
+                            count += (uint32_t)(tb - ta + 1);
+                            if (k < (int)kSpanRows) w[k] = (uint32_t)ta | ((uint32_t)tb << 16);
+                        }
                     }
+                    const uint32_t nr = rows <= (int)kSpanRows ? (uint32_t)rows : kSpanNone;
+                    if (count != 0u) spans[r] = make_uint4((uint32_t)(f.j0 >> sh) | (nr << 16), w[0], w[1], w[2]);
                 }
             }
         }
@@ -466,15 +473,14 @@ hipError_t launch_fill_f32(float *p, float value, int64_t n, hipStream_t s) {
 
 hipError_t launch_preprocess(const gspm_gaussians &g, const ViewTable &vt, const float *T_cw,
                              const RasterSettings &rs, float *records, uint32_t *counts,
-                             uint32_t *dkey, uint32_t *dval, uint32_t *big_list, uint32_t *big_count,
+                             uint32_t *dkey, uint4 *spans, uint32_t *big_list, uint32_t *big_count,
                              hipStream_t s) {
     const int64_t R = g.n * vt.n_views;
     if (R <= 0) return hipSuccess;
     hipError_t e = launch_fill_u32(big_count, 0u, 1, s);
     if (e != hipSuccess) return e;
-    (void)dval;
     hipLaunchKernelGGL(k_preprocess, dim3((unsigned)((g.n + 255) / 256), (unsigned)vt.n_views), dim3(256), 0, s, g,
-                       vt, T_cw, rs, reinterpret_cast<float4 *>(records), counts, dkey, big_list, big_count);
+                       vt, T_cw, rs, reinterpret_cast<float4 *>(records), counts, dkey, spans, big_list, big_count);
     hipLaunchKernelGGL(k_count_big, dim3(1024), dim3(256), 0, s, reinterpret_cast<const float4 *>(records), vt, rs,
                        g.n, counts, big_list, big_count);
     return hipGetLastError();
