@@ -375,7 +375,7 @@ gspm_status gspm_render_forward(gspm_ctx *ctx, const gspm_gaussians *g, const gs
         GSPM_HIP(radix_sort(static_cast<uint32_t *>(ctx->dval.p), static_cast<uint32_t *>(ctx->live.p),
                             static_cast<uint32_t *>(ctx->dkey_tmp.p), static_cast<uint32_t *>(ctx->dval_tmp.p),
                             static_cast<uint32_t *>(ctx->dkey_s.p), static_cast<uint32_t *>(ctx->dval_s.p), R, n_live,
-                            32, db, hist, &hdr->sort_stall, hs));
+                            32, db, hist, &hdr->sort_stall, nullptr, hs));
         t_ds.stop();
     }
     PhaseTimer t_bin(ctx, hs, GSPM_PHASE_BINNING);
@@ -390,7 +390,7 @@ gspm_status gspm_render_forward(gspm_ctx *ctx, const gspm_gaussians *g, const gs
         GSPM_HIP(launch_fill_u32(total, 0u, 3, hs));
     }
     // 4. Emit (tile, record) pairs; the header gets the pair count and overflow flag.
-    GSPM_HIP(launch_fill_u32(reinterpret_cast<uint32_t *>(ranges), 0u, 2 * P.n_tiles, hs));
+    GSPM_HIP(launch_fill_ranges(ranges, P.n_tiles, hs));
     GSPM_HIP(launch_keygen(static_cast<uint32_t *>(ctx->dval_s.p), static_cast<uint32_t *>(ctx->dkey_s.p),
                            static_cast<uint32_t *>(ctx->offsets.p),
                            records, static_cast<const uint4 *>(ctx->spans.p), P.rs, R, g->n > 0 ? g->n : 1, P.vt,
@@ -398,16 +398,14 @@ gspm_status gspm_render_forward(gspm_ctx *ctx, const gspm_gaussians *g, const gs
                            static_cast<uint32_t *>(ctx->pval.p), hdr, (uint32_t)cap, total,
                            static_cast<uint32_t *>(ctx->big.p), total + 1, n_live, hs));
     t_bin.stop();
-    // 5. Stable sort by tile id; 6. per-tile ranges.
+    // 5. Stable sort by tile id; its final pass writes the per-tile ranges (6).
     if (cap > 0) {
         PhaseTimer t_ts(ctx, hs, GSPM_PHASE_TILE_SORT);
         GSPM_HIP(radix_sort(static_cast<uint32_t *>(ctx->pkey.p), static_cast<uint32_t *>(ctx->pval.p),
                             static_cast<uint32_t *>(ctx->pkey_tmp.p), static_cast<uint32_t *>(ctx->pval_tmp.p),
                             static_cast<uint32_t *>(ctx->pkey_s.p), pair_vals, cap, &hdr->pairs,
-                            tile_bits(P.n_tiles), db, hist, &hdr->sort_stall, hs));
+                            tile_bits(P.n_tiles), db, hist, &hdr->sort_stall, ranges, hs));
         t_ts.stop();
-        PhaseTimer t_rg(ctx, hs, GSPM_PHASE_BINNING);
-        GSPM_HIP(launch_ranges(static_cast<uint32_t *>(ctx->pkey_s.p), hdr, ranges, P.n_tiles, cap, hs));
     }
     // Heaviest tiles first: by list length for the forward; the forward measures each
     // tile's contributing depth, which orders the backward.

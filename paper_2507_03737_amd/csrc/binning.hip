@@ -194,10 +194,11 @@ __global__ void __launch_bounds__(kSortBlock)
 k_radix_pass(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
              uint32_t *__restrict__ vout, const uint32_t *__restrict__ n_dev, int64_t n_max, int shift,
              const uint32_t *__restrict__ ghist, uint32_t *__restrict__ status,
-             uint32_t *__restrict__ status_next, uint32_t *__restrict__ stall) {
+             uint32_t *__restrict__ status_next, uint32_t *__restrict__ stall, uint2 *__restrict__ ranges) {
     constexpr int R = 1 << DB;
     __shared__ uint32_t wcnt[kSortWaves][R];
     __shared__ uint32_t dstart[R];
+    __shared__ uint32_t dcount[R];
     __shared__ uint32_t gbase[R];
     __shared__ uint32_t scan_lds[kSortWaves];
     __shared__ uint32_t lk[kSortTile];
@@ -262,6 +263,7 @@ k_radix_pass(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
     if (threadIdx.x < R) {
         const int d = threadIdx.x;
         dstart[d] = pre;
+        dcount[d] = tot;
         uint32_t prefix = 0;
         if (tile > 0) {
             // Words of kLookback earlier tiles are read at once (one memory latency per
@@ -317,6 +319,17 @@ k_radix_pass(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
         const uint32_t pos = gbase[d] + ((uint32_t)j - dstart[d]);
         kout[pos] = k;
         vout[pos] = lv[j];
+        if (ranges) {
+            // Final pass over tile ids: the tile is sorted in LDS, so the output neighbours of
+            // an element inside its digit's run are its LDS neighbours.  At the ends of the
+            // run they belong to other blocks: the first and last element then take the
+            // extreme position by atomics (the true start or end, wherever it lies, wins).
+            const uint32_t first = dstart[d], last = dstart[d] + dcount[d] - 1u;
+            if ((uint32_t)j == first) atomicMin(&ranges[k].x, pos);
+            else if (lk[j - 1] != k) ranges[k].x = pos;
+            if ((uint32_t)j == last) atomicMax(&ranges[k].y, pos + 1u);
+            else if (lk[j + 1] != k) ranges[k].y = pos + 1u;
+        }
     }
 }
 
@@ -464,17 +477,6 @@ k_keygen_big(const uint32_t *__restrict__ sorted_rec, const uint32_t *__restrict
     }
 }
 
-__global__ void __launch_bounds__(256)
-k_ranges(const uint32_t *__restrict__ keys, const FrameHeader *__restrict__ hdr, uint2 *__restrict__ ranges,
-         int64_t n_max) {
-    const int64_t n = (int64_t)hdr->pairs < n_max ? (int64_t)hdr->pairs : n_max;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t k = keys[i];
-        if (i == 0 || keys[i - 1] != k) ranges[k].x = (uint32_t)i;
-        if (i == n - 1 || keys[i + 1] != k) ranges[k].y = (uint32_t)(i + 1);
-    }
-}
-
 __global__ void __launch_bounds__(256) k_sum_u64(const uint32_t *__restrict__ x, int64_t n,
                                                 unsigned long long *__restrict__ out) {
     unsigned long long acc = 0;
@@ -556,7 +558,7 @@ int64_t radix_hist_words(int64_t n_max, int digit_bits) {
 template <int DB>
 static void sort_passes(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_tmp, uint32_t *vals_tmp,
                         uint32_t *keys_out, uint32_t *vals_out, int64_t n_max, const uint32_t *n_dev, int passes,
-                        uint32_t *scratch, uint32_t *stall, hipStream_t s) {
+                        uint32_t *scratch, uint32_t *stall, uint2 *ranges, hipStream_t s) {
     constexpr int R = 1 << DB;
     const int64_t tiles = sort_tiles(n_max);
     uint32_t *ghist = scratch;
@@ -572,7 +574,8 @@ static void sort_passes(const uint32_t *keys_in, const uint32_t *vals_in, uint32
         uint32_t *ko = to_out ? keys_out : keys_tmp;
         uint32_t *vo = to_out ? vals_out : vals_tmp;
         hipLaunchKernelGGL(k_radix_pass<DB>, dim3((unsigned)tiles), dim3(kSortBlock), 0, s, kin, vin, ko, vo, n_dev,
-                           n_max, p * DB, ghist + (int64_t)p * R, status[p & 1], status[(p + 1) & 1], stall);
+                           n_max, p * DB, ghist + (int64_t)p * R, status[p & 1], status[(p + 1) & 1], stall,
+                           p == passes - 1 ? ranges : nullptr);
         kin = ko;
         vin = vo;
     }
@@ -580,7 +583,7 @@ static void sort_passes(const uint32_t *keys_in, const uint32_t *vals_in, uint32
 
 hipError_t radix_sort(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_tmp, uint32_t *vals_tmp,
                       uint32_t *keys_out, uint32_t *vals_out, int64_t n_max, const uint32_t *n_dev, int bits,
-                      int digit_bits, uint32_t *scratch, uint32_t *stall, hipStream_t s) {
+                      int digit_bits, uint32_t *scratch, uint32_t *stall, uint2 *ranges, hipStream_t s) {
     if (n_max <= 0) return hipSuccess;
     if (bits < 1) bits = 1;
     if (digit_bits < 4 || digit_bits > 8) return hipErrorInvalidValue;
@@ -591,11 +594,11 @@ hipError_t radix_sort(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t
     int db = (bits + passes - 1) / passes;
     if (db < 4) db = 4;
     switch (db) {
-        case 4: sort_passes<4>(keys_in, vals_in, keys_tmp, vals_tmp, keys_out, vals_out, n_max, n_dev, passes, scratch, stall, s); break;
-        case 5: sort_passes<5>(keys_in, vals_in, keys_tmp, vals_tmp, keys_out, vals_out, n_max, n_dev, passes, scratch, stall, s); break;
-        case 6: sort_passes<6>(keys_in, vals_in, keys_tmp, vals_tmp, keys_out, vals_out, n_max, n_dev, passes, scratch, stall, s); break;
-        case 7: sort_passes<7>(keys_in, vals_in, keys_tmp, vals_tmp, keys_out, vals_out, n_max, n_dev, passes, scratch, stall, s); break;
-        default: sort_passes<8>(keys_in, vals_in, keys_tmp, vals_tmp, keys_out, vals_out, n_max, n_dev, passes, scratch, stall, s); break;
+        case 4: sort_passes<4>(keys_in, vals_in, keys_tmp, vals_tmp, keys_out, vals_out, n_max, n_dev, passes, scratch, stall, ranges, s); break;
+        case 5: sort_passes<5>(keys_in, vals_in, keys_tmp, vals_tmp, keys_out, vals_out, n_max, n_dev, passes, scratch, stall, ranges, s); break;
+        case 6: sort_passes<6>(keys_in, vals_in, keys_tmp, vals_tmp, keys_out, vals_out, n_max, n_dev, passes, scratch, stall, ranges, s); break;
+        case 7: sort_passes<7>(keys_in, vals_in, keys_tmp, vals_tmp, keys_out, vals_out, n_max, n_dev, passes, scratch, stall, ranges, s); break;
+        default: sort_passes<8>(keys_in, vals_in, keys_tmp, vals_tmp, keys_out, vals_out, n_max, n_dev, passes, scratch, stall, ranges, s); break;
     }
     return hipGetLastError();
 }
@@ -620,13 +623,14 @@ hipError_t launch_keygen(const uint32_t *sorted_rec, const uint32_t *sorted_coun
 
 // One workgroup: counting sort of the tiles into 256 work classes (32 list entries each,
 // the last one open-ended), heaviest class first.  The order inside a class is that of
-// the atomics; any order is a valid launch order.
+// the atomics; any order is a valid launch order.  Each tile is handled by the same
+// thread in both loops, so the reset of an empty range is seen by the second.
 constexpr int kOrderBlock = 1024;
 constexpr int kOrderClasses = 256;
 constexpr int kOrderShift = 5;
 
 __global__ void __launch_bounds__(kOrderBlock)
-k_order_tiles(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ work, int64_t n,
+k_order_tiles(uint2 *__restrict__ ranges, const uint32_t *__restrict__ work, int64_t n,
               uint32_t *__restrict__ order) {
     __shared__ uint32_t cnt[kOrderClasses];
     for (int b = threadIdx.x; b < kOrderClasses; b += kOrderBlock) cnt[b] = 0u;
@@ -635,7 +639,10 @@ k_order_tiles(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ wor
         const uint32_t w = ranges ? ranges[t].y - ranges[t].x : work[t];
         return (uint32_t)(kOrderClasses - 1) - min((uint32_t)(kOrderClasses - 1), w >> kOrderShift);
     };
-    for (int64_t t = threadIdx.x; t < n; t += kOrderBlock) atomicAdd(&cnt[cls(t)], 1u);
+    for (int64_t t = threadIdx.x; t < n; t += kOrderBlock) {
+        if (ranges && ranges[t].x > ranges[t].y) ranges[t] = make_uint2(0u, 0u);
+        atomicAdd(&cnt[cls(t)], 1u);
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         uint32_t acc = 0;
@@ -649,7 +656,7 @@ k_order_tiles(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ wor
     for (int64_t t = threadIdx.x; t < n; t += kOrderBlock) order[atomicAdd(&cnt[cls(t)], 1u)] = (uint32_t)t;
 }
 
-hipError_t launch_order_tiles(const uint2 *ranges, const uint32_t *work, int64_t n_tiles, uint32_t *order,
+hipError_t launch_order_tiles(uint2 *ranges, const uint32_t *work, int64_t n_tiles, uint32_t *order,
                               hipStream_t s) {
     if (n_tiles <= 0) return hipSuccess;
     if ((ranges == nullptr) == (work == nullptr)) return hipErrorInvalidValue;
@@ -657,13 +664,16 @@ hipError_t launch_order_tiles(const uint2 *ranges, const uint32_t *work, int64_t
     return hipGetLastError();
 }
 
-hipError_t launch_ranges(const uint32_t *sorted_keys, const FrameHeader *hdr, uint2 *ranges, int64_t n_tiles,
-                         int64_t n_max, hipStream_t s) {
-    (void)n_tiles;
-    if (n_max <= 0) return hipSuccess;
-    int64_t nb = (n_max + 255) / 256;
-    if (nb > 8192) nb = 8192;
-    hipLaunchKernelGGL(k_ranges, dim3((unsigned)nb), dim3(256), 0, s, sorted_keys, hdr, ranges, n_max);
+__global__ void k_fill_ranges(uint2 *ranges, int64_t n) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+        ranges[t] = make_uint2(0xffffffffu, 0u);
+}
+
+hipError_t launch_fill_ranges(uint2 *ranges, int64_t n_tiles, hipStream_t s) {
+    if (n_tiles <= 0) return hipSuccess;
+    int64_t nb = (n_tiles + 255) / 256;
+    if (nb > 1024) nb = 1024;
+    hipLaunchKernelGGL(k_fill_ranges, dim3((unsigned)nb), dim3(256), 0, s, ranges, n_tiles);
     return hipGetLastError();
 }
 

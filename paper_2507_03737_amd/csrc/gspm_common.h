@@ -376,12 +376,14 @@ hipError_t launch_compact(const uint32_t *counts, const uint32_t *flag_scan, con
 // count (may be NULL: n_max is then exact).  Buffers: keys/vals in, tmp, out (the sorted
 // result ends in keys_out/vals_out).  scratch: radix_hist_words(n_max, digit_bits) words.
 // *stall (device) is set if a pass gave up waiting for an earlier tile (the result is
-// then invalid); the caller clears it.
+// then invalid); the caller clears it.  ranges (optional): the keys are tile ids and the
+// final pass writes each tile's [first, end) positions; the caller fills it with
+// (0xffffffff, 0) beforehand, which empty tiles keep.
 int64_t radix_hist_words(int64_t n_max, int digit_bits);
 hipError_t radix_sort(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_tmp,
                       uint32_t *vals_tmp, uint32_t *keys_out, uint32_t *vals_out, int64_t n_max,
                       const uint32_t *n_dev, int bits, int digit_bits, uint32_t *scratch, uint32_t *stall,
-                      hipStream_t s);
+                      uint2 *ranges, hipStream_t s);
 
 // Emits the (global tile, record) pairs of every record in depth order.  Records with
 // more than kBigRecord pairs are queued in big_list (big_count zeroed here) and emitted
@@ -426,12 +428,13 @@ int64_t median_scratch_words(int V);
 hipError_t launch_median_depth(const ViewTable &vt, const float *depth, uint32_t *scratch, float *out,
                                hipStream_t s);
 
-hipError_t launch_ranges(const uint32_t *sorted_keys, const FrameHeader *hdr, uint2 *ranges,
-                         int64_t n_tiles, int64_t n_max, hipStream_t s);
+// Fills the ranges with (0xffffffff, 0) for radix_sort's final pass to narrow.
+hipError_t launch_fill_ranges(uint2 *ranges, int64_t n_tiles, hipStream_t s);
 
 // Launch order of the raster workgroups, heaviest tiles first: the tiles' work is the list
-// length (ranges) or a per-tile estimate (work); exactly one of the two is given.
-hipError_t launch_order_tiles(const uint2 *ranges, const uint32_t *work, int64_t n_tiles, uint32_t *order,
+// length (ranges) or a per-tile estimate (work); exactly one of the two is given.  Ranges
+// the sort left at (0xffffffff, 0) (tiles without pairs) are reset to (0, 0) on the way.
+hipError_t launch_order_tiles(uint2 *ranges, const uint32_t *work, int64_t n_tiles, uint32_t *order,
                               hipStream_t s);
 
 bool raster_config_supported(int tile, int ppt);
