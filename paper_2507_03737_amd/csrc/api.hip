@@ -364,6 +364,8 @@ gspm_status gspm_render_forward(gspm_ctx *ctx, const gspm_gaussians *g, const gs
     t_pre.stop();
     // Device-side counts: total[0] tile pairs, total[1] queued large records, total[2] live records.
     uint32_t *n_live = total + 2;
+    // Small enough windows carry each live record's pair count through the depth sort.
+    const bool pack = R <= (int64_t)kPackMask + 1;
     if (R > 0) {
         // 2. Keep the records that have tile pairs (in record order) and sort them by float32
         //    depth (stable, so ties keep record order).
@@ -371,7 +373,7 @@ gspm_status gspm_render_forward(gspm_ctx *ctx, const gspm_gaussians *g, const gs
         GSPM_HIP(launch_scan_indirect(counts, nullptr, R, static_cast<uint32_t *>(ctx->offsets.p), n_live, part, hs,
                                       nullptr, 1));
         GSPM_HIP(launch_compact(counts, static_cast<uint32_t *>(ctx->offsets.p), static_cast<uint32_t *>(ctx->dkey.p), R,
-                                static_cast<uint32_t *>(ctx->dval.p), static_cast<uint32_t *>(ctx->live.p), hs));
+                                static_cast<uint32_t *>(ctx->dval.p), static_cast<uint32_t *>(ctx->live.p), pack, hs));
         GSPM_HIP(radix_sort(static_cast<uint32_t *>(ctx->dval.p), static_cast<uint32_t *>(ctx->live.p),
                             static_cast<uint32_t *>(ctx->dkey_tmp.p), static_cast<uint32_t *>(ctx->dval_tmp.p),
                             static_cast<uint32_t *>(ctx->dkey_s.p), static_cast<uint32_t *>(ctx->dval_s.p), R, n_live,
@@ -382,16 +384,17 @@ gspm_status gspm_render_forward(gspm_ctx *ctx, const gspm_gaussians *g, const gs
     if (R > 0) {
         // 3. Offsets of each live record's tile pairs, in depth order.
         // The sorted depth keys are no longer needed: their buffer receives the pair counts
-        // in depth order, gathered once by the scan.
+        // in depth order, unpacked (or gathered) once by the scan.
         GSPM_HIP(launch_scan_indirect(counts, static_cast<uint32_t *>(ctx->dval_s.p), R,
-                                      static_cast<uint32_t *>(ctx->offsets.p), total, part, hs, n_live, 0,
+                                      static_cast<uint32_t *>(ctx->offsets.p), total, part, hs, n_live, pack ? 2 : 0,
                                       static_cast<uint32_t *>(ctx->dkey_s.p)));
     } else {
         GSPM_HIP(launch_fill_u32(total, 0u, 3, hs));
     }
     // 4. Emit (tile, record) pairs; the header gets the pair count and overflow flag.
     GSPM_HIP(launch_fill_ranges(ranges, P.n_tiles, hs));
-    GSPM_HIP(launch_keygen(static_cast<uint32_t *>(ctx->dval_s.p), static_cast<uint32_t *>(ctx->dkey_s.p),
+    GSPM_HIP(launch_keygen(static_cast<uint32_t *>(ctx->dval_s.p), pack ? kPackMask : 0xffffffffu,
+                           static_cast<uint32_t *>(ctx->dkey_s.p),
                            static_cast<uint32_t *>(ctx->offsets.p),
                            records, static_cast<const uint4 *>(ctx->spans.p), P.rs, R, g->n > 0 ? g->n : 1, P.vt,
                            static_cast<uint32_t *>(ctx->pkey.p),

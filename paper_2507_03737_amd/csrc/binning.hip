@@ -20,6 +20,11 @@ constexpr int kScanItems = 8;
 constexpr int kScanTile = kScanBlock * kScanItems;
 
 __device__ inline uint32_t load_count(const uint32_t *counts, const uint32_t *idx, int64_t p, int flag) {
+    if (flag == 2) {
+        const uint32_t v = idx[p];
+        const uint32_t c = v >> kPackShift;
+        return c < kPackCountMax ? c : counts[v & kPackMask];
+    }
     const uint32_t c = idx ? counts[idx[p]] : counts[p];
     return flag ? (c != 0u ? 1u : 0u) : c;
 }
@@ -358,7 +363,7 @@ constexpr int kKeygenBlock = 256;
 constexpr uint32_t kStagePairs = 1024;
 
 __global__ void __launch_bounds__(kKeygenBlock)
-k_keygen(const uint32_t *__restrict__ sorted_rec, const uint32_t *__restrict__ sorted_counts,
+k_keygen(const uint32_t *__restrict__ sorted_rec, uint32_t rec_mask, const uint32_t *__restrict__ sorted_counts,
          const uint32_t *__restrict__ offsets, const float4 *__restrict__ rec, const uint4 *__restrict__ spans,
          RasterSettings rs, int64_t n_records, int64_t n_per_view, ViewTable vt, uint32_t *__restrict__ pkey,
          uint32_t *__restrict__ pval, FrameHeader *__restrict__ hdr, uint32_t cap,
@@ -380,7 +385,7 @@ k_keygen(const uint32_t *__restrict__ sorted_rec, const uint32_t *__restrict__ s
     const bool act = p < n_records;
     uint32_t r = 0, c = 0, k = 0;
     if (act) {
-        r = sorted_rec[p];
+        r = sorted_rec[p] & rec_mask;
         c = sorted_counts[p];
         k = offsets[p];
     }
@@ -445,7 +450,7 @@ k_keygen(const uint32_t *__restrict__ sorted_rec, const uint32_t *__restrict__ s
 }
 
 __global__ void __launch_bounds__(256)
-k_keygen_big(const uint32_t *__restrict__ sorted_rec, const uint32_t *__restrict__ offsets,
+k_keygen_big(const uint32_t *__restrict__ sorted_rec, uint32_t rec_mask, const uint32_t *__restrict__ offsets,
              const float4 *__restrict__ rec, RasterSettings rs, int64_t n_per_view, ViewTable vt,
              uint32_t *__restrict__ pkey, uint32_t *__restrict__ pval, uint32_t cap,
              const uint32_t *__restrict__ big_list, const uint32_t *__restrict__ big_count) {
@@ -454,7 +459,7 @@ k_keygen_big(const uint32_t *__restrict__ sorted_rec, const uint32_t *__restrict
     const uint32_t n_waves = gridDim.x * (blockDim.x / kWave);
     for (uint32_t w = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; w < n_big; w += n_waves) {
         const uint32_t p = big_list[w];
-        const uint32_t r = sorted_rec[p];
+        const uint32_t r = sorted_rec[p] & rec_mask;
         const int v = (int)(r / (uint32_t)n_per_view);
         Footprint f;
         if (!record_footprint(rec[4 * (int64_t)r], rec[4 * (int64_t)r + 1], rs.alpha_min, vt.width[v],
@@ -530,19 +535,22 @@ hipError_t launch_scan_indirect(const uint32_t *counts, const uint32_t *idx, int
 // key and record index at position flag_scan[r].
 __global__ void __launch_bounds__(256)
 k_compact(const uint32_t *__restrict__ counts, const uint32_t *__restrict__ flag_scan, const uint32_t *__restrict__ dkey,
-          int64_t n, uint32_t *__restrict__ ckey, uint32_t *__restrict__ cval) {
+          int64_t n, uint32_t *__restrict__ ckey, uint32_t *__restrict__ cval, int pack) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n || counts[r] == 0u) return;
+    if (r >= n) return;
+    const uint32_t c = counts[r];
+    if (c == 0u) return;
     const uint32_t pos = flag_scan[r];
     ckey[pos] = dkey[r];
-    cval[pos] = (uint32_t)r;
+    cval[pos] = pack ? (uint32_t)r | (min(c, kPackCountMax) << kPackShift) : (uint32_t)r;
 }
 
 hipError_t launch_compact(const uint32_t *counts, const uint32_t *flag_scan, const uint32_t *dkey, int64_t n,
-                          uint32_t *ckey, uint32_t *cval, hipStream_t s) {
+                          uint32_t *ckey, uint32_t *cval, bool pack, hipStream_t s) {
     if (n <= 0) return hipSuccess;
+    if (pack && n > (int64_t)kPackMask + 1) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_compact, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, counts, flag_scan, dkey, n, ckey,
-                       cval);
+                       cval, pack ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -603,9 +611,9 @@ hipError_t radix_sort(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t
     return hipGetLastError();
 }
 
-hipError_t launch_keygen(const uint32_t *sorted_rec, const uint32_t *sorted_counts, const uint32_t *offsets,
-                         const float *records, const uint4 *spans, const RasterSettings &rs, int64_t n_records,
-                         int64_t n_per_view,
+hipError_t launch_keygen(const uint32_t *sorted_rec, uint32_t rec_mask, const uint32_t *sorted_counts,
+                         const uint32_t *offsets, const float *records, const uint4 *spans, const RasterSettings &rs,
+                         int64_t n_records, int64_t n_per_view,
                          const ViewTable &vt, uint32_t *pkey, uint32_t *pval, FrameHeader *hdr, uint32_t capacity,
                          const uint32_t *total, uint32_t *big_list, uint32_t *big_count, const uint32_t *n_dev,
                          hipStream_t s) {
@@ -613,11 +621,12 @@ hipError_t launch_keygen(const uint32_t *sorted_rec, const uint32_t *sorted_coun
     if (e != hipSuccess) return e;
     const float4 *rec = reinterpret_cast<const float4 *>(records);
     const int64_t nb = n_records > 0 ? (n_records + 255) / 256 : 1;
-    hipLaunchKernelGGL(k_keygen, dim3((unsigned)nb), dim3(256), 0, s, sorted_rec, sorted_counts, offsets, rec, spans, rs,
-                       n_records, n_per_view, vt, pkey, pval, hdr, capacity, total, big_list, big_count, n_dev);
+    hipLaunchKernelGGL(k_keygen, dim3((unsigned)nb), dim3(256), 0, s, sorted_rec, rec_mask, sorted_counts, offsets, rec,
+                       spans, rs, n_records, n_per_view, vt, pkey, pval, hdr, capacity, total, big_list, big_count,
+                       n_dev);
     if (n_records > 0)
-        hipLaunchKernelGGL(k_keygen_big, dim3(1024), dim3(256), 0, s, sorted_rec, offsets, rec, rs, n_per_view, vt,
-                           pkey, pval, capacity, big_list, big_count);
+        hipLaunchKernelGGL(k_keygen_big, dim3(1024), dim3(256), 0, s, sorted_rec, rec_mask, offsets, rec, rs,
+                           n_per_view, vt, pkey, pval, capacity, big_list, big_count);
     return hipGetLastError();
 }
 

@@ -358,18 +358,27 @@ hipError_t launch_preprocess(const gspm_gaussians &g, const ViewTable &vt, const
                              uint32_t *dkey, uint4 *spans, uint32_t *big_list, uint32_t *big_count,
                              hipStream_t s);
 
-// Exclusive scan of counts[idx[p]] (or of counts[idx[p]] != 0 when flag is set) for
-// p < n, idx NULL meaning the identity; n is min(*n_dev, n) when n_dev is given.  Writes
-// offsets[p] and the total to *total.  part: scratch of at least scan_partials(n) words.
+// A window of at most 2^kPackShift records carries each live record through the depth sort
+// as its index with its pair count in the top bits, so that the pair-offset scan reads
+// the counts in depth order without gathering them; a count of kPackCountMax or more is
+// looked up by index.
+constexpr uint32_t kPackShift = 26;
+constexpr uint32_t kPackMask = (1u << kPackShift) - 1u;
+constexpr uint32_t kPackCountMax = (1u << (32 - kPackShift)) - 1u;
+
+// Exclusive scan for p < n of: counts[idx[p]] (flag 0), counts[idx[p]] != 0 (flag 1), or
+// the pair count packed in idx[p] (flag 2); idx NULL means the identity.  n is
+// min(*n_dev, n) when n_dev is given.  Writes offsets[p] and the total to *total.  part:
+// scratch of at least scan_partials(n) words.
 int64_t scan_partials(int64_t n);
 hipError_t launch_scan_indirect(const uint32_t *counts, const uint32_t *idx, int64_t n,
                                 uint32_t *offsets, uint32_t *total, uint32_t *part, hipStream_t s,
                                 const uint32_t *n_dev = nullptr, int flag = 0, uint32_t *gathered = nullptr);
 
 // Compacts (depth key, record index) of the records with counts[r] != 0 to the positions
-// given by the flag scan.
+// given by the flag scan; with pack, the value also carries the pair count (see kPackShift).
 hipError_t launch_compact(const uint32_t *counts, const uint32_t *flag_scan, const uint32_t *dkey, int64_t n,
-                          uint32_t *ckey, uint32_t *cval, hipStream_t s);
+                          uint32_t *ckey, uint32_t *cval, bool pack, hipStream_t s);
 
 // Stable LSD radix sort of (key, value) uint32 pairs over the low `bits` key bits, in
 // ceil(bits / digit_bits) passes of equal width (digit_bits in [4, 8]).  n_dev: device
@@ -389,9 +398,10 @@ hipError_t radix_sort(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t
 // more than kBigRecord pairs are queued in big_list (big_count zeroed here) and emitted
 // by whole waves.  records: the projected records (for the support footprint of records
 // whose spans are not cached in spans).
-hipError_t launch_keygen(const uint32_t *sorted_rec, const uint32_t *sorted_counts, const uint32_t *offsets,
-                         const float *records, const uint4 *spans, const RasterSettings &rs, int64_t n_records,
-                         int64_t n_per_view,
+// rec_mask: kPackMask if sorted_rec carries packed counts, else all ones.
+hipError_t launch_keygen(const uint32_t *sorted_rec, uint32_t rec_mask, const uint32_t *sorted_counts,
+                         const uint32_t *offsets, const float *records, const uint4 *spans, const RasterSettings &rs,
+                         int64_t n_records, int64_t n_per_view,
                          const ViewTable &vt, uint32_t *pkey, uint32_t *pval, FrameHeader *hdr,
                          uint32_t capacity, const uint32_t *total, uint32_t *big_list, uint32_t *big_count,
                          const uint32_t *n_dev, hipStream_t s);
