@@ -35,14 +35,16 @@ __device__ inline int64_t scan_n(const uint32_t *n_dev, int64_t n_max) {
     return n < n_max ? n : n_max;
 }
 
-// Block-wide exclusive scan of one value per thread; returns the prefix, *total the sum.
+// Block-wide exclusive scan of one value per thread (NW waves); returns the prefix, *total
+// the sum.
+template <int NW = kScanBlock / kWave>
 __device__ inline uint32_t block_exclusive_scan(uint32_t x, uint32_t *lds, uint32_t &total) {
     const int lane = lane_id(), wid = threadIdx.x / kWave;
     const uint32_t inc = wave_inclusive_scan(x);
     if (lane == kWave - 1) lds[wid] = inc;
     __syncthreads();
     uint32_t wave_base = 0, tot = 0;
-    for (int k = 0; k < kScanBlock / kWave; ++k) {
+    for (int k = 0; k < NW; ++k) {
         const uint32_t t = lds[k];
         if (k < wid) wave_base += t;
         tot += t;
@@ -123,7 +125,7 @@ k_scan_apply(const uint32_t *__restrict__ counts, const uint32_t *__restrict__ i
 //
 // LSD radix sort with one histogram pass for every digit and one kernel per digit pass
 // (the single-sweep scheme with decoupled look-back of Merrill and Garland's scan and
-// Adinets and Merrill's Onesweep sort).  Keys are cut into tiles of 4096 (4 waves x 16
+// Adinets and Merrill's Onesweep sort).  Keys are cut into tiles of 8192 (8 waves x 16
 // steps of 64).  Block b of a pass kernel ranks tile b's keys stably (wave-level match of
 // equal digits by ballots, then per-digit offsets across the four waves), publishes its
 // per-digit counts, and finds the count of each digit in all earlier tiles by walking
@@ -135,12 +137,12 @@ k_scan_apply(const uint32_t *__restrict__ counts, const uint32_t *__restrict__ i
 // the sort is abandoned and the stall flag set) so that a broken ordering assumption or
 // a fault elsewhere cannot leave the kernel spinning.  The tile is staged in LDS in sorted order and
 // written so that consecutive lanes write consecutive addresses within each digit's run.
-// The key count may be read from device memory; only its ceil(n / 4096) tiles are used.
+// The key count may be read from device memory; only its ceil(n / 8192) tiles are used.
 
-constexpr int kSortBlock = 256;
+constexpr int kSortBlock = 512;
 constexpr int kSortWaves = kSortBlock / kWave;
 constexpr int kSortSteps = 16;
-constexpr int kSortTile = kSortBlock * kSortSteps;  // 4096 keys
+constexpr int kSortTile = kSortBlock * kSortSteps;  // 8192 keys (fewer tiles to look back over)
 constexpr int kSortMaxPasses = 8;
 // Published word per (tile, digit): flag in bits 31:30, count in bits 29:0.
 constexpr uint32_t kStatAgg = 1u << 30;  // the tile's own count
@@ -263,8 +265,8 @@ k_radix_pass(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
         status_next[tile * R + d] = 0u;  // the next pass's word for this tile
     }
     uint32_t all;
-    const uint32_t gpre = block_exclusive_scan(gcount, scan_lds, all);
-    const uint32_t pre = block_exclusive_scan(tot, scan_lds, all);
+    const uint32_t gpre = block_exclusive_scan<kSortWaves>(gcount, scan_lds, all);
+    const uint32_t pre = block_exclusive_scan<kSortWaves>(tot, scan_lds, all);
     if (threadIdx.x < R) {
         const int d = threadIdx.x;
         dstart[d] = pre;
