@@ -69,6 +69,9 @@ struct gspm_ctx {
     std::vector<int> phase_of;  // per recorded pair
     // Per record (n * V).
     DevBuf counts, big, live, dkey, dval, dkey_tmp, dval_tmp, dkey_s, dval_s, offsets, grad2d, spans;
+    // The image-plane gradient rows are all zero: the parameter pass clears every row it
+    // reads as nonzero, so only a new allocation or an interrupted backward needs a fill.
+    bool grad2d_clean = false;
     // Per pair (capacity).
     DevBuf pkey, pval, pkey_tmp, pval_tmp, pkey_s;
     // Small scratch.
@@ -253,11 +256,14 @@ gspm_status backward_common(gspm_ctx *ctx, const gspm_gaussians *g, const gspm_v
     hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
     const FrameLayout L = frame_layout(P.n_tiles, P.n_pixels, P.n_records, 0);
     const int64_t R = P.n_records;
+    const void *g2_before = ctx->grad2d.p;
     GSPM_HIP(grow(ctx->grad2d, 4 * kG2 * (R > 0 ? R : 1)));
+    if (ctx->grad2d.p != g2_before) ctx->grad2d_clean = false;
     const int64_t nb = pose_partial_blocks(g->n);
     GSPM_HIP(grow(ctx->pose_part, 8 * 6 * (nb > 0 ? nb : 1) * P.vt.n_views));
     float *g2 = static_cast<float *>(ctx->grad2d.p);
-    GSPM_HIP(launch_fill_f32(g2, 0.0f, kG2 * R, hs));
+    if (!ctx->grad2d_clean) GSPM_HIP(launch_fill_f32(g2, 0.0f, ctx->grad2d.bytes / 4, hs));
+    ctx->grad2d_clean = false;  // until both passes below have been launched
     PhaseTimer t_rb(ctx, hs, GSPM_PHASE_RASTER_BWD);
     GSPM_HIP(launch_raster_backward(P.vt, P.rs, at<uint2>(frame_state, L.ranges), at<uint32_t>(frame_state, L.pair_vals),
                                     at<float>(frame_state, L.records), at<uint32_t>(frame_state, L.last),
@@ -269,6 +275,7 @@ gspm_status backward_common(gspm_ctx *ctx, const gspm_gaussians *g, const gspm_v
     const gspm_gaussian_grads &out = (pose_only || !grads) ? none : *grads;
     GSPM_HIP(launch_preprocess_backward(*g, P.vt, views->T_cw, P.rs, g2, out, pose_grad != nullptr,
                                         static_cast<double *>(ctx->pose_part.p), hs));
+    ctx->grad2d_clean = true;
     if (pose_grad)
         GSPM_HIP(launch_pose_reduce(static_cast<double *>(ctx->pose_part.p), nb, P.vt.n_views, pose_grad, hs));
     return GSPM_OK;
@@ -305,7 +312,9 @@ gspm_status gspm_reserve(gspm_ctx *ctx, int64_t max_records, int64_t max_pairs, 
     (void)max_tiles;
     GSPM_HIP(ensure_records(ctx, max_records, 8));
     GSPM_HIP(ensure_pairs(ctx, max_pairs, 8));
+    const void *g2_before = ctx->grad2d.p;
     GSPM_HIP(grow(ctx->grad2d, 4 * kG2 * (max_records > 0 ? max_records : 1)));
+    if (ctx->grad2d.p != g2_before) ctx->grad2d_clean = false;
     return GSPM_OK;
 }
 

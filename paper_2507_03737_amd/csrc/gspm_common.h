@@ -463,8 +463,10 @@ hipError_t launch_raster_backward(const ViewTable &vt, const RasterSettings &rs,
                                   const gspm_const_images &up, float *grad2d, bool pose_only,
                                   const uint32_t *order, hipStream_t s);
 
+// Image-plane gradient rows -> parameter gradients (added into out) and per-block pose
+// partials; every row read as nonzero is cleared, so grad2d is all zero afterwards.
 hipError_t launch_preprocess_backward(const gspm_gaussians &g, const ViewTable &vt, const float *T_cw,
-                                      const RasterSettings &rs, const float *grad2d,
+                                      const RasterSettings &rs, float *grad2d,
                                       const gspm_gaussian_grads &out, bool want_pose,
                                       double *pose_partials, hipStream_t s);
 int64_t pose_partial_blocks(int64_t n);

@@ -225,7 +225,7 @@ __device__ inline void block_sum6(double x[6], double *lds) {
 
 __global__ void __launch_bounds__(kBwdBlock)
 k_preprocess_backward(gspm_gaussians G, ViewTable vt, const float *__restrict__ T_cw, RasterSettings rs,
-                      const float4 *__restrict__ grad2d, gspm_gaussian_grads out, int want_pose,
+                      float4 *__restrict__ grad2d, gspm_gaussian_grads out, int want_pose,
                       double *__restrict__ pose_part) {
     // One thread per (Gaussian, view) record: blockIdx.y is the view.  Parameter gradients
     // of the views are summed with float atomics; pose partials per block in FP64.
@@ -238,11 +238,15 @@ k_preprocess_backward(gspm_gaussians G, ViewTable vt, const float *__restrict__ 
     bool any = false;
     float4 q0 = make_float4(0, 0, 0, 0), q1 = q0, q2 = q0, q3 = q0;
     if (g < n) {
-        const float4 *src = grad2d + 4 * ((int64_t)v * n + g);
+        float4 *src = grad2d + 4 * ((int64_t)v * n + g);
         q0 = src[0]; q1 = src[1]; q2 = src[2]; q3 = src[3];
         any = q0.x != 0.f || q0.y != 0.f || q0.z != 0.f || q0.w != 0.f || q1.x != 0.f || q1.y != 0.f ||
               q1.z != 0.f || q1.w != 0.f || q2.x != 0.f || q2.y != 0.f || q2.z != 0.f || q2.w != 0.f ||
               q3.x != 0.f;
+        if (any) {  // leave the row cleared for the next backward
+            const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+            src[0] = z; src[1] = z; src[2] = z; src[3] = z;
+        }
     }
     Proj P;
     if (any) {
@@ -489,13 +493,13 @@ hipError_t launch_preprocess(const gspm_gaussians &g, const ViewTable &vt, const
 int64_t pose_partial_blocks(int64_t n) { return (n + kBwdBlock - 1) / kBwdBlock; }
 
 hipError_t launch_preprocess_backward(const gspm_gaussians &g, const ViewTable &vt, const float *T_cw,
-                                      const RasterSettings &rs, const float *grad2d,
+                                      const RasterSettings &rs, float *grad2d,
                                       const gspm_gaussian_grads &out, bool want_pose,
                                       double *pose_partials, hipStream_t s) {
     if (g.n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_preprocess_backward, dim3((unsigned)pose_partial_blocks(g.n), (unsigned)vt.n_views),
                        dim3(kBwdBlock), 0, s,
-                       g, vt, T_cw, rs, reinterpret_cast<const float4 *>(grad2d), out, want_pose ? 1 : 0,
+                       g, vt, T_cw, rs, reinterpret_cast<float4 *>(grad2d), out, want_pose ? 1 : 0,
                        pose_partials);
     return hipGetLastError();
 }
