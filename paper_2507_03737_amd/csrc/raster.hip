@@ -96,7 +96,8 @@ struct Layout {
     int lx, ly;                  // tile-local column and first row of this lane
     float rx0, rx1, ry0, ry1;    // this wave's rectangle of pixel centres, tile-local
     __device__ Layout() {
-        const int w = threadIdx.x / kWave, lane = lane_id();
+        // The wave index is uniform: keep it (and the rectangle) in scalar registers.
+        const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave)), lane = lane_id();
         const int wx = (w % (TILE / WW)) * WW, wy = (w / (TILE / WW)) * WH;
         lx = wx + lane % WW;
         ly = wy + (lane / WW) * PPT;
@@ -313,10 +314,14 @@ struct BwdValues {
         return c;
     }
     static constexpr uint64_t kColumns = columns();
+    // The per-pixel weighted sums (colour, depth, point: weight w times the pixel's upstream
+    // gradient), their count and their columns, 4 bits each.
+    static constexpr int NW = (kColour ? 3 : 0) + (kDepth ? 1 : 0) + (kPoint ? 3 : 0);
+    static constexpr uint32_t kWColumns = (uint32_t)(kColumns >> (4 * (N - NW)));
 };
 
 template <int TILE, int PPT, bool POSE_ONLY, int FRAME>
-__global__ void __launch_bounds__(TILE *TILE / PPT)
+__global__ void __launch_bounds__(TILE *TILE / PPT) __attribute__((amdgpu_waves_per_eu(PPT == 1 ? 6 : 1)))
 k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
              const float4 *__restrict__ rec, const uint32_t *__restrict__ last, const float *__restrict__ t_final,
              gspm_const_images fwd, gspm_const_images up, float *__restrict__ grad2d,
@@ -324,8 +329,23 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
     using L = Layout<TILE, PPT>;
     using V = BwdValues<POSE_ONLY, FRAME>;
     constexpr int NT = L::NT;
-    __shared__ float4 s0[NT], s1[NT], s2[NT], s3[NT];
+    // One pixel per lane: the per-record sums are a dense contraction done on the matrix
+    // cores (below); each wave keeps its operand columns for kSlots records in LDS.
+    constexpr bool kMfma = PPT == 1;
+    constexpr int kSlots = 8;
+    static_assert(!kMfma || (L::WW == 8 && L::WH == 8), "one pixel per lane means 8 x 8 wave rectangles");
+    // Records staged per batch: at one pixel per lane at most 128, so that the operand
+    // buffers below still leave room for six workgroups' worth of waves per compute unit.
+    constexpr int NS = kMfma && NT > 128 ? 128 : NT;
+    __shared__ float4 s0[NS], s1[NS], s2[NS], s3[NS];
     __shared__ uint32_t block_last;
+    // B operand of slot column j (g: j = slot, w: j = 8 + slot) for pixel p = 4 kb + c at
+    // 272 (kb / 4) + 68 c + 4 j + kb % 4: a lane's four values of one kb quarter are one
+    // 16-byte read, each read phase of 16 lanes is contiguous, and the 64 pixels of one
+    // column fall in 64 different banks (no conflicts either way).
+    constexpr int kBq = 272, kBc = 68;
+    __shared__ __align__(16) float mf_b[kMfma ? L::NW : 1][kMfma ? 4 * kBq : 4];
+    __shared__ float4 mf_meta[kMfma ? L::NW : 1][kSlots];
     const TilePos tp = tile_pos<TILE>(vt, order);
     const uint2 rg = ranges[tp.gt];
     const L lay;
@@ -394,19 +414,102 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
     __syncthreads();
     const uint32_t end = rg.x + block_last;
 
-    for (uint32_t base = rg.x; base < end; base += NT) {
+    // Matrix-core form of the per-record sums (PPT = 1).  For records j of a wave and its
+    // 64 pixels p, every sum is  Out[f][j] = sum_p F_f(p) H_j(p):  the six moments take
+    // F = 1, x, y, x^2, xy, y^2 (pixel offsets from the wave rectangle's centre) and
+    // H = g = alpha dL/dalpha; the colour, depth and point sums take F = the pixel's
+    // upstream gradient and H = w = alpha T.  Out is 16 x 16 with rows f (6 moments, then
+    // up to 7 weighted sums) and columns (H in {g, w}) x (8 record slots), the contraction
+    // runs over the 64 pixels: 16 v_mfma_f32_16x16x4f32 per 8 records.  The A operand
+    // (F, 16 values per lane) is constant for the wave; the B operand (g and w of each
+    // slot) is written by the walk.  Lane L supplies A[L % 16][4 kb + L / 16] and
+    // B[4 kb + L / 16][L % 16] for step kb and receives D[4 (L / 16) + r][L % 16].
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave)), lane = lane_id();
+    float Aop[kMfma ? 16 : 1];
+    const int bofs = (lane >> 4) * kBq + (lane & 3) * kBc + ((lane >> 2) & 3);  // this lane's pixel, column 0
+    int slot = 0;  // filled record slots of this wave (wave-uniform)
+    const float cxw = lay.rx0 + 3.5f, cyw = lay.ry0 + 3.5f;
+    if constexpr (kMfma) {
+        float *buf = mf_b[wv];
+        float wg[7];
+        int m = 0;
+        if (V::kColour) { wg[m++] = gC0[0]; wg[m++] = gC1[0]; wg[m++] = gC2[0]; }
+        if (V::kDepth) wg[m++] = gD[0];
+        if (V::kPoint) { wg[m++] = gX0[0]; wg[m++] = gX1[0]; wg[m++] = gX2[0]; }
+#pragma unroll
+        for (int t = 0; t < V::NW; ++t) buf[8 * lane + t] = wg[t];  // pixel-major: the reads below spread over the banks
+        __builtin_amdgcn_wave_barrier();
+        const int f = lane & 15, c = lane >> 4;
+#pragma unroll
+        for (int kb = 0; kb < 16; ++kb) {
+            const int p = 4 * kb + c;
+            const float x = (float)(p & 7) - 3.5f, y = (float)(p >> 3) - 3.5f;
+            float av = f == 0 ? 1.0f : f == 1 ? x : f == 2 ? y : f == 3 ? x * x : f == 4 ? x * y : y * y;
+            if (f >= 6) av = f < 6 + V::NW ? buf[8 * p + f - 6] : 0.0f;
+            Aop[kb] = av;
+        }
+        __builtin_amdgcn_wave_barrier();  // read before the walk overwrites the buffer
+    }
+    // Contract the first n slots and add the results to the records' rows.
+    auto flush = [&](int n) {
+        __builtin_amdgcn_wave_barrier();  // the slots are written (a wave's LDS accesses stay in order)
+        const int j = lane & 15, c = lane >> 4;
+        const float *src = mf_b[wv] + kBc * c + 4 * j;
+        const float4 q0 = *reinterpret_cast<const float4 *>(src), q1 = *reinterpret_cast<const float4 *>(src + kBq);
+        const float4 q2 = *reinterpret_cast<const float4 *>(src + 2 * kBq);
+        const float4 q3 = *reinterpret_cast<const float4 *>(src + 3 * kBq);
+        const float bq[16] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w,
+                              q2.x, q2.y, q2.z, q2.w, q3.x, q3.y, q3.z, q3.w};
+        v4f acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kb = 0; kb < 16; ++kb) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(Aop[kb], bq[kb], acc, 0, 0, 0);
+        // Transpose through LDS (over the B operand, read above) so that 16 adjacent lanes
+        // hold one record's row (one cache line per record and atomic instruction):
+        // dout[20 j + f] for column j, row f (the pitch of 20 keeps the 16-byte writes of a
+        // phase in distinct banks).
+        float *dout = mf_b[wv];
+        *reinterpret_cast<float4 *>(dout + j * 20 + 4 * c) = make_float4(acc[0], acc[1], acc[2], acc[3]);
+        __builtin_amdgcn_wave_barrier();
+        // The lane's grad2d column is j; its value is row f of B column (H, slot), coded as
+        // H << 4 | f (-1: the column is not produced).
+        int src_f = j <= 5 && (j > 0 || V::kOpacity) ? j : -1;
+#pragma unroll
+        for (int m = 0; m < V::NW; ++m)
+            if ((int)((V::kWColumns >> (4 * m)) & 15u) == j) src_f = 16 | (6 + m);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int sr = 4 * h + c;  // record slot of this lane
+            const float4 mt = mf_meta[wv][sr];
+            const float4 sm = *reinterpret_cast<const float4 *>(dout + sr * 20);  // S0, Sx, Sy, Sxx
+            const float val = src_f >= 0 ? dout[((src_f >> 4) * 8 + sr) * 20 + (src_f & 15)] : 0.0f;
+            // Moments about the wave centre -> about the record's mean (dx = x - ux).
+            const float ux = mt.x - cxw, uy = mt.y - cyw;
+            const float al = j == 1 ? -ux : j == 2 ? -uy : j == 3 ? ux * ux : j == 4 ? ux * uy : j == 5 ? uy * uy : 0.0f;
+            const float be = j == 3 ? -2.0f * ux : j == 4 ? -uy : 0.0f;
+            const float ga = j == 4 ? -ux : j == 5 ? -2.0f * uy : 0.0f;
+            const float out = fmaf(ga, sm.z, fmaf(be, sm.y, fmaf(al, sm.x, val)));
+            const uint32_t rid = __float_as_uint(mt.z);
+            if (sr < n && src_f >= 0 && out != 0.f) unsafeAtomicAdd(grad2d + (int64_t)rid * kG2 + j, out);
+        }
+        __builtin_amdgcn_wave_barrier();  // read before later records overwrite the buffer
+    };
+
+    for (uint32_t base = rg.x; base < end; base += NS) {
         const uint32_t kk = base + threadIdx.x;
-        if (kk < end) stage(rec, vals[kk], tp.x0, tp.y0, amin, s0, s1, s2, s3, threadIdx.x);
+        if (threadIdx.x < NS && kk < end) stage(rec, vals[kk], tp.x0, tp.y0, amin, s0, s1, s2, s3, threadIdx.x);
         __syncthreads();
-        const int cnt = (int)min((uint32_t)NT, end - base);
+        const int cnt = (int)min((uint32_t)NS, end - base);
         const uint32_t rel0 = base - rg.x;
         for (int c = 0; c < cnt && rel0 + (uint32_t)c < wave_last; c += kWave) {
             uint64_t m = batch_mask<L::CULL>(s0, s1, c, cnt, lay.rx0, lay.rx1, lay.ry0, lay.ry1);
+            // Entries at or past the wave's last contributing one are not walked.
+            const uint32_t lim = wave_last - (rel0 + (uint32_t)c);
+            if (lim < (uint32_t)kWave) m &= (1ull << lim) - 1ull;
             while (m != 0ull) {
                 const int q = c + (int)__builtin_ctzll(m);
                 m &= m - 1ull;
                 const uint32_t rel = rel0 + (uint32_t)q;
-                if (rel >= wave_last) break;  // wave-uniform
                 const float4 a = s0[q];
                 const float4 b = s1[q];
                 // One 16-byte read now rather than a second, split read after the test.
@@ -446,6 +549,13 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
                     const float one_m = __fsub_rn(1.0f, al);
                     const float dLda = T[k] * sv - (Gb[k] - Pfx[k]) * __builtin_amdgcn_rcpf(one_m);
                     const float g = (valid[k] && al < amax) ? dLda * al : 0.0f;
+                    if constexpr (kMfma) {
+                        T[k] = valid[k] ? __fmul_rn(T[k], one_m) : T[k];
+                        float *bw = mf_b[wv] + bofs + 4 * slot;
+                        bw[0] = g;
+                        bw[4 * kSlots] = w;
+                        continue;
+                    }
                     const float gdx = g * dx, gdy = g * dy;
                     int t = 0;
                     if (V::kOpacity) add(t++, g);
@@ -467,6 +577,14 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
                     }
                     T[k] = valid[k] ? __fmul_rn(T[k], one_m) : T[k];
                 }
+                if constexpr (kMfma) {
+                    if (lane == 0) mf_meta[wv][slot] = make_float4(a.x, a.y, b.w, 0.0f);
+                    if (++slot == kSlots) {
+                        flush(kSlots);
+                        slot = 0;
+                    }
+                    continue;
+                }
                 int idx;
                 const float tot = wave_reduce_scatter(v, idx);
                 if (idx >= 0 && idx < V::N && tot != 0.f) {
@@ -478,6 +596,9 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
             }
         }
         __syncthreads();
+    }
+    if constexpr (kMfma) {
+        if (slot > 0) flush(slot);  // wave-uniform
     }
 }
 
