@@ -321,7 +321,7 @@ struct BwdValues {
 };
 
 template <int TILE, int PPT, bool POSE_ONLY, int FRAME>
-__global__ void __launch_bounds__(TILE *TILE / PPT) __attribute__((amdgpu_waves_per_eu(PPT == 1 ? 6 : 1)))
+__global__ void __launch_bounds__(TILE *TILE / PPT) __attribute__((amdgpu_waves_per_eu(PPT == 1 ? 7 : 1)))
 k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
              const float4 *__restrict__ rec, const uint32_t *__restrict__ last, const float *__restrict__ t_final,
              gspm_const_images fwd, gspm_const_images up, float *__restrict__ grad2d,
@@ -334,9 +334,10 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
     constexpr bool kMfma = PPT == 1;
     constexpr int kSlots = 8;
     static_assert(!kMfma || (L::WW == 8 && L::WH == 8), "one pixel per lane means 8 x 8 wave rectangles");
-    // Records staged per batch: at one pixel per lane at most 128, so that the operand
-    // buffers below still leave room for six workgroups' worth of waves per compute unit.
-    constexpr int NS = kMfma && NT > 128 ? 128 : NT;
+    // Records staged per batch: at one pixel per lane at most 64, so that the operand
+    // buffers below still leave room for seven workgroups per compute unit (7 waves per
+    // SIMD, which the register budget is set for).
+    constexpr int NS = kMfma && NT > 64 ? 64 : NT;
     __shared__ float4 s0[NS], s1[NS], s2[NS], s3[NS];
     __shared__ uint32_t block_last;
     // B operand of slot column j (g: j = slot, w: j = 8 + slot) for pixel p = 4 kb + c at
