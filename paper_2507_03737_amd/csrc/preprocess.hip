@@ -227,159 +227,165 @@ __global__ void __launch_bounds__(kBwdBlock)
 k_preprocess_backward(gspm_gaussians G, ViewTable vt, const float *__restrict__ T_cw, RasterSettings rs,
                       float4 *__restrict__ grad2d, gspm_gaussian_grads out, int want_pose,
                       double *__restrict__ pose_part) {
-    // One thread per (Gaussian, view) record: blockIdx.y is the view.  Parameter gradients
-    // of the views are summed with float atomics; pose partials per block in FP64.
+    // One thread per Gaussian, looping over the views: the Gaussian's parameter gradients
+    // are summed over the views in registers and added once (one float atomic per
+    // parameter, not one per view), and its parameters stay in cache across the views.
+    // Pose partials per block and view in FP64.
     __shared__ double lds[6 * (kBwdBlock / 64)];
     const int64_t n = G.n;
-    const int v = blockIdx.y;
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double gmu[3] = {0, 0, 0}, gls[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go = 0.0, gc[3] = {0, 0, 0};
-    double pose[6] = {0, 0, 0, 0, 0, 0};
-    bool any = false;
-    float4 q0 = make_float4(0, 0, 0, 0), q1 = q0, q2 = q0, q3 = q0;
-    if (g < n) {
-        float4 *src = grad2d + 4 * ((int64_t)v * n + g);
-        q0 = src[0]; q1 = src[1]; q2 = src[2]; q3 = src[3];
-        any = q0.x != 0.f || q0.y != 0.f || q0.z != 0.f || q0.w != 0.f || q1.x != 0.f || q1.y != 0.f ||
-              q1.z != 0.f || q1.w != 0.f || q2.x != 0.f || q2.y != 0.f || q2.z != 0.f || q2.w != 0.f ||
-              q3.x != 0.f;
-        if (any) {  // leave the row cleared for the next backward
-            const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-            src[0] = z; src[1] = z; src[2] = z; src[3] = z;
+    bool touched = false;
+    for (int v = 0; v < vt.n_views; ++v) {
+        double pose[6] = {0, 0, 0, 0, 0, 0};
+        bool any = false;
+        float4 q0 = make_float4(0, 0, 0, 0), q1 = q0, q2 = q0, q3 = q0;
+        if (g < n) {
+            float4 *src = grad2d + 4 * ((int64_t)v * n + g);
+            q0 = src[0]; q1 = src[1]; q2 = src[2]; q3 = src[3];
+            any = q0.x != 0.f || q0.y != 0.f || q0.z != 0.f || q0.w != 0.f || q1.x != 0.f || q1.y != 0.f ||
+                  q1.z != 0.f || q1.w != 0.f || q2.x != 0.f || q2.y != 0.f || q2.z != 0.f || q2.w != 0.f ||
+                  q3.x != 0.f;
+            if (any) {  // leave the row cleared for the next backward
+                const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+                src[0] = z; src[1] = z; src[2] = z; src[3] = z;
+            }
         }
-    }
-    Proj P;
-    if (any) {
-        project_one(G, g, n, T_cw + 12 * v, vt.fx[v], vt.fy[v], vt.cx[v], vt.cy[v], vt.width[v], vt.height[v],
-                    rs, P);
-        any = P.visible;
-    }
-    {
+        Proj P;
         if (any) {
-            // Moments of g = alpha dL/dalpha over the pixel offsets d = pixel - mean.  With
-            // alpha = o 2^e and e = -log2(e) d^T Q d / 2: dL/de = ln 2 g, so
-            //   dL/du = sum g (Q d)_x, dL/dv = sum g (Q d)_y, dL/dQ = -sum g d d^T / 2,
-            //   dL/do = sum g / o, so the logit's gradient is sum g (1 - o).
-            const double R0 = q0.x, Rx = q0.y, Ry = q0.z, Rxx = q0.w, Rxy = q1.x, Ryy = q1.y, gz = q1.z;
-            gc[0] += q1.w; gc[1] += q2.x; gc[2] += q2.y;
-            const double gp[3] = {q2.z, q2.w, q3.x};
-            const double Qa = P.Q[0], Qb = P.Q[1], Qc = P.Q[2];
-            const double gu = Qa * Rx + Qb * Ry, gv = Qb * Rx + Qc * Ry;
-            const double gQxx = -0.5 * Rxx, gQxy = -Rxy, gQyy = -0.5 * Ryy;
-            // d L / d cov2 = -Q Ghat Q with Ghat the symmetric gradient wrt Q.
-            const double G00 = gQxx, G01 = 0.5 * gQxy, G11 = gQyy;
-            // X = Ghat Q
-            const double X00 = G00 * Qa + G01 * Qb, X01 = G00 * Qb + G01 * Qc;
-            const double X10 = G01 * Qa + G11 * Qb, X11 = G01 * Qb + G11 * Qc;
-            const double H00 = -(Qa * X00 + Qb * X10), H01 = -(Qa * X01 + Qb * X11);
-            const double H11 = -(Qb * X01 + Qc * X11);
-            // cov2 = J Sc J^T + eps: gradient wrt Sc is J^T H J (H symmetric, off-diagonal H01).
-            double GS[3][3];
-            for (int k = 0; k < 3; ++k)
-                for (int l = 0; l < 3; ++l)
-                    GS[k][l] = P.J[0][k] * (H00 * P.J[0][l] + H01 * P.J[1][l]) +
-                               P.J[1][k] * (H01 * P.J[0][l] + H11 * P.J[1][l]);
-            // d L / d J = 2 H J Sc.
-            double JS[2][3];
-            for (int r = 0; r < 2; ++r)
-                for (int c = 0; c < 3; ++c)
-                    JS[r][c] = P.J[r][0] * P.Sc[0][c] + P.J[r][1] * P.Sc[1][c] + P.J[r][2] * P.Sc[2][c];
-            const double gJ00 = 2.0 * (H00 * JS[0][0] + H01 * JS[1][0]);
-            const double gJ02 = 2.0 * (H00 * JS[0][2] + H01 * JS[1][2]);
-            const double gJ11 = 2.0 * (H01 * JS[0][1] + H11 * JS[1][1]);
-            const double gJ12 = 2.0 * (H01 * JS[0][2] + H11 * JS[1][2]);
-
-            // Camera-frame centre.
-            const double fx = vt.fx[v], fy = vt.fy[v];
-            const double iz = 1.0 / P.z, mx = P.m[0], my = P.m[1];
-            double gm[3];
-            gm[0] = gu * fx * iz;
-            gm[1] = gv * fy * iz;
-            gm[2] = -(gu * fx * mx + gv * fy * my) * iz * iz + gz;
-            gm[2] += -(gJ00 * P.J[0][0] + gJ11 * P.J[1][1]) * iz;
-            if (P.clamp_x) {
-                gm[2] += gJ02 * (-P.J[0][2] * iz);
-            } else {
-                gm[0] += gJ02 * (-fx * iz * iz);
-                gm[2] += gJ02 * (-2.0 * P.J[0][2] * iz);
-            }
-            if (P.clamp_y) {
-                gm[2] += gJ12 * (-P.J[1][2] * iz);
-            } else {
-                gm[1] += gJ12 * (-fy * iz * iz);
-                gm[2] += gJ12 * (-2.0 * P.J[1][2] * iz);
-            }
-            if (rs.frame == 1) { gm[0] += gp[0]; gm[1] += gp[1]; gm[2] += gp[2]; }
-            for (int c = 0; c < 3; ++c)
-                gmu[c] += P.W[0][c] * gm[0] + P.W[1][c] * gm[1] + P.W[2][c] * gm[2];
-            if (rs.frame == 0) { gmu[0] += gp[0]; gmu[1] += gp[1]; gmu[2] += gp[2]; }
-
-            if (want_pose) {
-                // Translation: dm = rho.  Rotation: dm = phi x m, dSc = [phi]x Sc - Sc [phi]x.
-                pose[0] = gm[0]; pose[1] = gm[1]; pose[2] = gm[2];
-                pose[3] = P.m[1] * gm[2] - P.m[2] * gm[1];
-                pose[4] = P.m[2] * gm[0] - P.m[0] * gm[2];
-                pose[5] = P.m[0] * gm[1] - P.m[1] * gm[0];
-                // A = Sc GS - GS Sc (antisymmetric); d L / d phi += 2 (A12, -A02, A01), GS symmetrised.
-                double Gs[3][3];
+            project_one(G, g, n, T_cw + 12 * v, vt.fx[v], vt.fy[v], vt.cx[v], vt.cy[v], vt.width[v], vt.height[v],
+                        rs, P);
+            any = P.visible;
+        }
+        {
+            if (any) {
+                // Moments of g = alpha dL/dalpha over the pixel offsets d = pixel - mean.  With
+                // alpha = o 2^e and e = -log2(e) d^T Q d / 2: dL/de = ln 2 g, so
+                //   dL/du = sum g (Q d)_x, dL/dv = sum g (Q d)_y, dL/dQ = -sum g d d^T / 2,
+                //   dL/do = sum g / o, so the logit's gradient is sum g (1 - o).
+                const double R0 = q0.x, Rx = q0.y, Ry = q0.z, Rxx = q0.w, Rxy = q1.x, Ryy = q1.y, gz = q1.z;
+                gc[0] += q1.w; gc[1] += q2.x; gc[2] += q2.y;
+                const double gp[3] = {q2.z, q2.w, q3.x};
+                const double Qa = P.Q[0], Qb = P.Q[1], Qc = P.Q[2];
+                const double gu = Qa * Rx + Qb * Ry, gv = Qb * Rx + Qc * Ry;
+                const double gQxx = -0.5 * Rxx, gQxy = -Rxy, gQyy = -0.5 * Ryy;
+                // d L / d cov2 = -Q Ghat Q with Ghat the symmetric gradient wrt Q.
+                const double G00 = gQxx, G01 = 0.5 * gQxy, G11 = gQyy;
+                // X = Ghat Q
+                const double X00 = G00 * Qa + G01 * Qb, X01 = G00 * Qb + G01 * Qc;
+                const double X10 = G01 * Qa + G11 * Qb, X11 = G01 * Qb + G11 * Qc;
+                const double H00 = -(Qa * X00 + Qb * X10), H01 = -(Qa * X01 + Qb * X11);
+                const double H11 = -(Qb * X01 + Qc * X11);
+                // cov2 = J Sc J^T + eps: gradient wrt Sc is J^T H J (H symmetric, off-diagonal H01).
+                double GS[3][3];
                 for (int k = 0; k < 3; ++k)
-                    for (int l = 0; l < 3; ++l) Gs[k][l] = 0.5 * (GS[k][l] + GS[l][k]);
-                double A01 = 0, A02 = 0, A12 = 0;
-                for (int k = 0; k < 3; ++k) {
-                    A01 += P.Sc[0][k] * Gs[k][1] - Gs[0][k] * P.Sc[k][1];
-                    A02 += P.Sc[0][k] * Gs[k][2] - Gs[0][k] * P.Sc[k][2];
-                    A12 += P.Sc[1][k] * Gs[k][2] - Gs[1][k] * P.Sc[k][2];
-                }
-                pose[3] += 2.0 * A12;
-                pose[4] += -2.0 * A02;
-                pose[5] += 2.0 * A01;
-            }
+                    for (int l = 0; l < 3; ++l)
+                        GS[k][l] = P.J[0][k] * (H00 * P.J[0][l] + H01 * P.J[1][l]) +
+                                   P.J[1][k] * (H01 * P.J[0][l] + H11 * P.J[1][l]);
+                // d L / d J = 2 H J Sc.
+                double JS[2][3];
+                for (int r = 0; r < 2; ++r)
+                    for (int c = 0; c < 3; ++c)
+                        JS[r][c] = P.J[r][0] * P.Sc[0][c] + P.J[r][1] * P.Sc[1][c] + P.J[r][2] * P.Sc[2][c];
+                const double gJ00 = 2.0 * (H00 * JS[0][0] + H01 * JS[1][0]);
+                const double gJ02 = 2.0 * (H00 * JS[0][2] + H01 * JS[1][2]);
+                const double gJ11 = 2.0 * (H01 * JS[0][1] + H11 * JS[1][1]);
+                const double gJ12 = 2.0 * (H01 * JS[0][2] + H11 * JS[1][2]);
 
-            // Sc = W Sigma W^T: G_Sigma = W^T GS W; Sigma = (Rq S)(Rq S)^T.
-            double T1[3][3], GSig[3][3];
-            for (int k = 0; k < 3; ++k)
-                for (int l = 0; l < 3; ++l)
-                    T1[k][l] = P.W[0][k] * GS[0][l] + P.W[1][k] * GS[1][l] + P.W[2][k] * GS[2][l];
-            for (int k = 0; k < 3; ++k)
-                for (int l = 0; l < 3; ++l)
-                    GSig[k][l] = T1[k][0] * P.W[0][l] + T1[k][1] * P.W[1][l] + T1[k][2] * P.W[2][l];
-            // d L / d M = (GSig + GSig^T) M, M = Rq diag(s).
-            double gR[3][3];
-            for (int r = 0; r < 3; ++r)
-                for (int c = 0; c < 3; ++c) {
-                    double acc = 0.0;
-                    for (int b = 0; b < 3; ++b) acc += (GSig[r][b] + GSig[b][r]) * P.Rq[b][c] * P.s[c];
-                    gR[r][c] = acc * P.s[c];
-                    // gR holds dL/dM * s = dL/dRq; reuse acc for the scale below.
+                // Camera-frame centre.
+                const double fx = vt.fx[v], fy = vt.fy[v];
+                const double iz = 1.0 / P.z, mx = P.m[0], my = P.m[1];
+                double gm[3];
+                gm[0] = gu * fx * iz;
+                gm[1] = gv * fy * iz;
+                gm[2] = -(gu * fx * mx + gv * fy * my) * iz * iz + gz;
+                gm[2] += -(gJ00 * P.J[0][0] + gJ11 * P.J[1][1]) * iz;
+                if (P.clamp_x) {
+                    gm[2] += gJ02 * (-P.J[0][2] * iz);
+                } else {
+                    gm[0] += gJ02 * (-fx * iz * iz);
+                    gm[2] += gJ02 * (-2.0 * P.J[0][2] * iz);
                 }
-            for (int c = 0; c < 3; ++c) {
-                // dL/ds_c = sum_r dL/dM_rc Rq_rc = sum_r gR_rc Rq_rc / s_c; dL/dlog s = s dL/ds.
-                double acc = 0.0;
-                for (int r = 0; r < 3; ++r) acc += gR[r][c] * P.Rq[r][c];
-                gls[c] += acc;
+                if (P.clamp_y) {
+                    gm[2] += gJ12 * (-P.J[1][2] * iz);
+                } else {
+                    gm[1] += gJ12 * (-fy * iz * iz);
+                    gm[2] += gJ12 * (-2.0 * P.J[1][2] * iz);
+                }
+                if (rs.frame == 1) { gm[0] += gp[0]; gm[1] += gp[1]; gm[2] += gp[2]; }
+                for (int c = 0; c < 3; ++c)
+                    gmu[c] += P.W[0][c] * gm[0] + P.W[1][c] * gm[1] + P.W[2][c] * gm[2];
+                if (rs.frame == 0) { gmu[0] += gp[0]; gmu[1] += gp[1]; gmu[2] += gp[2]; }
+
+                if (want_pose) {
+                    // Translation: dm = rho.  Rotation: dm = phi x m, dSc = [phi]x Sc - Sc [phi]x.
+                    pose[0] = gm[0]; pose[1] = gm[1]; pose[2] = gm[2];
+                    pose[3] = P.m[1] * gm[2] - P.m[2] * gm[1];
+                    pose[4] = P.m[2] * gm[0] - P.m[0] * gm[2];
+                    pose[5] = P.m[0] * gm[1] - P.m[1] * gm[0];
+                    // A = Sc GS - GS Sc (antisymmetric); d L / d phi += 2 (A12, -A02, A01), GS symmetrised.
+                    double Gs[3][3];
+                    for (int k = 0; k < 3; ++k)
+                        for (int l = 0; l < 3; ++l) Gs[k][l] = 0.5 * (GS[k][l] + GS[l][k]);
+                    double A01 = 0, A02 = 0, A12 = 0;
+                    for (int k = 0; k < 3; ++k) {
+                        A01 += P.Sc[0][k] * Gs[k][1] - Gs[0][k] * P.Sc[k][1];
+                        A02 += P.Sc[0][k] * Gs[k][2] - Gs[0][k] * P.Sc[k][2];
+                        A12 += P.Sc[1][k] * Gs[k][2] - Gs[1][k] * P.Sc[k][2];
+                    }
+                    pose[3] += 2.0 * A12;
+                    pose[4] += -2.0 * A02;
+                    pose[5] += 2.0 * A01;
+                }
+
+                // Sc = W Sigma W^T: G_Sigma = W^T GS W; Sigma = (Rq S)(Rq S)^T.
+                double T1[3][3], GSig[3][3];
+                for (int k = 0; k < 3; ++k)
+                    for (int l = 0; l < 3; ++l)
+                        T1[k][l] = P.W[0][k] * GS[0][l] + P.W[1][k] * GS[1][l] + P.W[2][k] * GS[2][l];
+                for (int k = 0; k < 3; ++k)
+                    for (int l = 0; l < 3; ++l)
+                        GSig[k][l] = T1[k][0] * P.W[0][l] + T1[k][1] * P.W[1][l] + T1[k][2] * P.W[2][l];
+                // d L / d M = (GSig + GSig^T) M, M = Rq diag(s).
+                double gR[3][3];
+                for (int r = 0; r < 3; ++r)
+                    for (int c = 0; c < 3; ++c) {
+                        double acc = 0.0;
+                        for (int b = 0; b < 3; ++b) acc += (GSig[r][b] + GSig[b][r]) * P.Rq[b][c] * P.s[c];
+                        gR[r][c] = acc * P.s[c];
+                        // gR holds dL/dM * s = dL/dRq; reuse acc for the scale below.
+                    }
+                for (int c = 0; c < 3; ++c) {
+                    // dL/ds_c = sum_r dL/dM_rc Rq_rc = sum_r gR_rc Rq_rc / s_c; dL/dlog s = s dL/ds.
+                    double acc = 0.0;
+                    for (int r = 0; r < 3; ++r) acc += gR[r][c] * P.Rq[r][c];
+                    gls[c] += acc;
+                }
+                const double w = P.qn[0], x = P.qn[1], y = P.qn[2], z = P.qn[3];
+                double gqn[4];
+                gqn[0] = 2.0 * (z * (gR[1][0] - gR[0][1]) + y * (gR[0][2] - gR[2][0]) + x * (gR[2][1] - gR[1][2]));
+                gqn[1] = 2.0 * (y * (gR[0][1] + gR[1][0]) + z * (gR[0][2] + gR[2][0]) + w * (gR[2][1] - gR[1][2])) -
+                         4.0 * x * (gR[1][1] + gR[2][2]);
+                gqn[2] = 2.0 * (x * (gR[0][1] + gR[1][0]) + w * (gR[0][2] - gR[2][0]) + z * (gR[1][2] + gR[2][1])) -
+                         4.0 * y * (gR[0][0] + gR[2][2]);
+                gqn[3] = 2.0 * (w * (gR[1][0] - gR[0][1]) + x * (gR[0][2] + gR[2][0]) + y * (gR[1][2] + gR[2][1])) -
+                         4.0 * z * (gR[0][0] + gR[1][1]);
+                const double dot = gqn[0] * w + gqn[1] * x + gqn[2] * y + gqn[3] * z;
+                const double iq = 1.0 / P.qnorm;
+                for (int k = 0; k < 4; ++k) gq[k] += (gqn[k] - P.qn[k] * dot) * iq;
+                go += R0 * (1.0 - P.a);
             }
-            const double w = P.qn[0], x = P.qn[1], y = P.qn[2], z = P.qn[3];
-            double gqn[4];
-            gqn[0] = 2.0 * (z * (gR[1][0] - gR[0][1]) + y * (gR[0][2] - gR[2][0]) + x * (gR[2][1] - gR[1][2]));
-            gqn[1] = 2.0 * (y * (gR[0][1] + gR[1][0]) + z * (gR[0][2] + gR[2][0]) + w * (gR[2][1] - gR[1][2])) -
-                     4.0 * x * (gR[1][1] + gR[2][2]);
-            gqn[2] = 2.0 * (x * (gR[0][1] + gR[1][0]) + w * (gR[0][2] - gR[2][0]) + z * (gR[1][2] + gR[2][1])) -
-                     4.0 * y * (gR[0][0] + gR[2][2]);
-            gqn[3] = 2.0 * (w * (gR[1][0] - gR[0][1]) + x * (gR[0][2] + gR[2][0]) + y * (gR[1][2] + gR[2][1])) -
-                     4.0 * z * (gR[0][0] + gR[1][1]);
-            const double dot = gqn[0] * w + gqn[1] * x + gqn[2] * y + gqn[3] * z;
-            const double iq = 1.0 / P.qnorm;
-            for (int k = 0; k < 4; ++k) gq[k] += (gqn[k] - P.qn[k] * dot) * iq;
-            go += R0 * (1.0 - P.a);
+        }
+        touched |= any;
+        if (want_pose) {
+            // Every thread of the block takes part (uniform branch).
+            block_sum6(pose, lds);
+            if (threadIdx.x == 0)
+                for (int k = 0; k < 6; ++k) pose_part[((int64_t)v * gridDim.x + blockIdx.x) * 6 + k] = pose[k];
+            __syncthreads();  // the sums are read before the next view's reduction reuses lds
         }
     }
-    if (want_pose) {
-        // Every thread of the block takes part (uniform branch).
-        block_sum6(pose, lds);
-        if (threadIdx.x == 0)
-            for (int k = 0; k < 6; ++k) pose_part[((int64_t)v * gridDim.x + blockIdx.x) * 6 + k] = pose[k];
-    }
-    if (!any) return;
+    if (!touched) return;
     if (out.means)
         for (int c = 0; c < 3; ++c) unsafeAtomicAdd(out.means + c * n + g, (float)gmu[c]);
     if (out.log_scales)
@@ -497,8 +503,7 @@ hipError_t launch_preprocess_backward(const gspm_gaussians &g, const ViewTable &
                                       const gspm_gaussian_grads &out, bool want_pose,
                                       double *pose_partials, hipStream_t s) {
     if (g.n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_preprocess_backward, dim3((unsigned)pose_partial_blocks(g.n), (unsigned)vt.n_views),
-                       dim3(kBwdBlock), 0, s,
+    hipLaunchKernelGGL(k_preprocess_backward, dim3((unsigned)pose_partial_blocks(g.n)), dim3(kBwdBlock), 0, s,
                        g, vt, T_cw, rs, reinterpret_cast<float4 *>(grad2d), out, want_pose ? 1 : 0,
                        pose_partials);
     return hipGetLastError();
