@@ -19,12 +19,14 @@
 // with the same instructions as the forward, so no per-fragment state is stored: only the
 // per-pixel count of list entries up to the last contributing fragment.  The suffix sums
 // that the alpha derivative needs are recovered as (sum over all fragments) - (prefix
-// sum), the total coming from the forward's outputs.  Each lane adds its pixels'
-// contributions to the per-record sums (up to 13: the moments of alpha dL/dalpha over the
-// pixel offsets, from which the mean, conic and opacity gradients follow, and the colour,
-// depth and point sums), the wave adds them up with one reduce-scatter (cross-half lane
-// swaps and DPP) of 8, 12 or 16 values, and one lane per value issues a float atomic, so
-// the reduction and the atomics are paid once per wave and list entry.
+// sum), the total coming from the forward's outputs.  Per record the wave needs up to 13
+// sums over its pixels: the moments of alpha dL/dalpha over the pixel offsets (from which
+// the mean, conic and opacity gradients follow) and the colour, depth and point sums.
+// With one pixel per lane these are a dense contraction (per-wave constant functions of
+// the pixel times per-record pixel values) done on the matrix cores for 8 records at a
+// time; with several pixels per lane each lane adds its pixels' contributions and the
+// wave adds them up with one reduce-scatter (cross-half lane swaps and DPP) of 8, 12 or
+// 16 values.  Either way the atomics are paid once per wave and record.
 #include "gspm_common.h"
 
 namespace gspm {
