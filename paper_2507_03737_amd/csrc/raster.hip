@@ -515,6 +515,8 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
                 const uint32_t rel = rel0 + (uint32_t)q;
                 const float4 a = s0[q];
                 const float4 b = s1[q];
+                const float4 cc = s2[q];
+                const float4 d = s3[q];
                 // One 16-byte read now rather than a second, split read after the test.
                 asm volatile("" ::"v"(b.z), "v"(b.w));
                 const float dx = px - a.x;
@@ -529,9 +531,11 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
                     valid[k] = (rel < my_last[k] ? e[k] : -INFINITY) >= b.y;
                     any |= ballot(valid[k]);
                 }
+                if constexpr (kMfma) {
+                    asm volatile("" ::"v"(cc.x), "v"(cc.y), "v"(cc.z), "v"(cc.w));
+                    if constexpr (V::kPoint) asm volatile("" ::"v"(d.x), "v"(d.y), "v"(d.z));
+                }
                 if (any == 0ull) continue;  // wave-uniform
-                const float4 cc = s2[q];
-                const float4 d = s3[q];
                 float v[V::NR];
 #pragma unroll
                 for (int t = V::N; t < V::NR; ++t) v[t] = 0.f;
