@@ -498,9 +498,14 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
         __builtin_amdgcn_wave_barrier();  // read before later records overwrite the buffer
     };
 
+    // The next batch's record indices are loaded one batch ahead, so staging waits on one
+    // global read (the record) rather than two dependent ones.
+    uint32_t vnext = (threadIdx.x < NS && rg.x + threadIdx.x < end) ? vals[rg.x + threadIdx.x] : 0u;
     for (uint32_t base = rg.x; base < end; base += NS) {
         const uint32_t kk = base + threadIdx.x;
-        if (threadIdx.x < NS && kk < end) stage(rec, vals[kk], tp.x0, tp.y0, amin, s0, s1, s2, s3, threadIdx.x);
+        const uint32_t vcur = vnext;
+        if (threadIdx.x < NS && kk + NS < end) vnext = vals[kk + NS];
+        if (threadIdx.x < NS && kk < end) stage(rec, vcur, tp.x0, tp.y0, amin, s0, s1, s2, s3, threadIdx.x);
         __syncthreads();
         const int cnt = (int)min((uint32_t)NS, end - base);
         const uint32_t rel0 = base - rg.x;
