@@ -428,6 +428,23 @@ def main():
     if cnt is not None and "valu_insts_per_launch" in cnt:
         roof["valu_issue_frac"] = cnt["valu_insts_per_launch"] / (ph_ms[dominant] * 1e-3) / cnt["valu_issue_peak_per_s"]
 
+    # At one pixel per lane the backward sums each record's values over a wave's pixels on
+    # the matrix cores; the same step with the cross-lane reduce-scatter instead, for
+    # comparison (same shape, same inputs).
+    bwd_forms = None
+    if cfg.pixels_per_lane == 1:
+        rast.cfg.bwd_lane_reduce = 1
+        rast.ctx.timing(True)
+        ms_lane, _ = time_steps(step.run, args.steps, args.warmup, torch)
+        ph_lane = rast.ctx.collect_timing()
+        rast.ctx.timing(False)
+        step.check()
+        rast.cfg.bwd_lane_reduce = 0
+        bwd_forms = {"matrix_cores": {"raster_bwd_ms": ph_ms["raster_bwd"], "step_ms": ms_batched},
+                     "lane_reduce_scatter": {"raster_bwd_ms": ph_lane["raster_bwd"][0] / max(1, ph_lane["raster_bwd"][1]),
+                                             "step_ms": ms_lane}}
+        log(f"[bench] backward with the lane reduce-scatter: {bwd_forms['lane_reduce_scatter']['raster_bwd_ms']:.3f} ms")
+
     mapping_ops = None
     tracking = None
     if not args.no_extras:
@@ -477,6 +494,7 @@ def main():
         "autotune_ms": ({f"{r['tile']}x{r['tile']}/ppl{r['pixels_per_lane']}/bits{r['sort_digit_bits']}": round(r["ms"], 3)
                          for r in tuned} if tuned else None),
         "roofline": roof,
+        "bwd_reduction_forms": bwd_forms,
         "memory": memory,
         "cpu_baseline": cpu,
         "mapping_ops": mapping_ops,

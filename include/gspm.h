@@ -110,6 +110,11 @@ typedef struct {
                                 contribute to at least one pixel, for gspm_covisibility [0] */
     int32_t count_work;      /* nonzero: the forward also counts each pixel's contributing
                                 fragments, which gspm_frame_work reports [0] */
+    int32_t bwd_lane_reduce; /* at one pixel per lane, the backward sums each record's
+                                values over a wave's pixels with the matrix cores (0) or
+                                with a cross-lane reduce-scatter (nonzero), the form it
+                                always uses at 2 and 4 pixels per lane; the results agree
+                                to float rounding [0] */
 } gspm_settings;
 
 /* Per-view packed output planes (device): rgb [3][H][W], depth [H][W] (Eq. 3, not

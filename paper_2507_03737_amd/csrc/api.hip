@@ -190,6 +190,7 @@ gspm_status prepare(const gspm_gaussians *g, const gspm_views *views, const gspm
     P.rs.frame = s->pointmap_frame;
     P.rs.mark_visible = s->mark_visible != 0 ? 1 : 0;
     P.rs.count_work = s->count_work != 0 ? 1 : 0;
+    P.rs.bwd_lane_reduce = s->bwd_lane_reduce != 0 ? 1 : 0;
     return GSPM_OK;
 }
 

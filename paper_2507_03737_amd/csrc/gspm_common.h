@@ -32,6 +32,7 @@ struct RasterSettings {
     int32_t frame;  // 0 world, 1 camera, 2 depth back-projection
     int32_t mark_visible;
     int32_t count_work;  // the forward writes each pixel's contributing-fragment count
+    int32_t bwd_lane_reduce;  // one pixel per lane: reduce-scatter instead of the matrix cores
 };
 
 // Projected record of one (Gaussian, view) pair: 64 bytes, 4 x float4.

@@ -322,8 +322,8 @@ struct BwdValues {
     static constexpr uint32_t kWColumns = (uint32_t)(kColumns >> (4 * (N - NW)));
 };
 
-template <int TILE, int PPT, bool POSE_ONLY, int FRAME>
-__global__ void __launch_bounds__(TILE *TILE / PPT) __attribute__((amdgpu_waves_per_eu(PPT == 1 ? 7 : 1)))
+template <int TILE, int PPT, bool POSE_ONLY, int FRAME, bool MX>
+__global__ void __launch_bounds__(TILE *TILE / PPT) __attribute__((amdgpu_waves_per_eu(MX && PPT == 1 ? 7 : 1)))
 k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
              const float4 *__restrict__ rec, const uint32_t *__restrict__ last, const float *__restrict__ t_final,
              gspm_const_images fwd, gspm_const_images up, float *__restrict__ grad2d,
@@ -333,10 +333,10 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
     constexpr int NT = L::NT;
     // One pixel per lane: the per-record sums are a dense contraction done on the matrix
     // cores (below); each wave keeps its operand columns for kSlots records in LDS.
-    constexpr bool kMfma = PPT == 1;
+    constexpr bool kMfma = MX && PPT == 1;
     constexpr int kSlots = 8;
     static_assert(!kMfma || (L::WW == 8 && L::WH == 8), "one pixel per lane means 8 x 8 wave rectangles");
-    // Records staged per batch: at one pixel per lane at most 64, so that the operand
+    // Records staged per batch: in the matrix-core form at most 64, so that the operand
     // buffers below still leave room for seven workgroups per compute unit (7 waves per
     // SIMD, which the register budget is set for).
     constexpr int NS = kMfma && NT > 64 ? 64 : NT;
@@ -664,24 +664,33 @@ hipError_t launch_raster_backward(const ViewTable &vt, const RasterSettings &rs,
     const int n_tiles = vt.tile_off[vt.n_views];
     const float4 *rec = reinterpret_cast<const float4 *>(records);
     if (rs.frame < 0 || rs.frame > 2) return hipErrorInvalidValue;
-#define GSPM_BWD1(T_, P_, PO_, F_)                                                                         \
-    hipLaunchKernelGGL((k_raster_bwd<T_, P_, PO_, F_>), dim3(n_tiles), dim3(T_ * T_ / P_), 0, s, vt, rs, \
+#define GSPM_BWD1(T_, P_, PO_, F_, MX_)                                                                         \
+    hipLaunchKernelGGL((k_raster_bwd<T_, P_, PO_, F_, MX_>), dim3(n_tiles), dim3(T_ * T_ / P_), 0, s, vt, rs, \
                        ranges, pair_vals, rec, last, t_final, fwd, up, grad2d, order)
-#define GSPM_BWD2(T_, P_, PO_)                            \
-    if (rs.frame == 0) GSPM_BWD1(T_, P_, PO_, 0);         \
-    else if (rs.frame == 1) GSPM_BWD1(T_, P_, PO_, 1);    \
-    else GSPM_BWD1(T_, P_, PO_, 2);
+#define GSPM_BWD2(T_, P_, PO_, MX_)                            \
+    if (rs.frame == 0) GSPM_BWD1(T_, P_, PO_, 0, MX_);         \
+    else if (rs.frame == 1) GSPM_BWD1(T_, P_, PO_, 1, MX_);    \
+    else GSPM_BWD1(T_, P_, PO_, 2, MX_);
+    // The matrix-core form exists at one pixel per lane only (MX = false elsewhere, so no
+    // kernel is instantiated twice).
+#define GSPM_BWD3(T_, P_, PO_)                                 \
+    if (!rs.bwd_lane_reduce) {                                 \
+        GSPM_BWD2(T_, P_, PO_, (P_ == 1))                      \
+    } else {                                                   \
+        GSPM_BWD2(T_, P_, PO_, false)                          \
+    }
 #define GSPM_BWD(T_, P_)                                  \
     if (vt.tile == T_ && vt.ppt == P_) {                  \
         if (pose_only) {                                  \
-            GSPM_BWD2(T_, P_, true)                       \
+            GSPM_BWD3(T_, P_, true)                       \
         } else {                                          \
-            GSPM_BWD2(T_, P_, false)                      \
+            GSPM_BWD3(T_, P_, false)                      \
         }                                                 \
         return hipGetLastError();                         \
     }
     GSPM_RASTER_CONFIGS(GSPM_BWD)
 #undef GSPM_BWD
+#undef GSPM_BWD3
 #undef GSPM_BWD2
 #undef GSPM_BWD1
     return hipErrorInvalidValue;

@@ -256,12 +256,15 @@ def _oracle_backward(O, sc, cfg, ups, pixel_sets=None):
     return tot
 
 
+@pytest.mark.parametrize("lane_reduce", [0, 1])
 @pytest.mark.parametrize("frame", [0, 1, 2])
-def test_backward_c0(lib, oracle, frame):
-    U.log(f"[gpu] backward c0 frame={frame}")
+def test_backward_c0(lib, oracle, frame, lane_reduce):
+    """Gradients against the oracle, with the per-record sums on the matrix cores
+    (lane_reduce=0) and with the cross-lane reduce-scatter (lane_reduce=1)."""
+    U.log(f"[gpu] backward c0 frame={frame} lane_reduce={lane_reduce}")
     O = oracle
     sc = _posed(scenes.make_scene("c0"))
-    cfg = lib.RasterConfig(pointmap_frame=frame)
+    cfg = lib.RasterConfig(pointmap_frame=frame, bwd_lane_reduce=lane_reduce)
     rast, params, out, fs = _render_gpu(lib, sc, cfg)
     ref = O.render_image(O.Params.from_scene(sc), sc.cams[0], sc.T_cw[0], _oracle_settings(O, cfg))
     ups = _upstream(sc, 21, [ref["ambiguous"] == 0])
@@ -274,10 +277,11 @@ def test_backward_c0(lib, oracle, frame):
     U.log(f"  pose gpu {g['pose'][0]} oracle {r['pose'][0]}")
 
 
-def test_pose_backward_matches_full_backward(lib, oracle):
-    U.log("[gpu] pose-only backward c0")
+@pytest.mark.parametrize("lane_reduce", [0, 1])
+def test_pose_backward_matches_full_backward(lib, oracle, lane_reduce):
+    U.log(f"[gpu] pose-only backward c0 lane_reduce={lane_reduce}")
     sc = _posed(scenes.make_scene("c0"))
-    cfg = lib.RasterConfig(pointmap_frame=1)
+    cfg = lib.RasterConfig(pointmap_frame=1, bwd_lane_reduce=lane_reduce)
     rast, params, out, fs = _render_gpu(lib, sc, cfg)
     ref = oracle.render_image(oracle.Params.from_scene(sc), sc.cams[0], sc.T_cw[0], _oracle_settings(oracle, cfg))
     ups = _upstream(sc, 22, [ref["ambiguous"] == 0])
