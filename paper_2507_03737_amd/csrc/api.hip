@@ -269,7 +269,8 @@ gspm_status backward_common(gspm_ctx *ctx, const gspm_gaussians *g, const gspm_v
     GSPM_HIP(launch_raster_backward(P.vt, P.rs, at<uint2>(frame_state, L.ranges), at<uint32_t>(frame_state, L.pair_vals),
                                     at<float>(frame_state, L.records), at<uint32_t>(frame_state, L.last),
                                     at<float>(frame_state, L.t_final), *fwd_out, *grad_out, g2, pose_only,
-                                    at<uint32_t>(frame_state, L.order) + P.n_tiles, hs));
+                                    at<uint32_t>(frame_state, L.order) + P.n_tiles,
+                                    at<FrameHeader>(frame_state, L.header), hs));
     t_rb.stop();
     PhaseTimer t_pb(ctx, hs, GSPM_PHASE_PARAM_BWD);
     gspm_gaussian_grads none = {nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -331,7 +332,7 @@ int64_t gspm_frame_state_bytes(const gspm_views *views, int64_t n_gaussians, int
     ViewTable vt;
     int64_t nt, np;
     if (build_views(views, tile, vt, nt, np) != GSPM_OK) return -1;
-    return frame_layout(nt, np, n_gaussians * views->n_views, max_pairs).total;
+    return frame_layout(nt, np, n_gaussians * views->n_views, max_pairs).total + wmask_bytes(max_pairs, tile);
 }
 
 gspm_status gspm_render_forward(gspm_ctx *ctx, const gspm_gaussians *g, const gspm_views *views,
@@ -348,7 +349,18 @@ gspm_status gspm_render_forward(gspm_ctx *ctx, const gspm_gaussians *g, const gs
     if (frame_state_bytes < L0.total)
         return fail(GSPM_ERR_INVALID_ARG, "frame_state_bytes = %lld < %lld (no room for pairs)",
                     (long long)frame_state_bytes, (long long)L0.total);
-    int64_t cap = (frame_state_bytes - L0.pair_vals) / 4;
+    // The pair list and, after it, the per-wave contribution bits: the largest capacity
+    // whose two regions fit.
+    const int64_t avail = frame_state_bytes - L0.pair_vals;
+    auto need = [&](int64_t c) { return align256(c * 4) + wmask_bytes(c, P.vt.tile); };
+    if (avail < need(0))
+        return fail(GSPM_ERR_INVALID_ARG, "frame_state_bytes = %lld < %lld (no room for pairs)",
+                    (long long)frame_state_bytes, (long long)(L0.pair_vals + need(0)));
+    int64_t cap = 0;
+    for (int64_t hi = avail / 4 + 1; hi - cap > 1;) {  // need(cap) fits, need(hi) does not
+        const int64_t mid = cap + (hi - cap) / 2;
+        if (need(mid) <= avail) cap = mid; else hi = mid;
+    }
     if (cap >= (1ll << 31)) cap = (1ll << 31) - 1;
     hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
     const int db = s->sort_digit_bits;
@@ -432,10 +444,14 @@ gspm_status gspm_render_forward(gspm_ctx *ctx, const gspm_gaussians *g, const gs
         visible = at<uint8_t>(frame_state, L0.visible);
         GSPM_HIP(launch_fill_u32(reinterpret_cast<uint32_t *>(visible), 0u, (R + 3) / 4, hs));
     }
+    uint64_t *wmask = wmask_at(pair_vals, cap);
+    const int64_t wstride = wmask_stride(cap);
+    GSPM_HIP(launch_fill_u32(reinterpret_cast<uint32_t *>(wmask), 0u,
+                             2 * wstride * (P.vt.tile * P.vt.tile / P.vt.ppt / kWave), hs));
     PhaseTimer t_fwd(ctx, hs, GSPM_PHASE_RASTER_FWD);
     GSPM_HIP(launch_raster_forward(P.vt, P.rs, ranges, pair_vals, records, out->rgb, out->depth, out->alpha,
                                    out->pointmap, at<float>(frame_state, L0.t_final), at<uint32_t>(frame_state, L0.last),
-                                   at<uint32_t>(frame_state, L0.contrib), visible, order, twork, hs));
+                                   at<uint32_t>(frame_state, L0.contrib), visible, order, twork, wmask, wstride, hs));
     GSPM_HIP(launch_order_tiles(nullptr, twork, P.n_tiles, order + P.n_tiles, hs));
     return GSPM_OK;
 }

@@ -85,7 +85,21 @@ struct FrameLayout {
     int64_t header, visible, ranges, t_final, last, contrib, order, records, pair_vals, total;
 };
 
-inline int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
+__host__ __device__ inline int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
+
+// Per-wave contribution bits of a forward, stored after the pair list: one plane per wave
+// of a tile, in which bit p (p = position in the sorted pair list) is set when one of that
+// wave's live pixels accepted entry p (it composited there, or it stopped that pixel).  The
+// backward walks these entries only.  Planes are sized for the tile's wave count at one
+// pixel per lane.
+inline int wmask_planes(int tile) { return tile * tile / kWave; }
+__host__ __device__ inline int64_t wmask_stride(int64_t cap) { return cap / 64 + 2; }  // words per plane
+inline int64_t wmask_bytes(int64_t cap, int tile) { return align256(wmask_planes(tile) * wmask_stride(cap) * 8); }
+// The bits start right after the pair list of a frame whose capacity is cap.
+__host__ __device__ inline uint64_t *wmask_at(const uint32_t *pair_vals, int64_t cap) {
+    return reinterpret_cast<uint64_t *>(
+        reinterpret_cast<char *>(const_cast<uint32_t *>(pair_vals)) + align256(cap * 4));
+}
 
 inline FrameLayout frame_layout(int64_t n_tiles, int64_t n_pixels, int64_t n_records, int64_t cap) {
     FrameLayout L;
@@ -456,13 +470,13 @@ hipError_t launch_raster_forward(const ViewTable &vt, const RasterSettings &rs, 
                                  const uint32_t *pair_vals, const float *records, float *rgb,
                                  float *depth, float *alpha, float *pointmap, float *t_final,
                                  uint32_t *last, uint32_t *contrib, uint8_t *visible, const uint32_t *order,
-                                 uint32_t *tile_work, hipStream_t s);
+                                 uint32_t *tile_work, uint64_t *wmask, int64_t wstride, hipStream_t s);
 
 hipError_t launch_raster_backward(const ViewTable &vt, const RasterSettings &rs, const uint2 *ranges,
                                   const uint32_t *pair_vals, const float *records, const uint32_t *last,
                                   const float *t_final, const gspm_const_images &fwd,
                                   const gspm_const_images &up, float *grad2d, bool pose_only,
-                                  const uint32_t *order, hipStream_t s);
+                                  const uint32_t *order, const FrameHeader *hdr, hipStream_t s);
 
 // Image-plane gradient rows -> parameter gradients (added into out) and per-block pose
 // partials; every row read as nonzero is cleared, so grad2d is all zero afterwards.

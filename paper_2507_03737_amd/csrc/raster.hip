@@ -97,9 +97,11 @@ struct Layout {
     static_assert(WW * WH == kWave * PPT && TILE % WW == 0 && TILE % WH == 0, "unsupported raster shape");
     int lx, ly;                  // tile-local column and first row of this lane
     float rx0, rx1, ry0, ry1;    // this wave's rectangle of pixel centres, tile-local
+    int w;                       // wave index within the workgroup
     __device__ Layout() {
         // The wave index is uniform: keep it (and the rectangle) in scalar registers.
-        const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave)), lane = lane_id();
+        w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+        const int lane = lane_id();
         const int wx = (w % (TILE / WW)) * WW, wy = (w / (TILE / WW)) * WH;
         lx = wx + lane % WW;
         ly = wy + (lane / WW) * PPT;
@@ -154,7 +156,8 @@ k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
              const float4 *__restrict__ rec, float *__restrict__ out_rgb, float *__restrict__ out_depth,
              float *__restrict__ out_alpha, float *__restrict__ out_pm, float *__restrict__ t_final,
              uint32_t *__restrict__ last, uint32_t *__restrict__ contrib, uint8_t *__restrict__ visible,
-             const uint32_t *__restrict__ order, uint32_t *__restrict__ tile_work) {
+             const uint32_t *__restrict__ order, uint32_t *__restrict__ tile_work, uint64_t *__restrict__ wmask,
+             int64_t wstride) {
     using L = Layout<TILE, PPT>;
     constexpr int NT = L::NT;
     __shared__ float4 s0[NT], s1[NT], s2[NT], s3[NT];
@@ -198,6 +201,7 @@ k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
         const int cnt = (int)min((uint32_t)NT, rg.y - base);
         for (int c = 0; c < cnt && wave_live; c += kWave) {
             uint64_t m = batch_mask<L::CULL>(s0, s1, c, cnt, lay.rx0, lay.rx1, lay.ry0, lay.ry1);
+            uint64_t composited = 0ull;  // entries of this chunk accepted by one of the wave's live pixels
             while (m != 0ull) {
                 const int q = c + (int)__builtin_ctzll(m);
                 m &= m - 1ull;
@@ -217,6 +221,10 @@ k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
                     pass |= ballot(ok[k]);
                 }
                 if (pass == 0ull) continue;  // wave-uniform: nothing composites this entry
+                // Some live pixel accepts the entry: it is composited there or stops that pixel.
+                // The backward walks these entries (a superset of those it finds a valid
+                // pixel for; it skips the rest), scalar work only.
+                composited |= 1ull << (q - c);
                 const float4 cc = s2[q];
                 const float4 d = s3[q];
                 const uint32_t rel = base - rg.x + (uint32_t)q + 1u;
@@ -246,6 +254,15 @@ k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
                 if (visible) {  // uniform: marking requested
                     if (ballot(added) != 0ull && lane_id() == 0) visible[__float_as_uint(b.w)] = 1;
                 }
+            }
+            if (composited != 0ull && lane_id() == 0) {
+                // Entry q sits at list position base + q; the chunk's bits straddle at most
+                // two words of this wave's plane.
+                const uint64_t pos = (uint64_t)base + (uint64_t)c;
+                uint64_t *w = wmask + (int64_t)lay.w * wstride + (int64_t)(pos >> 6);
+                const int sh = (int)(pos & 63u);
+                atomicOr((unsigned long long *)w, (unsigned long long)(composited << sh));
+                if (sh != 0) atomicOr((unsigned long long *)(w + 1), (unsigned long long)(composited >> (64 - sh)));
             }
             wave_live = ballot(lane_live()) != 0ull;
         }
@@ -327,7 +344,7 @@ __global__ void __launch_bounds__(TILE *TILE / PPT) __attribute__((amdgpu_waves_
 k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
              const float4 *__restrict__ rec, const uint32_t *__restrict__ last, const float *__restrict__ t_final,
              gspm_const_images fwd, gspm_const_images up, float *__restrict__ grad2d,
-             const uint32_t *__restrict__ order) {
+             const uint32_t *__restrict__ order, const FrameHeader *__restrict__ hdr) {
     using L = Layout<TILE, PPT>;
     using V = BwdValues<POSE_ONLY, FRAME>;
     constexpr int NT = L::NT;
@@ -498,6 +515,19 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
         __builtin_amdgcn_wave_barrier();  // read before later records overwrite the buffer
     };
 
+    // The entries that one of this wave's live pixels accepted in the forward (its bit plane
+    // after the pair list): every entry with a valid pixel here, plus the few that only
+    // stopped a pixel, so the walk needs no culling test and meets almost no entry without
+    // a contribution.
+    const int64_t cap = (int64_t)hdr->capacity;
+    const uint64_t *plane = wmask_at(vals, cap) + (int64_t)lay.w * wmask_stride(cap);
+    auto wave_bits = [&](uint32_t pos) {  // the 64 bits of list positions pos .. pos + 63
+        const uint64_t *wp = plane + (pos >> 6);
+        const int sh = (int)(pos & 63u);
+        uint64_t m = wp[0] >> sh;
+        if (sh != 0) m |= wp[1] << (64 - sh);
+        return m;
+    };
     // The next batch's record indices are loaded one batch ahead, so staging waits on one
     // global read (the record) rather than two dependent ones.
     uint32_t vnext = (threadIdx.x < NS && rg.x + threadIdx.x < end) ? vals[rg.x + threadIdx.x] : 0u;
@@ -505,12 +535,14 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
         const uint32_t kk = base + threadIdx.x;
         const uint32_t vcur = vnext;
         if (threadIdx.x < NS && kk + NS < end) vnext = vals[kk + NS];
+        const uint64_t bits0 = wave_bits(base);  // read while the batch is staged
         if (threadIdx.x < NS && kk < end) stage(rec, vcur, tp.x0, tp.y0, amin, s0, s1, s2, s3, threadIdx.x);
         __syncthreads();
         const int cnt = (int)min((uint32_t)NS, end - base);
         const uint32_t rel0 = base - rg.x;
         for (int c = 0; c < cnt && rel0 + (uint32_t)c < wave_last; c += kWave) {
-            uint64_t m = batch_mask<L::CULL>(s0, s1, c, cnt, lay.rx0, lay.rx1, lay.ry0, lay.ry1);
+            uint64_t m = c == 0 ? bits0 : wave_bits(base + (uint32_t)c);
+            if (cnt - c < kWave) m &= (1ull << (cnt - c)) - 1ull;  // the next tile's entries
             // Entries at or past the wave's last contributing one are not walked.
             const uint32_t lim = wave_last - (rel0 + (uint32_t)c);
             if (lim < (uint32_t)kWave) m &= (1ull << lim) - 1ull;
@@ -630,14 +662,15 @@ bool raster_config_supported(int tile, int ppt) {
 hipError_t launch_raster_forward(const ViewTable &vt, const RasterSettings &rs, const uint2 *ranges,
                                  const uint32_t *pair_vals, const float *records, float *rgb, float *depth,
                                  float *alpha, float *pointmap, float *t_final, uint32_t *last, uint32_t *contrib,
-                                 uint8_t *visible, const uint32_t *order, uint32_t *tile_work, hipStream_t s) {
+                                 uint8_t *visible, const uint32_t *order, uint32_t *tile_work, uint64_t *wmask,
+                                 int64_t wstride, hipStream_t s) {
     const int n_tiles = vt.tile_off[vt.n_views];
     const float4 *rec = reinterpret_cast<const float4 *>(records);
     if (rs.frame < 0 || rs.frame > 2) return hipErrorInvalidValue;
 #define GSPM_FWD2(T_, P_, F_, C_)                                                                        \
     hipLaunchKernelGGL((k_raster_fwd<T_, P_, F_, C_>), dim3(n_tiles), dim3(T_ * T_ / P_), 0, s, vt, rs, \
                        ranges, pair_vals, rec, rgb, depth, alpha, pointmap, t_final, last, contrib, visible,   \
-                       order, tile_work)
+                       order, tile_work, wmask, wstride)
 #define GSPM_FWD1(T_, P_, F_)                                                                  \
     do {                                                                                       \
         if (rs.count_work) GSPM_FWD2(T_, P_, F_, true);                                        \
@@ -660,13 +693,14 @@ hipError_t launch_raster_forward(const ViewTable &vt, const RasterSettings &rs, 
 hipError_t launch_raster_backward(const ViewTable &vt, const RasterSettings &rs, const uint2 *ranges,
                                   const uint32_t *pair_vals, const float *records, const uint32_t *last,
                                   const float *t_final, const gspm_const_images &fwd, const gspm_const_images &up,
-                                  float *grad2d, bool pose_only, const uint32_t *order, hipStream_t s) {
+                                  float *grad2d, bool pose_only, const uint32_t *order, const FrameHeader *hdr,
+                                  hipStream_t s) {
     const int n_tiles = vt.tile_off[vt.n_views];
     const float4 *rec = reinterpret_cast<const float4 *>(records);
     if (rs.frame < 0 || rs.frame > 2) return hipErrorInvalidValue;
 #define GSPM_BWD1(T_, P_, PO_, F_, MX_)                                                                         \
     hipLaunchKernelGGL((k_raster_bwd<T_, P_, PO_, F_, MX_>), dim3(n_tiles), dim3(T_ * T_ / P_), 0, s, vt, rs, \
-                       ranges, pair_vals, rec, last, t_final, fwd, up, grad2d, order)
+                       ranges, pair_vals, rec, last, t_final, fwd, up, grad2d, order, hdr)
 #define GSPM_BWD2(T_, P_, PO_, MX_)                            \
     if (rs.frame == 0) GSPM_BWD1(T_, P_, PO_, 0, MX_);         \
     else if (rs.frame == 1) GSPM_BWD1(T_, P_, PO_, 1, MX_);    \
