@@ -157,8 +157,7 @@ GSPM_API gspm_status gspm_reserve(gspm_ctx *ctx, int64_t max_records, int64_t ma
 /* Bytes of the caller-owned frame state that carries everything the backward needs
  * from its forward (projected records, sorted tile pairs, tile ranges, per-pixel
  * transmittance and last fragment, and per wave of a tile one bit per tile pair that
- * marks the pairs its pixels accepted).  max_pairs bounds the tile-pair list; a frame
- * state sized for tile t serves any tile <= t. */
+ * marks the pairs its pixels accepted).  max_pairs bounds the tile-pair list. */
 GSPM_API int64_t gspm_frame_state_bytes(const gspm_views *views, int64_t n_gaussians, int64_t max_pairs,
                                int32_t tile);
 
