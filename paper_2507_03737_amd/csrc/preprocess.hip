@@ -397,19 +397,17 @@ k_preprocess_backward(gspm_gaussians G, ViewTable vt, const float *__restrict__ 
         for (int c = 0; c < 3; ++c) unsafeAtomicAdd(out.rgb + c * n + g, (float)gc[c]);
 }
 
+// One block per (view, pose component); the sum runs in a fixed order (deterministic).
 __global__ void __launch_bounds__(256)
 k_pose_reduce(const double *__restrict__ part, int64_t nblocks, float *__restrict__ pose_grad) {
     __shared__ double lds[4];
-    const int v = blockIdx.x;
-    for (int k = 0; k < 6; ++k) {
-        double acc = 0.0;
-        for (int64_t b = threadIdx.x; b < nblocks; b += blockDim.x) acc += part[((int64_t)v * nblocks + b) * 6 + k];
-        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-        __syncthreads();
-        if (lane_id() == 0) lds[threadIdx.x / 64] = acc;
-        __syncthreads();
-        if (threadIdx.x == 0) pose_grad[v * 6 + k] += (float)(lds[0] + lds[1] + lds[2] + lds[3]);
-    }
+    const int v = blockIdx.x, k = blockIdx.y;
+    double acc = 0.0;
+    for (int64_t b = threadIdx.x; b < nblocks; b += blockDim.x) acc += part[((int64_t)v * nblocks + b) * 6 + k];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane_id() == 0) lds[threadIdx.x / 64] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) pose_grad[v * 6 + k] += (float)(lds[0] + lds[1] + lds[2] + lds[3]);
 }
 
 __global__ void k_fill_u32(uint32_t *p, uint32_t value, int64_t n) {
@@ -512,7 +510,7 @@ hipError_t launch_preprocess_backward(const gspm_gaussians &g, const ViewTable &
 hipError_t launch_pose_reduce(const double *pose_partials, int64_t n_blocks, int n_views, float *pose_grad,
                               hipStream_t s) {
     if (n_views <= 0 || n_blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_pose_reduce, dim3(n_views), dim3(256), 0, s, pose_partials, n_blocks, pose_grad);
+    hipLaunchKernelGGL(k_pose_reduce, dim3(n_views, 6), dim3(256), 0, s, pose_partials, n_blocks, pose_grad);
     return hipGetLastError();
 }
 
