@@ -6,7 +6,7 @@
 // and each lane PPT vertically adjacent pixels of one of its columns.  The tile's
 // depth-ordered record list is streamed through LDS in batches of one record per lane (a
 // 64-byte record, converted to tile-local coordinates on load).  When a tile holds several
-// waves, each wave first tests the whole batch against its own rectangle (one record per
+// waves, each wave of the forward first tests the whole batch against its own rectangle (one record per
 // lane: the maximum of the concave base-2 exponent over the rectangle, against the
 // record's threshold, with a rounding margin so that no record a pixel would accept is
 // dropped) and then walks only the records that meet it, taken from the ballot mask with
@@ -15,8 +15,11 @@
 // threshold, so the exponential is only evaluated for pixels that composite it; the
 // workgroup stops as soon as every pixel has reached the transmittance floor.
 //
-// The backward walks the same list front to back and recomputes alpha and transmittance
-// with the same instructions as the forward, so no per-fragment state is stored: only the
+// The forward also records, per wave, which list entries one of its live pixels accepted
+// (one bit per entry and wave, kept in the frame state).  The backward walks only those
+// entries, front to back, in batches staged through LDS (64 records in the matrix-core
+// form, one per lane otherwise), and recomputes alpha and transmittance with the same
+// instructions as the forward, so no per-fragment state is stored: only the bits and the
 // per-pixel count of list entries up to the last contributing fragment.  The suffix sums
 // that the alpha derivative needs are recovered as (sum over all fragments) - (prefix
 // sum), the total coming from the forward's outputs.  Per record the wave needs up to 13
