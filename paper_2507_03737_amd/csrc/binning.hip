@@ -383,6 +383,7 @@ k_keygen(const uint32_t *__restrict__ sorted_rec, uint32_t rec_mask, const uint3
         hdr->magic = kFrameMagic;
         hdr->visible = (uint32_t)rs.mark_visible;
         hdr->counted = (uint32_t)rs.count_work;
+        hdr->ppt = (uint32_t)vt.ppt;
     }
     const bool act = p < n_records;
     uint32_t r = 0, c = 0, k = 0;

@@ -77,7 +77,8 @@ struct FrameHeader {
     uint32_t visible;     // nonzero if the forward marked contributing records
     uint32_t sort_stall;  // nonzero if a radix sort pass abandoned its look-back
     uint32_t counted;     // nonzero if the forward wrote the contributing-fragment counts
-    uint32_t pad[2];
+    uint32_t ppt;         // pixels per lane of the forward, whose waves the contribution bits follow
+    uint32_t pad;
 };
 constexpr uint32_t kFrameMagic = 0x47535046u;  // "GSPF"
 

@@ -524,6 +524,8 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
     // a contribution.
     const int64_t cap = (int64_t)hdr->capacity;
     const uint64_t *plane = wmask_at(vals, cap) + (int64_t)lay.w * wmask_stride(cap);
+    // A forward with another number of pixels per lane had other waves: cull instead.
+    const bool use_bits = hdr->ppt == (uint32_t)PPT;
     auto wave_bits = [&](uint32_t pos) {  // the 64 bits of list positions pos .. pos + 63
         const uint64_t *wp = plane + (pos >> 6);
         const int sh = (int)(pos & 63u);
@@ -538,14 +540,19 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
         const uint32_t kk = base + threadIdx.x;
         const uint32_t vcur = vnext;
         if (threadIdx.x < NS && kk + NS < end) vnext = vals[kk + NS];
-        const uint64_t bits0 = wave_bits(base);  // read while the batch is staged
+        const uint64_t bits0 = use_bits ? wave_bits(base) : 0ull;  // read while the batch is staged
         if (threadIdx.x < NS && kk < end) stage(rec, vcur, tp.x0, tp.y0, amin, s0, s1, s2, s3, threadIdx.x);
         __syncthreads();
         const int cnt = (int)min((uint32_t)NS, end - base);
         const uint32_t rel0 = base - rg.x;
         for (int c = 0; c < cnt && rel0 + (uint32_t)c < wave_last; c += kWave) {
-            uint64_t m = c == 0 ? bits0 : wave_bits(base + (uint32_t)c);
-            if (cnt - c < kWave) m &= (1ull << (cnt - c)) - 1ull;  // the next tile's entries
+            uint64_t m;
+            if (use_bits) {
+                m = c == 0 ? bits0 : wave_bits(base + (uint32_t)c);
+                if (cnt - c < kWave) m &= (1ull << (cnt - c)) - 1ull;  // the next tile's entries
+            } else {
+                m = batch_mask<L::CULL>(s0, s1, c, cnt, lay.rx0, lay.rx1, lay.ry0, lay.ry1);
+            }
             // Entries at or past the wave's last contributing one are not walked.
             const uint32_t lim = wave_last - (rel0 + (uint32_t)c);
             if (lim < (uint32_t)kWave) m &= (1ull << lim) - 1ull;

@@ -277,6 +277,26 @@ def test_backward_c0(lib, oracle, frame, lane_reduce):
     U.log(f"  pose gpu {g['pose'][0]} oracle {r['pose'][0]}")
 
 
+@pytest.mark.parametrize("ppl_fwd,ppl_bwd", [(2, 1), (1, 2)])
+def test_backward_after_forward_with_other_shape(lib, oracle, ppl_fwd, ppl_bwd):
+    """A backward whose pixels per lane differ from its forward's: the forward's per-wave
+    contribution bits follow other waves, so the backward culls instead; gradients still
+    match the oracle."""
+    U.log(f"[gpu] backward c0 forward ppl={ppl_fwd} backward ppl={ppl_bwd}")
+    O = oracle
+    sc = _posed(scenes.make_scene("c0"))
+    cfg = lib.RasterConfig(pointmap_frame=1, pixels_per_lane=ppl_fwd)
+    rast, params, out, fs = _render_gpu(lib, sc, cfg)
+    ref = O.render_image(O.Params.from_scene(sc), sc.cams[0], sc.T_cw[0], _oracle_settings(O, cfg))
+    ups = _upstream(sc, 23, [ref["ambiguous"] == 0])
+    rast.cfg.pixels_per_lane = ppl_bwd
+    g = _gpu_backward(lib, rast, params, out, fs, ups)
+    r = _oracle_backward(O, sc, cfg, ups)
+    for k in ("means", "log_scales", "quats", "opacity_logit", "rgb"):
+        U.check_grad(f"c0 ppl {ppl_fwd}->{ppl_bwd} {k}", g[k], r[k])
+    U.check_grad(f"c0 ppl {ppl_fwd}->{ppl_bwd} pose", g["pose"], r["pose"], frac=1.0)
+
+
 @pytest.mark.parametrize("lane_reduce", [0, 1])
 def test_pose_backward_matches_full_backward(lib, oracle, lane_reduce):
     U.log(f"[gpu] pose-only backward c0 lane_reduce={lane_reduce}")
