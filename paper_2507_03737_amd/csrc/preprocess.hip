@@ -44,10 +44,10 @@ __device__ inline void project_one(const gspm_gaussians &G, int64_t g, int64_t n
     P.clamp_x = P.clamp_y = false;
     const double mu0 = G.means[g], mu1 = G.means[n + g], mu2 = G.means[2 * n + g];
     const double qw = G.quats[g], qx = G.quats[n + g], qy = G.quats[2 * n + g], qz = G.quats[3 * n + g];
-    P.s[0] = exp((double)G.log_scales[g]);
-    P.s[1] = exp((double)G.log_scales[n + g]);
-    P.s[2] = exp((double)G.log_scales[2 * n + g]);
-    P.a = 1.0 / (1.0 + exp(-(double)G.opacity_logit[g]));
+    P.s[0] = (double)expf(G.log_scales[g]);
+    P.s[1] = (double)expf(G.log_scales[n + g]);
+    P.s[2] = (double)expf(G.log_scales[2 * n + g]);
+    P.a = (double)(1.0f / (1.0f + expf(-G.opacity_logit[g])));
     P.qnorm = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
     if (!(P.qnorm > 0.0) || !isfinite(P.qnorm)) return;
     const double inv = 1.0 / P.qnorm;
