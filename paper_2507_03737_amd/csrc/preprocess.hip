@@ -104,7 +104,7 @@ __device__ inline void project_one(const gspm_gaussians &G, int64_t g, int64_t n
     P.Q[2] = P.cov[0] * idet;
 
     if (!(P.a >= (double)rs.alpha_min)) return;
-    const double qmax = 2.0 * log(P.a / (double)rs.alpha_min);
+    const double qmax = 2.0 * (double)logf((float)(P.a / (double)rs.alpha_min));
     const double rx = sqrt(qmax * P.cov[0]), ry = sqrt(qmax * P.cov[2]);
     double i0 = ceil(P.u - rx), i1 = floor(P.u + rx), j0 = ceil(P.v - ry), j1 = floor(P.v + ry);
     i0 = fmax(i0, 0.0); j0 = fmax(j0, 0.0);
