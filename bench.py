@@ -493,6 +493,8 @@ def main():
         "phase_ms": {k: round(v, 4) for k, v in ph_iter.items()},
         "autotune_ms": ({f"{r['tile']}x{r['tile']}/ppl{r['pixels_per_lane']}/bits{r['sort_digit_bits']}": round(r["ms"], 3)
                          for r in tuned} if tuned else None),
+        "autotune_refined_ms": ({f"{r['tile']}x{r['tile']}/ppl{r['pixels_per_lane']}/bits{r['sort_digit_bits']}":
+                                 round(r["ms_refined"], 3) for r in tuned if "ms_refined" in r} if tuned else None),
         "roofline": roof,
         "bwd_reduction_forms": bwd_forms,
         "memory": memory,

@@ -189,7 +189,11 @@ def test_autotune_picks_fastest_and_caches(lib, tmp_path):
     cfg, res = autotune(win, sc.n, params, target, prior, base=base, candidates=cands, steps=2, warmup=1,
                         cache_path=cache)
     assert len(res) == len(cands)
-    best = min(res, key=lambda r: r["ms"])
+    # The three fastest short timings are timed again; the choice is the fastest of those.
+    fastest = sorted(res, key=lambda r: r["ms"])[:3]
+    assert all("ms_refined" in r for r in fastest)
+    assert sum("ms_refined" in r for r in res) == 3
+    best = min(fastest, key=lambda r: r["ms_refined"])
     assert (cfg.tile, cfg.pixels_per_lane, cfg.sort_digit_bits) == (best["tile"], best["pixels_per_lane"],
                                                                      best["sort_digit_bits"])
     assert cfg.pointmap_frame == 1 and cfg.alpha_min == base.alpha_min
