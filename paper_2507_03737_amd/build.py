@@ -25,6 +25,8 @@ CFLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-munsafe-fp-atomics",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",
+    # Shapes whose LDS use already caps occupancy below the register target: not an error.
+    "-Wno-pass-failed",
     "-fvisibility=hidden",
 ]
 
