@@ -17,8 +17,9 @@
 //
 // The forward also records, per wave, which list entries one of its live pixels accepted
 // (one bit per entry and wave, kept in the frame state).  The backward walks only those
-// entries, front to back, in batches staged through LDS (64 records in the matrix-core
-// form, one per lane otherwise), and recomputes alpha and transmittance with the same
+// entries, front to back: in the matrix-core form each wave stages its own entries through
+// LDS, 32 at a time and with no workgroup barrier; otherwise the workgroup stages batches
+// of one record per lane.  It recomputes alpha and transmittance with the same
 // instructions as the forward, so no per-fragment state is stored: only the bits and the
 // per-pixel count of list entries up to the last contributing fragment.  The suffix sums
 // that the alpha derivative needs are recovered as (sum over all fragments) - (prefix
@@ -343,7 +344,7 @@ struct BwdValues {
 };
 
 template <int TILE, int PPT, bool POSE_ONLY, int FRAME, bool MX>
-__global__ void __launch_bounds__(TILE *TILE / PPT) __attribute__((amdgpu_waves_per_eu(MX && PPT == 1 ? 7 : 1)))
+__global__ void __launch_bounds__(TILE *TILE / PPT) __attribute__((amdgpu_waves_per_eu(MX && PPT == 1 ? 6 : 1)))
 k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
              const float4 *__restrict__ rec, const uint32_t *__restrict__ last, const float *__restrict__ t_final,
              gspm_const_images fwd, gspm_const_images up, float *__restrict__ grad2d,
@@ -356,11 +357,15 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
     constexpr bool kMfma = MX && PPT == 1;
     constexpr int kSlots = 8;
     static_assert(!kMfma || (L::WW == 8 && L::WH == 8), "one pixel per lane means 8 x 8 wave rectangles");
-    // Records staged per batch: in the matrix-core form at most 64, so that the operand
-    // buffers below still leave room for seven workgroups per compute unit (7 waves per
-    // SIMD, which the register budget is set for).
-    constexpr int NS = kMfma && NT > 64 ? 64 : NT;
+    // Records staged per batch for the whole workgroup; the matrix-core form stages per
+    // wave instead (kWS entries at a time), which with its operand buffers leaves room for
+    // six workgroups per compute unit (6 waves per SIMD, the register budget's target).
+    constexpr int NS = kMfma ? 1 : NT;
     __shared__ float4 s0[NS], s1[NS], s2[NS], s3[NS];
+    constexpr int kWS = 32;  // entries a wave stages at a time (matrix-core form)
+    constexpr uint32_t kWSMask = kWS == 32 ? 0xffffffffu : (1u << kWS) - 1u;
+    __shared__ float4 mw0[kMfma ? L::NW : 1][kMfma ? kWS : 1], mw1[kMfma ? L::NW : 1][kMfma ? kWS : 1],
+        mw2[kMfma ? L::NW : 1][kMfma ? kWS : 1], mw3[kMfma ? L::NW : 1][kMfma ? kWS : 1];
     __shared__ uint32_t block_last;
     // B operand of slot column j (g: j = slot, w: j = 8 + slot) for pixel p = 4 kb + c at
     // 272 (kb / 4) + 68 c + 4 j + kb % 4: a lane's four values of one kb quarter are one
@@ -533,123 +538,164 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
         if (sh != 0) m |= wp[1] << (64 - sh);
         return m;
     };
-    // The next batch's record indices are loaded one batch ahead, so staging waits on one
-    // global read (the record) rather than two dependent ones.
-    uint32_t vnext = (threadIdx.x < NS && rg.x + threadIdx.x < end) ? vals[rg.x + threadIdx.x] : 0u;
-    for (uint32_t base = rg.x; base < end; base += NS) {
-        const uint32_t kk = base + threadIdx.x;
-        const uint32_t vcur = vnext;
-        if (threadIdx.x < NS && kk + NS < end) vnext = vals[kk + NS];
-        const uint64_t bits0 = use_bits ? wave_bits(base) : 0ull;  // read while the batch is staged
-        if (threadIdx.x < NS && kk < end) stage(rec, vcur, tp.x0, tp.y0, amin, s0, s1, s2, s3, threadIdx.x);
-        __syncthreads();
-        const int cnt = (int)min((uint32_t)NS, end - base);
-        const uint32_t rel0 = base - rg.x;
-        for (int c = 0; c < cnt && rel0 + (uint32_t)c < wave_last; c += kWave) {
-            uint64_t m;
-            if (use_bits) {
-                m = c == 0 ? bits0 : wave_bits(base + (uint32_t)c);
-                if (cnt - c < kWave) m &= (1ull << (cnt - c)) - 1ull;  // the next tile's entries
-            } else {
-                m = batch_mask<L::CULL>(s0, s1, c, cnt, lay.rx0, lay.rx1, lay.ry0, lay.ry1);
+    // One list entry (its staged record, and its position rel in the tile's list): the
+    // per-pixel recomputation and this wave's sums for it.
+    auto walk_record = [&](const float4 &a, const float4 &b, const float4 &cc, const float4 &d, uint32_t rel) {
+        const float dx = px - a.x;
+        const float Adx2 = a.z * dx * dx, Bdx = a.w * dx;
+        float e[PPT];
+        bool valid[PPT];
+        uint64_t any = 0ull;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            e[k] = quad_e(Adx2, Bdx, b.x, py[k] - a.y);
+            // One comparison decides (its lane mask is the ballot as it stands).
+            valid[k] = (rel < my_last[k] ? e[k] : -INFINITY) >= b.y;
+            any |= ballot(valid[k]);
+        }
+        if constexpr (kMfma) {
+            asm volatile("" ::"v"(cc.x), "v"(cc.y), "v"(cc.z), "v"(cc.w));
+            if constexpr (V::kPoint) asm volatile("" ::"v"(d.x), "v"(d.y), "v"(d.z));
+        }
+        if (any == 0ull) return;  // wave-uniform
+        float v[V::NR];
+#pragma unroll
+        for (int t = V::N; t < V::NR; ++t) v[t] = 0.f;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            // The first pixel assigns, later ones accumulate (x + 0 is not folded).
+            auto add = [&](int t, float x) { v[t] = k == 0 ? x : v[t] + x; };
+            auto mad = [&](int t, float x, float y) { v[t] = k == 0 ? x * y : fmaf(x, y, v[t]); };
+            // Branch-free: an invalid pixel gets zero weight and leaves T unchanged
+            // (e <= 0, so alpha lies in [0, alpha_max] and 1 - alpha >= 1 - alpha_max).
+            const float dy = py[k] - a.y;
+            const float al = fminf(amax, b.z * __builtin_amdgcn_exp2f(e[k]));
+            const float w = valid[k] ? __fmul_rn(al, T[k]) : 0.0f;
+            float sv = fmaf(gC0[k], cc.x, fmaf(gC1[k], cc.y, fmaf(gC2[k], cc.z, gA[k])));
+            if (V::kDepth) sv = fmaf(gD[k], cc.w, sv);
+            if (V::kPoint) sv = fmaf(gX0[k], d.x, fmaf(gX1[k], d.y, fmaf(gX2[k], d.z, sv)));
+            Pfx[k] = fmaf(w, sv, Pfx[k]);
+            const float one_m = __fsub_rn(1.0f, al);
+            const float dLda = T[k] * sv - (Gb[k] - Pfx[k]) * __builtin_amdgcn_rcpf(one_m);
+            const float g = (valid[k] && al < amax) ? dLda * al : 0.0f;
+            if constexpr (kMfma) {
+                T[k] = valid[k] ? __fmul_rn(T[k], one_m) : T[k];
+                float *bw = mf_b[wv] + bofs + 4 * slot;
+                bw[0] = g;
+                bw[4 * kSlots] = w;
+                continue;
             }
-            // Entries at or past the wave's last contributing one are not walked.
-            const uint32_t lim = wave_last - (rel0 + (uint32_t)c);
+            const float gdx = g * dx, gdy = g * dy;
+            int t = 0;
+            if (V::kOpacity) add(t++, g);
+            add(t++, gdx);
+            add(t++, gdy);
+            mad(t++, gdx, dx);
+            mad(t++, gdy, dx);
+            mad(t++, gdy, dy);
+            if (V::kColour) {
+                mad(t++, w, gC0[k]);
+                mad(t++, w, gC1[k]);
+                mad(t++, w, gC2[k]);
+            }
+            if (V::kDepth) mad(t++, w, gD[k]);
+            if (V::kPoint) {
+                mad(t++, w, gX0[k]);
+                mad(t++, w, gX1[k]);
+                mad(t++, w, gX2[k]);
+            }
+            T[k] = valid[k] ? __fmul_rn(T[k], one_m) : T[k];
+        }
+        if constexpr (kMfma) {
+            if (lane == 0) mf_meta[wv][slot] = make_float4(a.x, a.y, b.w, 0.0f);
+            if (++slot == kSlots) {
+                flush(kSlots);
+                slot = 0;
+            }
+            return;
+        }
+        int idx;
+        const float tot = wave_reduce_scatter(v, idx);
+        if (idx >= 0 && idx < V::N && tot != 0.f) {
+            // The record index is wave-uniform: a scalar row base plus the lane's column.
+            const uint32_t r = (uint32_t)__builtin_amdgcn_readfirstlane((int)__float_as_uint(b.w));
+            const uint32_t col = (uint32_t)((V::kColumns >> (4 * idx)) & 15u);
+            unsafeAtomicAdd(grad2d + (int64_t)r * kG2 + col, tot);
+        }
+    };
+    if constexpr (kMfma) {
+        // Each wave stages only the entries its bits mark, kWS at a time, in its own LDS
+        // area, and walks them with no workgroup barrier.  The entry's list position rides
+        // in the staged point's fourth component.
+        float4 *w0 = mw0[wv], *w1 = mw1[wv], *w2 = mw2[wv], *w3 = mw3[wv];
+        const uint32_t wend = rg.x + wave_last;
+        for (uint32_t pos = rg.x; pos < wend; pos += kWave) {
+            uint64_t m = use_bits ? wave_bits(pos) : ~0ull;  // without bits every entry is tested
+            const uint32_t lim = wend - pos;
             if (lim < (uint32_t)kWave) m &= (1ull << lim) - 1ull;
-            while (m != 0ull) {
-                const int q = c + (int)__builtin_ctzll(m);
-                m &= m - 1ull;
-                const uint32_t rel = rel0 + (uint32_t)q;
-                const float4 a = s0[q];
-                const float4 b = s1[q];
-                const float4 cc = s2[q];
-                const float4 d = s3[q];
-                // One 16-byte read now rather than a second, split read after the test.
-                asm volatile("" ::"v"(b.z), "v"(b.w));
-                const float dx = px - a.x;
-                const float Adx2 = a.z * dx * dx, Bdx = a.w * dx;
-                float e[PPT];
-                bool valid[PPT];
-                uint64_t any = 0ull;
 #pragma unroll
-                for (int k = 0; k < PPT; ++k) {
-                    e[k] = quad_e(Adx2, Bdx, b.x, py[k] - a.y);
-                    // One comparison decides (its lane mask is the ballot as it stands).
-                    valid[k] = (rel < my_last[k] ? e[k] : -INFINITY) >= b.y;
-                    any |= ballot(valid[k]);
+            for (int h = 0; h < kWave / kWS; ++h) {
+                const uint32_t mh = (uint32_t)((m >> (kWS * h)) & kWSMask);
+                if (mh == 0u) continue;  // wave-uniform
+                if (lane < kWS && ((mh >> lane) & 1u)) {
+                    const uint32_t si = (uint32_t)__popc(mh & ((1u << lane) - 1u));
+                    const uint32_t p = pos + (uint32_t)(kWS * h + lane);
+                    stage(rec, vals[p], tp.x0, tp.y0, amin, w0, w1, w2, w3, (int)si);
+                    w3[si].w = __uint_as_float(p - rg.x);
                 }
-                if constexpr (kMfma) {
-                    asm volatile("" ::"v"(cc.x), "v"(cc.y), "v"(cc.z), "v"(cc.w));
-                    if constexpr (V::kPoint) asm volatile("" ::"v"(d.x), "v"(d.y), "v"(d.z));
+                __builtin_amdgcn_wave_barrier();  // staged (a wave's LDS accesses stay in order)
+                const int n_st = __popc(mh);
+                for (int i = 0; i < n_st; ++i) {
+                    const float4 a = w0[i];
+                    const float4 b = w1[i];
+                    const float4 cc = w2[i];
+                    const float4 d = w3[i];
+                    // One 16-byte read now rather than a second, split read after the test.
+                    asm volatile("" ::"v"(b.z), "v"(b.w));
+                    walk_record(a, b, cc, d, __float_as_uint(d.w));
                 }
-                if (any == 0ull) continue;  // wave-uniform
-                float v[V::NR];
-#pragma unroll
-                for (int t = V::N; t < V::NR; ++t) v[t] = 0.f;
-#pragma unroll
-                for (int k = 0; k < PPT; ++k) {
-                    // The first pixel assigns, later ones accumulate (x + 0 is not folded).
-                    auto add = [&](int t, float x) { v[t] = k == 0 ? x : v[t] + x; };
-                    auto mad = [&](int t, float x, float y) { v[t] = k == 0 ? x * y : fmaf(x, y, v[t]); };
-                    // Branch-free: an invalid pixel gets zero weight and leaves T unchanged
-                    // (e <= 0, so alpha lies in [0, alpha_max] and 1 - alpha >= 1 - alpha_max).
-                    const float dy = py[k] - a.y;
-                    const float al = fminf(amax, b.z * __builtin_amdgcn_exp2f(e[k]));
-                    const float w = valid[k] ? __fmul_rn(al, T[k]) : 0.0f;
-                    float sv = fmaf(gC0[k], cc.x, fmaf(gC1[k], cc.y, fmaf(gC2[k], cc.z, gA[k])));
-                    if (V::kDepth) sv = fmaf(gD[k], cc.w, sv);
-                    if (V::kPoint) sv = fmaf(gX0[k], d.x, fmaf(gX1[k], d.y, fmaf(gX2[k], d.z, sv)));
-                    Pfx[k] = fmaf(w, sv, Pfx[k]);
-                    const float one_m = __fsub_rn(1.0f, al);
-                    const float dLda = T[k] * sv - (Gb[k] - Pfx[k]) * __builtin_amdgcn_rcpf(one_m);
-                    const float g = (valid[k] && al < amax) ? dLda * al : 0.0f;
-                    if constexpr (kMfma) {
-                        T[k] = valid[k] ? __fmul_rn(T[k], one_m) : T[k];
-                        float *bw = mf_b[wv] + bofs + 4 * slot;
-                        bw[0] = g;
-                        bw[4 * kSlots] = w;
-                        continue;
-                    }
-                    const float gdx = g * dx, gdy = g * dy;
-                    int t = 0;
-                    if (V::kOpacity) add(t++, g);
-                    add(t++, gdx);
-                    add(t++, gdy);
-                    mad(t++, gdx, dx);
-                    mad(t++, gdy, dx);
-                    mad(t++, gdy, dy);
-                    if (V::kColour) {
-                        mad(t++, w, gC0[k]);
-                        mad(t++, w, gC1[k]);
-                        mad(t++, w, gC2[k]);
-                    }
-                    if (V::kDepth) mad(t++, w, gD[k]);
-                    if (V::kPoint) {
-                        mad(t++, w, gX0[k]);
-                        mad(t++, w, gX1[k]);
-                        mad(t++, w, gX2[k]);
-                    }
-                    T[k] = valid[k] ? __fmul_rn(T[k], one_m) : T[k];
-                }
-                if constexpr (kMfma) {
-                    if (lane == 0) mf_meta[wv][slot] = make_float4(a.x, a.y, b.w, 0.0f);
-                    if (++slot == kSlots) {
-                        flush(kSlots);
-                        slot = 0;
-                    }
-                    continue;
-                }
-                int idx;
-                const float tot = wave_reduce_scatter(v, idx);
-                if (idx >= 0 && idx < V::N && tot != 0.f) {
-                    // The record index is wave-uniform: a scalar row base plus the lane's column.
-                    const uint32_t r = (uint32_t)__builtin_amdgcn_readfirstlane((int)__float_as_uint(b.w));
-                    const uint32_t col = (uint32_t)((V::kColumns >> (4 * idx)) & 15u);
-                    unsafeAtomicAdd(grad2d + (int64_t)r * kG2 + col, tot);
-                }
+                __builtin_amdgcn_wave_barrier();  // read before the next entries are staged
             }
         }
-        __syncthreads();
+    } else {
+        // The next batch's record indices are loaded one batch ahead, so staging waits on one
+        // global read (the record) rather than two dependent ones.
+        uint32_t vnext = (threadIdx.x < NS && rg.x + threadIdx.x < end) ? vals[rg.x + threadIdx.x] : 0u;
+        for (uint32_t base = rg.x; base < end; base += NS) {
+            const uint32_t kk = base + threadIdx.x;
+            const uint32_t vcur = vnext;
+            if (threadIdx.x < NS && kk + NS < end) vnext = vals[kk + NS];
+            const uint64_t bits0 = use_bits ? wave_bits(base) : 0ull;  // read while the batch is staged
+            if (threadIdx.x < NS && kk < end) stage(rec, vcur, tp.x0, tp.y0, amin, s0, s1, s2, s3, threadIdx.x);
+            __syncthreads();
+            const int cnt = (int)min((uint32_t)NS, end - base);
+            const uint32_t rel0 = base - rg.x;
+            for (int c = 0; c < cnt && rel0 + (uint32_t)c < wave_last; c += kWave) {
+                uint64_t m;
+                if (use_bits) {
+                    m = c == 0 ? bits0 : wave_bits(base + (uint32_t)c);
+                    if (cnt - c < kWave) m &= (1ull << (cnt - c)) - 1ull;  // the next tile's entries
+                } else {
+                    m = batch_mask<L::CULL>(s0, s1, c, cnt, lay.rx0, lay.rx1, lay.ry0, lay.ry1);
+                }
+                // Entries at or past the wave's last contributing one are not walked.
+                const uint32_t lim = wave_last - (rel0 + (uint32_t)c);
+                if (lim < (uint32_t)kWave) m &= (1ull << lim) - 1ull;
+                while (m != 0ull) {
+                    const int q = c + (int)__builtin_ctzll(m);
+                    m &= m - 1ull;
+                    const uint32_t rel = rel0 + (uint32_t)q;
+                    const float4 a = s0[q];
+                    const float4 b = s1[q];
+                    const float4 cc = s2[q];
+                    const float4 d = s3[q];
+                    // One 16-byte read now rather than a second, split read after the test.
+                    asm volatile("" ::"v"(b.z), "v"(b.w));
+                    walk_record(a, b, cc, d, rel);
+                }
+            }
+            __syncthreads();
+        }
     }
     if constexpr (kMfma) {
         if (slot > 0) flush(slot);  // wave-uniform
