@@ -633,14 +633,18 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
             uint64_t m = use_bits ? wave_bits(pos) : ~0ull;  // without bits every entry is tested
             const uint32_t lim = wend - pos;
             if (lim < (uint32_t)kWave) m &= (1ull << lim) - 1ull;
+            // Lane L reads the record index of position pos + L (if marked) for the whole word.
+            const bool mine = (m >> lane) & 1ull;
+            const uint32_t my_rec = mine ? vals[pos + (uint32_t)lane] : 0u;
 #pragma unroll
             for (int h = 0; h < kWave / kWS; ++h) {
                 const uint32_t mh = (uint32_t)((m >> (kWS * h)) & kWSMask);
                 if (mh == 0u) continue;  // wave-uniform
-                if (lane < kWS && ((mh >> lane) & 1u)) {
-                    const uint32_t si = (uint32_t)__popc(mh & ((1u << lane) - 1u));
-                    const uint32_t p = pos + (uint32_t)(kWS * h + lane);
-                    stage(rec, vals[p], tp.x0, tp.y0, amin, w0, w1, w2, w3, (int)si);
+                const int sub = lane - kWS * h;  // this lane's bit within the half
+                if (mine && sub >= 0 && sub < kWS) {
+                    const uint32_t si = (uint32_t)__popc(mh & ((1u << sub) - 1u));
+                    const uint32_t p = pos + (uint32_t)lane;
+                    stage(rec, my_rec, tp.x0, tp.y0, amin, w0, w1, w2, w3, (int)si);
                     w3[si].w = __uint_as_float(p - rg.x);
                 }
                 __builtin_amdgcn_wave_barrier();  // staged (a wave's LDS accesses stay in order)
