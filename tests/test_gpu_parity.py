@@ -277,6 +277,25 @@ def test_backward_c0(lib, oracle, frame, lane_reduce):
     U.log(f"  pose gpu {g['pose'][0]} oracle {r['pose'][0]}")
 
 
+@pytest.mark.parametrize("tile,ppl", [(8, 1), (16, 1), (16, 2), (16, 4), (32, 1), (32, 2), (32, 4)])
+def test_backward_shapes(lib, oracle, tile, ppl):
+    """Gradients against the oracle for every launch shape of the raster kernels: the
+    matrix-core backward (one pixel per lane: 1, 4 or 16 waves per tile) and the
+    reduce-scatter backward (2 and 4 pixels per lane)."""
+    U.log(f"[gpu] backward c0 tile={tile} ppl={ppl}")
+    O = oracle
+    sc = _posed(scenes.make_scene("c0"))
+    cfg = lib.RasterConfig(pointmap_frame=1, tile=tile, pixels_per_lane=ppl)
+    rast, params, out, fs = _render_gpu(lib, sc, cfg)
+    ref = O.render_image(O.Params.from_scene(sc), sc.cams[0], sc.T_cw[0], _oracle_settings(O, cfg))
+    ups = _upstream(sc, 24, [ref["ambiguous"] == 0])
+    g = _gpu_backward(lib, rast, params, out, fs, ups)
+    r = _oracle_backward(O, sc, cfg, ups)
+    for k in ("means", "log_scales", "quats", "opacity_logit", "rgb"):
+        U.check_grad(f"c0 {tile}x{tile}/ppl{ppl} {k}", g[k], r[k])
+    U.check_grad(f"c0 {tile}x{tile}/ppl{ppl} pose", g["pose"], r["pose"], frac=1.0)
+
+
 @pytest.mark.parametrize("ppl_fwd,ppl_bwd", [(2, 1), (1, 2)])
 def test_backward_after_forward_with_other_shape(lib, oracle, ppl_fwd, ppl_bwd):
     """A backward whose pixels per lane differ from its forward's: the forward's per-wave
