@@ -22,6 +22,7 @@ constexpr double kLog2e = 1.4426950408889634074;
 struct Proj {
     bool visible;
     bool clamp_x, clamp_y;
+    double mu[3];         // world-frame centre
     double m[3];          // camera-frame centre
     double u, v, z;
     double a;             // sigmoid opacity
@@ -37,30 +38,37 @@ struct Proj {
     int32_t rect[4];      // pixel rect imin, imax, jmin, jmax
 };
 
-__device__ inline void project_one(const gspm_gaussians &G, int64_t g, int64_t n, const float *T12,
-                                   float fx, float fy, float cx, float cy, int W, int H,
-                                   const RasterSettings &rs, Proj &P) {
-    P.visible = false;
-    P.clamp_x = P.clamp_y = false;
-    const double mu0 = G.means[g], mu1 = G.means[n + g], mu2 = G.means[2 * n + g];
+// The view-independent part of the projection: activated scales and opacity, the unit
+// quaternion and its rotation.  False for a quaternion that cannot be normalised.
+__device__ inline bool gaussian_frame(const gspm_gaussians &G, int64_t g, int64_t n, Proj &P) {
+    P.mu[0] = G.means[g]; P.mu[1] = G.means[n + g]; P.mu[2] = G.means[2 * n + g];
     const double qw = G.quats[g], qx = G.quats[n + g], qy = G.quats[2 * n + g], qz = G.quats[3 * n + g];
     P.s[0] = (double)expf(G.log_scales[g]);
     P.s[1] = (double)expf(G.log_scales[n + g]);
     P.s[2] = (double)expf(G.log_scales[2 * n + g]);
     P.a = (double)(1.0f / (1.0f + expf(-G.opacity_logit[g])));
     P.qnorm = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
-    if (!(P.qnorm > 0.0) || !isfinite(P.qnorm)) return;
+    if (!(P.qnorm > 0.0) || !isfinite(P.qnorm)) return false;
     const double inv = 1.0 / P.qnorm;
     const double w = qw * inv, x = qx * inv, y = qy * inv, z = qz * inv;
     P.qn[0] = w; P.qn[1] = x; P.qn[2] = y; P.qn[3] = z;
     P.Rq[0][0] = 1.0 - 2.0 * (y * y + z * z); P.Rq[0][1] = 2.0 * (x * y - w * z); P.Rq[0][2] = 2.0 * (x * z + w * y);
     P.Rq[1][0] = 2.0 * (x * y + w * z); P.Rq[1][1] = 1.0 - 2.0 * (x * x + z * z); P.Rq[1][2] = 2.0 * (y * z - w * x);
     P.Rq[2][0] = 2.0 * (x * z - w * y); P.Rq[2][1] = 2.0 * (y * z + w * x); P.Rq[2][2] = 1.0 - 2.0 * (x * x + y * y);
+    return true;
+}
 
+// The view-dependent part (Eq. 1): camera-frame centre and covariance, the clamped
+// Jacobian, the 2D covariance, its conic and the pixel support.  Needs gaussian_frame's
+// fields of P.
+__device__ inline void project_view(const float *T12, float fx, float fy, float cx, float cy, int W, int H,
+                                    const RasterSettings &rs, Proj &P) {
+    P.visible = false;
+    P.clamp_x = P.clamp_y = false;
     for (int r = 0; r < 3; ++r)
         for (int c = 0; c < 3; ++c) P.W[r][c] = T12[4 * r + c];
     for (int r = 0; r < 3; ++r)
-        P.m[r] = P.W[r][0] * mu0 + P.W[r][1] * mu1 + P.W[r][2] * mu2 + (double)T12[4 * r + 3];
+        P.m[r] = P.W[r][0] * P.mu[0] + P.W[r][1] * P.mu[1] + P.W[r][2] * P.mu[2] + (double)T12[4 * r + 3];
     P.z = P.m[2];
     if (!(P.z > (double)rs.near_z) || !isfinite(P.z) || !isfinite(P.m[0]) || !isfinite(P.m[1])) return;
     const double iz = 1.0 / P.z;
@@ -112,6 +120,15 @@ __device__ inline void project_one(const gspm_gaussians &G, int64_t g, int64_t n
     if (i0 > i1 || j0 > j1) return;
     P.rect[0] = (int32_t)i0; P.rect[1] = (int32_t)i1; P.rect[2] = (int32_t)j0; P.rect[3] = (int32_t)j1;
     P.visible = true;
+}
+
+__device__ inline void project_one(const gspm_gaussians &G, int64_t g, int64_t n, const float *T12,
+                                   float fx, float fy, float cx, float cy, int W, int H,
+                                   const RasterSettings &rs, Proj &P) {
+    P.visible = false;
+    P.clamp_x = P.clamp_y = false;
+    if (!gaussian_frame(G, g, n, P)) return;
+    project_view(T12, fx, fy, cx, cy, W, H, rs, P);
 }
 
 __global__ void __launch_bounds__(256)
@@ -230,32 +247,44 @@ k_preprocess_backward(gspm_gaussians G, ViewTable vt, const float *__restrict__ 
     // One thread per Gaussian, looping over the views: the Gaussian's parameter gradients
     // are summed over the views in registers and added once (one float atomic per
     // parameter, not one per view), and its parameters stay in cache across the views.
+    // The view-independent part of the projection is computed once, and the next view's
+    // image-plane gradient row is loaded while this view's is processed.
     // Pose partials per block and view in FP64.
     __shared__ double lds[6 * (kBwdBlock / 64)];
     const int64_t n = G.n;
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double gmu[3] = {0, 0, 0}, gls[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go = 0.0, gc[3] = {0, 0, 0};
     bool touched = false;
+    Proj P;
+    const bool framed = g < n && gaussian_frame(G, g, n, P);
+    float4 n0 = make_float4(0, 0, 0, 0), n1 = n0, n2 = n0, n3 = n0;
+    if (g < n && vt.n_views > 0) {
+        const float4 *src = grad2d + 4 * g;
+        n0 = src[0]; n1 = src[1]; n2 = src[2]; n3 = src[3];
+    }
     for (int v = 0; v < vt.n_views; ++v) {
         double pose[6] = {0, 0, 0, 0, 0, 0};
         bool any = false;
-        float4 q0 = make_float4(0, 0, 0, 0), q1 = q0, q2 = q0, q3 = q0;
+        const float4 q0 = n0, q1 = n1, q2 = n2, q3 = n3;
         if (g < n) {
-            float4 *src = grad2d + 4 * ((int64_t)v * n + g);
-            q0 = src[0]; q1 = src[1]; q2 = src[2]; q3 = src[3];
+            if (v + 1 < vt.n_views) {
+                const float4 *nxt = grad2d + 4 * ((int64_t)(v + 1) * n + g);
+                n0 = nxt[0]; n1 = nxt[1]; n2 = nxt[2]; n3 = nxt[3];
+            }
             any = q0.x != 0.f || q0.y != 0.f || q0.z != 0.f || q0.w != 0.f || q1.x != 0.f || q1.y != 0.f ||
                   q1.z != 0.f || q1.w != 0.f || q2.x != 0.f || q2.y != 0.f || q2.z != 0.f || q2.w != 0.f ||
                   q3.x != 0.f;
             if (any) {  // leave the row cleared for the next backward
+                float4 *src = grad2d + 4 * ((int64_t)v * n + g);
                 const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
                 src[0] = z; src[1] = z; src[2] = z; src[3] = z;
             }
         }
-        Proj P;
-        if (any) {
-            project_one(G, g, n, T_cw + 12 * v, vt.fx[v], vt.fy[v], vt.cx[v], vt.cy[v], vt.width[v], vt.height[v],
-                        rs, P);
+        if (any && framed) {
+            project_view(T_cw + 12 * v, vt.fx[v], vt.fy[v], vt.cx[v], vt.cy[v], vt.width[v], vt.height[v], rs, P);
             any = P.visible;
+        } else {
+            any = false;
         }
         {
             if (any) {
