@@ -122,73 +122,67 @@ __device__ inline void project_view(const float *T12, float fx, float fy, float 
     P.visible = true;
 }
 
-__device__ inline void project_one(const gspm_gaussians &G, int64_t g, int64_t n, const float *T12,
-                                   float fx, float fy, float cx, float cy, int W, int H,
-                                   const RasterSettings &rs, Proj &P) {
-    P.visible = false;
-    P.clamp_x = P.clamp_y = false;
-    if (!gaussian_frame(G, g, n, P)) return;
-    project_view(T12, fx, fy, cx, cy, W, H, rs, P);
-}
-
 __global__ void __launch_bounds__(256)
 k_preprocess(gspm_gaussians G, ViewTable vt, const float *__restrict__ T_cw, RasterSettings rs,
              float4 *__restrict__ rec, uint32_t *__restrict__ counts, uint32_t *__restrict__ dkey,
              uint4 *__restrict__ spans, uint32_t *__restrict__ big_list, uint32_t *__restrict__ big_count) {
-    // blockIdx.y is the view: no 64-bit division to split the record index.
+    // One thread per Gaussian looping over the views: the view-independent part of the
+    // projection is computed once.
     const int64_t n = G.n;
-    const int v = (int)blockIdx.y;
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t r = (int64_t)v * n + g;
-    bool big = false;
-    if (g < n) {
-        Proj P;
-        project_one(G, g, n, T_cw + 12 * v, vt.fx[v], vt.fy[v], vt.cx[v], vt.cy[v], vt.width[v],
-                    vt.height[v], rs, P);
-        uint32_t count = 0;
-        if (P.visible) {
-            const float zf = (float)P.z;
-            dkey[r] = __float_as_uint(zf);
-            const float uhi = (float)P.u, vhi = (float)P.v;
-            const float ulo = (float)(P.u - (double)uhi), vlo = (float)(P.v - (double)vhi);
-            const float4 r0 = make_float4(uhi, vhi, ulo, vlo);
-            const float4 r1 = make_float4((float)(-0.5 * kLog2e * P.Q[0]), (float)(-kLog2e * P.Q[1]),
-                                          (float)(-0.5 * kLog2e * P.Q[2]), (float)P.a);
-            float4 *o = rec + 4 * r;
-            o[0] = r0;
-            o[1] = r1;
-            o[2] = make_float4(G.rgb[g], G.rgb[n + g], G.rgb[2 * n + g], zf);
-            if (rs.frame == 0)
-                o[3] = make_float4(G.means[g], G.means[n + g], G.means[2 * n + g], 0.0f);
-            else
-                o[3] = make_float4((float)P.m[0], (float)P.m[1], (float)P.m[2], 0.0f);
-            // Number of tiles the support meets, row by row (the pair emission repeats this).
-            // Records whose support box covers many tiles are counted by whole waves instead.
-            Footprint f;
-            if (record_footprint(r0, r1, rs.alpha_min, vt.width[v], vt.height[v], f)) {
-                const int T = vt.tile, sh = __builtin_ctz((unsigned)vt.tile);  // a power of two
-                const int rows = (f.j1 >> sh) - (f.j0 >> sh) + 1, cols = (f.i1 >> sh) - (f.i0 >> sh) + 1;
-                if ((uint32_t)(rows * cols) > kBigRecord) {
-                    big = true;  // its count may still come out at most kBigRecord: not cached
-                    spans[r] = make_uint4(kSpanNone << 16, 0u, 0u, 0u);
-                } else {
-                    uint32_t w[kSpanRows] = {1u, 1u, 1u};  // empty rows: first > last
-                    for (int ty = f.j0 >> sh, k = 0; ty <= f.j1 >> sh; ++ty, ++k) {
-                        int ta, tb;
-                        if (row_span(f, T, ty, ta, tb)) {
-                            count += (uint32_t)(tb - ta + 1);
-                            if (k < (int)kSpanRows) w[k] = (uint32_t)ta | ((uint32_t)tb << 16);
+    Proj P;
+    const bool framed = g < n && gaussian_frame(G, g, n, P);
+    for (int v = 0; v < vt.n_views; ++v) {
+        const int64_t r = (int64_t)v * n + g;
+        bool big = false;
+        if (g < n) {
+            if (framed)
+                project_view(T_cw + 12 * v, vt.fx[v], vt.fy[v], vt.cx[v], vt.cy[v], vt.width[v], vt.height[v], rs, P);
+            uint32_t count = 0;
+            if (framed && P.visible) {
+                const float zf = (float)P.z;
+                dkey[r] = __float_as_uint(zf);
+                const float uhi = (float)P.u, vhi = (float)P.v;
+                const float ulo = (float)(P.u - (double)uhi), vlo = (float)(P.v - (double)vhi);
+                const float4 r0 = make_float4(uhi, vhi, ulo, vlo);
+                const float4 r1 = make_float4((float)(-0.5 * kLog2e * P.Q[0]), (float)(-kLog2e * P.Q[1]),
+                                              (float)(-0.5 * kLog2e * P.Q[2]), (float)P.a);
+                float4 *o = rec + 4 * r;
+                o[0] = r0;
+                o[1] = r1;
+                o[2] = make_float4(G.rgb[g], G.rgb[n + g], G.rgb[2 * n + g], zf);
+                if (rs.frame == 0)
+                    o[3] = make_float4(G.means[g], G.means[n + g], G.means[2 * n + g], 0.0f);
+                else
+                    o[3] = make_float4((float)P.m[0], (float)P.m[1], (float)P.m[2], 0.0f);
+                // Number of tiles the support meets, row by row (the pair emission repeats this).
+                // Records whose support box covers many tiles are counted by whole waves instead.
+                Footprint f;
+                if (record_footprint(r0, r1, rs.alpha_min, vt.width[v], vt.height[v], f)) {
+                    const int T = vt.tile, sh = __builtin_ctz((unsigned)vt.tile);  // a power of two
+                    const int rows = (f.j1 >> sh) - (f.j0 >> sh) + 1, cols = (f.i1 >> sh) - (f.i0 >> sh) + 1;
+                    if ((uint32_t)(rows * cols) > kBigRecord) {
+                        big = true;  // its count may still come out at most kBigRecord: not cached
+                        spans[r] = make_uint4(kSpanNone << 16, 0u, 0u, 0u);
+                    } else {
+                        uint32_t w[kSpanRows] = {1u, 1u, 1u};  // empty rows: first > last
+                        for (int ty = f.j0 >> sh, k = 0; ty <= f.j1 >> sh; ++ty, ++k) {
+                            int ta, tb;
+                            if (row_span(f, T, ty, ta, tb)) {
+                                count += (uint32_t)(tb - ta + 1);
+                                if (k < (int)kSpanRows) w[k] = (uint32_t)ta | ((uint32_t)tb << 16);
+                            }
                         }
+                        const uint32_t nr = rows <= (int)kSpanRows ? (uint32_t)rows : kSpanNone;
+                        if (count != 0u) spans[r] = make_uint4((uint32_t)(f.j0 >> sh) | (nr << 16), w[0], w[1], w[2]);
                     }
-                    const uint32_t nr = rows <= (int)kSpanRows ? (uint32_t)rows : kSpanNone;
-                    if (count != 0u) spans[r] = make_uint4((uint32_t)(f.j0 >> sh) | (nr << 16), w[0], w[1], w[2]);
                 }
             }
+            counts[r] = count;
         }
-        counts[r] = count;
+        const uint32_t slot = wave_append(big_count, big);
+        if (big) big_list[slot] = (uint32_t)r;
     }
-    const uint32_t slot = wave_append(big_count, big);
-    if (big) big_list[slot] = (uint32_t)r;
 }
 
 // Exact pair count of the queued large records: one wave per record, one lane per tile row.
@@ -516,7 +510,7 @@ hipError_t launch_preprocess(const gspm_gaussians &g, const ViewTable &vt, const
     if (R <= 0) return hipSuccess;
     hipError_t e = launch_fill_u32(big_count, 0u, 1, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_preprocess, dim3((unsigned)((g.n + 255) / 256), (unsigned)vt.n_views), dim3(256), 0, s, g,
+    hipLaunchKernelGGL(k_preprocess, dim3((unsigned)((g.n + 255) / 256), 1u), dim3(256), 0, s, g,
                        vt, T_cw, rs, reinterpret_cast<float4 *>(records), counts, dkey, spans, big_list, big_count);
     hipLaunchKernelGGL(k_count_big, dim3(1024), dim3(256), 0, s, reinterpret_cast<const float4 *>(records), vt, rs,
                        g.n, counts, big_list, big_count);
