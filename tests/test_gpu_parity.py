@@ -296,6 +296,28 @@ def test_backward_shapes(lib, oracle, tile, ppl):
     U.check_grad(f"c0 {tile}x{tile}/ppl{ppl} pose", g["pose"], r["pose"], frac=1.0)
 
 
+def test_zero_quaternions(lib, oracle):
+    """Gaussians whose quaternion cannot be normalised are dropped from every view (the
+    view-independent part of the projection fails once per Gaussian): forward and backward
+    still match the oracle, and those Gaussians get no gradient."""
+    U.log("[gpu] c0 with zero quaternions")
+    O = oracle
+    sc = _posed(scenes.make_scene("c0"))
+    dead = np.arange(0, sc.quats.shape[1], 7)
+    sc.quats[:, dead] = 0.0
+    cfg = lib.RasterConfig(pointmap_frame=1)
+    rast, params, out, fs = _render_gpu(lib, sc, cfg)
+    _check_view_forward(O, sc, 0, out, 0, cfg, tag="c0/zero-quats")
+    ref = O.render_image(O.Params.from_scene(sc), sc.cams[0], sc.T_cw[0], _oracle_settings(O, cfg))
+    ups = _upstream(sc, 31, [ref["ambiguous"] == 0])
+    g = _gpu_backward(lib, rast, params, out, fs, ups)
+    r = _oracle_backward(O, sc, cfg, ups)
+    for k in ("means", "log_scales", "quats", "opacity_logit", "rgb"):
+        assert np.all(g[k][..., dead] == 0.0), k
+        U.check_grad(f"c0 zero-quats {k}", g[k], r[k])
+    U.check_grad("c0 zero-quats pose", g["pose"], r["pose"], frac=1.0)
+
+
 @pytest.mark.parametrize("ppl_fwd,ppl_bwd", [(2, 1), (1, 2)])
 def test_backward_after_forward_with_other_shape(lib, oracle, ppl_fwd, ppl_bwd):
     """A backward whose pixels per lane differ from its forward's: the forward's per-wave
