@@ -151,7 +151,8 @@ GSPM_API void gspm_destroy(gspm_ctx *ctx);
 
 /* Grow the context's scratch so that later calls with at most max_records
  * Gaussian-view records (n * n_views), max_pairs tile pairs and max_tiles tiles
- * allocate nothing.  Sizes never shrink. */
+ * allocate nothing.  Sizes never shrink.  Both counts must be below 2^30 (the radix
+ * sorts' limit; GSPM_ERR_INVALID_ARG otherwise). */
 GSPM_API gspm_status gspm_reserve(gspm_ctx *ctx, int64_t max_records, int64_t max_pairs, int64_t max_tiles);
 
 /* Bytes of the caller-owned frame state that carries everything the backward needs
@@ -165,6 +166,8 @@ GSPM_API int64_t gspm_frame_state_bytes(const gspm_views *views, int64_t n_gauss
 
 /* Render all views.  frame_state: device buffer of frame_state_bytes >=
  * gspm_frame_state_bytes(views, g->n, max_pairs, s->tile), written by this call.
+ * g->n * views->n_views must be below 2^30, and the pair capacity taken from the
+ * buffer's size is capped at 2^30 - 1 (the radix sorts' limit).
  * If the views need more than max_pairs tile pairs the images are incomplete and the
  * frame state records the overflow: gspm_frame_status then returns GSPM_ERR_CAPACITY
  * with the number of pairs needed. */
@@ -173,7 +176,8 @@ GSPM_API gspm_status gspm_render_forward(gspm_ctx *ctx, const gspm_gaussians *g,
                                 int64_t frame_state_bytes, void *stream);
 
 /* Synchronise the stream and read the frame state's header: *pairs = tile pairs the
- * forward produced (or needed).  Returns GSPM_ERR_CAPACITY on overflow. */
+ * forward produced (or needed).  Returns GSPM_ERR_CAPACITY on overflow, and
+ * GSPM_ERR_INVALID_ARG if a backward refused the frame state (see gspm_render_backward). */
 GSPM_API gspm_status gspm_frame_status(const void *frame_state, void *stream, int64_t *pairs);
 
 /* Synchronise the stream and report the work of a forward: out[0] = tile pairs,
@@ -191,7 +195,18 @@ GSPM_API gspm_status gspm_frame_work(gspm_ctx *ctx, const gspm_views *views, int
  * outputs; any plane may be NULL for zero).  fwd_out are the forward's outputs (rgb,
  * depth, alpha and pointmap are read).  grads: accumulated parameter gradients.
  * pose_grad: device [V][6] accumulated, or NULL; it is d L / d xi at xi = 0 for the
- * left perturbation T_cw <- Exp(xi) T_cw, xi = (rho, phi) with the translation first. */
+ * left perturbation T_cw <- Exp(xi) T_cw, xi = (rho, phi) with the translation first.
+ *
+ * Same-settings contract: g, views (sizes, intrinsics and the poses in T_cw) and the
+ * settings must be those of the forward that wrote frame_state; only pixels_per_lane and
+ * bwd_lane_reduce may differ.  The views' sizes, the Gaussian count, the tile and the
+ * pointmap frame are checked on the device against the frame state's header (so the
+ * check also holds inside a captured graph), together with the forward's overflow and
+ * sort-stall flags: on a mismatch, or on an incomplete forward, the backward reads
+ * nothing of the frame state, adds nothing to grads and pose_grad, and marks the frame
+ * state so that gspm_frame_status returns GSPM_ERR_INVALID_ARG until the next forward
+ * into it.  Changed poses or parameters are not detected: the gradients are then those
+ * of a render that was not made. */
 GSPM_API gspm_status gspm_render_backward(gspm_ctx *ctx, const gspm_gaussians *g, const gspm_views *views,
                                  const gspm_settings *s, const gspm_const_images *fwd_out,
                                  const gspm_const_images *grad_out, const void *frame_state,

@@ -179,7 +179,8 @@ gspm_status prepare(const gspm_gaussians *g, const gspm_views *views, const gspm
     if (st) return st;
     P.vt.ppt = s->pixels_per_lane;
     P.n_records = g->n * views->n_views;
-    if (P.n_records >= (1ll << 31)) return fail(GSPM_ERR_INVALID_ARG, "n * n_views must be < 2^31");
+    // The radix sorts' look-back words hold 30-bit counts.
+    if (P.n_records >= kMaxSortKeys) return fail(GSPM_ERR_INVALID_ARG, "n * n_views must be < 2^30");
     P.rs.near_z = s->near_z;
     P.rs.alpha_min = s->alpha_min;
     P.rs.alpha_max = s->alpha_max;
@@ -270,7 +271,7 @@ gspm_status backward_common(gspm_ctx *ctx, const gspm_gaussians *g, const gspm_v
                                     at<float>(frame_state, L.records), at<uint32_t>(frame_state, L.last),
                                     at<float>(frame_state, L.t_final), *fwd_out, *grad_out, g2, pose_only,
                                     at<uint32_t>(frame_state, L.order) + P.n_tiles,
-                                    at<FrameHeader>(frame_state, L.header), hs));
+                                    at<FrameHeader>(const_cast<void *>(frame_state), L.header), P.n_records, hs));
     t_rb.stop();
     PhaseTimer t_pb(ctx, hs, GSPM_PHASE_PARAM_BWD);
     gspm_gaussian_grads none = {nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -309,8 +310,8 @@ void gspm_destroy(gspm_ctx *ctx) {
 gspm_status gspm_reserve(gspm_ctx *ctx, int64_t max_records, int64_t max_pairs, int64_t max_tiles) {
     if (!ctx) return fail(GSPM_ERR_INVALID_ARG, "ctx is NULL");
     if (max_records < 0 || max_pairs < 0 || max_tiles < 0) return fail(GSPM_ERR_INVALID_ARG, "negative size");
-    if (max_pairs >= (1ll << 31) || max_records >= (1ll << 31))
-        return fail(GSPM_ERR_INVALID_ARG, "sizes must be < 2^31");
+    if (max_pairs >= kMaxSortKeys || max_records >= kMaxSortKeys)
+        return fail(GSPM_ERR_INVALID_ARG, "sizes must be < 2^30");
     (void)max_tiles;
     GSPM_HIP(ensure_records(ctx, max_records, 8));
     GSPM_HIP(ensure_pairs(ctx, max_pairs, 8));
@@ -361,7 +362,7 @@ gspm_status gspm_render_forward(gspm_ctx *ctx, const gspm_gaussians *g, const gs
         const int64_t mid = cap + (hi - cap) / 2;
         if (need(mid) <= avail) cap = mid; else hi = mid;
     }
-    if (cap >= (1ll << 31)) cap = (1ll << 31) - 1;
+    if (cap >= kMaxSortKeys) cap = kMaxSortKeys - 1;
     hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
     const int db = s->sort_digit_bits;
     const int64_t R = P.n_records;
@@ -467,6 +468,10 @@ gspm_status gspm_frame_status(const void *frame_state, void *stream, int64_t *pa
     if (h.sort_stall) return fail(GSPM_ERR_INTERNAL, "a radix sort pass stopped waiting for an earlier tile");
     if (h.overflow)
         return fail(GSPM_ERR_CAPACITY, "tile pairs %u exceed the frame state's capacity %u", h.pairs, h.capacity);
+    if (h.bwd_error)
+        return fail(GSPM_ERR_INVALID_ARG,
+                    "a backward refused this frame state: its views, Gaussian count, tile or pointmap frame "
+                    "differ from the forward's; its gradients were not computed");
     return GSPM_OK;
 }
 

@@ -374,17 +374,25 @@ k_keygen(const uint32_t *__restrict__ sorted_rec, uint32_t rec_mask, const uint3
     __shared__ uint2 stage[kKeygenBlock / kWave][kStagePairs];
     const int wid = threadIdx.x / kWave, lane = lane_id();
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    n_records = scan_n(n_dev, n_records);
     if (p == 0) {
+        // Everything a backward checks before it reads the frame state.
         const uint32_t t = *total;
         hdr->pairs = t;
         hdr->overflow = t > cap ? 1u : 0u;
         hdr->capacity = cap;
+        hdr->tile = (uint32_t)vt.tile;
+        hdr->n_views = (uint32_t)vt.n_views;
+        hdr->n_tiles = (uint32_t)vt.tile_off[vt.n_views];
+        hdr->n_pixels = (uint64_t)vt.pix_off[vt.n_views];
+        hdr->n_records = (uint64_t)n_records;
         hdr->magic = kFrameMagic;
         hdr->visible = (uint32_t)rs.mark_visible;
         hdr->counted = (uint32_t)rs.count_work;
         hdr->ppt = (uint32_t)vt.ppt;
+        hdr->frame = (uint32_t)rs.frame;
+        hdr->bwd_error = 0u;
     }
+    n_records = scan_n(n_dev, n_records);
     const bool act = p < n_records;
     uint32_t r = 0, c = 0, k = 0;
     if (act) {

@@ -53,6 +53,10 @@ constexpr int kRecFloats = 16;
 // frame the depth is the point's z, so its gradient is carried in column 12 and 6 stays 0.
 constexpr int kG2 = 16;
 
+// The radix sorts publish 30-bit counts in their look-back words, so a sort takes fewer
+// than 2^30 keys: records per window and tile pairs per frame are bounded by this.
+constexpr int64_t kMaxSortKeys = int64_t(1) << 30;
+
 // Records with more tile pairs than this are counted and emitted by whole waves.
 constexpr uint32_t kBigRecord = 64;
 
@@ -78,6 +82,8 @@ struct FrameHeader {
     uint32_t sort_stall;  // nonzero if a radix sort pass abandoned its look-back
     uint32_t counted;     // nonzero if the forward wrote the contributing-fragment counts
     uint32_t ppt;         // pixels per lane of the forward, whose waves the contribution bits follow
+    uint32_t frame;       // pointmap frame of the forward (the records carry that frame's point)
+    uint32_t bwd_error;   // set by a backward that found the frame state unusable (see k_raster_bwd)
     uint32_t pad;
 };
 constexpr uint32_t kFrameMagic = 0x47535046u;  // "GSPF"
@@ -477,7 +483,7 @@ hipError_t launch_raster_backward(const ViewTable &vt, const RasterSettings &rs,
                                   const uint32_t *pair_vals, const float *records, const uint32_t *last,
                                   const float *t_final, const gspm_const_images &fwd,
                                   const gspm_const_images &up, float *grad2d, bool pose_only,
-                                  const uint32_t *order, const FrameHeader *hdr, hipStream_t s);
+                                  const uint32_t *order, FrameHeader *hdr, int64_t n_records, hipStream_t s);
 
 // Image-plane gradient rows -> parameter gradients (added into out) and per-block pose
 // partials; every row read as nonzero is cleared, so grad2d is all zero afterwards.

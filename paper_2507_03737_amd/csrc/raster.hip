@@ -348,7 +348,18 @@ __global__ void __launch_bounds__(TILE *TILE / PPT) __attribute__((amdgpu_waves_
 k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
              const float4 *__restrict__ rec, const uint32_t *__restrict__ last, const float *__restrict__ t_final,
              gspm_const_images fwd, gspm_const_images up, float *__restrict__ grad2d,
-             const uint32_t *__restrict__ order, const FrameHeader *__restrict__ hdr) {
+             const uint32_t *__restrict__ order, FrameHeader *__restrict__ hdr, int64_t n_records) {
+    // The frame state's layout follows the views, Gaussian count and tile of this call:
+    // unless they (and the pointmap frame of the records) are the forward's, and the
+    // forward's lists are complete, nothing below may be read.  The test is uniform over
+    // the launch; one lane records the refusal for gspm_frame_status.
+    if (hdr->magic != kFrameMagic || hdr->overflow != 0u || hdr->sort_stall != 0u || hdr->tile != (uint32_t)TILE ||
+        hdr->n_views != (uint32_t)vt.n_views || hdr->n_tiles != (uint32_t)vt.tile_off[vt.n_views] ||
+        hdr->n_pixels != (uint64_t)vt.pix_off[vt.n_views] || hdr->n_records != (uint64_t)n_records ||
+        hdr->frame != (uint32_t)FRAME) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) hdr->bwd_error = 1u;
+        return;
+    }
     using L = Layout<TILE, PPT>;
     using V = BwdValues<POSE_ONLY, FRAME>;
     constexpr int NT = L::NT;
@@ -363,7 +374,7 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
     constexpr int NS = kMfma ? 1 : NT;
     __shared__ float4 s0[NS], s1[NS], s2[NS], s3[NS];
     constexpr int kWS = 32;  // entries a wave stages at a time (matrix-core form)
-    constexpr uint32_t kWSMask = kWS == 32 ? 0xffffffffu : (1u << kWS) - 1u;
+    constexpr uint32_t kWSMask = kWS >= 32 ? 0xffffffffu : (uint32_t)((1ull << kWS) - 1ull);
     __shared__ float4 mw0[kMfma ? L::NW : 1][kMfma ? kWS : 1], mw1[kMfma ? L::NW : 1][kMfma ? kWS : 1],
         mw2[kMfma ? L::NW : 1][kMfma ? kWS : 1], mw3[kMfma ? L::NW : 1][kMfma ? kWS : 1];
     __shared__ uint32_t block_last;
@@ -753,14 +764,14 @@ hipError_t launch_raster_forward(const ViewTable &vt, const RasterSettings &rs, 
 hipError_t launch_raster_backward(const ViewTable &vt, const RasterSettings &rs, const uint2 *ranges,
                                   const uint32_t *pair_vals, const float *records, const uint32_t *last,
                                   const float *t_final, const gspm_const_images &fwd, const gspm_const_images &up,
-                                  float *grad2d, bool pose_only, const uint32_t *order, const FrameHeader *hdr,
-                                  hipStream_t s) {
+                                  float *grad2d, bool pose_only, const uint32_t *order, FrameHeader *hdr,
+                                  int64_t n_records, hipStream_t s) {
     const int n_tiles = vt.tile_off[vt.n_views];
     const float4 *rec = reinterpret_cast<const float4 *>(records);
     if (rs.frame < 0 || rs.frame > 2) return hipErrorInvalidValue;
 #define GSPM_BWD1(T_, P_, PO_, F_, MX_)                                                                         \
     hipLaunchKernelGGL((k_raster_bwd<T_, P_, PO_, F_, MX_>), dim3(n_tiles), dim3(T_ * T_ / P_), 0, s, vt, rs, \
-                       ranges, pair_vals, rec, last, t_final, fwd, up, grad2d, order, hdr)
+                       ranges, pair_vals, rec, last, t_final, fwd, up, grad2d, order, hdr, n_records)
 #define GSPM_BWD2(T_, P_, PO_, MX_)                            \
     if (rs.frame == 0) GSPM_BWD1(T_, P_, PO_, 0, MX_);         \
     else if (rs.frame == 1) GSPM_BWD1(T_, P_, PO_, 1, MX_);    \

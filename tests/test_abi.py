@@ -127,3 +127,20 @@ def test_product_path_has_no_oracle_or_cpu_fallback():
             B.load(os.path.join(ROOT, "does-not-exist.so"))
         finally:
             B._lib = saved
+
+
+def test_sort_limits_checked_on_host(L):
+    """Counts the radix sorts cannot take (2^30 keys and more) are refused on the host,
+    before any HIP call."""
+    ctx = ctypes.c_void_p()
+    assert L.gspm_create(ctypes.byref(ctx)) == B.GSPM_OK
+    assert L.gspm_reserve(ctx, 1 << 30, 10, 10) == B.GSPM_ERR_INVALID_ARG and "2^30" in B.last_error()
+    assert L.gspm_reserve(ctx, 10, 1 << 30, 10) == B.GSPM_ERR_INVALID_ARG
+    intr = B.make_intrinsics([scenes.Camera(160, 120, 128.0, 128.0, 80.0, 60.0)] * 2)
+    v = _views(intr, 2)
+    g = B.Gaussians(1, 1, 1, 1, 1, 1 << 29)
+    cfg = B.RasterConfig().c()
+    assert L.gspm_render_forward(ctx, ctypes.byref(g), ctypes.byref(v), ctypes.byref(cfg),
+                                 ctypes.byref(B.Images(1, 1, 1, 1)), 1, 1 << 40, None) == B.GSPM_ERR_INVALID_ARG
+    assert "2^30" in B.last_error()
+    L.gspm_destroy(ctx)

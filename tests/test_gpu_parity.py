@@ -398,3 +398,41 @@ def test_capacity_overflow_reports_and_recovers(lib):
     assert need > 100
     out2, fs2 = rast.forward(params)  # grows and retries
     assert rast.pairs == need and rast.max_pairs >= need
+
+
+def test_backward_refuses_a_mismatched_or_incomplete_frame(lib):
+    """A backward whose tile or pointmap frame differs from its forward's, or that follows
+    a forward whose pair list overflowed, reads nothing of the frame state: it adds no
+    gradient and gspm_frame_status reports the refusal until the next forward."""
+    U.log("[gpu] backward refuses a mismatched frame state")
+    import dataclasses
+    from paper_2507_03737_amd.render import Rasterizer, Window
+    sc = _posed(scenes.make_scene("c0", n=500))
+    params, T = U.to_dev(sc, torch)
+    up = {"rgb": torch.ones(3 * 160 * 120, device="cuda"), "pointmap": torch.ones(3 * 160 * 120, device="cuda")}
+    for field, value in (("tile", 8), ("pointmap_frame", 0)):
+        rast = Rasterizer(Window(sc.cams, T), sc.n, lib.RasterConfig(tile=16, pointmap_frame=1))
+        out, fs = rast.forward(params)
+        rast.cfg = dataclasses.replace(rast.cfg, **{field: value})
+        grads = rast.zero_grads(params)
+        pg = torch.zeros(1, 6, device="cuda")
+        rast.backward_into(params, out, up, fs, grads, pg)
+        torch.cuda.synchronize()
+        assert all(float(t.abs().max()) == 0.0 for t in grads.values()) and float(pg.abs().max()) == 0.0, field
+        with pytest.raises(lib.GspmError) as ei:
+            lib.frame_status(fs, lib.stream_handle())
+        assert ei.value.status == lib.GSPM_ERR_INVALID_ARG and "refused" in str(ei.value), field
+        rast.cfg = dataclasses.replace(rast.cfg, **{field: {"tile": 16, "pointmap_frame": 1}[field]})
+        out, fs = rast.forward(params)  # a new forward clears the mark; the matching backward runs
+        rast.backward_into(params, out, up, fs, grads, pg)
+        assert lib.frame_status(fs, lib.stream_handle()) > 0
+        assert float(grads["means"].abs().max()) > 0.0
+    rast = Rasterizer(Window(sc.cams, T), sc.n, lib.RasterConfig(), max_pairs=100)
+    out, fs = rast.new_outputs(), rast.new_frame_state()
+    rast.forward_into(params, out, fs)
+    grads = rast.zero_grads(params)
+    rast.backward_into(params, out, up, fs, grads, None)
+    torch.cuda.synchronize()
+    assert all(float(t.abs().max()) == 0.0 for t in grads.values())
+    with pytest.raises(lib.CapacityError):
+        lib.frame_status(fs, lib.stream_handle())
