@@ -243,6 +243,27 @@ GSPM_API gspm_status gspm_window_loss(gspm_ctx *ctx, const gspm_views *views, co
                              float *scale_out, float *loss_out, float *grad_rgb, float *grad_pm,
                              void *stream);
 
+/* Allocation-free gspm_window_loss, for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, and harnesses that forbid
+ * hipMalloc.  Same arguments, results and kernels as gspm_window_loss, without the
+ * context: its per-wave loss partials live in a static device array of
+ * GSPM_WINDOW_LOSS_NOALLOC_SLOTS float64 slots (1 MiB) that the library holds on every
+ * GPU it runs on until the process ends.  A window needs one slot per strip of
+ * floor(64 / patch) horizontally adjacent patches of one patch row, i.e. the sum over its
+ * views of ceil(ceil(W / patch) / floor(64 / patch)) * ceil(H / patch) (7,308 for eight
+ * keyframes 3x960x640 + 3x1216x352 + 2x640x480 at patch 8; 64,800 for sixteen 1920x1080
+ * views); larger windows are rejected with GSPM_ERR_INVALID_ARG before any launch.  The
+ * call allocates nothing.  Every slot it reads is written by the same call, so nothing has
+ * to start at zero, but the array is shared by all calls on one GPU: calls that overlap
+ * on one GPU (on different streams) race and give wrong losses.  The first call on each
+ * GPU looks up that GPU's address of the array (hipGetSymbolAddress, no allocation);
+ * make that first call outside graph capture. */
+#define GSPM_WINDOW_LOSS_NOALLOC_SLOTS 131072
+GSPM_API gspm_status gspm_window_loss_noalloc(const gspm_views *views, const float *rgb, const float *rgb_target,
+                                              const float *pm, const float *Xp, int32_t patch, float alpha,
+                                              float *scale_out, float *loss_out, float *grad_rgb, float *grad_pm,
+                                              void *stream);
+
 /* ---- scale alignment and pointmap replacement (supplementary Alg. 1; Sec. 3.3.2, Eq. 14) */
 
 /* Parameters of the patch-based scale alignment (the supplementary parameter table gives

@@ -100,7 +100,7 @@ EXPORTS = (
     "gspm_frame_status", "gspm_render_backward", "gspm_pose_backward", "gspm_patch_scale_align",
     "gspm_window_loss", "gspm_pose_retract", "gspm_timing_enable", "gspm_timing_collect", "gspm_frame_work",
     "gspm_last_error", "gspm_version", "gspm_align_scale", "gspm_replace_pointmap", "gspm_iso_loss",
-    "gspm_covisibility", "gspm_median_depth", "gspm_pnp_ransac",
+    "gspm_covisibility", "gspm_median_depth", "gspm_pnp_ransac", "gspm_window_loss_noalloc",
 )
 
 PHASES = ("preprocess", "depth_sort", "binning", "tile_sort", "raster_fwd", "raster_bwd", "param_bwd")
@@ -130,6 +130,8 @@ def load(path: str = LIB_PATH):
     L.gspm_pose_backward.argtypes = [vp, P(Gaussians), P(Views), P(Settings), P(Images), P(Images), vp, vp, vp]
     L.gspm_patch_scale_align.argtypes = [P(Views), vp, vp, vp, ctypes.c_int32, vp, vp, vp]
     L.gspm_window_loss.argtypes = [vp, P(Views), vp, vp, vp, vp, ctypes.c_int32, ctypes.c_float, vp, vp, vp, vp, vp]
+    L.gspm_window_loss_noalloc.argtypes = [P(Views), vp, vp, vp, vp, ctypes.c_int32, ctypes.c_float, vp, vp, vp,
+                                           vp, vp]
     L.gspm_pose_retract.argtypes = [ctypes.c_int32, vp, vp, vp]
     L.gspm_align_scale.argtypes = [vp, P(Views), vp, vp, vp, P(AlignParams), vp, vp]
     L.gspm_replace_pointmap.argtypes = [P(Views), vp, vp, vp, ctypes.c_float, vp, vp, vp]
@@ -299,6 +301,14 @@ def window_loss(ctx: Context, views: Views, rgb, rgb_target, pm, Xp, patch, alph
                 grad_pm, stream):
     check(load().gspm_window_loss(ctx.h, ctypes.byref(views), ptr(rgb), ptr(rgb_target), ptr(pm), ptr(Xp), int(patch),
                                   float(alpha), ptr(scale_out), ptr(loss_out), ptr(grad_rgb), ptr(grad_pm), stream))
+
+
+def window_loss_noalloc(views: Views, rgb, rgb_target, pm, Xp, patch, alpha, scale_out, loss_out, grad_rgb, grad_pm,
+                        stream):
+    """gspm_window_loss without a context: its partial sums use the library's static device array."""
+    check(load().gspm_window_loss_noalloc(ctypes.byref(views), ptr(rgb), ptr(rgb_target), ptr(pm), ptr(Xp),
+                                          int(patch), float(alpha), ptr(scale_out), ptr(loss_out), ptr(grad_rgb),
+                                          ptr(grad_pm), stream))
 
 
 def align_scale(ctx: Context, views: Views, Xr, Xp, mask, params: AlignParams, result, stream):

@@ -555,6 +555,28 @@ gspm_status gspm_window_loss(gspm_ctx *ctx, const gspm_views *views, const float
                         grad_rgb, grad_pm, stream);
 }
 
+gspm_status gspm_window_loss_noalloc(const gspm_views *views, const float *rgb, const float *rgb_target,
+                                     const float *pm, const float *Xp, int32_t patch, float alpha, float *scale_out,
+                                     float *loss_out, float *grad_rgb, float *grad_pm, void *stream) {
+    if (!rgb || !rgb_target || !pm || !Xp || !scale_out || !loss_out || !grad_rgb || !grad_pm)
+        return fail(GSPM_ERR_INVALID_ARG, "rgb, rgb_target, pm, Xp, scale_out, loss_out, grad_rgb and grad_pm are required");
+    if (!(alpha >= 0.0f && alpha <= 1.0f)) return fail(GSPM_ERR_INVALID_ARG, "alpha must lie in [0, 1]");
+    if (patch < 1 || patch > 64) return fail(GSPM_ERR_INVALID_ARG, "patch = %d outside [1, 64]", patch);
+    ViewTable vt;
+    int64_t nt, np;
+    gspm_status st = build_views(views, 16, vt, nt, np);
+    if (st) return st;
+    const int64_t need = patch_loss_partials(vt, patch);
+    if (need > kStaticLossPartials)
+        return fail(GSPM_ERR_INVALID_ARG, "the window needs %lld loss partials, more than the %lld this call holds",
+                    (long long)need, (long long)kStaticLossPartials);
+    double *part = nullptr;
+    GSPM_HIP(static_loss_partials(&part));
+    GSPM_HIP(launch_patch_loss(vt, pm, Xp, nullptr, patch, rgb, rgb_target, alpha, scale_out, nullptr, part, loss_out,
+                               grad_rgb, grad_pm, reinterpret_cast<hipStream_t>(stream)));
+    return GSPM_OK;
+}
+
 gspm_status gspm_align_scale(gspm_ctx *ctx, const gspm_views *views, const float *Xr, const float *Xp,
                              const float *mask, const gspm_align_params *prm, gspm_align_result *result,
                              void *stream) {

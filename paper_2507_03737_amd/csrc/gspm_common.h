@@ -496,6 +496,11 @@ hipError_t launch_pose_reduce(const double *pose_partials, int64_t n_blocks, int
                               float *pose_grad, hipStream_t s);
 
 int64_t patch_loss_partials(const ViewTable &vt, int patch);
+// Slots of the static partials array behind gspm_window_loss_noalloc (1 MiB of float64),
+// and the current device's address of that array (looked up once per device).
+constexpr int64_t kStaticLossPartials = GSPM_WINDOW_LOSS_NOALLOC_SLOTS;
+constexpr int kMaxDevices = 64;
+hipError_t static_loss_partials(double **out);
 hipError_t launch_patch_loss(const ViewTable &vt, const float *Xr, const float *Xp, const float *mask,
                              int patch, const float *rgb, const float *rgb_target, float alpha,
                              float *scale_out, int32_t *count_out, double *loss_part, float *loss_out,

@@ -9,9 +9,41 @@
 // scale is formed, and the same lanes revisit their (now cached) pixels to write the
 // sign-based L1 gradients.  Loss partials go to one slot per wave and are summed per view
 // in a fixed order by a second small kernel.
+#include <mutex>
+
 #include "gspm_common.h"
 
 namespace gspm {
+
+// Loss partials of the allocation-free entry point (gspm_window_loss_noalloc): one float64
+// slot per wave strip, in a static device array that the code object holds on every GPU
+// the library runs on.  In host code this name is only a stand-in for the symbol; kernels
+// get the device address that static_loss_partials() looks up.
+static __device__ __align__(256) double scratch[kStaticLossPartials];
+
+namespace {
+
+std::mutex g_scratch_mu;
+double *g_scratch_addr[kMaxDevices] = {};
+
+}  // namespace
+
+hipError_t static_loss_partials(double **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));  // this device's copy of the array
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_addr[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch_addr[dev];
+    return hipSuccess;
+}
 
 namespace {
 

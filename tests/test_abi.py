@@ -129,9 +129,9 @@ def test_product_path_has_no_oracle_or_cpu_fallback():
             B._lib = saved
 
 
-def test_sort_limits_checked_on_host(L):
-    """Counts the radix sorts cannot take (2^30 keys and more) are refused on the host,
-    before any HIP call."""
+def test_sort_limits_and_noalloc_size_checked_on_host(L):
+    """Counts the radix sorts cannot take (2^30 keys and more) and windows beyond the
+    allocation-free loss's static array are refused on the host, before any HIP call."""
     ctx = ctypes.c_void_p()
     assert L.gspm_create(ctypes.byref(ctx)) == B.GSPM_OK
     assert L.gspm_reserve(ctx, 1 << 30, 10, 10) == B.GSPM_ERR_INVALID_ARG and "2^30" in B.last_error()
@@ -143,4 +143,12 @@ def test_sort_limits_checked_on_host(L):
     assert L.gspm_render_forward(ctx, ctypes.byref(g), ctypes.byref(v), ctypes.byref(cfg),
                                  ctypes.byref(B.Images(1, 1, 1, 1)), 1, 1 << 40, None) == B.GSPM_ERR_INVALID_ARG
     assert "2^30" in B.last_error()
+    big = B.make_intrinsics([scenes.Camera(4096, 4096, 2000.0, 2000.0, 2048.0, 2048.0)] * 8)
+    st = L.gspm_window_loss_noalloc(ctypes.byref(_views(big, 8)), 1, 1, 1, 1, 1, ctypes.c_float(0.5), 1, 1, 1, 1,
+                                    None)
+    assert st == B.GSPM_ERR_INVALID_ARG and "partials" in B.last_error()
+    assert L.gspm_window_loss_noalloc(ctypes.byref(v), 1, 1, None, 1, 8, ctypes.c_float(0.5), 1, 1, 1, 1,
+                                      None) == B.GSPM_ERR_INVALID_ARG
+    assert L.gspm_window_loss_noalloc(ctypes.byref(v), 1, 1, 1, 1, 8, ctypes.c_float(2.0), 1, 1, 1, 1,
+                                      None) == B.GSPM_ERR_INVALID_ARG
     L.gspm_destroy(ctx)
