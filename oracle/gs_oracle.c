@@ -28,19 +28,27 @@
  * Gaussians with z <= near_z are dropped; pixel (i, j) (i = column) is sampled at
  * exactly (i, j), as Eq. 4 writes it; ties in depth are broken by Gaussian index.
  *
- * Everything is double precision.  No tiling: each pixel looks at every Gaussian.
- * The support rectangle of a Gaussian (the bounding box of the ellipse where its
- * alpha reaches alpha_min) is only used to skip Gaussians that provably cannot reach
- * alpha_min at the pixel; it is widened by one pixel so that the ambiguity flags
- * below also see Gaussians that graze the pixel.
+ * Everything is double precision.  No tiling: a pixel's candidates are all Gaussians
+ * whose candidate box contains it, taken from a per-pixel-row list of Gaussians (an index
+ * that only avoids scanning every Gaussian for every pixel; the candidate set is the
+ * same).  The candidate box is the bounding box of the ellipse where alpha reaches
+ * alpha_min, at an opacity widened by a relative 1e-4 and grown by one pixel: it skips
+ * only Gaussians that provably cannot reach alpha_min at the pixel, and it keeps those
+ * whose alpha comes within float32 rounding of alpha_min (including Gaussians whose
+ * opacity itself lies just below alpha_min), so that the ambiguity flags below see them.
+ *
+ * Depth order.  Gaussians are composited in ascending order of their depth rounded to
+ * float32, ties by index.  The paper sorts by z_k without fixing a precision, and an
+ * ordering is a discrete decision taken on floating-point values, so the oracle takes it
+ * in the precision of the kernels it checks: its double depth rounded to float32.
  *
  * Ambiguity flags.  A float32 implementation may take a different discrete decision
  * than this oracle where a value sits on a threshold.  Each pixel is flagged when,
  * within a first-order float32 error bound (times a safety factor), a fragment's alpha
- * is at alpha_min or alpha_max or a transmittance step is at t_min, or when two
- * consecutive contributing fragments would swap places under an ordering by (float32
- * depth, index): equal float32 depths, different double depths, indices in the opposite
- * order.  Parity tests compare unflagged pixels only.
+ * is at alpha_min or alpha_max or a transmittance step is at t_min, or when a
+ * contributing fragment's double depth lies within a few double ulps of a float32
+ * rounding midpoint (a depth computed with another rounding of its last bit may round to
+ * the other float32 neighbour).  Parity tests compare unflagged pixels only.
  */
 #include <math.h>
 #include <stdint.h>
@@ -71,13 +79,16 @@ typedef struct {
 typedef struct {
     double near_z, alpha_min, alpha_max, t_min, eps2d, jac_clamp;
     double bg[3];
+    double flag_factor; /* width of the ambiguity bands, in first-order error bounds */
 } orc_settings;
 
 /* Projection of one Gaussian into one view. */
 typedef struct {
-    int32_t visible;
+    int32_t visible; /* the support box below is not empty */
     int32_t clamp_x, clamp_y;
     int32_t rect[4]; /* imin, imax, jmin, jmax (inclusive pixel indices) */
+    int32_t cand;    /* the candidate box below is not empty */
+    int32_t crect[4];/* candidate box (see the header), inclusive pixel indices */
     double m[3];     /* camera-frame centre */
     double u, v, z;
     double a;        /* sigmoid(logit) */
@@ -105,8 +116,10 @@ typedef struct {
     double T_final;
     int32_t n_frag;    /* contributing fragments */
     int32_t n_cand;    /* candidates looked at (support box contains the pixel) */
-    int32_t ambiguous; /* bit 0 alpha_min, 1 t_min, 2 alpha_max, 3 depth tie */
+    int32_t ambiguous; /* bit 0 alpha_min, 1 t_min, 2 alpha_max, 3 depth at a float32 midpoint */
     int32_t pad;
+    double margin;     /* smallest |value - threshold| / (first-order bound) over the
+                          pixel's alpha_min, alpha_max and t_min decisions */
 } orc_pixel;
 
 /* Gradients, accumulated (+=). */
@@ -251,6 +264,24 @@ void orc_project_one(const orc_gaussians *G, int64_t g, const orc_view *V,
     P->Q[1] = -P->cov2[1] / det;
     P->Q[2] = P->cov2[0] / det;
 
+    /* Candidate box: the bounding box of the same ellipse at a level where the opacity is
+     * widened by a relative 1e-4, plus one pixel on each side. */
+    const double qc = 2.0 * log(P->a * (1.0 + 1e-4) / S->alpha_min);
+    if (qc > 0.0) {
+        const double rcx = sqrt(qc * P->cov2[0]), rcy = sqrt(qc * P->cov2[2]);
+        double c0 = ceil(P->u - rcx) - 1.0, c1 = floor(P->u + rcx) + 1.0;
+        double c2 = ceil(P->v - rcy) - 1.0, c3 = floor(P->v + rcy) + 1.0;
+        if (c0 < 0.0) c0 = 0.0;
+        if (c2 < 0.0) c2 = 0.0;
+        if (c1 > V->width - 1) c1 = V->width - 1;
+        if (c3 > V->height - 1) c3 = V->height - 1;
+        if (c0 <= c1 && c2 <= c3) {
+            P->cand = 1;
+            P->crect[0] = (int32_t)c0; P->crect[1] = (int32_t)c1;
+            P->crect[2] = (int32_t)c2; P->crect[3] = (int32_t)c3;
+        }
+    }
+
     /* Support: the alpha >= alpha_min ellipse {d : d^T Q d <= 2 ln(a / alpha_min)}. */
     if (!(P->a >= S->alpha_min)) return;
     const double qmax = 2.0 * log(P->a / S->alpha_min);
@@ -284,8 +315,18 @@ int orc_project(const orc_gaussians *G, const orc_view *V, const orc_settings *S
 
 typedef struct {
     int64_t g;
-    double z;
+    double z; /* the depth rounded to float32 (the ordering key, see the header) */
 } cand_t;
+
+/* Whether z lies within 8 double ulps of a midpoint between two float32 values. */
+static int near_f32_midpoint(double z)
+{
+    const float f = (float)z;
+    const double lo = 0.5 * ((double)f + (double)nextafterf(f, -INFINITY));
+    const double hi = 0.5 * ((double)f + (double)nextafterf(f, INFINITY));
+    const double tol = 8.0 * (nextafter(fabs(z), INFINITY) - fabs(z));
+    return fabs(z - lo) <= tol || fabs(z - hi) <= tol;
+}
 
 static int cand_cmp(const void *pa, const void *pb)
 {
@@ -305,16 +346,58 @@ typedef struct {
     int32_t pad;
 } frag_t;
 
-/* Gather candidates (support box widened by one pixel contains (i, j)), sorted by (z, g). */
-static int64_t gather(const orc_proj *P, int64_t n, int32_t i, int32_t j, cand_t *buf)
+/* Per pixel row j, the Gaussians whose candidate box spans row j (in index order). */
+typedef struct {
+    int32_t height;
+    int64_t *start; /* [height + 1] */
+    int64_t *items;
+} rows_t;
+
+static void rows_free(rows_t *r)
+{
+    free(r->start);
+    free(r->items);
+    r->start = NULL;
+    r->items = NULL;
+}
+
+static int rows_build(const orc_proj *P, int64_t n, int32_t height, rows_t *r)
+{
+    r->height = height;
+    r->start = (int64_t *)calloc((size_t)height + 1, sizeof(int64_t));
+    r->items = NULL;
+    if (!r->start) return -1;
+    for (int64_t g = 0; g < n; ++g)
+        if (P[g].cand)
+            for (int32_t j = P[g].crect[2]; j <= P[g].crect[3]; ++j) r->start[j + 1]++;
+    for (int32_t j = 0; j < height; ++j) r->start[j + 1] += r->start[j];
+    int64_t *cur = (int64_t *)malloc(sizeof(int64_t) * (size_t)(height > 0 ? height : 1));
+    r->items = (int64_t *)malloc(sizeof(int64_t) * (size_t)(r->start[height] > 0 ? r->start[height] : 1));
+    if (!cur || !r->items) {
+        free(cur);
+        rows_free(r);
+        return -1;
+    }
+    memcpy(cur, r->start, sizeof(int64_t) * (size_t)height);
+    for (int64_t g = 0; g < n; ++g)
+        if (P[g].cand)
+            for (int32_t j = P[g].crect[2]; j <= P[g].crect[3]; ++j) r->items[cur[j]++] = g;
+    free(cur);
+    return 0;
+}
+
+/* Candidates of pixel (i, j): the Gaussians whose candidate box contains it, sorted by
+ * (float32 depth, g). */
+static int64_t gather(const orc_proj *P, const rows_t *rows, int32_t i, int32_t j, cand_t *buf)
 {
     int64_t c = 0;
-    for (int64_t g = 0; g < n; ++g) {
+    if (j < 0 || j >= rows->height) return 0;
+    for (int64_t k = rows->start[j]; k < rows->start[j + 1]; ++k) {
+        const int64_t g = rows->items[k];
         const orc_proj *p = &P[g];
-        if (!p->visible) continue;
-        if (i < p->rect[0] - 1 || i > p->rect[1] + 1 || j < p->rect[2] - 1 || j > p->rect[3] + 1) continue;
+        if (i < p->crect[0] || i > p->crect[1]) continue;
         buf[c].g = g;
-        buf[c].z = p->z;
+        buf[c].z = (double)(float)p->z;
         ++c;
     }
     qsort(buf, (size_t)c, sizeof(cand_t), cand_cmp);
@@ -332,42 +415,38 @@ static int64_t composite(const orc_gaussians *G, const orc_proj *P, const orc_vi
     double errT = 0.0; /* first-order float32 relative error bound on T */
     int64_t nf = 0;
     int amb = 0;
-    float last_z32 = 0.0f;
-    double last_z64 = 0.0;
-    int64_t last_g = -1;
-    int have_last = 0;
     int64_t looked = 0;
+    double margin = INFINITY;
+    const double ff = S->flag_factor;
     for (int64_t k = 0; k < nc; ++k) {
         const orc_proj *p = &P[cand[k].g];
         const double dx = (double)i - p->u, dy = (double)j - p->v;
         const double e = p->Q[0] * dx * dx + 2.0 * p->Q[1] * dx * dy + p->Q[2] * dy * dy;
         const double gval = exp(-0.5 * e);
         const double a_pre = p->a * gval;
-        /* float32 error bound of alpha (relative): rounding of the quadratic form's terms
-         * and of exp, amplified by 4 for safety. */
+        /* First-order float32 error bound of alpha (relative): 8 roundings of the
+         * quadratic form's terms and 8 of the exponential and the products. */
         const double sabs = fabs(p->Q[0]) * dx * dx + 2.0 * fabs(p->Q[1] * dx * dy) + fabs(p->Q[2]) * dy * dy;
-        const double erra = 4.0 * (0.5 * 16.0 * ORC_EPS32 * sabs + 8.0 * ORC_EPS32);
+        const double erra = 8.0 * ORC_EPS32 * sabs + 8.0 * ORC_EPS32;
         ++looked;
-        if (fabs(a_pre - S->alpha_min) <= erra * S->alpha_min) amb |= 1;
+        const double r_min = fabs(a_pre - S->alpha_min) / (erra * S->alpha_min);
+        if (r_min < margin) margin = r_min;
+        if (r_min <= ff) amb |= 1;
         if (a_pre < S->alpha_min) continue;
         double alpha = a_pre;
         int clamped = 0;
-        if (fabs(a_pre - S->alpha_max) <= erra * S->alpha_max) amb |= 4;
+        const double r_max = fabs(a_pre - S->alpha_max) / (erra * S->alpha_max);
+        if (r_max < margin) margin = r_max;
+        if (r_max <= ff) amb |= 4;
         if (alpha > S->alpha_max) { alpha = S->alpha_max; clamped = 1; }
         const double Tn = T * (1.0 - alpha);
-        const double errTn = errT + (clamped ? 0.0 : erra * alpha / (1.0 - alpha)) + 4.0 * ORC_EPS32;
-        if (fabs(Tn - S->t_min) <= errTn * S->t_min) amb |= 2;
+        /* T picks up alpha's error through 1 - alpha, and one rounding per step. */
+        const double errTn = errT + (clamped ? 0.0 : erra * alpha / (1.0 - alpha)) + ORC_EPS32;
+        const double r_t = fabs(Tn - S->t_min) / (errTn * S->t_min);
+        if (r_t < margin) margin = r_t;
+        if (r_t <= ff) amb |= 2;
         if (Tn < S->t_min) break;
-        /* An implementation that orders by (float32 depth, index) reverses two
-         * consecutive contributing fragments exactly when their depths differ in double
-         * precision, round to the same float32 value and their indices are in the
-         * opposite order. */
-        const float z32 = (float)p->z;
-        if (have_last && z32 == last_z32 && p->z != last_z64 && cand[k].g < last_g) amb |= 8;
-        last_z32 = z32;
-        last_z64 = p->z;
-        last_g = cand[k].g;
-        have_last = 1;
+        if (near_f32_midpoint(p->z)) amb |= 8;
 
         const double w = alpha * T;
         const int64_t g = cand[k].g;
@@ -402,15 +481,16 @@ static int64_t composite(const orc_gaussians *G, const orc_proj *P, const orc_vi
         px->n_frag = (int32_t)nf;
         px->n_cand = (int32_t)looked;
         px->ambiguous = amb;
+        px->margin = margin;
         (void)A;
     }
     return nf;
 }
 
-static int64_t count_visible(const orc_proj *P, int64_t n)
+static int64_t count_cand(const orc_proj *P, int64_t n)
 {
     int64_t c = 0;
-    for (int64_t g = 0; g < n; ++g) c += P[g].visible ? 1 : 0;
+    for (int64_t g = 0; g < n; ++g) c += P[g].cand ? 1 : 0;
     return c;
 }
 
@@ -418,24 +498,27 @@ static int64_t count_visible(const orc_proj *P, int64_t n)
 int orc_render(const orc_gaussians *G, const orc_view *V, const orc_settings *S,
                const orc_proj *proj, int64_t npix, const int32_t *pix, orc_pixel *out)
 {
-    const int64_t nvis = count_visible(proj, G->n);
+    const int64_t ncand = count_cand(proj, G->n);
+    rows_t rows;
+    if (rows_build(proj, G->n, V->height, &rows)) return -1;
     int err = 0;
 #pragma omp parallel
     {
-        cand_t *buf = (cand_t *)malloc(sizeof(cand_t) * (size_t)(nvis > 0 ? nvis : 1));
+        cand_t *buf = (cand_t *)malloc(sizeof(cand_t) * (size_t)(ncand > 0 ? ncand : 1));
         if (!buf) {
 #pragma omp atomic write
             err = 1;
-        } else {
-#pragma omp for schedule(dynamic, 16)
-            for (int64_t p = 0; p < npix; ++p) {
-                const int32_t i = pix[2 * p], j = pix[2 * p + 1];
-                const int64_t nc = gather(proj, G->n, i, j, buf);
-                composite(G, proj, V, S, i, j, buf, nc, &out[p], NULL);
-            }
-            free(buf);
         }
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t p = 0; p < npix; ++p) {
+            if (!buf) continue;
+            const int32_t i = pix[2 * p], j = pix[2 * p + 1];
+            const int64_t nc = gather(proj, &rows, i, j, buf);
+            composite(G, proj, V, S, i, j, buf, nc, &out[p], NULL);
+        }
+        free(buf);
     }
+    rows_free(&rows);
     return err ? -1 : 0;
 }
 
@@ -449,16 +532,21 @@ int64_t orc_trace(const orc_gaussians *G, const orc_view *V, const orc_settings 
                   const orc_proj *proj, int64_t npix, const int32_t *pix, int64_t cap,
                   int64_t *offsets, int64_t *frag_g, int8_t *frag_clamped)
 {
-    const int64_t nvis = count_visible(proj, G->n);
+    const int64_t ncand = count_cand(proj, G->n);
     int64_t *counts = (int64_t *)calloc((size_t)npix + 1, sizeof(int64_t));
-    if (!counts) return 0;
+    rows_t rows;
+    if (!counts || rows_build(proj, G->n, V->height, &rows)) {
+        free(counts);
+        return 0;
+    }
+    const size_t nb = (size_t)(ncand > 0 ? ncand : 1);
 #pragma omp parallel
     {
-        cand_t *buf = (cand_t *)malloc(sizeof(cand_t) * (size_t)(nvis > 0 ? nvis : 1));
-        frag_t *fr = (frag_t *)malloc(sizeof(frag_t) * (size_t)(nvis > 0 ? nvis : 1));
+        cand_t *buf = (cand_t *)malloc(sizeof(cand_t) * nb);
+        frag_t *fr = (frag_t *)malloc(sizeof(frag_t) * nb);
 #pragma omp for schedule(dynamic, 16)
         for (int64_t p = 0; p < npix; ++p) {
-            const int64_t nc = gather(proj, G->n, pix[2 * p], pix[2 * p + 1], buf);
+            const int64_t nc = gather(proj, &rows, pix[2 * p], pix[2 * p + 1], buf);
             counts[p] = composite(G, proj, V, S, pix[2 * p], pix[2 * p + 1], buf, nc, NULL, fr);
         }
         free(buf);
@@ -471,14 +559,17 @@ int64_t orc_trace(const orc_gaussians *G, const orc_view *V, const orc_settings 
     }
     offsets[npix] = total;
     free(counts);
-    if (total > cap) return -total;
+    if (total > cap) {
+        rows_free(&rows);
+        return -total;
+    }
 #pragma omp parallel
     {
-        cand_t *buf = (cand_t *)malloc(sizeof(cand_t) * (size_t)(nvis > 0 ? nvis : 1));
-        frag_t *fr = (frag_t *)malloc(sizeof(frag_t) * (size_t)(nvis > 0 ? nvis : 1));
+        cand_t *buf = (cand_t *)malloc(sizeof(cand_t) * nb);
+        frag_t *fr = (frag_t *)malloc(sizeof(frag_t) * nb);
 #pragma omp for schedule(dynamic, 16)
         for (int64_t p = 0; p < npix; ++p) {
-            const int64_t nc = gather(proj, G->n, pix[2 * p], pix[2 * p + 1], buf);
+            const int64_t nc = gather(proj, &rows, pix[2 * p], pix[2 * p + 1], buf);
             const int64_t nf = composite(G, proj, V, S, pix[2 * p], pix[2 * p + 1], buf, nc, NULL, fr);
             for (int64_t k = 0; k < nf; ++k) {
                 frag_g[offsets[p] + k] = fr[k].g;
@@ -488,6 +579,7 @@ int64_t orc_trace(const orc_gaussians *G, const orc_view *V, const orc_settings 
         free(buf);
         free(fr);
     }
+    rows_free(&rows);
     return total;
 }
 
@@ -599,79 +691,140 @@ int orc_backward(const orc_gaussians *G, const orc_view *V, const orc_settings *
                  const double *g_pm, orc_grads *out)
 {
     const int64_t n = G->n;
-    const int64_t nvis = count_visible(proj, n);
-    acc2d_t *acc = (acc2d_t *)calloc((size_t)n, sizeof(acc2d_t));
-    cand_t *buf = (cand_t *)malloc(sizeof(cand_t) * (size_t)(nvis > 0 ? nvis : 1));
-    frag_t *fr = (frag_t *)malloc(sizeof(frag_t) * (size_t)(nvis > 0 ? nvis : 1));
-    if (!acc || !buf || !fr) {
-        free(acc); free(buf); free(fr);
+    const int64_t ncand = count_cand(proj, n);
+    rows_t rows;
+    if (rows_build(proj, n, V->height, &rows)) return -1;
+    /* The Gaussians some requested pixel has as a candidate get a slot in the per-thread
+     * accumulators (a crop of a large view touches few of them). */
+    int8_t *touched = (int8_t *)calloc((size_t)(n > 0 ? n : 1), 1);
+    int64_t *slot = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    if (!touched || !slot) {
+        free(touched); free(slot); rows_free(&rows);
         return -1;
     }
-
+#pragma omp parallel for schedule(dynamic, 64)
     for (int64_t px = 0; px < npix; ++px) {
         const int32_t i = pix[2 * px], j = pix[2 * px + 1];
-        double gC[3] = {g_rgb[3 * px], g_rgb[3 * px + 1], g_rgb[3 * px + 2]};
-        double gD = g_depth[px], gA = g_alpha[px];
-        double gX[3] = {g_pm[3 * px], g_pm[3 * px + 1], g_pm[3 * px + 2]};
-        if (gC[0] == 0.0 && gC[1] == 0.0 && gC[2] == 0.0 && gD == 0.0 && gA == 0.0 &&
-            gX[0] == 0.0 && gX[1] == 0.0 && gX[2] == 0.0)
-            continue;
-        if (pointmap_frame == 2) {
-            /* Eq. 5 pointmap is a function of D only. */
-            gD += gX[0] * ((double)i - V->cx) / V->fx + gX[1] * ((double)j - V->cy) / V->fy + gX[2];
-            gX[0] = gX[1] = gX[2] = 0.0;
+        if (j < 0 || j >= rows.height) continue;
+        for (int64_t k = rows.start[j]; k < rows.start[j + 1]; ++k) {
+            const int64_t g = rows.items[k];
+            if (i < proj[g].crect[0] || i > proj[g].crect[1] || touched[g]) continue;
+#pragma omp atomic write
+            touched[g] = 1;
         }
-        const int64_t nc = gather(proj, n, i, j, buf);
-        const int64_t nf = composite(G, proj, V, S, i, j, buf, nc, NULL, fr);
-        double Tfin = 1.0;
-        for (int64_t k = 0; k < nf; ++k) Tfin *= (1.0 - fr[k].alpha);
+    }
+    int64_t nslot = 0;
+    for (int64_t g = 0; g < n; ++g) slot[g] = touched[g] ? nslot++ : -1;
+    free(touched);
 
-        /* s_k = g . e_k with e_k the per-fragment value composited into each channel. */
-        double *sk = (double *)malloc(sizeof(double) * (size_t)(nf > 0 ? nf : 1));
-        for (int64_t k = 0; k < nf; ++k) {
-            const int64_t g = fr[k].g;
-            const orc_proj *p = &proj[g];
-            double s = 0.0;
-            for (int c = 0; c < 3; ++c) s += gC[c] * G->rgb[c * n + g];
-            s += gD * p->z + gA;
-            for (int c = 0; c < 3; ++c)
-                s += gX[c] * (pointmap_frame == 0 ? G->means[c * n + g] : p->m[c]);
-            sk[k] = s;
+    /* Pixels are split statically over the threads; each thread sums its pixels'
+     * image-plane gradients into its own accumulators, which are then added in thread
+     * order, so the result depends only on the thread count. */
+    int nthreads = 1;
+#ifdef _OPENMP
+    nthreads = omp_get_max_threads();
+#endif
+    acc2d_t *acc = (acc2d_t *)calloc((size_t)nthreads * (size_t)(nslot > 0 ? nslot : 1), sizeof(acc2d_t));
+    if (!acc) {
+        free(slot); rows_free(&rows);
+        return -1;
+    }
+    int err = 0;
+#pragma omp parallel num_threads(nthreads)
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        acc2d_t *mine = acc + (size_t)tid * (size_t)(nslot > 0 ? nslot : 1);
+        const size_t nb = (size_t)(ncand > 0 ? ncand : 1);
+        cand_t *buf = (cand_t *)malloc(sizeof(cand_t) * nb);
+        frag_t *fr = (frag_t *)malloc(sizeof(frag_t) * nb);
+        double *sk = (double *)malloc(sizeof(double) * nb);
+        if (!buf || !fr || !sk) {
+#pragma omp atomic write
+            err = 1;
         }
-        /* Suffix sums, accumulated back to front: after_k = sum_{j > k} w_j s_j. */
-        double after = 0.0;
-        const double bgterm = Tfin * (gC[0] * S->bg[0] + gC[1] * S->bg[1] + gC[2] * S->bg[2]);
-        for (int64_t k = nf - 1; k >= 0; --k) {
-            const frag_t *f = &fr[k];
-            const int64_t g = f->g;
-            const orc_proj *p = &proj[g];
-            const double w = f->alpha * f->T;
-            acc2d_t *ag = &acc[g];
-            for (int c = 0; c < 3; ++c) ag->gc[c] += w * gC[c];
-            ag->gz += w * gD;
-            if (pointmap_frame == 0)
-                for (int c = 0; c < 3; ++c) ag->gpw[c] += w * gX[c];
-            else
-                for (int c = 0; c < 3; ++c) ag->gpc[c] += w * gX[c];
-            const double dLda = f->T * sk[k] - (after + bgterm) / (1.0 - f->alpha);
-            if (!f->clamped) {
-                /* alpha = a exp(-e/2), e = Qxx dx^2 + 2 Qxy dx dy + Qyy dy^2. */
-                const double dx = f->dx, dy = f->dy;
-                const double dLde = dLda * (-0.5 * f->alpha);
-                ag->ga += dLda * f->alpha / p->a;
-                ag->gQ[0] += dLde * dx * dx;
-                ag->gQ[1] += dLde * 2.0 * dx * dy;
-                ag->gQ[2] += dLde * dy * dy;
-                /* de/du = -2 (Qxx dx + Qxy dy), de/dv = -2 (Qxy dx + Qyy dy). */
-                ag->gu += dLde * (-2.0) * (p->Q[0] * dx + p->Q[1] * dy);
-                ag->gv += dLde * (-2.0) * (p->Q[1] * dx + p->Q[2] * dy);
+#pragma omp for schedule(static)
+        for (int64_t px = 0; px < npix; ++px) {
+            if (!buf || !fr || !sk) continue;
+            const int32_t i = pix[2 * px], j = pix[2 * px + 1];
+            double gC[3] = {g_rgb[3 * px], g_rgb[3 * px + 1], g_rgb[3 * px + 2]};
+            double gD = g_depth[px], gA = g_alpha[px];
+            double gX[3] = {g_pm[3 * px], g_pm[3 * px + 1], g_pm[3 * px + 2]};
+            if (gC[0] == 0.0 && gC[1] == 0.0 && gC[2] == 0.0 && gD == 0.0 && gA == 0.0 &&
+                gX[0] == 0.0 && gX[1] == 0.0 && gX[2] == 0.0)
+                continue;
+            if (pointmap_frame == 2) {
+                /* Eq. 5 pointmap is a function of D only. */
+                gD += gX[0] * ((double)i - V->cx) / V->fx + gX[1] * ((double)j - V->cy) / V->fy + gX[2];
+                gX[0] = gX[1] = gX[2] = 0.0;
             }
-            after += w * sk[k];
+            const int64_t nc = gather(proj, &rows, i, j, buf);
+            const int64_t nf = composite(G, proj, V, S, i, j, buf, nc, NULL, fr);
+            double Tfin = 1.0;
+            for (int64_t k = 0; k < nf; ++k) Tfin *= (1.0 - fr[k].alpha);
+
+            /* s_k = g . e_k with e_k the per-fragment value composited into each channel. */
+            for (int64_t k = 0; k < nf; ++k) {
+                const int64_t g = fr[k].g;
+                const orc_proj *p = &proj[g];
+                double sv = 0.0;
+                for (int c = 0; c < 3; ++c) sv += gC[c] * G->rgb[c * n + g];
+                sv += gD * p->z + gA;
+                for (int c = 0; c < 3; ++c)
+                    sv += gX[c] * (pointmap_frame == 0 ? G->means[c * n + g] : p->m[c]);
+                sk[k] = sv;
+            }
+            /* Suffix sums, accumulated back to front: after_k = sum_{j > k} w_j s_j. */
+            double after = 0.0;
+            const double bgterm = Tfin * (gC[0] * S->bg[0] + gC[1] * S->bg[1] + gC[2] * S->bg[2]);
+            for (int64_t k = nf - 1; k >= 0; --k) {
+                const frag_t *f = &fr[k];
+                const int64_t g = f->g;
+                const orc_proj *p = &proj[g];
+                const double w = f->alpha * f->T;
+                acc2d_t *ag = &mine[slot[g]];
+                for (int c = 0; c < 3; ++c) ag->gc[c] += w * gC[c];
+                ag->gz += w * gD;
+                if (pointmap_frame == 0)
+                    for (int c = 0; c < 3; ++c) ag->gpw[c] += w * gX[c];
+                else
+                    for (int c = 0; c < 3; ++c) ag->gpc[c] += w * gX[c];
+                const double dLda = f->T * sk[k] - (after + bgterm) / (1.0 - f->alpha);
+                if (!f->clamped) {
+                    /* alpha = a exp(-e/2), e = Qxx dx^2 + 2 Qxy dx dy + Qyy dy^2. */
+                    const double dx = f->dx, dy = f->dy;
+                    const double dLde = dLda * (-0.5 * f->alpha);
+                    ag->ga += dLda * f->alpha / p->a;
+                    ag->gQ[0] += dLde * dx * dx;
+                    ag->gQ[1] += dLde * 2.0 * dx * dy;
+                    ag->gQ[2] += dLde * dy * dy;
+                    /* de/du = -2 (Qxx dx + Qxy dy), de/dv = -2 (Qxy dx + Qyy dy). */
+                    ag->gu += dLde * (-2.0) * (p->Q[0] * dx + p->Q[1] * dy);
+                    ag->gv += dLde * (-2.0) * (p->Q[1] * dx + p->Q[2] * dy);
+                }
+                after += w * sk[k];
+            }
         }
+        free(buf);
+        free(fr);
         free(sk);
     }
-    free(buf);
-    free(fr);
+    rows_free(&rows);
+    if (err) {
+        free(acc); free(slot);
+        return -1;
+    }
+    /* Thread partials, added in thread order. */
+    for (int t = 1; t < nthreads; ++t) {
+        const acc2d_t *src = acc + (size_t)t * (size_t)nslot;
+        for (int64_t k = 0; k < nslot; ++k) {
+            const double *a = (const double *)&src[k];
+            double *b = (double *)&acc[k];
+            for (size_t q = 0; q < sizeof(acc2d_t) / sizeof(double); ++q) b[q] += a[q];
+        }
+    }
 
     /* Image plane -> Gaussian parameters and pose. */
     double pose[6] = {0, 0, 0, 0, 0, 0};
@@ -681,8 +834,8 @@ int orc_backward(const orc_gaussians *G, const orc_view *V, const orc_settings *
         for (int c = 0; c < 3; ++c) W[3 * r + c] = T[4 * r + c];
     for (int64_t g = 0; g < n; ++g) {
         const orc_proj *p = &proj[g];
-        const acc2d_t *ag = &acc[g];
-        if (!p->visible) continue;
+        if (!p->visible || slot[g] < 0) continue;
+        const acc2d_t *ag = &acc[slot[g]];
         for (int c = 0; c < 3; ++c) out->rgb[c * n + g] += ag->gc[c];
         out->opacity_logit[g] += ag->ga * p->a * (1.0 - p->a);
 
@@ -790,91 +943,100 @@ int orc_backward(const orc_gaussians *G, const orc_view *V, const orc_settings *
     }
     for (int c = 0; c < 6; ++c) out->pose[c] += pose[c];
     free(acc);
+    free(slot);
     return 0;
 }
 
 /* ------------------------------------------------------------------------- */
-/* Tile-pair list, brute force.                                               */
+/* Tile lists of the supports (the tile-based rasterization of Sec. 3.1).      */
 
-/* Minimum over integer pixel columns i in [ia, ib] and real y in [ya, yb] of
- * f = Qxx dx^2 + 2 Qxy dx dy + Qyy dy^2 with dx = i - u, dy = y - v: for each column the
- * parabola in y is minimised at its vertex clamped to the interval. */
-static double quad_min_columns(const double Q[3], double u, double v, int32_t ia, int32_t ib, double ya, double yb)
-{
-    double best = INFINITY;
-    for (int32_t i = ia; i <= ib; ++i) {
-        const double dx = (double)i - u;
-        double dy = -Q[1] * dx / Q[2];
-        if (dy < ya - v) dy = ya - v;
-        if (dy > yb - v) dy = yb - v;
-        const double f = Q[0] * dx * dx + 2.0 * Q[1] * dx * dy + Q[2] * dy * dy;
-        if (f < best) best = f;
-    }
-    return best;
-}
-
-/* For tile size B, list every (tile, Gaussian) pair whose support ellipse
- * {d : d^T Q d <= 2 ln(a / alpha_min) (1 + margin)} contains a point (i, y) with i an
- * integer pixel column of the tile and y between the tile's first and last pixel rows,
- * columns and rows clipped to the Gaussian's support pixel box; ordered by (tile, z,
- * Gaussian index).  Every pixel centre of the ellipse lies in a listed tile.  Tiles are numbered row-major, tiles_x = ceil(W / B).  near[g] is set
- * when some tile's membership is decided within a relative tol of the support level.
- * Returns the number of pairs or -(needed) if cap is short. */
-int64_t orc_tile_pairs(const orc_proj *P, int64_t n, int32_t width, int32_t height, int32_t B,
-                       double alpha_min, double margin, double tol, int64_t cap, int32_t *tile_out,
-                       int64_t *g_out, int8_t *near)
+/* Two definitions, both from the support of O7 alone, for tile size B (tiles numbered
+ * row-major, tiles_x = ceil(W / B)):
+ *   rect:  Gaussian g is in tile t when t holds a pixel of g's support box;
+ *   exact: g is in tile t when t holds a pixel centre (i, j) of the view at which
+ *          e = d^T Q d <= q = 2 ln(a / alpha_min), i.e. where the Gaussian's alpha before
+ *          the clamp reaches alpha_min.
+ * Every pixel centre with e <= q lies in the support box, so exact is a subset of rect,
+ * and a fragment the per-pixel compositing keeps always has its Gaussian in the exact
+ * list of its pixel's tile.  Writes the rect pairs ordered by (tile, float32 depth,
+ * index), the compositing order, and per
+ * pair ratio = (min over the tile's pixels of the box of e) / q, so that the pair is in
+ * the exact set iff ratio <= 1.  Returns the number of pairs, or -(needed) if cap is
+ * short. */
+int64_t orc_tile_sets(const orc_proj *P, int64_t n, int32_t width, int32_t height, int32_t B,
+                      double alpha_min, int64_t cap, int32_t *tile_out, int64_t *g_out, double *ratio_out)
 {
     const int32_t tx = (width + B - 1) / B, ty = (height + B - 1) / B;
     const int64_t ntiles = (int64_t)tx * ty;
-    int64_t total = 0;
-    /* Pass 1 counts, pass 2 fills the buckets. */
     int64_t *cnt = (int64_t *)calloc((size_t)ntiles + 1, sizeof(int64_t));
-    for (int pass = 0; pass < 2; ++pass) {
-        int64_t *cur = NULL;
-        cand_t *tmp = NULL;
-        if (pass == 1) {
-            for (int64_t t = 0; t < ntiles; ++t) cnt[t + 1] += cnt[t];
-            total = cnt[ntiles];
-            if (total > cap) { free(cnt); return -total; }
-            cur = (int64_t *)malloc(sizeof(int64_t) * (size_t)(ntiles > 0 ? ntiles : 1));
-            memcpy(cur, cnt, sizeof(int64_t) * (size_t)ntiles);
-            tmp = (cand_t *)malloc(sizeof(cand_t) * (size_t)(total > 0 ? total : 1));
-        }
-        for (int64_t g = 0; g < n; ++g) {
-            const orc_proj *p = &P[g];
-            if (pass == 0 && near) near[g] = 0;
-            if (!p->visible) continue;
-            const double q = 2.0 * log(p->a / alpha_min) * (1.0 + margin);
-            for (int32_t y = p->rect[2] / B; y <= p->rect[3] / B; ++y)
-                for (int32_t x = p->rect[0] / B; x <= p->rect[1] / B; ++x) {
-                    const int32_t ia = x * B > p->rect[0] ? x * B : p->rect[0];
-                    const int32_t ib = x * B + B - 1 < p->rect[1] ? x * B + B - 1 : p->rect[1];
-                    const double ya = fmax(y * B, p->rect[2]), yb = fmin(y * B + B - 1, p->rect[3]);
-                    const double m = quad_min_columns(p->Q, p->u, p->v, ia, ib, ya, yb);
-                    if (pass == 0 && near && fabs(m - q) <= tol * q) near[g] = 1;
-                    if (!(m <= q)) continue;
-                    const int64_t t = (int64_t)y * tx + x;
-                    if (pass == 0) {
-                        cnt[t + 1]++;
-                    } else {
-                        tmp[cur[t]].g = g;
-                        tmp[cur[t]].z = p->z;
-                        cur[t]++;
+    if (!cnt) return 0;
+    for (int64_t g = 0; g < n; ++g) {
+        const orc_proj *p = &P[g];
+        if (!p->visible) continue;
+        for (int32_t y = p->rect[2] / B; y <= p->rect[3] / B; ++y)
+            for (int32_t x = p->rect[0] / B; x <= p->rect[1] / B; ++x) cnt[(int64_t)y * tx + x + 1]++;
+    }
+    for (int64_t t = 0; t < ntiles; ++t) cnt[t + 1] += cnt[t];
+    const int64_t total = cnt[ntiles];
+    if (total > cap) {
+        free(cnt);
+        return -total;
+    }
+    typedef struct {
+        int64_t g;
+        double z, ratio;
+    } entry_t;
+    entry_t *tmp = (entry_t *)malloc(sizeof(entry_t) * (size_t)(total > 0 ? total : 1));
+    int64_t *cur = (int64_t *)malloc(sizeof(int64_t) * (size_t)(ntiles > 0 ? ntiles : 1));
+    if (!tmp || !cur) {
+        free(tmp); free(cur); free(cnt);
+        return 0;
+    }
+    memcpy(cur, cnt, sizeof(int64_t) * (size_t)ntiles);
+    for (int64_t g = 0; g < n; ++g) {
+        const orc_proj *p = &P[g];
+        if (!p->visible) continue;
+        const double q = 2.0 * log(p->a / alpha_min);
+        for (int32_t y = p->rect[2] / B; y <= p->rect[3] / B; ++y)
+            for (int32_t x = p->rect[0] / B; x <= p->rect[1] / B; ++x) {
+                /* Smallest e over the pixel centres of this tile inside the box. */
+                double emin = INFINITY;
+                const int32_t ia = x * B > p->rect[0] ? x * B : p->rect[0];
+                const int32_t ib = x * B + B - 1 < p->rect[1] ? x * B + B - 1 : p->rect[1];
+                const int32_t ja = y * B > p->rect[2] ? y * B : p->rect[2];
+                const int32_t jb = y * B + B - 1 < p->rect[3] ? y * B + B - 1 : p->rect[3];
+                for (int32_t j = ja; j <= jb; ++j)
+                    for (int32_t i = ia; i <= ib; ++i) {
+                        const double dx = (double)i - p->u, dy = (double)j - p->v;
+                        const double e = p->Q[0] * dx * dx + 2.0 * p->Q[1] * dx * dy + p->Q[2] * dy * dy;
+                        if (e < emin) emin = e;
                     }
-                }
-        }
-        if (pass == 1) {
-            for (int64_t t = 0; t < ntiles; ++t) {
-                qsort(tmp + cnt[t], (size_t)(cnt[t + 1] - cnt[t]), sizeof(cand_t), cand_cmp);
-                for (int64_t k = cnt[t]; k < cnt[t + 1]; ++k) {
-                    tile_out[k] = (int32_t)t;
-                    g_out[k] = tmp[k].g;
-                }
+                const int64_t t = (int64_t)y * tx + x;
+                tmp[cur[t]].g = g;
+                tmp[cur[t]].z = (double)(float)p->z;
+                tmp[cur[t]].ratio = emin / q;
+                cur[t]++;
             }
-            free(cur);
-            free(tmp);
+    }
+    for (int64_t t = 0; t < ntiles; ++t) {
+        /* Order of a tile's list: (float32 depth, index), by insertion (lists are short). */
+        for (int64_t k = cnt[t] + 1; k < cnt[t + 1]; ++k) {
+            const entry_t e = tmp[k];
+            int64_t m = k - 1;
+            while (m >= cnt[t] && (tmp[m].z > e.z || (tmp[m].z == e.z && tmp[m].g > e.g))) {
+                tmp[m + 1] = tmp[m];
+                --m;
+            }
+            tmp[m + 1] = e;
+        }
+        for (int64_t k = cnt[t]; k < cnt[t + 1]; ++k) {
+            tile_out[k] = (int32_t)t;
+            g_out[k] = tmp[k].g;
+            ratio_out[k] = tmp[k].ratio;
         }
     }
+    free(tmp);
+    free(cur);
     free(cnt);
     return total;
 }
@@ -919,5 +1081,15 @@ int orc_num_threads(void)
     return omp_get_max_threads();
 #else
     return 1;
+#endif
+}
+
+/* Threads of the following parallel regions (the CPU baseline's one-thread run). */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
 #endif
 }

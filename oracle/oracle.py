@@ -4,7 +4,7 @@ TEST INFRASTRUCTURE ONLY: imported by ``tests/``, the smoke check and the benchm
 CPU-baseline leg.  The product path never imports it.
 
 The per-pixel renderer, its analytic backward, the frozen-decision replay used for
-finite differences and the brute-force tile lists live in ``gs_oracle.c`` (plain C,
+finite differences and the tile lists of the supports live in ``gs_oracle.c`` (plain C,
 double precision, OpenMP over pixels).  This module marshals arrays for it and adds
 the two oracle steps that are short enough to state directly in numpy:
 
@@ -59,12 +59,13 @@ class _Settings(ctypes.Structure):
     _fields_ = [("near_z", ctypes.c_double), ("alpha_min", ctypes.c_double),
                 ("alpha_max", ctypes.c_double), ("t_min", ctypes.c_double),
                 ("eps2d", ctypes.c_double), ("jac_clamp", ctypes.c_double),
-                ("bg", ctypes.c_double * 3)]
+                ("bg", ctypes.c_double * 3), ("flag_factor", ctypes.c_double)]
 
 
 class _Proj(ctypes.Structure):
     _fields_ = [("visible", ctypes.c_int32), ("clamp_x", ctypes.c_int32), ("clamp_y", ctypes.c_int32),
-                ("rect", ctypes.c_int32 * 4), ("m", ctypes.c_double * 3), ("u", ctypes.c_double),
+                ("rect", ctypes.c_int32 * 4), ("cand", ctypes.c_int32), ("crect", ctypes.c_int32 * 4),
+                ("m", ctypes.c_double * 3), ("u", ctypes.c_double),
                 ("v", ctypes.c_double), ("z", ctypes.c_double), ("a", ctypes.c_double),
                 ("s", ctypes.c_double * 3), ("qn", ctypes.c_double * 4), ("qnorm", ctypes.c_double),
                 ("Rq", ctypes.c_double * 9), ("Sig", ctypes.c_double * 9), ("Sigc", ctypes.c_double * 9),
@@ -77,7 +78,7 @@ class _Pixel(ctypes.Structure):
                 ("pm_world", ctypes.c_double * 3), ("pm_cam", ctypes.c_double * 3),
                 ("pm_eq5", ctypes.c_double * 3), ("T_final", ctypes.c_double),
                 ("n_frag", ctypes.c_int32), ("n_cand", ctypes.c_int32),
-                ("ambiguous", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("ambiguous", ctypes.c_int32), ("pad", ctypes.c_int32), ("margin", ctypes.c_double)]
 
 
 class _Grads(ctypes.Structure):
@@ -110,12 +111,14 @@ def lib():
                                    ctypes.POINTER(_Settings), ctypes.POINTER(_Proj), ctypes.c_int32,
                                    ctypes.c_int64, i32p, f64p, f64p, f64p, f64p,
                                    ctypes.POINTER(_Grads)]
-        L.orc_tile_pairs.argtypes = [ctypes.POINTER(_Proj), ctypes.c_int64, ctypes.c_int32,
-                                     ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
-                                     ctypes.c_double, ctypes.c_int64, i32p, i64p, i8p]
-        L.orc_tile_pairs.restype = ctypes.c_int64
+        L.orc_tile_sets.argtypes = [ctypes.POINTER(_Proj), ctypes.c_int64, ctypes.c_int32,
+                                    ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_int64, i32p,
+                                    i64p, f64p]
+        L.orc_tile_sets.restype = ctypes.c_int64
         L.orc_se3_exp_left.argtypes = [f64p, f64p, f64p]
         L.orc_num_threads.restype = ctypes.c_int
+        L.orc_set_num_threads.argtypes = [ctypes.c_int]
+        L.orc_set_num_threads.restype = None
         _lib = L
     return _lib
 
@@ -134,11 +137,15 @@ class Settings:
     eps2d: float = 0.3
     jac_clamp: float = 1.3
     bg: tuple = (0.0, 0.0, 0.0)
+    # A pixel is flagged as ambiguous when one of its alpha_min, alpha_max or t_min
+    # decisions lies within flag_factor first-order float32 error bounds of its threshold.
+    flag_factor: float = 1.0
 
     def c(self):
         f = lambda x: float(np.float32(x))  # noqa: E731
         return _Settings(f(self.near_z), f(self.alpha_min), f(self.alpha_max), f(self.t_min),
-                         f(self.eps2d), f(self.jac_clamp), (ctypes.c_double * 3)(*[f(b) for b in self.bg]))
+                         f(self.eps2d), f(self.jac_clamp), (ctypes.c_double * 3)(*[f(b) for b in self.bg]),
+                         float(self.flag_factor))
 
 
 class Params:
@@ -211,7 +218,7 @@ def render(params: Params, view, settings: Settings, pixels, proj=None):
         "pm_world": np.array(a["pm_world"]), "pm_cam": np.array(a["pm_cam"]),
         "pm_eq5": np.array(a["pm_eq5"]), "T_final": np.array(a["T_final"]),
         "n_frag": np.array(a["n_frag"]), "n_cand": np.array(a["n_cand"]),
-        "ambiguous": np.array(a["ambiguous"]),
+        "ambiguous": np.array(a["ambiguous"]), "margin": np.array(a["margin"]),
     }
 
 
@@ -224,7 +231,7 @@ def render_image(params: Params, cam, T12, settings: Settings):
     img = {}
     for k in ("rgb", "pm_world", "pm_cam", "pm_eq5"):
         img[k] = r[k].reshape(H, W, 3).transpose(2, 0, 1).copy()
-    for k in ("depth", "alpha", "T_final", "n_frag", "n_cand", "ambiguous"):
+    for k in ("depth", "alpha", "T_final", "n_frag", "n_cand", "ambiguous", "margin"):
         img[k] = r[k].reshape(H, W)
     return img
 
@@ -303,28 +310,24 @@ def backward(params: Params, view, settings: Settings, pixels, up, pointmap_fram
     return g
 
 
-# Relative widening of the support level used for tile membership (kept conservative so
-# that float32 evaluation never finds a fragment outside its listed tiles).
-SUPPORT_MARGIN = 1e-6
-
-
-def tile_pairs(proj, n, width, height, B, settings=None, tol=1e-5):
-    """Brute-force (tile, Gaussian) pairs ordered by (tile, z, index): a Gaussian is listed
-    in a tile when its support ellipse contains a point on one of the tile's integer pixel
-    columns between the tile's first and last pixel rows (clipped to its support box).  Returns (tiles, gaussians, near) where near[g] marks a
-    membership decided within relative ``tol`` of the support level."""
+def tile_sets(proj, n, width, height, B, settings=None):
+    """Tile lists of the supports for tile size B (the tile-based rasterization of
+    Sec. 3.1), ordered by (tile, z, index).  Returns (tiles, gaussians, ratio) for the
+    *rect* pairs (the tile holds a pixel of the Gaussian's support box); the pair is also
+    in the *exact* set (the tile holds a pixel centre where the Gaussian's alpha reaches
+    alpha_min) iff ratio <= 1, ratio being the smallest Mahalanobis term over the tile's
+    pixels of the box divided by the support level 2 ln(a / alpha_min)."""
     s = settings or Settings()
     amin = float(np.float32(s.alpha_min))
     L = lib()
-    near = np.zeros(max(n, 1), dtype=np.int8)
-    need = L.orc_tile_pairs(proj, n, width, height, B, amin, SUPPORT_MARGIN, tol, 0, None, None, _p(near, i8p))
+    need = L.orc_tile_sets(proj, n, width, height, B, amin, 0, None, None, None)
     total = -need if need < 0 else need
     tiles = np.zeros(max(total, 1), dtype=np.int32)
     gs = np.zeros(max(total, 1), dtype=np.int64)
-    got = L.orc_tile_pairs(proj, n, width, height, B, amin, SUPPORT_MARGIN, tol, total, _p(tiles, i32p),
-                           _p(gs, i64p), _p(near, i8p))
+    ratio = np.zeros(max(total, 1), dtype=np.float64)
+    got = L.orc_tile_sets(proj, n, width, height, B, amin, total, _p(tiles, i32p), _p(gs, i64p), _p(ratio))
     assert got == total
-    return tiles[:total], gs[:total], near[:n].astype(bool)
+    return tiles[:total], gs[:total], ratio[:total]
 
 
 def se3_exp_left(xi, T12):
@@ -337,6 +340,11 @@ def se3_exp_left(xi, T12):
 
 def num_threads():
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n: int):
+    """Threads the oracle's parallel loops use from now on (OpenMP)."""
+    lib().orc_set_num_threads(int(n))
 
 
 # ---------------------------------------------------------------------------

@@ -63,11 +63,11 @@ def check_grad(name, got, ref, frac=0.9999):
     return rel
 
 
-def oracle_view_images(O, params_o, cam, T12, S, pixels=None):
+def oracle_view_images(O, params_o, cam, T12, S, pixels=None, proj=None):
     """Oracle render of a full view or of the given pixels (returns per-pixel dict)."""
     view = O.make_view(cam, T12)
     pix = O.full_pixels(cam) if pixels is None else pixels
-    return O.render(params_o, view, S, pix), pix
+    return O.render(params_o, view, S, pix, proj=proj), pix
 
 
 def gpu_pixels(packed, cam, off, channels, pix):
@@ -89,6 +89,14 @@ def crops(cam, size, n, seed):
         y0 = int(rng.integers(0, max(1, cam.height - size)))
         out.append((x0, y0, min(size, cam.width - x0), min(size, cam.height - y0)))
     return out
+
+
+def box_pixels(O, boxes):
+    """The pixels [npix][2] (i, j) covered by a list of crop boxes, each once (boxes may
+    overlap, and a pixel listed twice would count twice in the oracle's sums)."""
+    pix = np.concatenate([O.crop_pixels(*b) for b in boxes])
+    pix = np.unique(pix[:, [1, 0]], axis=0)[:, [1, 0]]
+    return np.ascontiguousarray(pix, dtype=np.int32)
 
 
 def crop_mask(cam, boxes):

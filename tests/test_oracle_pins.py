@@ -452,53 +452,91 @@ def test_unfrozen_fd_on_margin_scene(oracle):
 
 
 # ---------------------------------------------------------------------------
-# P9 (oracle side): every contributing fragment's tile lists its Gaussian, and each
-# listed tile really meets the support ellipse (checked by dense sampling).
+# P9: tile lists of the supports, pinned in both directions.
 
-def test_p9_tile_lists_cover_every_fragment(oracle):
+def _tiles_of_pixels(mask, B):
+    """Row-major tile ids of the tiles holding a True pixel of mask [H][W]."""
+    H, W = mask.shape
+    tx = -(-W // B)
+    jj, ii = np.nonzero(mask)
+    return set(((jj // B) * tx + ii // B).tolist())
+
+
+def test_p9_exact_tiles_are_where_a_lone_gaussian_composites(oracle):
+    """Exact set, both ways: a Gaussian rendered alone composites every pixel where its alpha
+    reaches alpha_min (one fragment never reaches the transmittance floor), so the tiles
+    holding a composited pixel of that render are exactly the Gaussian's exact tiles."""
+    O = oracle
+    sc = scenes.make_scene("c0")
+    S = O.Settings()
+    p = O.Params.from_scene(sc)
+    cam = sc.cams[0]
+    view = O.make_view(cam, sc.T_cw[0])
+    pa = O.proj_numpy(O.project(p, view, S))
+    for B in (8, 16):
+        tiles, gs, ratio = O.tile_sets(O.project(p, view, S), p.n, cam.width, cam.height, B)
+        rng = np.random.default_rng(B)
+        for g in rng.choice(np.flatnonzero(pa["visible"] == 1), 60, replace=False):
+            alone = O.Params(*[a[..., g:g + 1] for a in p.flat()])
+            img = O.render_image(alone, cam, sc.T_cw[0], S)
+            sel = gs == g
+            exact = set(tiles[sel][ratio[sel] <= 1.0].tolist())
+            grazing = set(tiles[sel][np.abs(ratio[sel] - 1.0) <= 1e-9].tolist())
+            rendered = _tiles_of_pixels(img["n_frag"] > 0, B)
+            assert exact ^ rendered <= grazing, (B, g, sorted(exact ^ rendered))
+
+
+def test_p9_support_box_is_the_ellipse_bounding_box(oracle):
+    """Rect set: the support box is the bounding box of the ellipse d^T Q d <= 2 ln(a/alpha_min)
+    (its extreme points taken from an eigen-decomposition of the conic Q), clipped to the
+    image, and a Gaussian is listed in exactly the tiles that box overlaps."""
+    O = oracle
+    sc = scenes.make_scene("c0")
+    S = O.Settings()
+    p = O.Params.from_scene(sc)
+    cam = sc.cams[0]
+    proj = O.project(p, O.make_view(cam, sc.T_cw[0]), S)
+    pa = O.proj_numpy(proj)
+    amin = float(np.float32(1.0 / 255.0))
+    B = 16
+    tiles, gs, ratio = O.tile_sets(proj, p.n, cam.width, cam.height, B)
+    tx = -(-cam.width // B)
+    for g in np.flatnonzero(pa["visible"] == 1)[::7]:
+        pr = pa[g]
+        q = 2.0 * math.log(pr["a"] / amin)
+        Q = np.array([[pr["Q"][0], pr["Q"][1]], [pr["Q"][1], pr["Q"][2]]])
+        lam, U = np.linalg.eigh(Q)
+        M = math.sqrt(q) * U / np.sqrt(lam)  # boundary points: M (cos t, sin t)
+        rx, ry = np.hypot(M[0, 0], M[0, 1]), np.hypot(M[1, 0], M[1, 1])
+        assert abs(pr["rx"] - rx) <= 1e-9 * rx and abs(pr["ry"] - ry) <= 1e-9 * ry
+        box = [max(0, math.ceil(pr["u"] - rx)), min(cam.width - 1, math.floor(pr["u"] + rx)),
+               max(0, math.ceil(pr["v"] - ry)), min(cam.height - 1, math.floor(pr["v"] + ry))]
+        assert list(pr["rect"]) == box, g
+        want = {ty * tx + x for ty in range(box[2] // B, box[3] // B + 1) for x in range(box[0] // B, box[1] // B + 1)}
+        assert set(tiles[gs == g].tolist()) == want
+    # Exact is a subset of rect by construction of the ratio; both lists are ordered by
+    # (tile, float32 depth, index), the compositing order.
+    z = pa["z"][gs].astype(np.float32)
+    np.testing.assert_array_equal(np.lexsort((gs, z, tiles)), np.arange(len(tiles)))
+
+
+def test_p9_every_fragment_is_in_its_tiles_exact_list(oracle):
     O = oracle
     sc = scenes.make_scene("c0")
     S = O.Settings()
     p = O.Params.from_scene(sc)
     view = O.make_view(sc.cams[0], sc.T_cw[0])
-    proj = O.project(p, view, S)
     B = 16
-    tiles, gs, _ = O.tile_pairs(proj, p.n, sc.cams[0].width, sc.cams[0].height, B)
-    pairs = set(zip(tiles.tolist(), gs.tolist()))
+    tiles, gs, ratio = O.tile_sets(O.project(p, view, S), p.n, sc.cams[0].width, sc.cams[0].height, B)
+    exact = set(zip(tiles[ratio <= 1.0].tolist(), gs[ratio <= 1.0].tolist()))
     pix = O.full_pixels(sc.cams[0])
     tr = O.trace(p, view, S, pix)
     tx = -(-sc.cams[0].width // B)
-    for pi in range(0, pix.shape[0], 7):
+    for pi in range(pix.shape[0]):
         i, j = pix[pi]
         t = (j // B) * tx + i // B
         for k in range(tr.offsets[pi], tr.offsets[pi + 1]):
-            assert (t, int(tr.frag_g[k])) in pairs
-    # Membership: the ellipse holds a point on one of the tile's pixel columns between its
-    # first and last pixel rows; compare with dense sampling along the columns.
-    pa = O.proj_numpy(proj)
-    amin = float(np.float32(1.0 / 255.0))
-    rng = np.random.default_rng(2)
-    listed = set(zip(tiles.tolist(), gs.tolist()))
-    for g in rng.choice(np.flatnonzero(pa["visible"] == 1), 60, replace=False):
-        pr = pa[g]
-        q = 2.0 * np.log(pr["a"] / amin)
-        Q = pr["Q"]
-        for ty in range(pr["rect"][2] // B, pr["rect"][3] // B + 1):
-            for tx_ in range(pr["rect"][0] // B, pr["rect"][1] // B + 1):
-                xs = np.arange(max(tx_ * B, pr["rect"][0]), min(tx_ * B + B - 1, pr["rect"][1]) + 1) - pr["u"]
-                ys = np.linspace(max(ty * B, pr["rect"][2]), min(ty * B + B - 1, pr["rect"][3]), 161) - pr["v"]
-                X, Y = np.meshgrid(xs, ys)
-                m = (Q[0] * X * X + 2 * Q[1] * X * Y + Q[2] * Y * Y).min()
-                t = ty * tx + tx_
-                if m < q * 0.999:
-                    assert (t, int(g)) in listed
-                elif m > q * 1.01:
-                    # Sampling overestimates the minimum by at most the grid step's effect.
-                    pass
-    # Ordered by (tile, depth, index).
-    z = O.proj_numpy(proj)["z"][gs]
-    key = np.lexsort((gs, z, tiles))
-    np.testing.assert_array_equal(key, np.arange(len(tiles)))
+            assert (t, int(tr.frag_g[k])) in exact
 
 
 # ---------------------------------------------------------------------------
