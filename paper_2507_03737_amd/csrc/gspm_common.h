@@ -37,10 +37,15 @@ struct RasterSettings {
 
 // Projected record of one (Gaussian, view) pair: 64 bytes, 4 x float4.
 //   r0 = (u_hi, v_hi, u_lo, v_lo)     mean2D as a float32 pair (u = u_hi + u_lo)
-//   r1 = (A, B, C, opacity)           exponent base 2: alpha = opacity * 2^(A dx^2 + B dx dy + C dy^2)
+//   r1 = (a, b, c, opacity)           factored conic, base 2:
+//                                     alpha = opacity * 2^-((a dx + b dy)^2 + (c dy)^2)
 //   r2 = (c_r, c_g, c_b, z)           colour and camera depth
 //   r3 = (p_x, p_y, p_z, 0)           composited point (world centre or camera centre)
-// A = -0.5 log2(e) Q_xx, B = -log2(e) Q_xy, C = -0.5 log2(e) Q_yy for the conic Q.
+// With k = log2(e) / 2, k Q = L^T L for L = [[a, b], [0, c]] (the Cholesky factor of the
+// scaled conic Q).  The exponent is a sum of two squares: an elongated footprint (a near
+// Gaussian seen at a grazing angle) would lose ~1e-4 of alpha to cancellation between the
+// terms of the expanded form A dx^2 + B dx dy + C dy^2 in float32, the factored form
+// keeps it near float32 rounding.
 constexpr int kRecFloats = 16;
 
 // Per-record image-plane gradient accumulator (16 floats, 13 used).  With
@@ -325,9 +330,11 @@ __device__ inline bool record_footprint(const float4 r0, const float4 r1, float 
     if (!(r1.w >= alpha_min)) return false;
     f.u = (double)r0.x + (double)r0.z;
     f.v = (double)r0.y + (double)r0.w;
-    f.qxx = -2.0 * kLn2d * (double)r1.x;
-    f.qxy = -kLn2d * (double)r1.y;
-    f.qyy = -2.0 * kLn2d * (double)r1.z;
+    // Q = L^T L / k with 1 / k = 2 ln 2 (products of two floats are exact in double).
+    const double a = r1.x, b = r1.y, c = r1.z;
+    f.qxx = 2.0 * kLn2d * (a * a);
+    f.qxy = 2.0 * kLn2d * (a * b);
+    f.qyy = 2.0 * kLn2d * (b * b + c * c);
     const double det = f.qxx * f.qyy - f.qxy * f.qxy;
     if (!(det > 0.0) || !(f.qxx > 0.0)) return false;
     f.q = 2.0 * log((double)r1.w / (double)alpha_min) * (1.0 + kSupportMargin);

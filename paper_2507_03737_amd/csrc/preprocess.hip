@@ -145,8 +145,13 @@ k_preprocess(gspm_gaussians G, ViewTable vt, const float *__restrict__ T_cw, Ras
                 const float uhi = (float)P.u, vhi = (float)P.v;
                 const float ulo = (float)(P.u - (double)uhi), vlo = (float)(P.v - (double)vhi);
                 const float4 r0 = make_float4(uhi, vhi, ulo, vlo);
-                const float4 r1 = make_float4((float)(-0.5 * kLog2e * P.Q[0]), (float)(-kLog2e * P.Q[1]),
-                                              (float)(-0.5 * kLog2e * P.Q[2]), (float)P.a);
+                // Factored conic: k Q = L^T L, L = [[a, b], [0, c]], k = log2(e) / 2; c^2 is
+                // k det(Q) / Q_xx, which stays positive (det > 0) without cancellation.
+                const double kq = 0.5 * kLog2e;
+                const double fa = sqrt(kq * P.Q[0]);
+                const double fb = kq * P.Q[1] / fa;
+                const double fc = sqrt(kq * (P.Q[0] * P.Q[2] - P.Q[1] * P.Q[1]) / P.Q[0]);
+                const float4 r1 = make_float4((float)fa, (float)fb, (float)fc, (float)P.a);
                 float4 *o = rec + 4 * r;
                 o[0] = r0;
                 o[1] = r1;

@@ -70,7 +70,8 @@ __device__ inline TilePos tile_pos(const ViewTable &vt, const uint32_t *order) {
 // Stage record r into LDS slot q, in tile-local pixel coordinates, with the exponent
 // threshold e_min = log2(alpha_min / opacity): alpha >= alpha_min exactly when the
 // base-2 exponent e >= e_min, so rejected pixels never evaluate the exponential.
-//   s0 = (u, v, A, B), s1 = (C, e_min, opacity, record index), s2 = (colour, z), s3 = point
+//   s0 = (u, v, a, b), s1 = (c, e_min, opacity, record index), s2 = (colour, z), s3 = point
+// with (a, b, c) the factored conic of the record.
 // The acceptance test reads s0 and s1 only.
 __device__ inline void stage(const float4 *__restrict__ rec, uint32_t r, float x0, float y0, float alpha_min,
                              float4 *s0, float4 *s1, float4 *s2, float4 *s3, int q) {
@@ -84,10 +85,11 @@ __device__ inline void stage(const float4 *__restrict__ rec, uint32_t r, float x
     s3[q] = d;
 }
 
-// Base-2 exponent of a Gaussian at a pixel, from the per-column terms A dx^2 and B dx:
-// e = A dx^2 + B dx dy + C dy^2.
-__device__ inline float quad_e(float Adx2, float Bdx, float C, float dy) {
-    return fmaf(fmaf(C, dy, Bdx), dy, Adx2);
+// Base-2 exponent of a Gaussian at a pixel offset (dx, dy) from its mean, from the
+// factored conic and the per-column term a dx: e = -((a dx + b dy)^2 + (c dy)^2).
+__device__ inline float quad_e(float adx, float b, float c, float dy) {
+    const float q1 = fmaf(b, dy, adx), q2 = c * dy;
+    return -fmaf(q1, q1, q2 * q2);
 }
 
 // Lane layout of a (TILE, PPT) workgroup: wave w owns a WW x WH pixel rectangle.
@@ -130,7 +132,9 @@ __device__ inline float edge_max(float P, float Q, float R, float d, float lo, f
 // of the sum of the terms' magnitudes), so the test never drops a record that a pixel
 // accepts; it may keep a few that none does.
 __device__ inline bool meets_rect(const float4 a, const float4 b, float x0, float x1, float y0, float y1) {
-    const float A = a.z, B = a.w, C = b.x;
+    // Expanded coefficients e = A dx^2 + B dx dy + C dy^2 of the factored conic (their
+    // rounding is far inside the margin below).
+    const float A = -a.z * a.z, B = -2.0f * a.z * a.w, C = -fmaf(a.w, a.w, b.x * b.x);
     const float ax = x0 - a.x, bx = x1 - a.x, ay = y0 - a.y, by = y1 - a.y;
     if (ax <= 0.f && bx >= 0.f && ay <= 0.f && by >= 0.f) return b.y <= 0x1p-10f;
     float m = fmaxf(edge_max(A, B, C, ax, ay, by), edge_max(A, B, C, bx, ay, by));
@@ -214,13 +218,13 @@ k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
                 // One 16-byte read now rather than a second, split read after the test.
                 asm volatile("" ::"v"(b.z), "v"(b.w));
                 const float dx = px - a.x;
-                const float Adx2 = a.z * dx * dx, Bdx = a.w * dx;
+                const float adx = a.z * dx;
                 float e[PPT];
                 bool ok[PPT];
                 uint64_t pass = 0ull;
 #pragma unroll
                 for (int k = 0; k < PPT; ++k) {
-                    e[k] = quad_e(Adx2, Bdx, b.x, py[k] - a.y) + bias[k];
+                    e[k] = quad_e(adx, a.w, b.x, py[k] - a.y) + bias[k];
                     ok[k] = e[k] >= b.y;
                     pass |= ballot(ok[k]);
                 }
@@ -553,13 +557,13 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
     // per-pixel recomputation and this wave's sums for it.
     auto walk_record = [&](const float4 &a, const float4 &b, const float4 &cc, const float4 &d, uint32_t rel) {
         const float dx = px - a.x;
-        const float Adx2 = a.z * dx * dx, Bdx = a.w * dx;
+        const float adx = a.z * dx;
         float e[PPT];
         bool valid[PPT];
         uint64_t any = 0ull;
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
-            e[k] = quad_e(Adx2, Bdx, b.x, py[k] - a.y);
+            e[k] = quad_e(adx, a.w, b.x, py[k] - a.y);
             // One comparison decides (its lane mask is the ballot as it stands).
             valid[k] = (rel < my_last[k] ? e[k] : -INFINITY) >= b.y;
             any |= ballot(valid[k]);

@@ -1,19 +1,30 @@
-"""Full-size parity in the benchmark's launch configurations: the c3 mapping window (1M
-Gaussians, 8 views of uneven size, 16x16 tiles, 1 pixel per lane) and the c4 window (3M
-Gaussians, 16 views of 1920x1080, 32x32 tiles, 2 pixels per lane), checked against the
-oracle on sampled crops of every view (forward) and with upstream gradients confined to
-those crops (backward to every parameter and every pose)."""
+"""Full-size parity in the benchmark's launch configurations.
+
+* c3, the mapping window (1M Gaussians, 8 views of uneven size, 16x16 tiles, 1 pixel per
+  lane): one 640x480 view compared on every pixel, with dense upstream gradients on all of
+  it, and 16 crops of 32x32 pixels on each of the other seven views;
+* c4, the large window (3M Gaussians, 16 views of 1920x1080, 32x32 tiles, 2 pixels per
+  lane): 8 crops of 32x32 pixels on every view.
+
+The forward is checked on those pixels, the backward to every parameter and every pose
+with upstream gradients on those pixels (zero elsewhere and on flagged pixels), and the
+fraction of pixels the oracle flags as ambiguous is asserted small on every view."""
 import numpy as np
 import pytest
 
 from paper_2507_03737_amd import scenes
 from tests import gpu_util as U
-from tests.test_gpu_parity import (_check_view_forward, _gpu_backward, _oracle_backward, _render_gpu,
-                                   _upstream)
+from tests.test_gpu_parity import (_check_view_forward, _gpu_backward, _oracle_backward, _oracle_settings,
+                                   _render_gpu, _upstream)
 
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
+
+# Largest fraction of the compared pixels the oracle may flag as ambiguous: over the
+# window, and on one view (a view's few crops can fall where flags cluster).
+MAX_FLAGGED = 0.01
+MAX_FLAGGED_VIEW = 0.02
 
 
 @pytest.fixture(scope="module")
@@ -25,25 +36,42 @@ def lib():
     return binding
 
 
-@pytest.mark.parametrize("name,tile,ppl,crop", [("c3", 16, 1, 16), ("c4", 32, 2, 8)])
-def test_full_window_on_crops(lib, oracle, name, tile, ppl, crop):
-    U.log(f"[gpu] {name} full size, tile {tile} ppl {ppl}, {crop}x{crop} crop per view")
+@pytest.mark.parametrize("name,tile,ppl,full_view,crops", [("c3", 16, 1, 7, 16), ("c4", 32, 2, None, 8)])
+def test_full_window(lib, oracle, name, tile, ppl, full_view, crops):
+    U.log(f"[gpu] {name} full size, tile {tile} ppl {ppl}: view {full_view} whole, {crops} crops of 32x32 elsewhere")
     O = oracle
     sc = scenes.make_scene(name)
     cfg = lib.RasterConfig(pointmap_frame=1, tile=tile, pixels_per_lane=ppl)
     rast, params, out, fs = _render_gpu(lib, sc, cfg)
-    pix_sets, oks = [], []
+    S = _oracle_settings(O, cfg)
+    po = O.Params.from_scene(sc)
+    pix_sets, oks, projs = [], [], []
+    keep = sc.n * len(sc.cams) <= 10_000_000  # projections of c4 (~1.6 GB a view) are made again below
+    n_flag = n_cmp = 0
     for v, cam in enumerate(sc.cams):
-        boxes = U.crops(cam, crop, 1, seed=100 + v)
-        pix = np.concatenate([O.crop_pixels(*b) for b in boxes])
-        ref = _check_view_forward(O, sc, v, out, rast.win.pix_off[v], cfg, pixels=pix, tag=f"{name} v{v}")
+        proj = O.project(po, O.make_view(cam, sc.T_cw[v]), S)
+        if v == full_view:
+            pix = O.full_pixels(cam)
+        else:
+            pix = U.box_pixels(O, U.crops(cam, 32, crops, seed=100 + v))
+        ref = _check_view_forward(O, sc, v, out, rast.win.pix_off[v], cfg, pixels=pix, tag=f"{name} v{v}", po=po,
+                                  proj=proj)
+        flagged = float((ref["ambiguous"] != 0).mean())
+        n_flag += int((ref["ambiguous"] != 0).sum())
+        n_cmp += pix.shape[0]
+        U.log(f"  v{v}: {pix.shape[0]} px compared, flagged {flagged:.4%}, fragments/px {ref['n_frag'].mean():.1f}")
+        assert flagged < MAX_FLAGGED_VIEW, f"{name} v{v}: {flagged:.4%} of the pixels flagged"
         ok = np.zeros((cam.height, cam.width), bool)
         ok[pix[:, 1], pix[:, 0]] = ref["ambiguous"] == 0
         pix_sets.append(pix)
         oks.append(ok)
+        projs.append(proj if keep else None)
+        del proj
+    U.log(f"  window: {n_cmp} px compared, flagged {n_flag / n_cmp:.4%}")
+    assert n_flag / n_cmp < MAX_FLAGGED
     ups = _upstream(sc, 9, oks)
     g = _gpu_backward(lib, rast, params, out, fs, ups)
-    r = _oracle_backward(O, sc, cfg, ups, pixel_sets=pix_sets)
+    r = _oracle_backward(O, sc, cfg, ups, pixel_sets=pix_sets, po=po, projs=projs if keep else None)
     for k in ("means", "log_scales", "quats", "opacity_logit", "rgb"):
         U.log(f"  {k}: rel {U.check_grad(name + ' ' + k, g[k], r[k]):.2e}")
     for v in range(len(sc.cams)):

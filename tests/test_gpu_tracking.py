@@ -41,8 +41,8 @@ def _pose_error(T12, T_true12):
 
 def test_c2_pose_gradient_vs_oracle_and_fd(lib, oracle, c2):
     """First tracking step at the perturbed pose: the GPU pose-only gradient (upstream on
-    sampled crops) against the oracle's analytic gradient, and that gradient against FP64
-    central differences at h = 1e-6 with the fragment decisions frozen."""
+    16 crops of 32x32 pixels) against the oracle's analytic gradient, and that gradient
+    against FP64 central differences at h = 1e-6 with the fragment decisions frozen."""
     U.log("[gpu] c2 pose gradient vs oracle and finite differences")
     O = oracle
     from paper_2507_03737_amd.render import Rasterizer, Window
@@ -54,8 +54,8 @@ def test_c2_pose_gradient_vs_oracle_and_fd(lib, oracle, c2):
     cfg = lib.RasterConfig(pointmap_frame=1)
     rast = Rasterizer(Window(sc.cams, T), sc.n, cfg)
     out, fs = rast.forward(params)
-    boxes = U.crops(cam, 16, 4, seed=5)
-    pix = np.concatenate([O.crop_pixels(*b) for b in boxes])
+    boxes = U.crops(cam, 32, 16, seed=5)
+    pix = U.box_pixels(O, boxes)
     view_sc = dataclasses.replace(sc, T_cw=T0[None])
     ref = _check_view_forward(O, view_sc, 0, out, 0, cfg, pixels=pix, tag="c2 crops")
     ok = np.zeros((cam.height, cam.width), bool)
