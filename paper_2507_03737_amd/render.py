@@ -13,7 +13,8 @@ import torch
 
 from . import binding as B
 
-__all__ = ["Window", "Rasterizer", "RasterizePointmap", "rasterize", "MappingStep", "split_views", "align_results"]
+__all__ = ["Window", "Rasterizer", "RasterizePointmap", "rasterize", "MappingStep", "AutogradMappingStep",
+           "split_views", "align_results"]
 
 
 class Window:
@@ -80,6 +81,8 @@ class Rasterizer:
         self.ctx = B.Context()
         # Initial pair capacity: a generous multiple of the pixel count; grown on overflow.
         self.max_pairs = int(max_pairs) if max_pairs else max(1 << 16, 8 * win.n_pixels)
+        self.pairs = None
+        self.last_frame = None  # frame state of the last forward made through the autograd function
 
     # -- buffers -----------------------------------------------------------------------
     def frame_bytes(self):
@@ -116,6 +119,21 @@ class Rasterizer:
                 return out, fs
             except B.CapacityError as e:
                 self.max_pairs = int(e.pairs * 1.25) + 1024
+
+    def check(self, frame_state=None):
+        """Synchronise and read the status of a forward (by default the last one made through
+        the autograd function).  On overflow the pair capacity grows and CapacityError is
+        raised: that forward's images are incomplete and its backward computed nothing, so
+        the step is to be run again (or re-captured)."""
+        fs = self.last_frame if frame_state is None else frame_state
+        if fs is None:
+            raise RuntimeError("no forward to check")
+        try:
+            self.pairs = B.frame_status(fs, B.stream_handle())
+        except B.CapacityError as e:
+            self.max_pairs = int(e.pairs * 1.25) + 1024
+            raise
+        return self.pairs
 
     def work(self, frame_state, stream=None):
         """(tile pairs, contributing fragments F, evaluated-list bound) of a forward."""
@@ -202,12 +220,25 @@ class RasterizePointmap(torch.autograd.Function):
     ``xi`` [V][6] is the left se(3) perturbation of each pose (rho first); the forward
     renders at the window's poses T_cw and the pose gradient returned for ``xi`` is
     d L / d xi at xi = 0, so callers keep xi at zero and fold pose updates into T_cw with
-    ``binding.pose_retract`` (Exp(xi) T_cw)."""
+    ``binding.pose_retract`` (Exp(xi) T_cw).
+
+    With ``check`` False the forward does not synchronise: it renders with the
+    Rasterizer's current pair capacity, and the overflow flag stays in the frame state
+    until ``rast.check()`` reads it after the step.  A backward on an overflowed frame
+    computes nothing (the library refuses it on the device), so the forward and its
+    backward can be captured in one graph.  With ``check`` True the forward synchronises
+    and re-renders with a larger capacity on overflow (eager use only)."""
 
     @staticmethod
-    def forward(ctx, means, log_scales, quats, opacity_logit, rgb, xi, rast: Rasterizer):
+    def forward(ctx, means, log_scales, quats, opacity_logit, rgb, xi, rast: Rasterizer, check: bool = False):
         params = (means.detach(), log_scales.detach(), quats.detach(), opacity_logit.detach(), rgb.detach())
-        out, fs = rast.forward(params)
+        if check:
+            out, fs = rast.forward(params)
+        else:
+            out = rast.new_outputs()
+            fs = rast.new_frame_state()
+            rast.forward_into(params, out, fs)
+        rast.last_frame = fs
         ctx.rast = rast
         ctx.fs = fs
         ctx.save_for_backward(*params, out["rgb"], out["depth"], out["alpha"], out["pointmap"])
@@ -224,11 +255,12 @@ class RasterizePointmap(torch.autograd.Function):
         grads = rast.zero_grads(params)
         pose = torch.zeros(rast.win.n_views, 6, device=o_rgb.device) if ctx.want_pose else None
         rast.backward_into(params, fwd, up, ctx.fs, grads, pose)
-        return (grads["means"], grads["log_scales"], grads["quats"], grads["opacity_logit"], grads["rgb"], pose, None)
+        return (grads["means"], grads["log_scales"], grads["quats"], grads["opacity_logit"], grads["rgb"], pose, None,
+                None)
 
 
-def rasterize(rast: Rasterizer, means, log_scales, quats, opacity_logit, rgb, xi=None):
-    return RasterizePointmap.apply(means, log_scales, quats, opacity_logit, rgb, xi, rast)
+def rasterize(rast: Rasterizer, means, log_scales, quats, opacity_logit, rgb, xi=None, check=False):
+    return RasterizePointmap.apply(means, log_scales, quats, opacity_logit, rgb, xi, rast, check)
 
 
 class MappingStep:
@@ -284,6 +316,70 @@ class MappingStep:
             self.run()
         torch.cuda.current_stream().wait_stream(s)
         torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self.run()
+        return self.graph
+
+    def replay(self):
+        if self.graph is None:
+            raise RuntimeError("capture() first")
+        self.graph.replay()
+
+
+class AutogradMappingStep:
+    """One mapping iteration driven by torch.autograd: the window is rendered through
+    ``RasterizePointmap`` from leaf tensors (the Gaussian parameters and a zero se(3)
+    increment per pose), the library's window-loss kernel refits the per-patch scale and
+    writes the loss and its image gradients, and ``torch.autograd.backward`` takes them
+    through the function's backward into the leaves' ``.grad``.  Nothing synchronises, so
+    ``capture`` records the whole step (forward, loss, backward) in one graph; ``check``
+    reads the forward's overflow flag afterwards."""
+
+    def __init__(self, rast: Rasterizer, params, target_rgb, prior_pm, patch=8, alpha=0.98):
+        self.rast = rast
+        self.leaves = [p.detach().clone().requires_grad_(True) for p in params]
+        win = rast.win
+        dev = win.T_cw.device
+        self.xi = torch.zeros(win.n_views, 6, device=dev, requires_grad=True)
+        self.target = target_rgb
+        self.prior = prior_pm
+        self.patch = patch
+        self.alpha = alpha
+        self.scale = torch.empty(win.n_patches(patch), device=dev)
+        self.loss = torch.empty(win.n_views, device=dev)
+        self.g_rgb = torch.empty(3 * win.n_pixels, device=dev)
+        self.g_pm = torch.empty(3 * win.n_pixels, device=dev)
+        rast.reserve()
+        self.graph = None
+
+    def run(self):
+        for t in (*self.leaves, self.xi):
+            t.grad = None
+        rgb, _, _, pm = rasterize(self.rast, *self.leaves, self.xi)
+        self.rast.window_loss_into(rgb.detach(), self.target, pm.detach(), self.prior, self.patch, self.alpha,
+                                   self.scale, self.loss, self.g_rgb, self.g_pm)
+        torch.autograd.backward([rgb, pm], [self.g_rgb, self.g_pm])
+
+    def grads(self):
+        names = ("means", "log_scales", "quats", "opacity_logit", "rgb")
+        g = {k: t.grad for k, t in zip(names, self.leaves)}
+        g["pose"] = self.xi.grad
+        return g
+
+    def check(self):
+        return self.rast.check()
+
+    def capture(self):
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            self.run()
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        self.check()
+        for t in (*self.leaves, self.xi):
+            t.grad = None
         self.graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(self.graph):
             self.run()

@@ -203,30 +203,119 @@ def test_autotune_picks_fastest_and_caches(lib, tmp_path):
     assert res2 == res
 
 
-def test_autograd_function(lib):
-    U.log("[gpu] autograd function")
+def _autograd_grads(lib, sc, cfg, ups, seed_leaves=None):
+    """Gradients of sum_k <up_k, out_k> taken by torch.autograd through RasterizePointmap,
+    for the five parameter groups and the se(3) increment of every pose."""
     from paper_2507_03737_amd.render import Rasterizer, Window, rasterize
+    params, T = U.to_dev(sc, torch)
+    rast = Rasterizer(Window(sc.cams, T), sc.n, cfg)
+    rast.forward(params)  # sizes the pair capacity; the autograd forward below does not synchronise
+    leaves = [p.clone().requires_grad_(True) for p in params]
+    xi = torch.zeros(len(sc.cams), 6, device="cuda", requires_grad=True)
+    outs = rasterize(rast, *leaves, xi)
+    w = [torch.from_numpy(_pack(ups, k, c)).cuda() for k, c in (("rgb", 3), ("depth", 1), ("alpha", 1),
+                                                                ("pointmap", 3))]
+    torch.autograd.backward(list(outs), w)
+    assert rast.check() > 0
+    g = {k: t.grad.cpu().numpy() for k, t in zip(("means", "log_scales", "quats", "opacity_logit", "rgb"), leaves)}
+    g["pose"] = xi.grad.cpu().numpy()
+    return g
+
+
+@pytest.mark.parametrize("frame", [0, 1, 2])
+def test_autograd_function_vs_oracle(lib, oracle, frame):
+    """The autograd function's gradients for means, log-scales, quaternions, opacity
+    logits, colours and each pose's se(3) increment against the oracle's analytic VJP, on a
+    3-view window of uneven sizes, all four output channels carrying upstream gradient."""
+    U.log(f"[gpu] autograd function vs oracle, frame {frame}")
+    O = oracle
     sc = _window_scene(seed=14, n=1500)
+    cfg = lib.RasterConfig(pointmap_frame=frame)
+    S = _oracle_settings(O, cfg)
+    po = O.Params.from_scene(sc)
+    oks = [O.render_image(po, cam, sc.T_cw[v], S)["ambiguous"] == 0 for v, cam in enumerate(sc.cams)]
+    ups = _upstream(sc, 70 + frame, oks)
+    g = _autograd_grads(lib, sc, cfg, ups)
+    r = _oracle_backward(O, sc, cfg, ups)
+    for k in ("means", "log_scales", "quats", "opacity_logit", "rgb"):
+        U.log(f"  {k}: rel {U.check_grad('autograd ' + k, g[k], r[k]):.2e}")
+    for v in range(len(sc.cams)):
+        U.check_grad(f"autograd pose v{v}", g["pose"][v], r["pose"][v], frac=1.0)
+
+
+def test_autograd_function_vs_finite_differences(lib, oracle):
+    """On a tiny scene (300 Gaussians, one 160x120 view): directional derivatives of the
+    loss sum_k <up_k, out_k> from the autograd gradients against FP64 central differences
+    (h = 1e-6) of the oracle's frozen-decision replay, one random direction per parameter
+    group and one per pose component."""
+    U.log("[gpu] autograd function vs FP64 finite differences")
+    O = oracle
+    sc = _posed(scenes.make_scene("c0").subset(300))
+    cfg = lib.RasterConfig(pointmap_frame=1)
+    S = _oracle_settings(O, cfg)
+    po = O.Params.from_scene(sc)
+    cam = sc.cams[0]
+    ok = O.render_image(po, cam, sc.T_cw[0], S)["ambiguous"] == 0
+    ups = _upstream(sc, 77, [ok])
+    g = _autograd_grads(lib, sc, cfg, ups)
+    view = O.make_view(cam, sc.T_cw[0])
+    pix = O.full_pixels(cam)
+    up = O.pixel_upstream(ups[0], pix)
+    tr = O.trace(po, view, S, pix)
+    h = 1e-6
+    rng = np.random.default_rng(5)
+    names = ("means", "log_scales", "quats", "opacity_logit", "rgb")
+    for gi, name in enumerate(names):
+        d = rng.standard_normal(po.flat()[gi].shape)
+        qp, qm = po.copy(), po.copy()
+        qp.flat()[gi][...] += h * d
+        qm.flat()[gi][...] -= h * d
+        fd = (O.replay_loss(O.Params(*qp.flat()), view, S, tr, up, 1) -
+              O.replay_loss(O.Params(*qm.flat()), view, S, tr, up, 1)) / (2 * h)
+        an = float((g[name].astype(np.float64) * d).sum())
+        U.log(f"  {name}: fd {fd:.6e} autograd {an:.6e}")
+        assert abs(an - fd) <= 2e-3 * abs(fd), name
+    for k in range(6):
+        e = np.zeros(6)
+        e[k] = h
+        fd = (O.replay_loss(po, O.make_view(cam, O.se3_exp_left(e, sc.T_cw[0])), S, tr, up, 1) -
+              O.replay_loss(po, O.make_view(cam, O.se3_exp_left(-e, sc.T_cw[0])), S, tr, up, 1)) / (2 * h)
+        U.log(f"  xi[{k}]: fd {fd:.6e} autograd {g['pose'][0][k]:.6e}")
+        assert abs(g["pose"][0][k] - fd) <= 2e-3 * np.abs(g["pose"][0]).max()
+
+
+def test_autograd_step_capture_replays(lib):
+    """The autograd-driven mapping step (render through the autograd function, window loss,
+    torch.autograd.backward) captured in one graph: each replay equals an eager run at the
+    same poses, with in-place pose updates and eager work between replays."""
+    U.log("[gpu] autograd mapping step, graph replay vs eager")
+    from paper_2507_03737_amd.render import AutogradMappingStep, Rasterizer, Window
+    sc = _window_scene(seed=19)
     params, T = U.to_dev(sc, torch)
     win = Window(sc.cams, T)
-    rast = Rasterizer(win, sc.n, lib.RasterConfig(pointmap_frame=1))
-    leaves = [p.clone().requires_grad_(True) for p in params]
-    xi = torch.zeros(3, 6, device="cuda", requires_grad=True)
-    rgb, depth, alpha, pm = rasterize(rast, *leaves, xi)
-    w = [torch.randn_like(t) for t in (rgb, depth, alpha, pm)]
-    loss = sum((a * b).sum() for a, b in zip((rgb, depth, alpha, pm), w))
-    loss.backward()
-    out, fs = rast.forward(params)
-    up = {"rgb": w[0], "depth": w[1], "alpha": w[2], "pointmap": w[3]}
-    grads = rast.zero_grads(params)
-    pose = torch.zeros(3, 6, device="cuda")
-    rast.backward_into(params, out, up, fs, grads, pose)
-    torch.cuda.synchronize()
-    # Same kernels on the same inputs; float atomics make the summation order differ, so a
-    # cancelling element may differ by rounding relative to the tensor's scale.
-    for leaf, k in zip(leaves, ("means", "log_scales", "quats", "opacity_logit", "rgb")):
-        torch.testing.assert_close(leaf.grad, grads[k], rtol=1e-4, atol=1e-5 * float(grads[k].abs().max()))
-    torch.testing.assert_close(xi.grad, pose, rtol=1e-4, atol=1e-3)
+    cfg = lib.RasterConfig(pointmap_frame=1)
+    base, _ = Rasterizer(win, sc.n, cfg).forward(params)
+    target = (base["rgb"] + 0.05 * torch.randn_like(base["rgb"])).contiguous()
+    prior = (base["pointmap"] * 1.1).contiguous()
+    rast = Rasterizer(win, sc.n, cfg)
+    rast.forward(params)
+    step = AutogradMappingStep(rast, params, target, prior)
+    step.capture()
+    eager = AutogradMappingStep(Rasterizer(win, sc.n, cfg, max_pairs=rast.max_pairs), params, target, prior)
+    xi = torch.tensor([[0.01, -0.02, 0.0, 0.002, 0.0, -0.001]] * len(sc.cams), device="cuda")
+    for rep in range(3):
+        step.replay()
+        step.check()
+        got = {k: v.clone() for k, v in step.grads().items()}
+        loss = step.loss.clone()
+        eager.run()
+        eager.check()
+        ref = eager.grads()
+        torch.testing.assert_close(loss, eager.loss, rtol=1e-6, atol=0.0)
+        for k in got:
+            torch.testing.assert_close(got[k], ref[k], rtol=1e-4, atol=1e-5 * float(ref[k].abs().max()))
+        lib.pose_retract(len(sc.cams), T, xi, lib.stream_handle())  # the next replay sees the new poses
+        torch.cuda.synchronize()
 
 
 def test_c1_full_size_crops(lib, oracle):
@@ -239,7 +328,7 @@ def test_c1_full_size_crops(lib, oracle):
     rast, params, out, fs = _render_gpu(lib, sc, cfg)
     cam = sc.cams[0]
     boxes = U.crops(cam, 24, 6, seed=3) + [(0, cam.height - 24, 24, 24), (cam.width // 2, cam.height - 30, 24, 24)]
-    pix = np.concatenate([O.crop_pixels(*b) for b in boxes])
+    pix = U.box_pixels(O, boxes)
     ref = _check_view_forward_pixels(O, sc, out, cfg, pix)
     ok = np.zeros((cam.height, cam.width), bool)
     ok[pix[:, 1], pix[:, 0]] = ref["ambiguous"] == 0

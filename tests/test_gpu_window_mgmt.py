@@ -45,6 +45,11 @@ def test_iso_loss_vs_oracle(lib):
 
 
 def test_covisibility_vs_oracle(lib, oracle):
+    """Visible sets (Gaussians contributing to at least one pixel of a view) equal the
+    oracle's, except for Gaussians that are candidates of a pixel the oracle flags as
+    ambiguous, where a float32 decision may legitimately differ.  IOU and OC (Eq. S1-S2)
+    computed from the oracle's sets bound the GPU's: changing k set members moves an
+    intersection and a union by at most k each."""
     from oracle import mapping as M
     from paper_2507_03737_amd.render import Rasterizer, Window
     from tests.test_gpu_window import _window_scene
@@ -62,24 +67,37 @@ def test_covisibility_vs_oracle(lib, oracle):
     vis = fs.cpu().numpy()[lay["visible"]:lay["visible"] + sc.n * V].reshape(V, sc.n) != 0
     S = _oracle_settings(O, rast.cfg)
     po = O.Params.from_scene(sc)
+    ref_vis = np.zeros_like(vis)
+    unsure = np.zeros_like(vis)
     for v, cam in enumerate(sc.cams):
         view = O.make_view(cam, sc.T_cw[v])
         pix = O.full_pixels(cam)
         r = O.render(po, view, S, pix)
         tr = O.trace(po, view, S, pix)
-        amb = r["ambiguous"] != 0
-        sure, loose = set(), set()
-        for k in range(pix.shape[0]):
-            gs = tr.frag_g[tr.offsets[k]:tr.offsets[k + 1]].tolist()
-            (loose if amb[k] else sure).update(gs)
-        got = set(np.flatnonzero(vis[v]).tolist())
-        U.log(f"  view {v}: gpu {len(got)} oracle {len(sure)} (+{len(loose - sure)} on ambiguous pixels)")
-        assert sure <= got
-        assert len(got - sure - loose) <= max(2, len(got) // 200)
-    ref_iou, ref_oc, ref_cnt = M.covisibility(vis)
-    np.testing.assert_array_equal(iou.cpu().numpy(), ref_iou)
-    np.testing.assert_array_equal(oc.cpu().numpy(), ref_oc)
-    np.testing.assert_array_equal(cnt.cpu().numpy(), ref_cnt)
+        ref_vis[v, np.unique(tr.frag_g)] = True
+        pa = O.proj_numpy(O.project(po, view, S))
+        cr = pa["crect"]
+        for i, j in pix[r["ambiguous"] != 0]:
+            unsure[v] |= (pa["cand"] == 1) & (cr[:, 0] <= i) & (i <= cr[:, 1]) & (cr[:, 2] <= j) & (j <= cr[:, 3])
+        diff = vis[v] != ref_vis[v]
+        U.log(f"  view {v}: gpu {int(vis[v].sum())} oracle {int(ref_vis[v].sum())}, differing {int(diff.sum())}, "
+              f"candidates of flagged pixels {int(unsure[v].sum())}")
+        assert not (diff & ~unsure[v]).any(), f"view {v}: sets differ off ambiguous pixels"
+    got_iou, got_oc, got_cnt = iou.cpu().numpy(), oc.cpu().numpy(), cnt.cpu().numpy()
+    # The GPU's IOU/OC are those of its own sets, exactly ...
+    g_iou, g_oc, g_cnt = M.covisibility(vis)
+    np.testing.assert_array_equal(got_iou, g_iou)
+    np.testing.assert_array_equal(got_oc, g_oc)
+    np.testing.assert_array_equal(got_cnt, g_cnt)
+    # ... and within the bound of the oracle's.
+    r_iou, r_oc, _ = M.covisibility(ref_vis)
+    for i in range(V):
+        for j in range(V):
+            k = int((unsure[i] | unsure[j]).sum())
+            union = int((ref_vis[i] | ref_vis[j]).sum())
+            small = int(min(ref_vis[i].sum(), ref_vis[j].sum()))
+            assert abs(got_iou[i, j] - r_iou[i, j]) <= 2 * k / max(1, union - k) + 1e-12
+            assert abs(got_oc[i, j] - r_oc[i, j]) <= 2 * k / max(1, small - k) + 1e-12
     # Without marking, the call reports it instead of returning stale sets.
     rast2 = Rasterizer(win, sc.n, lib.RasterConfig())
     _, fs2 = rast2.forward(params)
