@@ -494,6 +494,23 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
         }
         __builtin_amdgcn_wave_barrier();  // read before the walk overwrites the buffer
     }
+    // What each lane of the flush produces: grad2d column j = lane % 16 of a record, from
+    // row f of B column (H, slot) of the product (src: its offset in the transposed block,
+    // has: the column is produced at all), and which moment it is (c1..c5: j = 1..5).
+    struct FlushLane {
+        bool has, c1, c2, c3, c4, c5;
+        int src;
+    } fl;
+    {
+        const int j = lane & 15;
+        int src_f = j <= 5 && (j > 0 || V::kOpacity) ? j : -1;
+#pragma unroll
+        for (int m = 0; m < V::NW; ++m)
+            if ((int)((V::kWColumns >> (4 * m)) & 15u) == j) src_f = 16 | (6 + m);
+        fl.has = src_f >= 0;
+        fl.src = fl.has ? (src_f >> 4) * 8 * 20 + (src_f & 15) : 0;
+        fl.c1 = j == 1; fl.c2 = j == 2; fl.c3 = j == 3; fl.c4 = j == 4; fl.c5 = j == 5;
+    }
     // Contract the first n slots and add the results to the records' rows.
     auto flush = [&](int n) {
         __builtin_amdgcn_wave_barrier();  // the slots are written (a wave's LDS accesses stay in order)
@@ -514,26 +531,29 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
         float *dout = mf_b[wv];
         *reinterpret_cast<float4 *>(dout + j * 20 + 4 * c) = make_float4(acc[0], acc[1], acc[2], acc[3]);
         __builtin_amdgcn_wave_barrier();
-        // The lane's grad2d column is j; its value is row f of B column (H, slot), coded as
-        // H << 4 | f (-1: the column is not produced).
-        int src_f = j <= 5 && (j > 0 || V::kOpacity) ? j : -1;
-#pragma unroll
-        for (int m = 0; m < V::NW; ++m)
-            if ((int)((V::kWColumns >> (4 * m)) & 15u) == j) src_f = 16 | (6 + m);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int sr = 4 * h + c;  // record slot of this lane
             const float4 mt = mf_meta[wv][sr];
             const float4 sm = *reinterpret_cast<const float4 *>(dout + sr * 20);  // S0, Sx, Sy, Sxx
-            const float val = src_f >= 0 ? dout[((src_f >> 4) * 8 + sr) * 20 + (src_f & 15)] : 0.0f;
-            // Moments about the wave centre -> about the record's mean (dx = x - ux).
+            const float val = fl.has ? dout[fl.src + sr * 20] : 0.0f;
+            // Moments about the wave centre -> about the record's mean (dx = x - ux):
+            // R_x = S_x - ux S0, R_xx = S_xx - 2 ux S_x + ux^2 S0, R_xy = S_xy - uy S_x -
+            // ux S_y + ux uy S0, and likewise in y.  The column of each lane picks its
+            // coefficients by selects on wave-constant lane masks (no branches).
             const float ux = mt.x - cxw, uy = mt.y - cyw;
-            const float al = j == 1 ? -ux : j == 2 ? -uy : j == 3 ? ux * ux : j == 4 ? ux * uy : j == 5 ? uy * uy : 0.0f;
-            const float be = j == 3 ? -2.0f * ux : j == 4 ? -uy : 0.0f;
-            const float ga = j == 4 ? -ux : j == 5 ? -2.0f * uy : 0.0f;
+            float al = fl.c1 ? -ux : 0.0f;
+            al = fl.c2 ? -uy : al;
+            al = fl.c3 ? ux * ux : al;
+            al = fl.c4 ? ux * uy : al;
+            al = fl.c5 ? uy * uy : al;
+            float be = fl.c3 ? -2.0f * ux : 0.0f;
+            be = fl.c4 ? -uy : be;
+            float ga = fl.c4 ? -ux : 0.0f;
+            ga = fl.c5 ? -2.0f * uy : ga;
             const float out = fmaf(ga, sm.z, fmaf(be, sm.y, fmaf(al, sm.x, val)));
             const uint32_t rid = __float_as_uint(mt.z);
-            if (sr < n && src_f >= 0 && out != 0.f) unsafeAtomicAdd(grad2d + (int64_t)rid * kG2 + j, out);
+            if (sr < n && fl.has && out != 0.f) unsafeAtomicAdd(grad2d + (int64_t)rid * kG2 + j, out);
         }
         __builtin_amdgcn_wave_barrier();  // read before later records overwrite the buffer
     };
