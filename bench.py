@@ -34,15 +34,18 @@ if ROOT not in sys.path:
 
 METRIC = "fwd+bwd ms/mapping iter & Gaussian-px evals/s, batched vs per-view, at oracle tol"
 
-# Algorithmic work per contributing fragment (float32 operations in the definition of
-# the compositing step and of its derivative; the exponential counts as one).
-FWD_FLOPS_PER_FRAG = 29
-BWD_FLOPS_PER_FRAG = 64
+# Algorithmic work per contributing fragment: about 20 float32 operations and one
+# exponential in the forward, about 60 and one exponential in the backward (the exponential
+# counts as one operation).
+FWD_FLOPS_PER_FRAG = 21
+BWD_FLOPS_PER_FRAG = 61
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0
 # Measured HBM traffic of the dominant kernel (rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by
 # the same counters on a copy of known size) and the hash of the sources it was taken on.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "raster_bwd_c3_traffic.txt")
+# HBM bytes of a whole mapping iteration of the large window (sum over its kernels).
+STEP_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "mapping_step_c4_traffic.txt")
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "raster_c3_counters.md")
 KERNEL_SOURCES = ("paper_2507_03737_amd/csrc/raster.hip", "paper_2507_03737_amd/csrc/gspm_common.h")
 COPY_BYTES = 1 << 29  # 512 MiB read + 512 MiB written by the calibration copy
@@ -94,6 +97,17 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
+def all_kernel_sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2507_03737_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
 def stored_record(path, kernel, workload, tile, ppl):
     """The machine-readable line of a committed counter summary, if it was taken on the
     current kernel sources and the same launch shape; else None."""
@@ -104,7 +118,7 @@ def stored_record(path, kernel, workload, tile, ppl):
         return None
     if (rec.get("kernel"), rec.get("workload"), rec.get("tile"), rec.get("ppl")) != (kernel, workload, tile, ppl):
         return None
-    if rec.get("source_sha256") != kernel_source_hash():
+    if rec.get("source_sha256") not in (kernel_source_hash(), all_kernel_sources_hash()):
         return None
     return rec
 
@@ -241,43 +255,81 @@ def time_tracking(torch, dev, iters=20):
     return {"workload": "500k Gaussians, one 960x640 view, pose-only backward", "ms_per_iter": ms}
 
 
-def time_steps(fn, steps, warmup, torch):
+def time_steps(fn, steps, warmup, torch, stats=None):
+    """Mean milliseconds per step over `steps` steps bracketed by synchronisations (one
+    event pair around all of them), and the wall time.  With a dict `stats`, each step is
+    also bracketed by its own event pair and the dict receives the per-step median, p10
+    and p90."""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)] if stats is not None else None
     w0 = time.perf_counter()
     t0.record()
-    for _ in range(steps):
+    for k in range(steps):
+        if marks:
+            marks[k].record()
         fn()
+    if marks:
+        marks[steps].record()
     t1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
+    if marks:
+        per = np.array([marks[k].elapsed_time(marks[k + 1]) for k in range(steps)])
+        stats.update({"median": float(np.median(per)), "p10": float(np.percentile(per, 10)),
+                      "p90": float(np.percentile(per, 90)), "steps": steps})
     return t0.elapsed_time(t1) / steps, wall
 
 
+def gpu_clocks():
+    """Current shader and memory clocks as rocm-smi reports them (None if unavailable)."""
+    import subprocess
+    try:
+        r = subprocess.run(["rocm-smi", "--showclocks"], capture_output=True, text=True, timeout=20)
+    except (OSError, subprocess.SubprocessError):
+        return None
+    lines = [ln.strip() for ln in r.stdout.splitlines() if "clock level" in ln and ("sclk" in ln or "mclk" in ln)]
+    return lines or None
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(sc, opt_host, win_cams, T_host, seed, budget_px):
-    """Oracle forward + backward on a bounded sample of pixel crops of the same window."""
+    """Oracle forward + backward on a bounded sample of pixel crops of the same window:
+    32x32 crops spread evenly over the views (each view projected once)."""
     from oracle import oracle as O
-    from paper_2507_03737_amd import scenes
 
     O.build()
     p = O.Params(*opt_host)
     S = O.Settings()
     rng = np.random.default_rng(seed)
     views = len(win_cams)
-    crop = 16
-    n_crops = max(1, budget_px // (crop * crop))
+    crop = 32
+    per_view = max(1, budget_px // (crop * crop * views))
     frags = 0
     npx = 0
     t0 = time.perf_counter()
-    for k in range(n_crops):
-        v = k % views
+    for v in range(views):
         cam = win_cams[v]
-        x0 = int(rng.integers(0, cam.width - crop))
-        y0 = int(rng.integers(0, cam.height - crop))
-        pix = O.crop_pixels(x0, y0, crop, crop)
+        boxes = []
+        for _ in range(per_view):
+            x0 = int(rng.integers(0, cam.width - crop))
+            y0 = int(rng.integers(0, cam.height - crop))
+            boxes.append((x0, y0, crop, crop))
+        pix = np.concatenate([O.crop_pixels(*b) for b in boxes])
+        pix = np.ascontiguousarray(np.unique(pix[:, [1, 0]], axis=0)[:, [1, 0]], dtype=np.int32)
         view = O.make_view(cam, T_host[v])
         proj = O.project(p, view, S)
         r = O.render(p, view, S, pix, proj=proj)
@@ -288,8 +340,135 @@ def cpu_baseline(sc, opt_host, win_cams, T_host, seed, budget_px):
         npx += pix.shape[0]
     dt = time.perf_counter() - t0
     return {"value": 2.0 * frags / dt, "unit": "Gaussian-px evals/s", "cores": O.num_threads(), "kind": "oracle",
-            "sample": f"{n_crops} crops of {crop}x{crop} px ({npx} px) over the {views} views, FP64 forward + "
-                      f"backward, {frags} contributing fragments, {dt:.1f} s"}
+            "cpu_model": cpu_model(),
+            "sample": f"{per_view} crops of {crop}x{crop} px per view ({npx} px) over the {views} views, FP64 "
+                      f"projection + forward + backward (OpenMP), {frags} contributing fragments, {dt:.1f} s"}
+
+
+def cpu_baseline_c0_one_thread():
+    """The oracle's full-frame forward + backward of the small configuration (2,000
+    Gaussians, 160x120) on one thread."""
+    from oracle import oracle as O
+    from paper_2507_03737_amd import scenes
+
+    O.build()
+    sc = scenes.make_scene("c0")
+    p = O.Params.from_scene(sc)
+    S = O.Settings()
+    cam = sc.cams[0]
+    view = O.make_view(cam, sc.T_cw[0])
+    pix = O.full_pixels(cam)
+    up = O.pixel_upstream(scenes.upstream_grads(sc, seed=1)[0], pix)
+    n0 = O.num_threads()
+    O.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        proj = O.project(p, view, S)
+        r = O.render(p, view, S, pix, proj=proj)
+        O.backward(p, view, S, pix, up, pointmap_frame=1, proj=proj)
+        dt = time.perf_counter() - t0
+    finally:
+        O.set_num_threads(n0)
+    frags = int(r["n_frag"].sum())
+    return {"value": 2.0 * frags / dt, "unit": "Gaussian-px evals/s", "cores": 1, "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "sample": f"c0 full frame (2,000 Gaussians, 160x120), FP64 forward + backward, {frags} contributing "
+                      f"fragments, {dt:.2f} s"}
+
+
+def sized_step(rast, opt, target, prior, MappingStep, B):
+    """A mapping step whose pair capacity fits the window with 30% headroom."""
+    probe = MappingStep(rast, opt, target, prior)
+    probe.run()
+    try:
+        pairs = probe.check()
+    except B.CapacityError as e:
+        pairs = e.pairs
+    del probe
+    rast.max_pairs = int(pairs * 1.3) + 4096
+    return MappingStep(rast, opt, target, prior)
+
+
+def time_autograd_step(rast, opt, target, prior, steps, warmup, torch):
+    """The same mapping iteration driven by torch.autograd (render through the autograd
+    function, window loss, torch.autograd.backward into the leaves), eager and as one
+    captured graph."""
+    from paper_2507_03737_amd.render import AutogradMappingStep
+    step = AutogradMappingStep(rast, opt, target, prior)
+    st_e, st_g = {}, {}
+    ms_e, _ = time_steps(step.run, steps, warmup, torch, st_e)
+    step.check()
+    ms_g = None
+    try:
+        step.capture()
+        ms_g, _ = time_steps(step.replay, steps, 2, torch, st_g)
+        step.check()
+    except Exception as e:  # report eager only
+        log(f"[bench] autograd step capture failed: {e}")
+    del step
+    return {"eager_ms": ms_e, "eager_stats": st_e, "graph_ms": ms_g, "graph_stats": st_g or None}
+
+
+def large_window(steps, warmup, torch, dev):
+    """The large window (16 keyframes of 1920x1080, 3M Gaussians): autotuned ms per mapping
+    iteration with per-pixel transmittance recomputed in the backward (8 bytes of state per
+    pixel), its HBM traffic from the committed counter summary of this launch shape (when
+    it was taken on the current kernel sources), and the device memory the window uses."""
+    from paper_2507_03737_amd import binding as B
+    from paper_2507_03737_amd.autotune import autotune
+    from paper_2507_03737_amd.render import MappingStep, Rasterizer
+
+    torch.cuda.empty_cache()
+    torch.cuda.reset_peak_memory_stats(dev)
+    free0, _ = torch.cuda.mem_get_info(dev)
+    log("[bench] building c4 inputs")
+    sc, win, cfg, opt, target, prior = build_inputs("c4", 4, torch, dev)
+    cfg, tuned = autotune(win, sc.n, opt, target, prior, base=cfg,
+                          candidates=[(16, 1, 8), (16, 2, 8), (32, 1, 8), (32, 2, 8)], steps=3, warmup=1,
+                          refine=2, refine_steps=8, log=log)
+    rast = Rasterizer(win, sc.n, cfg)
+    step = sized_step(rast, opt, target, prior, MappingStep, B)
+    rast.cfg.count_work = 1
+    step.run()
+    pairs, frags, _ = rast.work(step.fs)
+    rast.cfg.count_work = 0
+    st = {}
+    rast.ctx.timing(True)
+    ms, _ = time_steps(step.run, steps, warmup, torch, st)
+    phases = rast.ctx.collect_timing()
+    rast.ctx.timing(False)
+    step.check()
+    st_g = {}
+    ms_g = None
+    try:
+        step.capture()
+        ms_g, _ = time_steps(step.replay, steps, 2, torch, st_g)
+        step.check()
+    except Exception as e:
+        log(f"[bench] c4 graph capture failed: {e}")
+    free1, _ = torch.cuda.mem_get_info(dev)
+    n_iter = max(1, phases["raster_fwd"][1])
+    rec = stored_record(STEP_TRAFFIC_FILE, "mapping_step", "c4", cfg.tile, cfg.pixels_per_lane)
+    hbm = None
+    if rec is not None:
+        hbm = {"bytes_per_iter": rec["hbm_bytes_per_iter"], "GB/s": rec["hbm_bytes_per_iter"] / (ms * 1e-3) / 1e9,
+               "frac": rec["hbm_bytes_per_iter"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    log(f"[bench] c4 {ms:.3f} ms/iter (tile {cfg.tile}, {cfg.pixels_per_lane} px/lane)")
+    out = {"workload": "c4 large window: 3M Gaussians, 16 keyframes 1920x1080, render + patch-scale L1 loss + "
+                       "backward to all params and poses, transmittance recomputed in the backward",
+           "tile": cfg.tile, "pixels_per_lane": cfg.pixels_per_lane, "sort_digit_bits": cfg.sort_digit_bits,
+           "autotune_ms": {f"{r['tile']}x{r['tile']}/ppl{r['pixels_per_lane']}": round(r.get("ms_refined", r["ms"]), 3)
+                           for r in tuned},
+           "ms_per_iter": ms, "stats": st, "graph_ms_per_iter": ms_g, "graph_stats": st_g or None,
+           "tile_pairs": pairs, "contributing_fragments": frags, "gaussian_px_evals_per_s": 2.0 * frags / (ms * 1e-3),
+           "phase_ms": {k: round(v[0] / n_iter, 4) for k, v in phases.items()},
+           "hbm": hbm,
+           "memory": {"device_used_bytes": int(free0 - free1),
+                      "torch_peak_bytes": int(torch.cuda.max_memory_allocated(dev)),
+                      "per_pixel_state_bytes": 12}}
+    del step, rast, opt, target, prior
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -305,8 +484,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
-    ap.add_argument("--cpu-px", type=int, default=2048, help="pixels in the CPU-baseline sample")
+    ap.add_argument("--cpu-px", type=int, default=131072, help="pixels in the CPU-baseline sample")
     ap.add_argument("--no-extras", action="store_true", help="skip timing the mapping-side operations")
+    ap.add_argument("--no-c4", action="store_true", help="skip the large-window (c4) leg")
+    ap.add_argument("--no-autograd", action="store_true", help="skip the autograd-driven step")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a copy of known size (for scaling HBM traffic counters)")
     args = ap.parse_args()
@@ -356,8 +537,10 @@ def main():
     rast.cfg.count_work = 0
     log(f"[bench] pairs={pairs} contributing fragments={frags}")
 
+    clocks_before = gpu_clocks()
+    stats = {"batched_eager": {}, "batched_graph": {}, "per_view_eager": {}}
     rast.ctx.timing(True)
-    ms_batched, wall = time_steps(step.run, args.steps, args.warmup, torch)
+    ms_batched, wall = time_steps(step.run, args.steps, args.warmup, torch, stats["batched_eager"])
     phases = rast.ctx.collect_timing()
     rast.ctx.timing(False)
     step.check()
@@ -367,7 +550,7 @@ def main():
     if not args.no_graph:
         try:
             step.capture()
-            ms_graph, _ = time_steps(step.replay, args.steps, 2, torch)
+            ms_graph, _ = time_steps(step.replay, args.steps, 2, torch, stats["batched_graph"])
             step.check()
             log(f"[bench] batched graph {ms_graph:.3f} ms/step")
         except Exception as e:  # graph capture unsupported -> report eager only
@@ -394,7 +577,7 @@ def main():
         def per_view():
             for s_v in steps_v:
                 s_v.run()
-        ms_per_view, _ = time_steps(per_view, args.steps, args.warmup, torch)
+        ms_per_view, _ = time_steps(per_view, args.steps, args.warmup, torch, stats["per_view_eager"])
         log(f"[bench] per-view eager {ms_per_view:.3f} ms/step")
         del steps_v
 
@@ -445,6 +628,13 @@ def main():
                                              "step_ms": ms_lane}}
         log(f"[bench] backward with the lane reduce-scatter: {bwd_forms['lane_reduce_scatter']['raster_bwd_ms']:.3f} ms")
 
+    autograd = None
+    if not args.no_autograd:
+        log("[bench] autograd-driven step")
+        autograd = time_autograd_step(Rasterizer(win, sc.n, cfg, max_pairs=rast.max_pairs), opt, target, prior,
+                                      args.steps, args.warmup, torch)
+        log(f"[bench] autograd step {autograd['eager_ms']:.3f} ms eager, {autograd['graph_ms']} ms graph")
+
     mapping_ops = None
     tracking = None
     if not args.no_extras:
@@ -453,15 +643,22 @@ def main():
         log("[bench] tracking iteration")
         tracking = time_tracking(torch, dev)
 
-    cpu = None
+    free1, _ = torch.cuda.mem_get_info(dev)
+    memory = {"device_used_bytes": int(free0 - free1), "torch_peak_bytes": int(torch.cuda.max_memory_allocated(dev)),
+              "device_total_bytes": int(total_mem)}
+    clocks_after = gpu_clocks()
+
+    c4 = None
+    if not args.no_c4 and args.workload == "c3":
+        del step, rast
+        c4 = large_window(max(5, args.steps // 2), 2, torch, dev)
+
+    cpu = cpu1 = None
     if not args.no_cpu:
         log("[bench] CPU oracle baseline")
         opt_host = [t.cpu().numpy() for t in opt]
         cpu = cpu_baseline(sc, opt_host, sc.cams, sc.T_cw, 7, args.cpu_px)
-
-    free1, _ = torch.cuda.mem_get_info(dev)
-    memory = {"device_used_bytes": int(free0 - free1), "torch_peak_bytes": int(torch.cuda.max_memory_allocated(dev)),
-              "device_total_bytes": int(total_mem)}
+        cpu1 = cpu_baseline_c0_one_thread()
     fps_evals = 2.0 * frags / (ms_batched * 1e-3)
     res = {
         "metric": METRIC,
@@ -486,8 +683,15 @@ def main():
             "pixels_per_lane": cfg.pixels_per_lane, "sort_digit_bits": cfg.sort_digit_bits,
             "autotuned": tuned is not None,
             "patch": 8, "loss_alpha": 0.98, "pointmap_frame": "camera",
+            "bwd_reduction": ("matrix cores: each wave's per-record sums as a v_mfma_f32_16x16x4f32 contraction "
+                              "(the cross-lane DPP reduce-scatter form is timed beside it)"
+                              if cfg.pixels_per_lane == 1 else "cross-lane DPP reduce-scatter"),
         },
-        "fwd_bwd_ms_per_iter": {"batched_eager": ms_batched, "batched_graph": ms_graph, "per_view_eager": ms_per_view},
+        "fwd_bwd_ms_per_iter": {"batched_eager": ms_batched, "batched_graph": ms_graph, "per_view_eager": ms_per_view,
+                                "batched_eager_lane_reduce_scatter": bwd_forms["lane_reduce_scatter"]["step_ms"]
+                                if bwd_forms else None},
+        "step_stats_ms": stats,
+        "gpu_clocks": {"before": clocks_before, "after": clocks_after},
         "batched_speedup_vs_per_view": (ms_per_view / ms_batched) if ms_per_view else None,
         "work": {"tile_pairs": pairs, "contributing_fragments": frags, "evaluated_bound": evals_bound},
         "phase_ms": {k: round(v, 4) for k, v in ph_iter.items()},
@@ -499,6 +703,9 @@ def main():
         "bwd_reduction_forms": bwd_forms,
         "memory": memory,
         "cpu_baseline": cpu,
+        "cpu_baseline_c0_one_thread": cpu1,
+        "autograd_step": autograd,
+        "c4": c4,
         "mapping_ops": mapping_ops,
         "tracking": tracking,
         "wall_s_timed": wall,
