@@ -22,8 +22,8 @@
 // of one record per lane.  It recomputes alpha and transmittance with the same
 // instructions as the forward, so no per-fragment state is stored: only the bits and the
 // per-pixel count of list entries up to the last contributing fragment.  The suffix sums
-// that the alpha derivative needs are recovered as (sum over all fragments) - (prefix
-// sum), the total coming from the forward's outputs.  Per record the wave needs up to 13
+// that the alpha derivative needs are carried as a remainder: it starts at the sum over
+// all fragments (from the forward's outputs) and each walked fragment subtracts its share.  Per record the wave needs up to 13
 // sums over its pixels: the moments of alpha dL/dalpha over the pixel offsets (from which
 // the mean, conic and opacity gradients follow) and the colour, depth and point sums.
 // With one pixel per lane these are a dense contraction (per-wave constant functions of
@@ -396,18 +396,17 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
     const float px = (float)lx;
     const float amin = rs.alpha_min, amax = rs.alpha_max;
     const int i = tp.tx * TILE + lx;
-    // Per-pixel upstream gradient and G = sum_k w_k (g . e_k) + T_final (g_C . bg), the
-    // total that the forward's outputs give.
+    // Per-pixel upstream gradient and, to start the walk's remainder Rem, the total
+    // G = sum_k w_k (g . e_k) + T_final (g_C . bg) that the forward's outputs give.
     uint32_t my_last[PPT];
-    float gC0[PPT], gC1[PPT], gC2[PPT], gD[PPT], gA[PPT], gX0[PPT], gX1[PPT], gX2[PPT], Gb[PPT], py[PPT];
-    float T[PPT], Pfx[PPT];
+    float gC0[PPT], gC1[PPT], gC2[PPT], gD[PPT], gA[PPT], gX0[PPT], gX1[PPT], gX2[PPT], Rem[PPT], py[PPT];
+    float T[PPT];
     uint32_t thread_last = 0;
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
         my_last[k] = 0;
-        gC0[k] = gC1[k] = gC2[k] = gD[k] = gA[k] = gX0[k] = gX1[k] = gX2[k] = Gb[k] = 0.f;
+        gC0[k] = gC1[k] = gC2[k] = gD[k] = gA[k] = gX0[k] = gX1[k] = gX2[k] = Rem[k] = 0.f;
         T[k] = 1.0f;
-        Pfx[k] = 0.0f;
         py[k] = (float)(ly + k);
         const int j = tp.ty * TILE + ly + k;
         if (!(i < tp.W && j < tp.H)) continue;
@@ -426,18 +425,18 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
         const bool none = gC0[k] == 0.f && gC1[k] == 0.f && gC2[k] == 0.f && gD[k] == 0.f && gA[k] == 0.f &&
                           gX0[k] == 0.f && gX1[k] == 0.f && gX2[k] == 0.f;
         // The rgb output holds sum_k w_k c_k + T_final bg, which is exactly what G needs.
-        Gb[k] = gC0[k] * fwd.rgb[o3] + gC1[k] * fwd.rgb[o3 + plane] + gC2[k] * fwd.rgb[o3 + 2 * plane] +
+        Rem[k] = gC0[k] * fwd.rgb[o3] + gC1[k] * fwd.rgb[o3 + plane] + gC2[k] * fwd.rgb[o3 + 2 * plane] +
                 gD[k] * fwd.depth[pix] + gA[k] * (1.0f - Tf);
         if (FRAME == 2) {
             // Eq. 5: the pointmap is D K^-1 [i, j, 1]^T, a function of the depth only.
             const float rx = ((float)i - vt.cx[tp.v]) / vt.fx[tp.v];
             const float ry = ((float)j - vt.cy[tp.v]) / vt.fy[tp.v];
             const float gXD = gX0[k] * rx + gX1[k] * ry + gX2[k];
-            Gb[k] += gXD * fwd.depth[pix];
+            Rem[k] += gXD * fwd.depth[pix];
             gD[k] += gXD;
             gX0[k] = gX1[k] = gX2[k] = 0.f;
         } else {
-            Gb[k] += gX0[k] * fwd.pointmap[o3] + gX1[k] * fwd.pointmap[o3 + plane] +
+            Rem[k] += gX0[k] * fwd.pointmap[o3] + gX1[k] * fwd.pointmap[o3 + plane] +
                      gX2[k] * fwd.pointmap[o3 + 2 * plane];
         }
         if (FRAME == 1) {
@@ -601,20 +600,22 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
             // The first pixel assigns, later ones accumulate (x + 0 is not folded).
             auto add = [&](int t, float x) { v[t] = k == 0 ? x : v[t] + x; };
             auto mad = [&](int t, float x, float y) { v[t] = k == 0 ? x * y : fmaf(x, y, v[t]); };
-            // Branch-free: an invalid pixel gets zero weight and leaves T unchanged
-            // (e <= 0, so alpha lies in [0, alpha_max] and 1 - alpha >= 1 - alpha_max).
+            // Branch-free: an invalid pixel takes alpha = 0, so its weight and its alpha
+            // gradient are 0 and T * (1 - 0) leaves T unchanged.
             const float dy = py[k] - a.y;
-            const float al = fminf(amax, b.z * __builtin_amdgcn_exp2f(e[k]));
-            const float w = valid[k] ? __fmul_rn(al, T[k]) : 0.0f;
+            const float al = valid[k] ? fminf(amax, b.z * __builtin_amdgcn_exp2f(e[k])) : 0.0f;
+            const float w = __fmul_rn(al, T[k]);
             float sv = fmaf(gC0[k], cc.x, fmaf(gC1[k], cc.y, fmaf(gC2[k], cc.z, gA[k])));
             if (V::kDepth) sv = fmaf(gD[k], cc.w, sv);
             if (V::kPoint) sv = fmaf(gX0[k], d.x, fmaf(gX1[k], d.y, fmaf(gX2[k], d.z, sv)));
-            Pfx[k] = fmaf(w, sv, Pfx[k]);
+            // Rem = G - sum of w s over this and earlier fragments: the later fragments'
+            // share plus the background term.
+            Rem[k] = fmaf(-w, sv, Rem[k]);
             const float one_m = __fsub_rn(1.0f, al);
-            const float dLda = T[k] * sv - (Gb[k] - Pfx[k]) * __builtin_amdgcn_rcpf(one_m);
-            const float g = (valid[k] && al < amax) ? dLda * al : 0.0f;
+            const float dLda = T[k] * sv - Rem[k] * __builtin_amdgcn_rcpf(one_m);
+            const float g = al < amax ? dLda * al : 0.0f;  // 0 where alpha is clamped
+            T[k] = __fmul_rn(T[k], one_m);
             if constexpr (kMfma) {
-                T[k] = valid[k] ? __fmul_rn(T[k], one_m) : T[k];
                 float *bw = mf_b[wv] + bofs + 4 * slot;
                 bw[0] = g;
                 bw[4 * kSlots] = w;
@@ -639,7 +640,6 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
                 mad(t++, w, gX1[k]);
                 mad(t++, w, gX2[k]);
             }
-            T[k] = valid[k] ? __fmul_rn(T[k], one_m) : T[k];
         }
         if constexpr (kMfma) {
             if (lane == 0) mf_meta[wv][slot] = make_float4(a.x, a.y, b.w, 0.0f);
