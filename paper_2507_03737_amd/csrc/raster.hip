@@ -67,10 +67,11 @@ __device__ inline TilePos tile_pos(const ViewTable &vt, const uint32_t *order) {
     return p;
 }
 
-// Stage record r into LDS slot q, in tile-local pixel coordinates, with the exponent
-// threshold e_min = log2(alpha_min / opacity): alpha >= alpha_min exactly when the
-// base-2 exponent e >= e_min, so rejected pixels never evaluate the exponential.
-//   s0 = (u, v, a, b), s1 = (c, e_min, opacity, record index), s2 = (colour, z), s3 = point
+// Stage record r into LDS slot q, in tile-local pixel coordinates, with the threshold
+// -e_min, e_min = log2(alpha_min / opacity): alpha >= alpha_min exactly when the base-2
+// exponent e = -s >= e_min, i.e. s <= -e_min, so rejected pixels never evaluate the
+// exponential.
+//   s0 = (u, v, a, b), s1 = (c, -e_min, opacity, record index), s2 = (colour, z), s3 = point
 // with (a, b, c) the factored conic of the record.
 // The acceptance test reads s0 and s1 only.
 __device__ inline void stage(const float4 *__restrict__ rec, uint32_t r, float x0, float y0, float alpha_min,
@@ -80,16 +81,17 @@ __device__ inline void stage(const float4 *__restrict__ rec, uint32_t r, float x
     const float ul = (a.x - x0) + a.z;
     const float vl = (a.y - y0) + a.w;
     s0[q] = make_float4(ul, vl, b.x, b.y);
-    s1[q] = make_float4(b.z, __log2f(alpha_min / b.w), b.w, __uint_as_float(r));
+    s1[q] = make_float4(b.z, -__log2f(alpha_min / b.w), b.w, __uint_as_float(r));
     s2[q] = c;
     s3[q] = d;
 }
 
-// Base-2 exponent of a Gaussian at a pixel offset (dx, dy) from its mean, from the
-// factored conic and the per-column term a dx: e = -((a dx + b dy)^2 + (c dy)^2).
-__device__ inline float quad_e(float adx, float b, float c, float dy) {
+// Negated base-2 exponent of a Gaussian at a pixel offset (dx, dy) from its mean, from
+// the factored conic and the per-column term a dx: s = -e = (a dx + b dy)^2 + (c dy)^2.
+// A NaN offset gives NaN, which fails every threshold test.
+__device__ inline float quad_s(float adx, float b, float c, float dy) {
     const float q1 = fmaf(b, dy, adx), q2 = c * dy;
-    return -fmaf(q1, q1, q2 * q2);
+    return fmaf(q1, q1, q2 * q2);
 }
 
 // Lane layout of a (TILE, PPT) workgroup: wave w owns a WW x WH pixel rectangle.
@@ -124,7 +126,7 @@ __device__ inline float edge_max(float P, float Q, float R, float d, float lo, f
     return fmaf(fmaf(R, t, Q * d), t, P * d * d);
 }
 
-// Whether a staged record (s0 = (u, v, A, B), s1 = (C, e_min, ...)) can reach its threshold
+// Whether a staged record (s0 = (u, v, a, b), s1 = (c, -e_min, ...)) can reach its threshold
 // at a pixel centre of the rectangle [x0, x1] x [y0, y1].  The exponent is concave, so its
 // maximum over the rectangle is 0 when the mean lies inside and otherwise lies on an edge,
 // where it is a one-dimensional concave quadratic.  The margin exceeds the float rounding
@@ -136,12 +138,12 @@ __device__ inline bool meets_rect(const float4 a, const float4 b, float x0, floa
     // rounding is far inside the margin below).
     const float A = -a.z * a.z, B = -2.0f * a.z * a.w, C = -fmaf(a.w, a.w, b.x * b.x);
     const float ax = x0 - a.x, bx = x1 - a.x, ay = y0 - a.y, by = y1 - a.y;
-    if (ax <= 0.f && bx >= 0.f && ay <= 0.f && by >= 0.f) return b.y <= 0x1p-10f;
+    if (ax <= 0.f && bx >= 0.f && ay <= 0.f && by >= 0.f) return -b.y <= 0x1p-10f;
     float m = fmaxf(edge_max(A, B, C, ax, ay, by), edge_max(A, B, C, bx, ay, by));
     m = fmaxf(m, fmaxf(edge_max(C, B, A, ay, ax, bx), edge_max(C, B, A, by, ax, bx)));
     const float DX = fmaxf(fabsf(ax), fabsf(bx)), DY = fmaxf(fabsf(ay), fabsf(by));
     const float S = fmaf(fabsf(A) * DX, DX, fmaf(fabsf(B) * DX, DY, fabsf(C) * DY * DY));
-    return m >= b.y - fmaf(0x1p-16f, S, 0x1p-10f);
+    return m >= -b.y - fmaf(0x1p-16f, S, 0x1p-10f);
 }
 
 // Ballot mask of the batch entries [c, c + 64) that this wave must walk.
@@ -178,27 +180,26 @@ k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
     const float amin = rs.alpha_min, amax = rs.alpha_max, tmin = rs.t_min;
     const int i = tp.tx * TILE + lx;
 
-    float T[PPT], C0[PPT], C1[PPT], C2[PPT], D[PPT], X0[PPT], X1[PPT], X2[PPT], py[PPT];
-    // 0 while the pixel composites, -inf once it has stopped (or lies outside the view).
-    // Added to the exponent, it turns the acceptance test into one comparison, whose lane
-    // mask is the wave's ballot as it stands.
-    float bias[PPT];
+    float T[PPT], C0[PPT], C1[PPT], C2[PPT], D[PPT], X0[PPT], X1[PPT], X2[PPT];
+    // The pixel's tile-local row while it composites; NaN once it has stopped (or if it
+    // lies outside the view), which makes the exponent NaN, so that the acceptance test
+    // stays one comparison whose lane mask is the wave's ballot as it stands.
+    float py[PPT];
     uint32_t n_last[PPT], n_contrib[PPT];
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
         T[k] = 1.0f;
         C0[k] = C1[k] = C2[k] = D[k] = X0[k] = X1[k] = X2[k] = 0.f;
         n_last[k] = n_contrib[k] = 0u;
-        py[k] = (float)(ly + k);
         const int j = tp.ty * TILE + ly + k;
-        bias[k] = (i < tp.W && j < tp.H) ? 0.0f : -INFINITY;
+        py[k] = (i < tp.W && j < tp.H) ? (float)(ly + k) : __builtin_nanf("");
     }
     // Whether any pixel of this lane is still compositing.  Re-evaluated once per 64
     // entries: a wave whose pixels have all stopped walks at most the rest of one mask.
     auto lane_live = [&]() {
         bool l = false;
 #pragma unroll
-        for (int k = 0; k < PPT; ++k) l |= bias[k] == 0.0f;
+        for (int k = 0; k < PPT; ++k) l |= py[k] == py[k];
         return l;
     };
     bool wave_live = ballot(lane_live()) != 0ull;
@@ -219,13 +220,13 @@ k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
                 asm volatile("" ::"v"(b.z), "v"(b.w));
                 const float dx = px - a.x;
                 const float adx = a.z * dx;
-                float e[PPT];
+                float sq[PPT];
                 bool ok[PPT];
                 uint64_t pass = 0ull;
 #pragma unroll
                 for (int k = 0; k < PPT; ++k) {
-                    e[k] = quad_e(adx, a.w, b.x, py[k] - a.y) + bias[k];
-                    ok[k] = e[k] >= b.y;
+                    sq[k] = quad_s(adx, a.w, b.x, py[k] - a.y);
+                    ok[k] = sq[k] <= b.y;
                     pass |= ballot(ok[k]);
                 }
                 if (pass == 0ull) continue;  // wave-uniform: nothing composites this entry
@@ -239,10 +240,11 @@ k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
                 bool added = false;
 #pragma unroll
                 for (int k = 0; k < PPT; ++k) {
-                    const float al = fminf(amax, b.z * __builtin_amdgcn_exp2f(e[k]));
-                    const float Tn = __fmul_rn(T[k], __fsub_rn(1.0f, al));
-                    const bool stop = ok[k] && Tn < tmin;
-                    const bool add = ok[k] && !stop;
+                    const float al = fminf(amax, b.z * __builtin_amdgcn_exp2f(-sq[k]));
+                    const float Tn = fmaf(-al, T[k], T[k]);  // T (1 - alpha), rounded once
+                    const bool low = Tn < tmin;
+                    const bool stop = ok[k] && low;
+                    const bool add = ok[k] && !low;
                     const float w = add ? __fmul_rn(al, T[k]) : 0.0f;
                     C0[k] = fmaf(w, cc.x, C0[k]);
                     C1[k] = fmaf(w, cc.y, C1[k]);
@@ -256,7 +258,7 @@ k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
                     T[k] = add ? Tn : T[k];
                     n_last[k] = add ? rel : n_last[k];
                     if (COUNT) n_contrib[k] += add ? 1u : 0u;
-                    bias[k] = stop ? -INFINITY : bias[k];
+                    py[k] = stop ? __builtin_nanf("") : py[k];
                     added |= add;
                 }
                 if (visible) {  // uniform: marking requested
@@ -577,14 +579,14 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
     auto walk_record = [&](const float4 &a, const float4 &b, const float4 &cc, const float4 &d, uint32_t rel) {
         const float dx = px - a.x;
         const float adx = a.z * dx;
-        float e[PPT];
+        float sq[PPT];
         bool valid[PPT];
         uint64_t any = 0ull;
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
-            e[k] = quad_e(adx, a.w, b.x, py[k] - a.y);
+            sq[k] = quad_s(adx, a.w, b.x, py[k] - a.y);
             // One comparison decides (its lane mask is the ballot as it stands).
-            valid[k] = (rel < my_last[k] ? e[k] : -INFINITY) >= b.y;
+            valid[k] = (rel < my_last[k] ? sq[k] : __builtin_nanf("")) <= b.y;
             any |= ballot(valid[k]);
         }
         if constexpr (kMfma) {
@@ -603,7 +605,7 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
             // Branch-free: an invalid pixel takes alpha = 0, so its weight and its alpha
             // gradient are 0 and T * (1 - 0) leaves T unchanged.
             const float dy = py[k] - a.y;
-            const float al = valid[k] ? fminf(amax, b.z * __builtin_amdgcn_exp2f(e[k])) : 0.0f;
+            const float al = valid[k] ? fminf(amax, b.z * __builtin_amdgcn_exp2f(-sq[k])) : 0.0f;
             const float w = __fmul_rn(al, T[k]);
             float sv = fmaf(gC0[k], cc.x, fmaf(gC1[k], cc.y, fmaf(gC2[k], cc.z, gA[k])));
             if (V::kDepth) sv = fmaf(gD[k], cc.w, sv);
@@ -614,7 +616,7 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
             const float one_m = __fsub_rn(1.0f, al);
             const float dLda = T[k] * sv - Rem[k] * __builtin_amdgcn_rcpf(one_m);
             const float g = al < amax ? dLda * al : 0.0f;  // 0 where alpha is clamped
-            T[k] = __fmul_rn(T[k], one_m);
+            T[k] = fmaf(-al, T[k], T[k]);  // as in the forward
             if constexpr (kMfma) {
                 float *bw = mf_b[wv] + bofs + 4 * slot;
                 bw[0] = g;
