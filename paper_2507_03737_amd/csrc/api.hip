@@ -393,10 +393,8 @@ gspm_status gspm_render_forward(gspm_ctx *ctx, const gspm_gaussians *g, const gs
         // 2. Keep the records that have tile pairs (in record order) and sort them by float32
         //    depth (stable, so ties keep record order).
         PhaseTimer t_ds(ctx, hs, GSPM_PHASE_DEPTH_SORT);
-        GSPM_HIP(launch_scan_indirect(counts, nullptr, R, static_cast<uint32_t *>(ctx->offsets.p), n_live, part, hs,
-                                      nullptr, 1));
-        GSPM_HIP(launch_compact(counts, static_cast<uint32_t *>(ctx->offsets.p), static_cast<uint32_t *>(ctx->dkey.p), R,
-                                static_cast<uint32_t *>(ctx->dval.p), static_cast<uint32_t *>(ctx->live.p), pack, hs));
+        GSPM_HIP(launch_compact(counts, static_cast<uint32_t *>(ctx->dkey.p), R, static_cast<uint32_t *>(ctx->dval.p),
+                                static_cast<uint32_t *>(ctx->live.p), n_live, part, pack, hs));
         GSPM_HIP(radix_sort(static_cast<uint32_t *>(ctx->dval.p), static_cast<uint32_t *>(ctx->live.p),
                             static_cast<uint32_t *>(ctx->dkey_tmp.p), static_cast<uint32_t *>(ctx->dval_tmp.p),
                             static_cast<uint32_t *>(ctx->dkey_s.p), static_cast<uint32_t *>(ctx->dval_s.p), R, n_live,

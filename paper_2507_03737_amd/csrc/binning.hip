@@ -121,6 +121,43 @@ k_scan_apply(const uint32_t *__restrict__ counts, const uint32_t *__restrict__ i
     }
 }
 
+// The flag scan's second half fused with the compaction: the records with counts[r] != 0
+// go to consecutive positions in record order, with the depth key in ckey and the record
+// index (with pack, also its pair count) in cval.  Same chunking as k_scan_apply; part
+// holds each block's exclusive prefix of live records.
+__global__ void __launch_bounds__(kScanBlock)
+k_scan_compact(const uint32_t *__restrict__ counts, const uint32_t *__restrict__ dkey, int64_t n,
+               const uint32_t *__restrict__ part, uint32_t *__restrict__ ckey, uint32_t *__restrict__ cval,
+               int pack) {
+    __shared__ uint32_t lds[kScanBlock / kWave];
+    const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t b0 = (int64_t)blockIdx.x * chunk;
+    const int64_t b1 = b0 + chunk < n ? b0 + chunk : n;
+    uint32_t running = part[blockIdx.x];
+    for (int64_t base = b0; base < b1; base += kScanTile) {
+        uint32_t c[kScanItems];
+        uint32_t live = 0;
+        const int64_t p0 = base + (int64_t)threadIdx.x * kScanItems;
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            const int64_t p = p0 + k;
+            c[k] = p < b1 ? counts[p] : 0u;
+            live += c[k] != 0u ? 1u : 0u;
+        }
+        uint32_t tot;
+        uint32_t pos = running + block_exclusive_scan(live, lds, tot);
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            if (c[k] == 0u) continue;
+            const int64_t p = p0 + k;
+            ckey[pos] = dkey[p];
+            cval[pos] = pack ? (uint32_t)p | (min(c[k], kPackCountMax) << kPackShift) : (uint32_t)p;
+            ++pos;
+        }
+        running += tot;
+    }
+}
+
 // ------------------------------- radix sort -------------------------------------------
 //
 // LSD radix sort with one histogram pass for every digit and one kernel per digit pass
@@ -542,26 +579,16 @@ hipError_t launch_scan_indirect(const uint32_t *counts, const uint32_t *idx, int
     return hipGetLastError();
 }
 
-// Records with at least one tile pair, compacted in record order: ckey/cval get the depth
-// key and record index at position flag_scan[r].
-__global__ void __launch_bounds__(256)
-k_compact(const uint32_t *__restrict__ counts, const uint32_t *__restrict__ flag_scan, const uint32_t *__restrict__ dkey,
-          int64_t n, uint32_t *__restrict__ ckey, uint32_t *__restrict__ cval, int pack) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n) return;
-    const uint32_t c = counts[r];
-    if (c == 0u) return;
-    const uint32_t pos = flag_scan[r];
-    ckey[pos] = dkey[r];
-    cval[pos] = pack ? (uint32_t)r | (min(c, kPackCountMax) << kPackShift) : (uint32_t)r;
-}
-
-hipError_t launch_compact(const uint32_t *counts, const uint32_t *flag_scan, const uint32_t *dkey, int64_t n,
-                          uint32_t *ckey, uint32_t *cval, bool pack, hipStream_t s) {
+hipError_t launch_compact(const uint32_t *counts, const uint32_t *dkey, int64_t n, uint32_t *ckey, uint32_t *cval,
+                          uint32_t *n_live, uint32_t *part, bool pack, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     if (pack && n > (int64_t)kPackMask + 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_compact, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, counts, flag_scan, dkey, n, ckey,
-                       cval, pack ? 1 : 0);
+    const int64_t nb = scan_blocks(n);
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanBlock), 0, s, counts, nullptr, nullptr, n, 1, part,
+                       nullptr);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, part, (int)nb, n_live);
+    hipLaunchKernelGGL(k_scan_compact, dim3((unsigned)nb), dim3(kScanBlock), 0, s, counts, dkey, n, part, ckey, cval,
+                       pack ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -404,10 +404,11 @@ hipError_t launch_scan_indirect(const uint32_t *counts, const uint32_t *idx, int
                                 uint32_t *offsets, uint32_t *total, uint32_t *part, hipStream_t s,
                                 const uint32_t *n_dev = nullptr, int flag = 0, uint32_t *gathered = nullptr);
 
-// Compacts (depth key, record index) of the records with counts[r] != 0 to the positions
-// given by the flag scan; with pack, the value also carries the pair count (see kPackShift).
-hipError_t launch_compact(const uint32_t *counts, const uint32_t *flag_scan, const uint32_t *dkey, int64_t n,
-                          uint32_t *ckey, uint32_t *cval, bool pack, hipStream_t s);
+// Compacts (depth key, record index) of the records with counts[r] != 0, in record order,
+// and writes their number to *n_live; with pack, the value also carries the pair count
+// (see kPackShift).  part: scratch of at least scan_partials(n) words.
+hipError_t launch_compact(const uint32_t *counts, const uint32_t *dkey, int64_t n, uint32_t *ckey, uint32_t *cval,
+                          uint32_t *n_live, uint32_t *part, bool pack, hipStream_t s);
 
 // Stable LSD radix sort of (key, value) uint32 pairs over the low `bits` key bits, in
 // ceil(bits / digit_bits) passes of equal width (digit_bits in [4, 8]).  n_dev: device
