@@ -392,14 +392,17 @@ __device__ inline void emit_row(uint32_t *__restrict__ pkey, uint32_t *__restric
 // Records with many pairs are queued for k_keygen_big.
 //
 // A wave's records are consecutive in depth order, so their pairs form one contiguous run
-// of the output.  Each lane puts its pairs into the wave's LDS window (the first
-// kStagePairs positions of the run) and the wave then copies the window out with
-// consecutive lanes on consecutive addresses, instead of 64 lanes storing 4 bytes at 64
-// scattered places; pairs past the window are stored directly.  The window positions of
-// queued large records are copied as they stand and rewritten by k_keygen_big, which
-// runs after this kernel.
+// of the output.  The wave lists the tile rows of its records in LDS (output position,
+// first global tile, length, record; in output order) and then fills its run 64
+// positions at a time, one position per lane: the row that a position falls in is the
+// last row starting at or before it, found from the rows starting inside the 64-position
+// window (a ballot and a prefix count), so every lane emits one pair per step whatever
+// the records' sizes and the stores are consecutive.  Records whose rows the counting pass
+// did not cache (more than kSpanRowsMax rows) are emitted by their own lane, row by row;
+// positions of queued large records are left to k_keygen_big.
 constexpr int kKeygenBlock = 256;
-constexpr uint32_t kStagePairs = 1024;
+constexpr int kKeygenWaves = kKeygenBlock / kWave;
+constexpr int kKeygenRows = kWave * (int)kSpanRowsMax;  // rows of one wave's records, at most
 
 __global__ void __launch_bounds__(kKeygenBlock)
 k_keygen(const uint32_t *__restrict__ sorted_rec, uint32_t rec_mask, const uint32_t *__restrict__ sorted_counts,
@@ -408,7 +411,11 @@ k_keygen(const uint32_t *__restrict__ sorted_rec, uint32_t rec_mask, const uint3
          uint32_t *__restrict__ pval, FrameHeader *__restrict__ hdr, uint32_t cap,
          const uint32_t *__restrict__ total, uint32_t *__restrict__ big_list, uint32_t *__restrict__ big_count,
          const uint32_t *__restrict__ n_dev) {
-    __shared__ uint2 stage[kKeygenBlock / kWave][kStagePairs];
+    __shared__ uint32_t row_pos[kKeygenWaves][kKeygenRows];   // first output position
+    __shared__ uint32_t row_tile[kKeygenWaves][kKeygenRows];  // global tile id of the first tile
+    __shared__ uint32_t row_rec[kKeygenWaves][kKeygenRows];   // record index
+    __shared__ uint8_t row_len[kKeygenWaves][kKeygenRows];    // tiles (at most kBigRecord)
+    __shared__ uint8_t starts[kKeygenWaves][kWave];          // rows starting at window position
     const int wid = threadIdx.x / kWave, lane = lane_id();
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p == 0) {
@@ -440,60 +447,87 @@ k_keygen(const uint32_t *__restrict__ sorted_rec, uint32_t rec_mask, const uint3
     const bool big = c > kBigRecord;
     const uint32_t slot = wave_append(big_count, big);
     if (big) big_list[slot] = (uint32_t)p;
-    // Lane 0 holds the wave's first record (if it has none, neither has any other lane).
-    const uint32_t run0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)k);
-    const uint64_t win_end = (uint64_t)run0 + kStagePairs;
-    uint2 *win = stage[wid];
-    auto put = [&](uint32_t pos, uint32_t key) {
-        if (pos >= cap) return;
-        if ((uint64_t)pos < win_end) {
-            win[pos - run0] = make_uint2(key, r);
-        } else {
-            pkey[pos] = key;
-            pval[pos] = r;
+    const bool own = act && c != 0u && !big;
+    int v = 0, ty0 = 0, nr = 0;
+    uint32_t base = 0, tiles_x = 0;
+    uint4 sp = make_uint4(0u, 0u, 0u, 0u);
+    if (own) {
+        v = (int)(r / (uint32_t)n_per_view);  // 32-bit: record indices fit
+        base = (uint32_t)vt.tile_off[v];
+        tiles_x = (uint32_t)vt.tiles_x[v];
+        sp = spans[r];
+        nr = (int)(sp.x >> 16);
+        ty0 = (int)(sp.x & 0xffffu);
+    }
+    const bool cached = own && nr <= (int)kSpanRowsMax;
+    // This lane's non-empty rows, their place in the wave's row list, then the list.
+    uint32_t n_rows = 0;
+    if (cached) {
+        for (int i = 0; i < nr; ++i) {
+            int ta, tb;
+            span_row(sp, nr, i, ta, tb);
+            n_rows += ta <= tb ? 1u : 0u;
         }
-    };
-    if (act && c != 0u && !big) {
-        const int v = (int)(r / (uint32_t)n_per_view);  // 32-bit: record indices fit
-        const uint32_t base = (uint32_t)vt.tile_off[v], tiles_x = (uint32_t)vt.tiles_x[v];
-        uint32_t pos = k;
-        auto row = [&](int ty, int ta, int tb) {
-            for (int tx = ta; tx <= tb; ++tx) put(pos++, base + (uint32_t)ty * tiles_x + (uint32_t)tx);
-        };
-        const uint4 sp = spans[r];
-        const uint32_t nr = sp.x >> 16;
-        if (nr <= kSpanRows) {  // the counting pass cached the rows
-            const int ty0 = (int)(sp.x & 0xffffu);
-#pragma unroll
-            for (uint32_t i = 0; i < kSpanRows; ++i) {
-                if (i >= nr) break;
-                const uint32_t w = i == 0 ? sp.y : (i == 1 ? sp.z : sp.w);
-                const int ta = (int)(w & 0xffffu), tb = (int)(w >> 16);
-                if (ta <= tb) row(ty0 + (int)i, ta, tb);
-            }
-        } else {
-            Footprint f;
-            if (record_footprint(rec[4 * (int64_t)r], rec[4 * (int64_t)r + 1], rs.alpha_min, vt.width[v],
-                                 vt.height[v], f)) {
-                const int T = vt.tile, sh = __builtin_ctz((unsigned)vt.tile);
-                for (int ty = f.j0 >> sh; ty <= f.j1 >> sh; ++ty) {
-                    int ta, tb;
-                    if (row_span(f, T, ty, ta, tb)) row(ty, ta, tb);
-                }
+    }
+    const uint32_t inc = wave_inclusive_scan(n_rows);
+    const uint32_t rows_wave = (uint32_t)__shfl((int)inc, kWave - 1, kWave);
+    if (cached) {
+        uint32_t t = inc - n_rows, pos = k;
+        for (int i = 0; i < nr; ++i) {
+            int ta, tb;
+            span_row(sp, nr, i, ta, tb);
+            if (ta > tb) continue;
+            row_pos[wid][t] = pos;
+            row_tile[wid][t] = base + (uint32_t)(ty0 + i) * tiles_x + (uint32_t)ta;
+            row_rec[wid][t] = r;
+            row_len[wid][t] = (uint8_t)(tb - ta + 1);
+            pos += (uint32_t)(tb - ta + 1);
+            ++t;
+        }
+    } else if (own) {
+        // Not cached: this lane evaluates its rows and stores its pairs itself.
+        Footprint f;
+        if (record_footprint(rec[4 * (int64_t)r], rec[4 * (int64_t)r + 1], rs.alpha_min, vt.width[v], vt.height[v],
+                             f)) {
+            const int T = vt.tile, sh = __builtin_ctz((unsigned)vt.tile);
+            uint32_t kk = k;
+            for (int ty = f.j0 >> sh; ty <= f.j1 >> sh; ++ty) {
+                int ta, tb;
+                if (row_span(f, T, ty, ta, tb)) emit_row(pkey, pval, cap, kk, base, tiles_x, ty, ta, tb, r);
             }
         }
     }
-    // The run ends at the largest end of the wave's records (queued ones included).
+    // The run ends at the largest end of the wave's records (queued ones included); lane 0
+    // holds the wave's first record (if it has none, neither has any other lane).
+    const uint32_t run0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)k);
     uint32_t end = act ? k + c : run0;
     for (int off = 32; off > 0; off >>= 1) end = max(end, (uint32_t)__shfl_xor((int)end, off, 64));
-    uint64_t stop = end;
-    if (stop > win_end) stop = win_end;
-    if (stop > cap) stop = cap;
-    __builtin_amdgcn_wave_barrier();  // the window is complete (one wave's LDS accesses stay in order)
-    for (uint64_t j = run0 + (uint32_t)lane; j < stop; j += kWave) {
-        const uint2 e = win[j - run0];
-        pkey[j] = e.x;
-        pval[j] = e.y;
+    if (end > cap) end = cap;
+    const uint64_t le = (lane == kWave - 1) ? ~0ull : ((2ull << lane) - 1ull);  // lanes <= this one
+    uint32_t before = 0;  // rows starting before the window
+    __builtin_amdgcn_wave_barrier();  // the row list is written (one wave's LDS accesses stay in order)
+    for (uint32_t j0 = run0; j0 < end; j0 += kWave) {
+        starts[wid][lane] = 0;
+        __builtin_amdgcn_wave_barrier();
+        // Rows are in output order: those starting in this window follow the earlier ones.
+        const uint32_t t = before + (uint32_t)lane;
+        if (t < rows_wave) {
+            const uint32_t s0 = row_pos[wid][t];
+            if (s0 < j0 + kWave) starts[wid][s0 - j0] = 1;
+        }
+        __builtin_amdgcn_wave_barrier();
+        const uint64_t m = ballot(starts[wid][lane] != 0);
+        const uint32_t j = j0 + (uint32_t)lane;
+        const int owner = (int)(before + (uint32_t)__popcll(m & le)) - 1;
+        if (owner >= 0 && j < end) {
+            const uint32_t d = j - row_pos[wid][owner];
+            if (d < (uint32_t)row_len[wid][owner]) {  // else a position of an uncached or queued record
+                pkey[j] = row_tile[wid][owner] + d;
+                pval[j] = row_rec[wid][owner];
+            }
+        }
+        before += (uint32_t)__popcll(m);
+        __builtin_amdgcn_wave_barrier();  // the marks are read before the next window clears them
     }
 }
 

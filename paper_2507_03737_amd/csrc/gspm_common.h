@@ -66,11 +66,28 @@ constexpr int64_t kMaxSortKeys = int64_t(1) << 30;
 constexpr uint32_t kBigRecord = 64;
 
 // Tile-row spans of a record, cached by the counting pass for the emission pass: x = first
-// tile row | rows << 16, then one row per word (first | last tile << 16; first > last
-// when the row is empty).  Records with more than kSpanRows rows are not cached
-// (rows = kSpanNone) and the emission evaluates them again.
+// tile row | rows << 16, then the rows (first > last when a row is empty).  Up to
+// kSpanRows rows take one word each (first | last tile << 16); kSpanRows + 1 to
+// kSpanRowsMax rows take half a word each (first | last tile << 8, the lower half first),
+// when every tile column is below 256.  Other records are not cached (rows = kSpanNone)
+// and the emission evaluates them again.
 constexpr uint32_t kSpanRows = 3;
+constexpr uint32_t kSpanRowsMax = 6;
 constexpr uint32_t kSpanNone = 0xffffu;
+
+// Row i < rows of a cached span: tiles [ta, tb] of tile row (x & 0xffff) + i.
+__device__ inline void span_row(const uint4 sp, int rows, int i, int &ta, int &tb) {
+    if (rows <= (int)kSpanRows) {
+        const uint32_t w = i == 0 ? sp.y : (i == 1 ? sp.z : sp.w);
+        ta = (int)(w & 0xffffu);
+        tb = (int)(w >> 16);
+    } else {
+        const uint32_t w = (i >> 1) == 0 ? sp.y : ((i >> 1) == 1 ? sp.z : sp.w);
+        const uint32_t h = (w >> (16 * (i & 1))) & 0xffffu;
+        ta = (int)(h & 0xffu);
+        tb = (int)(h >> 8);
+    }
+}
 
 // Frame-state layout (caller-owned device buffer).
 struct FrameHeader {

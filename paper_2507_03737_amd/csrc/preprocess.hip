@@ -171,15 +171,29 @@ k_preprocess(gspm_gaussians G, ViewTable vt, const float *__restrict__ T_cw, Ras
                         spans[r] = make_uint4(kSpanNone << 16, 0u, 0u, 0u);
                     } else {
                         uint32_t w[kSpanRows] = {1u, 1u, 1u};  // empty rows: first > last
+                        uint32_t h[kSpanRows] = {0x00010001u, 0x00010001u, 0x00010001u};  // two rows a word
+                        bool narrow = true;  // every tile column below 256
                         for (int ty = f.j0 >> sh, k = 0; ty <= f.j1 >> sh; ++ty, ++k) {
                             int ta, tb;
                             if (row_span(f, T, ty, ta, tb)) {
                                 count += (uint32_t)(tb - ta + 1);
                                 if (k < (int)kSpanRows) w[k] = (uint32_t)ta | ((uint32_t)tb << 16);
+                                if (k < (int)kSpanRowsMax) {
+                                    narrow = narrow && tb < 256;
+                                    const int q = k >> 1, sft = 16 * (k & 1);
+                                    h[q] = (h[q] & ~(0xffffu << sft)) | (((uint32_t)ta | ((uint32_t)tb << 8)) << sft);
+                                }
                             }
                         }
-                        const uint32_t nr = rows <= (int)kSpanRows ? (uint32_t)rows : kSpanNone;
-                        if (count != 0u) spans[r] = make_uint4((uint32_t)(f.j0 >> sh) | (nr << 16), w[0], w[1], w[2]);
+                        if (count != 0u) {
+                            const uint32_t x0 = (uint32_t)(f.j0 >> sh);
+                            if (rows <= (int)kSpanRows)
+                                spans[r] = make_uint4(x0 | ((uint32_t)rows << 16), w[0], w[1], w[2]);
+                            else if (rows <= (int)kSpanRowsMax && narrow)
+                                spans[r] = make_uint4(x0 | ((uint32_t)rows << 16), h[0], h[1], h[2]);
+                            else
+                                spans[r] = make_uint4(x0 | (kSpanNone << 16), 0u, 0u, 0u);
+                        }
                     }
                 }
             }
