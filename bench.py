@@ -488,6 +488,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip timing the mapping-side operations")
     ap.add_argument("--no-c4", action="store_true", help="skip the large-window (c4) leg")
     ap.add_argument("--no-autograd", action="store_true", help="skip the autograd-driven step")
+    ap.add_argument("--no-clocks", action="store_true",
+                    help="do not query clocks with rocm-smi (a child process; under a profiler that preloads "
+                         "itself into children, its interpreter start is refused)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a copy of known size (for scaling HBM traffic counters)")
     args = ap.parse_args()
@@ -537,7 +540,7 @@ def main():
     rast.cfg.count_work = 0
     log(f"[bench] pairs={pairs} contributing fragments={frags}")
 
-    clocks_before = gpu_clocks()
+    clocks_before = None if args.no_clocks else gpu_clocks()
     stats = {"batched_eager": {}, "batched_graph": {}, "per_view_eager": {}}
     rast.ctx.timing(True)
     ms_batched, wall = time_steps(step.run, args.steps, args.warmup, torch, stats["batched_eager"])
@@ -646,7 +649,7 @@ def main():
     free1, _ = torch.cuda.mem_get_info(dev)
     memory = {"device_used_bytes": int(free0 - free1), "torch_peak_bytes": int(torch.cuda.max_memory_allocated(dev)),
               "device_total_bytes": int(total_mem)}
-    clocks_after = gpu_clocks()
+    clocks_after = None if args.no_clocks else gpu_clocks()
 
     c4 = None
     if not args.no_c4 and args.workload == "c3":
