@@ -31,6 +31,8 @@
 // time; with several pixels per lane each lane adds its pixels' contributions and the
 // wave adds them up with one reduce-scatter (cross-half lane swaps and DPP) of 8, 12 or
 // 16 values.  Either way the atomics are paid once per wave and record.
+#include <type_traits>
+
 #include "gspm_common.h"
 
 namespace gspm {
@@ -85,6 +87,10 @@ __device__ inline void stage(const float4 *__restrict__ rec, uint32_t r, float x
     s2[q] = c;
     s3[q] = d;
 }
+
+// min(alpha_max, a) for a >= 0, as one median instruction (min would first quiet a
+// signalling NaN in the kernel-argument operand, on every call).
+__device__ inline float clamp_alpha(float a, float amax) { return __builtin_amdgcn_fmed3f(a, 0.0f, amax); }
 
 // Negated base-2 exponent of a Gaussian at a pixel offset (dx, dy) from its mean, from
 // the factored conic and the per-column term a dx: s = -e = (a dx + b dy)^2 + (c dy)^2.
@@ -388,9 +394,9 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
     // 272 (kb / 4) + 68 c + 4 j + kb % 4: a lane's four values of one kb quarter are one
     // 16-byte read, each read phase of 16 lanes is contiguous, and the 64 pixels of one
     // column fall in 64 different banks (no conflicts either way).
-    constexpr int kBq = 272, kBc = 68;
-    __shared__ __align__(16) float mf_b[kMfma ? L::NW : 1][kMfma ? 4 * kBq : 4];
-    __shared__ float4 mf_meta[kMfma ? L::NW : 1][kSlots];
+    // Slot s's record (mean, index) follows at kMeta + 4 s: (u, v, -, index).
+    constexpr int kBq = 272, kBc = 68, kMeta = 4 * kBq;
+    __shared__ __align__(16) float mf_b[kMfma ? L::NW : 1][kMfma ? kMeta + 4 * kSlots : 4];
     const TilePos tp = tile_pos<TILE>(vt, order);
     const uint2 rg = ranges[tp.gt];
     const L lay;
@@ -535,7 +541,7 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int sr = 4 * h + c;  // record slot of this lane
-            const float4 mt = mf_meta[wv][sr];
+            const float4 mt = *reinterpret_cast<const float4 *>(mf_b[wv] + kMeta + 4 * sr);
             const float4 sm = *reinterpret_cast<const float4 *>(dout + sr * 20);  // S0, Sx, Sy, Sxx
             const float val = fl.has ? dout[fl.src + sr * 20] : 0.0f;
             // Moments about the wave centre -> about the record's mean (dx = x - ux):
@@ -553,7 +559,7 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
             float ga = fl.c4 ? -ux : 0.0f;
             ga = fl.c5 ? -2.0f * uy : ga;
             const float out = fmaf(ga, sm.z, fmaf(be, sm.y, fmaf(al, sm.x, val)));
-            const uint32_t rid = __float_as_uint(mt.z);
+            const uint32_t rid = __float_as_uint(mt.w);
             if (sr < n && fl.has && out != 0.f) unsafeAtomicAdd(grad2d + (int64_t)rid * kG2 + j, out);
         }
         __builtin_amdgcn_wave_barrier();  // read before later records overwrite the buffer
@@ -585,8 +591,8 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
             sq[k] = quad_s(adx, a.w, b.x, py[k] - a.y);
-            // One comparison decides (its lane mask is the ballot as it stands).
-            valid[k] = (rel < my_last[k] ? sq[k] : __builtin_nanf("")) <= b.y;
+            // Two comparisons whose lane masks are combined by a scalar AND.
+            valid[k] = rel < my_last[k] && sq[k] <= b.y;
             any |= ballot(valid[k]);
         }
         if constexpr (kMfma) {
@@ -597,54 +603,72 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
         float v[V::NR];
 #pragma unroll
         for (int t = V::N; t < V::NR; ++t) v[t] = 0.f;
+        // The per-pixel terms, in two forms.  alpha = min(alpha_max, o exp2(-s)) can only be
+        // clamped when the opacity o reaches alpha_max (rare), where a clamped alpha passes
+        // no gradient; otherwise alpha is o exp2(-s) itself (o exp2(-s) <= o for s >= 0).
+        auto pixel_terms = [&](auto may_clamp) {
+            constexpr bool kClamp = decltype(may_clamp)::value;
 #pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            // The first pixel assigns, later ones accumulate (x + 0 is not folded).
-            auto add = [&](int t, float x) { v[t] = k == 0 ? x : v[t] + x; };
-            auto mad = [&](int t, float x, float y) { v[t] = k == 0 ? x * y : fmaf(x, y, v[t]); };
-            // Branch-free: an invalid pixel takes alpha = 0, so its weight and its alpha
-            // gradient are 0 and T * (1 - 0) leaves T unchanged.
-            const float dy = py[k] - a.y;
-            const float al = valid[k] ? fminf(amax, b.z * __builtin_amdgcn_exp2f(-sq[k])) : 0.0f;
-            const float w = __fmul_rn(al, T[k]);
-            float sv = fmaf(gC0[k], cc.x, fmaf(gC1[k], cc.y, fmaf(gC2[k], cc.z, gA[k])));
-            if (V::kDepth) sv = fmaf(gD[k], cc.w, sv);
-            if (V::kPoint) sv = fmaf(gX0[k], d.x, fmaf(gX1[k], d.y, fmaf(gX2[k], d.z, sv)));
-            // Rem = G - sum of w s over this and earlier fragments: the later fragments'
-            // share plus the background term.
-            Rem[k] = fmaf(-w, sv, Rem[k]);
-            const float one_m = __fsub_rn(1.0f, al);
-            const float dLda = T[k] * sv - Rem[k] * __builtin_amdgcn_rcpf(one_m);
-            const float g = al < amax ? dLda * al : 0.0f;  // 0 where alpha is clamped
-            T[k] = fmaf(-al, T[k], T[k]);  // as in the forward
-            if constexpr (kMfma) {
-                float *bw = mf_b[wv] + bofs + 4 * slot;
-                bw[0] = g;
-                bw[4 * kSlots] = w;
-                continue;
+            for (int k = 0; k < PPT; ++k) {
+                // The first pixel assigns, later ones accumulate (x + 0 is not folded).
+                auto add = [&](int t, float x) { v[t] = k == 0 ? x : v[t] + x; };
+                auto mad = [&](int t, float x, float y) { v[t] = k == 0 ? x * y : fmaf(x, y, v[t]); };
+                // Branch-free: an invalid pixel takes alpha = 0, so its weight and its alpha
+                // gradient are 0 and T * (1 - 0) leaves T unchanged.
+                const float dy = py[k] - a.y;
+                const float ao = b.z * __builtin_amdgcn_exp2f(-sq[k]);
+                const float al = valid[k] ? (kClamp ? clamp_alpha(ao, amax) : ao) : 0.0f;
+                const float w = __fmul_rn(al, T[k]);
+                float sv = fmaf(gC0[k], cc.x, fmaf(gC1[k], cc.y, fmaf(gC2[k], cc.z, gA[k])));
+                if (V::kDepth) sv = fmaf(gD[k], cc.w, sv);
+                if (V::kPoint) sv = fmaf(gX0[k], d.x, fmaf(gX1[k], d.y, fmaf(gX2[k], d.z, sv)));
+                // Rem = G - sum of w s over this and earlier fragments: the later fragments'
+                // share plus the background term.
+                Rem[k] = fmaf(-w, sv, Rem[k]);
+                const float one_m = __fsub_rn(1.0f, al);
+                const float dLda = T[k] * sv - Rem[k] * __builtin_amdgcn_rcpf(one_m);
+                const float g = kClamp && al >= amax ? 0.0f : dLda * al;
+                T[k] = fmaf(-al, T[k], T[k]);  // as in the forward
+                if constexpr (kMfma) {
+                    float *bw = mf_b[wv] + bofs + 4 * slot;
+                    bw[0] = g;
+                    bw[4 * kSlots] = w;
+                    // The slot's record mean and index, stored by lane 0 (whose pixel offset is
+                    // 0) behind the B operand, straight from the registers they were read into.
+                    if (lane == 0) {
+                        *reinterpret_cast<float2 *>(bw + kMeta) = make_float2(a.x, a.y);
+                        bw[kMeta + 3] = b.w;
+                    }
+                    continue;
+                }
+                const float gdx = g * dx, gdy = g * dy;
+                int t = 0;
+                if (V::kOpacity) add(t++, g);
+                add(t++, gdx);
+                add(t++, gdy);
+                mad(t++, gdx, dx);
+                mad(t++, gdy, dx);
+                mad(t++, gdy, dy);
+                if (V::kColour) {
+                    mad(t++, w, gC0[k]);
+                    mad(t++, w, gC1[k]);
+                    mad(t++, w, gC2[k]);
+                }
+                if (V::kDepth) mad(t++, w, gD[k]);
+                if (V::kPoint) {
+                    mad(t++, w, gX0[k]);
+                    mad(t++, w, gX1[k]);
+                    mad(t++, w, gX2[k]);
+                }
             }
-            const float gdx = g * dx, gdy = g * dy;
-            int t = 0;
-            if (V::kOpacity) add(t++, g);
-            add(t++, gdx);
-            add(t++, gdy);
-            mad(t++, gdx, dx);
-            mad(t++, gdy, dx);
-            mad(t++, gdy, dy);
-            if (V::kColour) {
-                mad(t++, w, gC0[k]);
-                mad(t++, w, gC1[k]);
-                mad(t++, w, gC2[k]);
-            }
-            if (V::kDepth) mad(t++, w, gD[k]);
-            if (V::kPoint) {
-                mad(t++, w, gX0[k]);
-                mad(t++, w, gX1[k]);
-                mad(t++, w, gX2[k]);
-            }
+        };
+        // The opacity is wave-uniform; both are positive, so their bit patterns order as they do.
+        if (__builtin_amdgcn_readfirstlane(__float_as_int(b.z)) >= __float_as_int(amax)) {
+            pixel_terms(std::true_type{});
+        } else {
+            pixel_terms(std::false_type{});
         }
         if constexpr (kMfma) {
-            if (lane == 0) mf_meta[wv][slot] = make_float4(a.x, a.y, b.w, 0.0f);
             if (++slot == kSlots) {
                 flush(kSlots);
                 slot = 0;
