@@ -242,6 +242,9 @@ k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
                 composited |= 1ull << (q - c);
                 const float4 cc = s2[q];
                 const float4 d = s3[q];
+                // Whole 16-byte reads: a 12-byte read of one address for the whole wave keeps
+                // the LDS busy twice as long as a 16-byte one.
+                asm volatile("" ::"v"(cc.w), "v"(d.w));
                 const uint32_t rel = base - rg.x + (uint32_t)q + 1u;
                 bool added = false;
 #pragma unroll
@@ -597,7 +600,9 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
         }
         if constexpr (kMfma) {
             asm volatile("" ::"v"(cc.x), "v"(cc.y), "v"(cc.z), "v"(cc.w));
-            if constexpr (V::kPoint) asm volatile("" ::"v"(d.x), "v"(d.y), "v"(d.z));
+            // Whole 16-byte reads (a 12-byte read of one address for the whole wave keeps the
+            // LDS busy twice as long).
+            if constexpr (V::kPoint) asm volatile("" ::"v"(d.x), "v"(d.y), "v"(d.z), "v"(d.w));
         }
         if (any == 0ull) return;  // wave-uniform
         float v[V::NR];
