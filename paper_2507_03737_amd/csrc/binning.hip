@@ -714,6 +714,7 @@ __global__ void __launch_bounds__(kOrderBlock)
 k_order_tiles(uint2 *__restrict__ ranges, const uint32_t *__restrict__ work, int64_t n,
               uint32_t *__restrict__ order) {
     __shared__ uint32_t cnt[kOrderClasses];
+    __shared__ uint32_t scan_lds[kOrderBlock / kWave];
     for (int b = threadIdx.x; b < kOrderClasses; b += kOrderBlock) cnt[b] = 0u;
     __syncthreads();
     auto cls = [&](int64_t t) {
@@ -725,14 +726,12 @@ k_order_tiles(uint2 *__restrict__ ranges, const uint32_t *__restrict__ work, int
         atomicAdd(&cnt[cls(t)], 1u);
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t acc = 0;
-        for (int b = 0; b < kOrderClasses; ++b) {
-            const uint32_t c = cnt[b];
-            cnt[b] = acc;
-            acc += c;
-        }
-    }
+    // Class starts: a block-wide scan (one class per thread), not a serial loop of 256
+    // dependent LDS round trips.
+    uint32_t total;
+    const uint32_t c = threadIdx.x < kOrderClasses ? cnt[threadIdx.x] : 0u;
+    const uint32_t start = block_exclusive_scan<kOrderBlock / kWave>(c, scan_lds, total);
+    if (threadIdx.x < kOrderClasses) cnt[threadIdx.x] = start;
     __syncthreads();
     for (int64_t t = threadIdx.x; t < n; t += kOrderBlock) order[atomicAdd(&cnt[cls(t)], 1u)] = (uint32_t)t;
 }
