@@ -430,7 +430,7 @@ def large_window(steps, warmup, torch, dev):
     step = sized_step(rast, opt, target, prior, MappingStep, B)
     rast.cfg.count_work = 1
     step.run()
-    pairs, frags, _ = rast.work(step.fs)
+    pairs, frags = rast.work(step.fs)[:2]
     rast.cfg.count_work = 0
     st = {}
     rast.ctx.timing(True)
@@ -536,7 +536,7 @@ def main():
     step = MappingStep(rast, opt, target, prior)
     rast.cfg.count_work = 1  # one forward that also counts its contributing fragments
     step.run()
-    pairs, frags, evals_bound = rast.work(step.fs)
+    pairs, frags, evals_bound, walked, accepted = rast.work(step.fs)
     rast.cfg.count_work = 0
     log(f"[bench] pairs={pairs} contributing fragments={frags}")
 
@@ -696,7 +696,10 @@ def main():
         "step_stats_ms": stats,
         "gpu_clocks": {"before": clocks_before, "after": clocks_after},
         "batched_speedup_vs_per_view": (ms_per_view / ms_batched) if ms_per_view else None,
-        "work": {"tile_pairs": pairs, "contributing_fragments": frags, "evaluated_bound": evals_bound},
+        "work": {"tile_pairs": pairs, "contributing_fragments": frags, "evaluated_bound": evals_bound,
+                 "fwd_walked_wave_entries": walked, "accepted_wave_entries": accepted,
+                 "fwd_lane_evals_per_fragment": 64.0 * walked / max(1, frags),
+                 "bwd_lane_evals_per_fragment": 64.0 * accepted / max(1, frags)},
         "phase_ms": {k: round(v, 4) for k, v in ph_iter.items()},
         "autotune_ms": ({f"{r['tile']}x{r['tile']}/ppl{r['pixels_per_lane']}/bits{r['sort_digit_bits']}": round(r["ms"], 3)
                          for r in tuned} if tuned else None),

@@ -180,12 +180,15 @@ GSPM_API gspm_status gspm_render_forward(gspm_ctx *ctx, const gspm_gaussians *g,
  * GSPM_ERR_INVALID_ARG if a backward refused the frame state (see gspm_render_backward). */
 GSPM_API gspm_status gspm_frame_status(const void *frame_state, void *stream, int64_t *pairs);
 
-/* Synchronise the stream and report the work of a forward: out[0] = tile pairs,
+/* Synchronise the stream and report the work of a forward in out[5]: out[0] = tile pairs,
  * out[1] = contributing fragments (Gaussian-pixel pairs composited with alpha >=
  * alpha_min before the transmittance floor), out[2] = sum over pixels of the list
- * entries evaluated up to each pixel's last contributing fragment.  The frame state must
- * come from a forward with the same views, n_gaussians and tile, run with
- * settings.count_work != 0 (GSPM_ERR_INVALID_ARG otherwise). */
+ * entries up to each pixel's last contributing fragment, out[3] = (wave, list entry)
+ * pairs the forward's waves walked (those that passed the wave's rectangle test; each
+ * evaluates 64 lanes), out[4] = the walked pairs that a live pixel of the wave accepted
+ * (those the backward walks).  The frame state must come from a forward with the same
+ * views, n_gaussians and tile, run with settings.count_work != 0 (GSPM_ERR_INVALID_ARG
+ * otherwise). */
 GSPM_API gspm_status gspm_frame_work(gspm_ctx *ctx, const gspm_views *views, int64_t n_gaussians, int32_t tile,
                                      const void *frame_state, void *stream, int64_t *out);
 

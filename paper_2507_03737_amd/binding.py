@@ -274,10 +274,11 @@ def frame_status(frame_state, stream) -> int:
 
 
 def frame_work(ctx: Context, views: Views, n, tile, frame_state, stream):
-    """(tile pairs, contributing fragments, evaluated-list bound) of a forward; synchronises."""
-    out = (ctypes.c_int64 * 3)()
+    """(tile pairs, contributing fragments, evaluated-list bound, walked wave entries,
+    accepted wave entries) of a counting forward; synchronises."""
+    out = (ctypes.c_int64 * 5)()
     check(load().gspm_frame_work(ctx.h, ctypes.byref(views), int(n), int(tile), ptr(frame_state), stream, out))
-    return int(out[0]), int(out[1]), int(out[2])
+    return tuple(int(x) for x in out)
 
 
 def render_backward(ctx, g, views, cfg, fwd: Images, up: Images, frame_state, grads: GaussianGrads | None,

@@ -450,7 +450,8 @@ gspm_status gspm_render_forward(gspm_ctx *ctx, const gspm_gaussians *g, const gs
     PhaseTimer t_fwd(ctx, hs, GSPM_PHASE_RASTER_FWD);
     GSPM_HIP(launch_raster_forward(P.vt, P.rs, ranges, pair_vals, records, out->rgb, out->depth, out->alpha,
                                    out->pointmap, at<float>(frame_state, L0.t_final), at<uint32_t>(frame_state, L0.last),
-                                   at<uint32_t>(frame_state, L0.contrib), visible, order, twork, wmask, wstride, hs));
+                                   at<uint32_t>(frame_state, L0.contrib), visible, order, twork, wmask, wstride, hdr,
+                                   hs));
     GSPM_HIP(launch_order_tiles(nullptr, twork, P.n_tiles, order + P.n_tiles, hs));
     return GSPM_OK;
 }
@@ -498,6 +499,8 @@ gspm_status gspm_frame_work(gspm_ctx *ctx, const gspm_views *views, int64_t n_ga
     out[0] = h.pairs;
     out[1] = (int64_t)host[0];
     out[2] = (int64_t)host[1];
+    out[3] = (int64_t)h.walked;
+    out[4] = (int64_t)h.accepted;
     return GSPM_OK;
 }
 

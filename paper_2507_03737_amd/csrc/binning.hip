@@ -435,6 +435,7 @@ k_keygen(const uint32_t *__restrict__ sorted_rec, uint32_t rec_mask, const uint3
         hdr->ppt = (uint32_t)vt.ppt;
         hdr->frame = (uint32_t)rs.frame;
         hdr->bwd_error = 0u;
+        hdr->walked = hdr->accepted = 0u;
     }
     n_records = scan_n(n_dev, n_records);
     const bool act = p < n_records;

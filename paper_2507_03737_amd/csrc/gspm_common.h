@@ -107,6 +107,8 @@ struct FrameHeader {
     uint32_t frame;       // pointmap frame of the forward (the records carry that frame's point)
     uint32_t bwd_error;   // set by a backward that found the frame state unusable (see k_raster_bwd)
     uint32_t pad;
+    uint64_t walked;      // counting forward: (wave, list entry) pairs its waves walked
+    uint64_t accepted;    // counting forward: of those, the ones a live pixel of the wave accepted
 };
 constexpr uint32_t kFrameMagic = 0x47535046u;  // "GSPF"
 
@@ -502,7 +504,7 @@ hipError_t launch_raster_forward(const ViewTable &vt, const RasterSettings &rs, 
                                  const uint32_t *pair_vals, const float *records, float *rgb,
                                  float *depth, float *alpha, float *pointmap, float *t_final,
                                  uint32_t *last, uint32_t *contrib, uint8_t *visible, const uint32_t *order,
-                                 uint32_t *tile_work, uint64_t *wmask, int64_t wstride, hipStream_t s);
+                                 uint32_t *tile_work, uint64_t *wmask, int64_t wstride, FrameHeader *hdr, hipStream_t s);
 
 hipError_t launch_raster_backward(const ViewTable &vt, const RasterSettings &rs, const uint2 *ranges,
                                   const uint32_t *pair_vals, const float *records, const uint32_t *last,

@@ -173,11 +173,12 @@ k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
              float *__restrict__ out_alpha, float *__restrict__ out_pm, float *__restrict__ t_final,
              uint32_t *__restrict__ last, uint32_t *__restrict__ contrib, uint8_t *__restrict__ visible,
              const uint32_t *__restrict__ order, uint32_t *__restrict__ tile_work, uint64_t *__restrict__ wmask,
-             int64_t wstride) {
+             int64_t wstride, FrameHeader *__restrict__ hdr) {
     using L = Layout<TILE, PPT>;
     constexpr int NT = L::NT;
     __shared__ float4 s0[NT], s1[NT], s2[NT], s3[NT];
     __shared__ uint32_t block_work;
+    __shared__ uint32_t block_walk[2];  // COUNT: list entries walked and accepted by the waves
     const TilePos tp = tile_pos<TILE>(vt, order);
     const uint2 rg = ranges[tp.gt];
     const L lay;
@@ -209,6 +210,7 @@ k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
         return l;
     };
     bool wave_live = ballot(lane_live()) != 0ull;
+    uint32_t n_walked = 0u, n_accepted = 0u;  // COUNT: this wave's walked and accepted entries
     for (uint32_t base = rg.x; base < rg.y; base += NT) {
         const uint32_t kk = base + threadIdx.x;
         if (kk < rg.y) stage(rec, vals[kk], tp.x0, tp.y0, amin, s0, s1, s2, s3, threadIdx.x);
@@ -216,6 +218,7 @@ k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
         const int cnt = (int)min((uint32_t)NT, rg.y - base);
         for (int c = 0; c < cnt && wave_live; c += kWave) {
             uint64_t m = batch_mask<L::CULL>(s0, s1, c, cnt, lay.rx0, lay.rx1, lay.ry0, lay.ry1);
+            if (COUNT) n_walked += (uint32_t)__popcll(m);
             uint64_t composited = 0ull;  // entries of this chunk accepted by one of the wave's live pixels
             while (m != 0ull) {
                 const int q = c + (int)__builtin_ctzll(m);
@@ -274,6 +277,7 @@ k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
                     if (ballot(added) != 0ull && lane_id() == 0) visible[__float_as_uint(b.w)] = 1;
                 }
             }
+            if (COUNT) n_accepted += (uint32_t)__popcll(composited);
             if (composited != 0ull && lane_id() == 0) {
                 // Entry q sits at list position base + q; the chunk's bits straddle at most
                 // two words of this wave's plane.
@@ -313,6 +317,19 @@ k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
         t_final[pix] = T[k];
         last[pix] = n_last[k];
         if (COUNT) contrib[pix] = n_contrib[k];
+    }
+    if (COUNT) {  // the launch's walked and accepted (wave, entry) pairs, one atomic pair per workgroup
+        if (threadIdx.x == 0) block_walk[0] = block_walk[1] = 0u;
+        __syncthreads();
+        if (lane_id() == 0) {
+            atomicAdd(&block_walk[0], n_walked);
+            atomicAdd(&block_walk[1], n_accepted);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            atomicAdd(reinterpret_cast<unsigned long long *>(&hdr->walked), (unsigned long long)block_walk[0]);
+            atomicAdd(reinterpret_cast<unsigned long long *>(&hdr->accepted), (unsigned long long)block_walk[1]);
+        }
     }
     if (tile_work) {  // uniform
         if (threadIdx.x == 0) block_work = 0u;
@@ -789,14 +806,14 @@ hipError_t launch_raster_forward(const ViewTable &vt, const RasterSettings &rs, 
                                  const uint32_t *pair_vals, const float *records, float *rgb, float *depth,
                                  float *alpha, float *pointmap, float *t_final, uint32_t *last, uint32_t *contrib,
                                  uint8_t *visible, const uint32_t *order, uint32_t *tile_work, uint64_t *wmask,
-                                 int64_t wstride, hipStream_t s) {
+                                 int64_t wstride, FrameHeader *hdr, hipStream_t s) {
     const int n_tiles = vt.tile_off[vt.n_views];
     const float4 *rec = reinterpret_cast<const float4 *>(records);
     if (rs.frame < 0 || rs.frame > 2) return hipErrorInvalidValue;
 #define GSPM_FWD2(T_, P_, F_, C_)                                                                        \
     hipLaunchKernelGGL((k_raster_fwd<T_, P_, F_, C_>), dim3(n_tiles), dim3(T_ * T_ / P_), 0, s, vt, rs, \
                        ranges, pair_vals, rec, rgb, depth, alpha, pointmap, t_final, last, contrib, visible,   \
-                       order, tile_work, wmask, wstride)
+                       order, tile_work, wmask, wstride, hdr)
 #define GSPM_FWD1(T_, P_, F_)                                                                  \
     do {                                                                                       \
         if (rs.count_work) GSPM_FWD2(T_, P_, F_, true);                                        \

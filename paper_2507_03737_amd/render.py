@@ -136,7 +136,8 @@ class Rasterizer:
         return self.pairs
 
     def work(self, frame_state, stream=None):
-        """(tile pairs, contributing fragments F, evaluated-list bound) of a forward."""
+        """(tile pairs, contributing fragments F, evaluated-list bound, walked (wave, entry)
+        pairs, accepted (wave, entry) pairs) of a counting forward."""
         return B.frame_work(self.ctx, self.win.c(), self.n, self.cfg.tile, frame_state, B.stream_handle(stream))
 
     def backward_into(self, params, fwd, up, frame_state, grads=None, pose_grad=None, stream=None):

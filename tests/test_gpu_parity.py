@@ -114,7 +114,8 @@ def test_contributing_counts_exact(lib, oracle, tile, ppl):
     """Per-pixel counts of contributing fragments (alpha >= alpha_min before the
     transmittance floor) equal the oracle's, bit for bit, wherever no decision lies within
     rounding of its threshold; the work query reports their sum and refuses a frame state
-    whose forward did not count."""
+    whose forward did not count.  Its accepted (wave, entry) count equals the bits of the
+    per-wave planes, and bounds the walked count from below and F / 64 from above."""
     U.log(f"[gpu] contributing counts c0 tile {tile} ppl {ppl}")
     sc = _posed(scenes.make_scene("c0"))
     cam = sc.cams[0]
@@ -125,7 +126,7 @@ def test_contributing_counts_exact(lib, oracle, tile, ppl):
     cfg.count_work = 1
     out, fs = rast.forward(params)
     torch.cuda.synchronize()
-    pairs, frags, _ = rast.work(fs)
+    pairs, frags, _, walked, accepted = rast.work(fs)
     n_tiles = math.ceil(cam.width / tile) * math.ceil(cam.height / tile)
     lay = U.frame_layout(n_tiles, cam.width * cam.height, sc.n)
     raw = fs.cpu().numpy()
@@ -139,6 +140,17 @@ def test_contributing_counts_exact(lib, oracle, tile, ppl):
     U.log(f"  fragments {frags} (oracle {int(n_ref.sum())}), pixels checked {int(ok.sum())}, mismatches {bad}")
     assert bad == 0
     assert frags == int(got.astype(np.int64).sum())
+    # The accepted (wave, entry) count is the number of bits in the per-wave planes; every
+    # contributing fragment lies in an accepted entry of its pixel's wave.
+    cap = int(raw[lay["header"]:lay["header"] + 16].view(np.uint32)[2])
+    a = lambda x: (x + 255) & ~255  # noqa: E731
+    w0 = lay["pair_vals"] + a(4 * cap)
+    planes = tile * tile // ppl // 64  # one plane per wave of the forward (the rest is not cleared)
+    words = raw[w0:w0 + 8 * planes * (cap // 64 + 2)].view(np.uint64)
+    bits = int(np.unpackbits(words.view(np.uint8)).sum())
+    U.log(f"  walked {walked}, accepted {accepted} (bits {bits}), 64 x accepted / F = {64 * accepted / frags:.2f}")
+    assert accepted == bits
+    assert walked >= accepted and 64 * accepted >= frags
 
 
 def test_launch_orders(lib):
