@@ -209,7 +209,25 @@ k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
         for (int k = 0; k < PPT; ++k) l |= py[k] == py[k];
         return l;
     };
-    bool wave_live = ballot(lane_live()) != 0ull;
+    uint64_t live = ballot(lane_live());  // lanes with a pixel still compositing
+    bool wave_live = live != 0ull;
+    // The rectangle of the wave's live pixels, which the chunks are culled against: once
+    // pixels stop, the entries that only they would take are not walked.  Scalar bit work on
+    // the live-lane mask (lane = column + WW x lane row, PPT pixel rows per lane row).
+    float lrx0 = lay.rx0, lrx1 = lay.rx1, lry0 = lay.ry0, lry1 = lay.ry1;
+    auto live_rect = [&]() {
+        uint64_t cols = live;
+#pragma unroll
+        for (int sh = 32; sh >= L::WW; sh >>= 1) cols |= cols >> sh;
+        cols &= (L::WW >= 64 ? ~0ull : (1ull << L::WW) - 1ull);
+        const int c0 = (int)__builtin_ctzll(cols), c1 = 63 - (int)__builtin_clzll(cols);
+        const int r0 = (int)__builtin_ctzll(live) / L::WW, r1 = (63 - (int)__builtin_clzll(live)) / L::WW;
+        lrx0 = lay.rx0 + (float)c0;
+        lrx1 = lay.rx0 + (float)c1;
+        lry0 = lay.ry0 + (float)(r0 * PPT);
+        lry1 = lay.ry0 + (float)(r1 * PPT + PPT - 1);
+    };
+    if (wave_live) live_rect();
     uint32_t n_walked = 0u, n_accepted = 0u;  // COUNT: this wave's walked and accepted entries
     for (uint32_t base = rg.x; base < rg.y; base += NT) {
         const uint32_t kk = base + threadIdx.x;
@@ -217,7 +235,7 @@ k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
         __syncthreads();
         const int cnt = (int)min((uint32_t)NT, rg.y - base);
         for (int c = 0; c < cnt && wave_live; c += kWave) {
-            uint64_t m = batch_mask<L::CULL>(s0, s1, c, cnt, lay.rx0, lay.rx1, lay.ry0, lay.ry1);
+            uint64_t m = batch_mask<L::CULL>(s0, s1, c, cnt, lrx0, lrx1, lry0, lry1);
             if (COUNT) n_walked += (uint32_t)__popcll(m);
             uint64_t composited = 0ull;  // entries of this chunk accepted by one of the wave's live pixels
             while (m != 0ull) {
@@ -287,7 +305,12 @@ k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
                 atomicOr((unsigned long long *)w, (unsigned long long)(composited << sh));
                 if (sh != 0) atomicOr((unsigned long long *)(w + 1), (unsigned long long)(composited >> (64 - sh)));
             }
-            wave_live = ballot(lane_live()) != 0ull;
+            const uint64_t now = ballot(lane_live());
+            if (now != live) {  // wave-uniform: some pixels stopped in this chunk
+                live = now;
+                wave_live = live != 0ull;
+                if (wave_live) live_rect();
+            }
         }
         if (!__syncthreads_or(lane_live() ? 1 : 0)) break;
     }
