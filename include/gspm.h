@@ -35,7 +35,8 @@
  *     must not allocate (graph capture) should follow gspm_reserve with large enough
  *     capacities.
  *   - Gradient outputs are accumulated (+=), so one Gaussian set can be shared across
- *     calls; the caller zeroes them.
+ *     calls; the caller zeroes them (or sets settings.grads_overwrite, which makes the
+ *     backward write them instead).
  *   - A context is not thread safe and its calls must be ordered on one stream.
  */
 #ifndef GSPM_H
@@ -115,6 +116,10 @@ typedef struct {
                                 with a cross-lane reduce-scatter (nonzero), the form it
                                 always uses at 2 and 4 pixels per lane; the results agree
                                 to float rounding [0] */
+    int32_t grads_overwrite; /* nonzero: gspm_render_backward and gspm_pose_backward write the
+                                parameter and pose gradients (0 where none flows) instead of
+                                adding them to the arrays' contents, so a training loop
+                                need not clear them first [0] */
 } gspm_settings;
 
 /* Per-view packed output planes (device): rgb [3][H][W], depth [H][W] (Eq. 3, not
@@ -196,8 +201,9 @@ GSPM_API gspm_status gspm_frame_work(gspm_ctx *ctx, const gspm_views *views, int
 
 /* Backward of gspm_render_forward for upstream gradients grad_out (same planes as the
  * outputs; any plane may be NULL for zero).  fwd_out are the forward's outputs (rgb,
- * depth, alpha and pointmap are read).  grads: accumulated parameter gradients.
- * pose_grad: device [V][6] accumulated, or NULL; it is d L / d xi at xi = 0 for the
+ * depth, alpha and pointmap are read).  grads: accumulated parameter gradients (written
+ * instead, 0 where none flows, with settings.grads_overwrite).
+ * pose_grad: device [V][6] accumulated (or written), or NULL; it is d L / d xi at xi = 0 for the
  * left perturbation T_cw <- Exp(xi) T_cw, xi = (rho, phi) with the translation first.
  *
  * Same-settings contract: g, views (sizes, intrinsics and the poses in T_cw) and the
@@ -206,7 +212,8 @@ GSPM_API gspm_status gspm_frame_work(gspm_ctx *ctx, const gspm_views *views, int
  * pointmap frame are checked on the device against the frame state's header (so the
  * check also holds inside a captured graph), together with the forward's overflow and
  * sort-stall flags: on a mismatch, or on an incomplete forward, the backward reads
- * nothing of the frame state, adds nothing to grads and pose_grad, and marks the frame
+ * nothing of the frame state, adds nothing to grads and pose_grad (writes zeros with
+ * settings.grads_overwrite), and marks the frame
  * state so that gspm_frame_status returns GSPM_ERR_INVALID_ARG until the next forward
  * into it.  Changed poses or parameters are not detected: the gradients are then those
  * of a render that was not made. */
@@ -216,7 +223,8 @@ GSPM_API gspm_status gspm_render_backward(gspm_ctx *ctx, const gspm_gaussians *g
                                  const gspm_gaussian_grads *grads, float *pose_grad, void *stream);
 
 /* Pose-only backward (Gaussians frozen, the tracking loop of Sec. 3.2.2): writes
- * pose_grad [V][6] (accumulated) and skips the colour and opacity terms. */
+ * pose_grad [V][6] (accumulated, or written with settings.grads_overwrite) and skips the
+ * colour and opacity terms. */
 GSPM_API gspm_status gspm_pose_backward(gspm_ctx *ctx, const gspm_gaussians *g, const gspm_views *views,
                                const gspm_settings *s, const gspm_const_images *fwd_out,
                                const gspm_const_images *grad_out, const void *frame_state,

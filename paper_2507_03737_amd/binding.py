@@ -54,7 +54,8 @@ class Settings(ctypes.Structure):
                 ("pixels_per_lane", ctypes.c_int32), ("near_z", ctypes.c_float), ("alpha_min", ctypes.c_float),
                 ("alpha_max", ctypes.c_float), ("t_min", ctypes.c_float), ("eps2d", ctypes.c_float),
                 ("jac_clamp", ctypes.c_float), ("bg", ctypes.c_float * 3), ("mark_visible", ctypes.c_int32),
-                ("count_work", ctypes.c_int32), ("bwd_lane_reduce", ctypes.c_int32)]
+                ("count_work", ctypes.c_int32), ("bwd_lane_reduce", ctypes.c_int32),
+                ("grads_overwrite", ctypes.c_int32)]
 
 
 class Images(ctypes.Structure):
@@ -188,12 +189,14 @@ class RasterConfig:
     mark_visible: int = 0
     count_work: int = 0
     bwd_lane_reduce: int = 0
+    grads_overwrite: int = 0
 
     def c(self) -> Settings:
         return Settings(self.tile, self.sort_digit_bits, self.pointmap_frame, self.pixels_per_lane, self.near_z,
                         self.alpha_min,
                         self.alpha_max, self.t_min, self.eps2d, self.jac_clamp, (ctypes.c_float * 3)(*self.bg),
-                        int(self.mark_visible), int(self.count_work), int(self.bwd_lane_reduce))
+                        int(self.mark_visible), int(self.count_work), int(self.bwd_lane_reduce),
+                        int(self.grads_overwrite))
 
     # Supported (tile, pixels_per_lane) launch shapes of the raster kernels.
     SHAPES = ((8, 1), (16, 1), (16, 2), (16, 4), (32, 1), (32, 2), (32, 4))

@@ -192,6 +192,7 @@ gspm_status prepare(const gspm_gaussians *g, const gspm_views *views, const gspm
     P.rs.mark_visible = s->mark_visible != 0 ? 1 : 0;
     P.rs.count_work = s->count_work != 0 ? 1 : 0;
     P.rs.bwd_lane_reduce = s->bwd_lane_reduce != 0 ? 1 : 0;
+    P.rs.grads_overwrite = s->grads_overwrite != 0 ? 1 : 0;
     return GSPM_OK;
 }
 
@@ -279,8 +280,11 @@ gspm_status backward_common(gspm_ctx *ctx, const gspm_gaussians *g, const gspm_v
     GSPM_HIP(launch_preprocess_backward(*g, P.vt, views->T_cw, P.rs, g2, out, pose_grad != nullptr,
                                         static_cast<double *>(ctx->pose_part.p), hs));
     ctx->grad2d_clean = true;
-    if (pose_grad)
-        GSPM_HIP(launch_pose_reduce(static_cast<double *>(ctx->pose_part.p), nb, P.vt.n_views, pose_grad, hs));
+    if (pose_grad && nb > 0)
+        GSPM_HIP(launch_pose_reduce(static_cast<double *>(ctx->pose_part.p), nb, P.vt.n_views, pose_grad,
+                                     P.rs.grads_overwrite != 0, hs));
+    else if (pose_grad && P.rs.grads_overwrite)  // no Gaussians: the written gradient is zero
+        GSPM_HIP(launch_fill_f32(pose_grad, 0.0f, 6 * (int64_t)P.vt.n_views, hs));
     return GSPM_OK;
 }
 

@@ -33,6 +33,7 @@ struct RasterSettings {
     int32_t mark_visible;
     int32_t count_work;  // the forward writes each pixel's contributing-fragment count
     int32_t bwd_lane_reduce;  // one pixel per lane: reduce-scatter instead of the matrix cores
+    int32_t grads_overwrite;  // the backward writes the gradients instead of adding them
 };
 
 // Projected record of one (Gaussian, view) pair: 64 bytes, 4 x float4.
@@ -520,7 +521,7 @@ hipError_t launch_preprocess_backward(const gspm_gaussians &g, const ViewTable &
                                       double *pose_partials, hipStream_t s);
 int64_t pose_partial_blocks(int64_t n);
 hipError_t launch_pose_reduce(const double *pose_partials, int64_t n_blocks, int n_views,
-                              float *pose_grad, hipStream_t s);
+                              float *pose_grad, bool overwrite, hipStream_t s);
 
 int64_t patch_loss_partials(const ViewTable &vt, int patch);
 // Slots of the static partials array behind gspm_window_loss_noalloc (1 MiB of float64),

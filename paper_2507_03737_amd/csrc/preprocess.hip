@@ -427,6 +427,19 @@ k_preprocess_backward(gspm_gaussians G, ViewTable vt, const float *__restrict__ 
             __syncthreads();  // the sums are read before the next view's reduction reuses lds
         }
     }
+    if (g >= n) return;
+    if (rs.grads_overwrite) {  // each Gaussian's gradients belong to this thread alone: plain stores
+        if (out.means)
+            for (int c = 0; c < 3; ++c) out.means[c * n + g] = (float)gmu[c];
+        if (out.log_scales)
+            for (int c = 0; c < 3; ++c) out.log_scales[c * n + g] = (float)gls[c];
+        if (out.quats)
+            for (int c = 0; c < 4; ++c) out.quats[c * n + g] = (float)gq[c];
+        if (out.opacity_logit) out.opacity_logit[g] = (float)go;
+        if (out.rgb)
+            for (int c = 0; c < 3; ++c) out.rgb[c * n + g] = (float)gc[c];
+        return;
+    }
     if (!touched) return;
     if (out.means)
         for (int c = 0; c < 3; ++c) unsafeAtomicAdd(out.means + c * n + g, (float)gmu[c]);
@@ -441,7 +454,7 @@ k_preprocess_backward(gspm_gaussians G, ViewTable vt, const float *__restrict__ 
 
 // One block per (view, pose component); the sum runs in a fixed order (deterministic).
 __global__ void __launch_bounds__(256)
-k_pose_reduce(const double *__restrict__ part, int64_t nblocks, float *__restrict__ pose_grad) {
+k_pose_reduce(const double *__restrict__ part, int64_t nblocks, float *__restrict__ pose_grad, int overwrite) {
     __shared__ double lds[4];
     const int v = blockIdx.x, k = blockIdx.y;
     double acc = 0.0;
@@ -449,7 +462,10 @@ k_pose_reduce(const double *__restrict__ part, int64_t nblocks, float *__restric
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
     if (lane_id() == 0) lds[threadIdx.x / 64] = acc;
     __syncthreads();
-    if (threadIdx.x == 0) pose_grad[v * 6 + k] += (float)(lds[0] + lds[1] + lds[2] + lds[3]);
+    if (threadIdx.x == 0) {
+        const float sum = (float)(lds[0] + lds[1] + lds[2] + lds[3]);
+        pose_grad[v * 6 + k] = overwrite ? sum : pose_grad[v * 6 + k] + sum;
+    }
 }
 
 __global__ void k_fill_u32(uint32_t *p, uint32_t value, int64_t n) {
@@ -550,9 +566,10 @@ hipError_t launch_preprocess_backward(const gspm_gaussians &g, const ViewTable &
 }
 
 hipError_t launch_pose_reduce(const double *pose_partials, int64_t n_blocks, int n_views, float *pose_grad,
-                              hipStream_t s) {
+                              bool overwrite, hipStream_t s) {
     if (n_views <= 0 || n_blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_pose_reduce, dim3(n_views, 6), dim3(256), 0, s, pose_partials, n_blocks, pose_grad);
+    hipLaunchKernelGGL(k_pose_reduce, dim3(n_views, 6), dim3(256), 0, s, pose_partials, n_blocks, pose_grad,
+                       overwrite ? 1 : 0);
     return hipGetLastError();
 }
 

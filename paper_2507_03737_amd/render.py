@@ -6,6 +6,7 @@ backward, the patch scale and the loss runs in libgspm's HIP kernels.
 """
 from __future__ import annotations
 
+import dataclasses
 import math
 from typing import List, Sequence
 
@@ -140,7 +141,10 @@ class Rasterizer:
         pairs, accepted (wave, entry) pairs) of a counting forward."""
         return B.frame_work(self.ctx, self.win.c(), self.n, self.cfg.tile, frame_state, B.stream_handle(stream))
 
-    def backward_into(self, params, fwd, up, frame_state, grads=None, pose_grad=None, stream=None):
+    def backward_into(self, params, fwd, up, frame_state, grads=None, pose_grad=None, stream=None,
+                      overwrite=False):
+        """Backward of a forward into grads / pose_grad: added to their contents, or with
+        overwrite=True written over them (no clearing needed)."""
         g = _params(params)
         f = B.Images(B.ptr(fwd["rgb"]), B.ptr(fwd["depth"]), B.ptr(fwd["alpha"]), B.ptr(fwd["pointmap"]))
         u = B.Images(B.ptr(up.get("rgb")), B.ptr(up.get("depth")), B.ptr(up.get("alpha")), B.ptr(up.get("pointmap")))
@@ -148,7 +152,8 @@ class Rasterizer:
         if grads is not None:
             gg = B.GaussianGrads(B.ptr(grads.get("means")), B.ptr(grads.get("log_scales")), B.ptr(grads.get("quats")),
                                  B.ptr(grads.get("opacity_logit")), B.ptr(grads.get("rgb")))
-        B.render_backward(self.ctx, g, self.win.c(), self.cfg.c(), f, u, frame_state, gg, pose_grad,
+        cfg = dataclasses.replace(self.cfg, grads_overwrite=1) if overwrite else self.cfg
+        B.render_backward(self.ctx, g, self.win.c(), cfg.c(), f, u, frame_state, gg, pose_grad,
                           B.stream_handle(stream))
 
     def pose_backward_into(self, params, fwd, up, frame_state, pose_grad, stream=None):
@@ -253,9 +258,10 @@ class RasterizePointmap(torch.autograd.Function):
         fwd = {"rgb": o_rgb, "depth": o_depth, "alpha": o_alpha, "pointmap": o_pm}
         up = {k: (v.contiguous() if v is not None else None)
               for k, v in (("rgb", g_rgb), ("depth", g_depth), ("alpha", g_alpha), ("pointmap", g_pm))}
-        grads = rast.zero_grads(params)
-        pose = torch.zeros(rast.win.n_views, 6, device=o_rgb.device) if ctx.want_pose else None
-        rast.backward_into(params, fwd, up, ctx.fs, grads, pose)
+        grads = {k: torch.empty_like(t) for k, t in zip(("means", "log_scales", "quats", "opacity_logit", "rgb"),
+                                                          params)}
+        pose = torch.empty(rast.win.n_views, 6, device=o_rgb.device) if ctx.want_pose else None
+        rast.backward_into(params, fwd, up, ctx.fs, grads, pose, overwrite=True)
         return (grads["means"], grads["log_scales"], grads["quats"], grads["opacity_logit"], grads["rgb"], pose, None,
                 None)
 
@@ -297,14 +303,11 @@ class MappingStep:
 
     def run(self, stream=None):
         r = self.rast
-        for t in self.grads.values():
-            t.zero_()
-        self.pose_grad.zero_()
         r.forward_into(self.params, self.out, self.fs, stream)
         r.window_loss_into(self.out["rgb"], self.target, self.out["pointmap"], self.prior, self.patch, self.alpha,
                            self.scale, self.loss, self.g_rgb, self.g_pm, stream)
         r.backward_into(self.params, self.out, {"rgb": self.g_rgb, "pointmap": self.g_pm}, self.fs, self.grads,
-                        self.pose_grad, stream)
+                        self.pose_grad, stream, overwrite=True)
 
     def check(self):
         return B.frame_status(self.fs, B.stream_handle())

@@ -3,6 +3,7 @@
 Every test calls the library through its C ABI (via the ctypes binding) on seeded
 synthetic inputs and compares with the oracle on the same inputs.
 """
+import dataclasses
 import math
 
 import numpy as np
@@ -301,6 +302,47 @@ def test_backward_c0(lib, oracle, frame, lane_reduce):
         U.log(f"  {k}: rel {rel:.2e}")
     U.check_grad(f"c0/f{frame} pose", g["pose"], r["pose"], frac=1.0)
     U.log(f"  pose gpu {g['pose'][0]} oracle {r['pose'][0]}")
+
+
+@pytest.mark.parametrize("pose_only", [False, True])
+def test_grads_overwrite(lib, pose_only):
+    """With settings.grads_overwrite the backward writes the parameter and pose gradients
+    over whatever the arrays held (NaN here): what it adds into zeroed arrays, up to the
+    order of the float atomics that sum each record's image-plane terms (which differs
+    from run to run), and zeros for Gaussians that get none."""
+    U.log(f"[gpu] gradients written over the arrays, pose_only={pose_only}")
+    sc = _posed(scenes.make_scene("c0"))
+    sc.opacity_logit[:50] = -30.0  # Gaussians below alpha_min everywhere: no gradient flows to them
+    cfg = lib.RasterConfig(pointmap_frame=1)
+    rast, params, out, fs = _render_gpu(lib, sc, cfg)
+    ups = _upstream(sc, 23, [np.ones((sc.cams[0].height, sc.cams[0].width), dtype=bool)])
+    up = {k: torch.from_numpy(_pack(ups, k, c)).cuda() for k, c in (("rgb", 3), ("depth", 1), ("alpha", 1),
+                                                                     ("pointmap", 3))}
+    res = []
+    for overwrite in (False, True):
+        fill = float("nan") if overwrite else 0.0
+        grads = {k: torch.full_like(t, fill) for k, t in rast.zero_grads(params).items()}
+        pg = torch.full((1, 6), fill, device="cuda")
+        if pose_only:
+            c = dataclasses.replace(rast.cfg, grads_overwrite=int(overwrite))
+            saved, rast.cfg = rast.cfg, c
+            rast.pose_backward_into(params, out, up, fs, pg)
+            rast.cfg = saved
+        else:
+            rast.backward_into(params, out, up, fs, grads, pg, overwrite=overwrite)
+        torch.cuda.synchronize()
+        res.append(({k: t.cpu().numpy() for k, t in grads.items()}, pg.cpu().numpy()))
+    (g0, p0), (g1, p1) = res
+
+    def same(a, b, tag):
+        assert np.isfinite(b).all(), tag
+        assert np.allclose(a, b, rtol=1e-5, atol=1e-6 * float(np.abs(a).max())), tag
+
+    same(p0, p1, "pose")
+    if not pose_only:
+        for k in g0:
+            same(g0[k], g1[k], k)
+        assert not np.any(g1["means"][:, :50]) and not np.any(g1["opacity_logit"][:50])
 
 
 @pytest.mark.parametrize("tile,ppl", [(8, 1), (16, 1), (16, 2), (16, 4), (32, 1), (32, 2), (32, 4)])
