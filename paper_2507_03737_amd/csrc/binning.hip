@@ -164,10 +164,12 @@ k_scan_compact(const uint32_t *__restrict__ counts, const uint32_t *__restrict__
 // (the single-sweep scheme with decoupled look-back of Merrill and Garland's scan and
 // Adinets and Merrill's Onesweep sort).  Keys are cut into tiles of 8192 (8 waves x 16
 // steps of 64).  Block b of a pass kernel ranks tile b's keys stably (wave-level match of
-// equal digits by ballots, then per-digit offsets across the four waves), publishes its
-// per-digit counts, and finds the count of each digit in all earlier tiles by walking
-// back over their published words until one carries an inclusive prefix; it then
-// publishes its own inclusive prefix.  Workgroups are dispatched in index order, so a
+// equal digits by ballots, then per-digit offsets across the eight waves).  In the first
+// pass the count of each digit in all earlier tiles comes from the histogram kernel,
+// which counts the first digit per tile, and a scan of those counts.  Later passes see
+// the tiles in an order only the previous pass knows: block b publishes its per-digit
+// counts and finds the earlier tiles' counts by walking back over their published words
+// until one carries an inclusive prefix; it then publishes its own inclusive prefix.  Workgroups are dispatched in index order, so a
 // block only waits for blocks that are already running, which never wait for later ones:
 // the walk ends.  (Taking tile numbers from a global counter instead would serialise the
 // blocks on one atomic address, tens of nanoseconds each.)  A wait is still bounded (then
@@ -187,6 +189,7 @@ constexpr uint32_t kStatInc = 2u << 30;  // count over this and every earlier ti
 constexpr uint32_t kStatCount = (1u << 30) - 1u;
 constexpr uint32_t kSortSpinLimit = 1u << 20;
 constexpr int kLookback = 16;  // earlier tiles read per look-back step
+constexpr int kHistBlocks = 1024;
 
 __device__ inline int64_t sort_count(const uint32_t *n_dev, int64_t n_max) {
     if (!n_dev) return n_max;
@@ -197,33 +200,100 @@ __device__ inline int64_t sort_count(const uint32_t *n_dev, int64_t n_max) {
 // Tiles holding the n live keys.
 __device__ inline int64_t sort_active_tiles(int64_t n) { return (n + kSortTile - 1) / kSortTile; }
 
-// Digit histograms of every pass (ghist[p * R + d], zeroed by the caller); also clears the
-// first pass's published words of the live tiles.
+// Per-block digit counts of the later passes (bhist) and the first pass's per-tile digit
+// counts (tcount[d * tstride + tile]): a block takes whole tiles, so the first pass finds
+// each tile's offsets by a scan of these counts (k_radix_tile_prefix) instead of by
+// look-back.  Later passes read tiles in an order that only the pass before them knows,
+// so they keep the look-back.
 template <int DB>
 __global__ void __launch_bounds__(kSortBlock)
 k_radix_hist(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ n_dev, int64_t n_max, int passes,
-             uint32_t *__restrict__ ghist, uint32_t *__restrict__ status0) {
+             uint32_t *__restrict__ bhist, uint32_t *__restrict__ tcount, int64_t tstride) {
     constexpr int R = 1 << DB;
     __shared__ uint32_t h[kSortMaxPasses * R];
+    __shared__ uint32_t tc[kSortWaves][R];  // this tile's first-pass digits, one row per wave
+    const int wid = threadIdx.x / kWave, lane = lane_id();
     for (int i = threadIdx.x; i < passes * R; i += kSortBlock) h[i] = 0u;
-    __syncthreads();
     const int64_t n = sort_count(n_dev, n_max);
-    const int64_t stride = (int64_t)gridDim.x * kSortBlock;
-    constexpr int kItems = 8;  // keys loaded before any is counted
-    for (int64_t i0 = (int64_t)blockIdx.x * kSortBlock + threadIdx.x; i0 < n; i0 += kItems * stride) {
-        uint32_t k[kItems];
+    const int64_t tiles = sort_active_tiles(n);
+    for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        for (int d = lane; d < R; d += kWave) tc[wid][d] = 0u;
+        __syncthreads();
+        const int64_t b = tile * kSortTile + threadIdx.x;
+        uint32_t k[kSortSteps];
 #pragma unroll
-        for (int q = 0; q < kItems; ++q) k[q] = i0 + q * stride < n ? keys[i0 + q * stride] : 0u;
+        for (int st = 0; st < kSortSteps; ++st) k[st] = b + st * kSortBlock < n ? keys[b + st * kSortBlock] : 0u;
 #pragma unroll
-        for (int q = 0; q < kItems; ++q)
-            if (i0 + q * stride < n)
-                for (int p = 0; p < passes; ++p) atomicAdd(&h[p * R + ((k[q] >> (p * DB)) & (R - 1))], 1u);
+        for (int st = 0; st < kSortSteps; ++st) {
+            if (b + st * kSortBlock >= n) continue;
+            atomicAdd(&tc[wid][k[st] & (R - 1)], 1u);
+            for (int p = 1; p < passes; ++p) atomicAdd(&h[p * R + ((k[st] >> (p * DB)) & (R - 1))], 1u);
+        }
+        __syncthreads();
+        for (int d = threadIdx.x; d < R; d += kSortBlock) {
+            uint32_t c = 0u;
+#pragma unroll
+            for (int w = 0; w < kSortWaves; ++w) c += tc[w][d];
+            tcount[d * tstride + tile] = c;
+        }
+        __syncthreads();  // the rows are read before the next tile clears them
     }
-    const int64_t words = sort_active_tiles(n) * R;
-    for (int64_t i = (int64_t)blockIdx.x * kSortBlock + threadIdx.x; i < words; i += stride) status0[i] = 0u;
     __syncthreads();
-    for (int i = threadIdx.x; i < passes * R; i += kSortBlock)
-        if (h[i] != 0u) atomicAdd(&ghist[i], h[i]);
+    // This block's counts of the later passes' digits (summed over the blocks by
+    // k_radix_tile_prefix: plain stores, where atomics from every block on the same few
+    // hundred words would queue behind each other).
+    for (int i = R + threadIdx.x; i < passes * R; i += kSortBlock) bhist[(int64_t)blockIdx.x * passes * R + i] = h[i];
+}
+
+// Exclusive prefix over the tiles of each first-pass digit's per-tile counts, in place:
+// block d scans row d and writes the digit's total to ghist[d]; it also sums digit d of
+// every later pass over the histogram blocks' partial counts into ghist[p R + d].
+template <int DB>
+__global__ void __launch_bounds__(kScanBlock)
+k_radix_tile_prefix(uint32_t *__restrict__ tcount, int64_t tstride, const uint32_t *__restrict__ n_dev,
+                    int64_t n_max, int passes, const uint32_t *__restrict__ bhist, int hist_blocks,
+                    uint32_t *__restrict__ ghist) {
+    constexpr int R = 1 << DB;
+    __shared__ uint32_t lds[kScanBlock / kWave];
+    const int d = blockIdx.x;
+    // Every partial is loaded before any is added (one memory latency, not one per block).
+    uint32_t c[kSortMaxPasses] = {};
+#pragma unroll
+    for (int j = 0; j < kHistBlocks / kScanBlock; ++j) {
+        const int b = threadIdx.x + j * kScanBlock;
+#pragma unroll
+        for (int p = 1; p < kSortMaxPasses; ++p)
+            if (p < passes && b < hist_blocks) c[p] += bhist[((int64_t)b * passes + p) * R + d];
+    }
+#pragma unroll
+    for (int p = 1; p < kSortMaxPasses; ++p) {
+        if (p >= passes) break;
+        uint32_t tot;
+        block_exclusive_scan(c[p], lds, tot);
+        if (threadIdx.x == 0) ghist[p * R + d] = tot;
+    }
+    const int64_t tiles = sort_active_tiles(sort_count(n_dev, n_max));
+    uint32_t *row = tcount + blockIdx.x * tstride;
+    uint32_t running = 0u;
+    for (int64_t base = 0; base < tiles; base += kScanTile) {
+        uint32_t v[kScanItems];
+        uint32_t sum = 0u;
+        const int64_t t0 = base + (int64_t)threadIdx.x * kScanItems;
+#pragma unroll
+        for (int q = 0; q < kScanItems; ++q) {
+            v[q] = t0 + q < tiles ? row[t0 + q] : 0u;
+            sum += v[q];
+        }
+        uint32_t tot;
+        uint32_t pre = running + block_exclusive_scan(sum, lds, tot);
+#pragma unroll
+        for (int q = 0; q < kScanItems; ++q) {
+            if (t0 + q < tiles) row[t0 + q] = pre;
+            pre += v[q];
+        }
+        running += tot;
+    }
+    if (threadIdx.x == 0) ghist[d] = running;
 }
 
 __device__ inline uint32_t load_status(const uint32_t *p) {
@@ -238,7 +308,8 @@ __global__ void __launch_bounds__(kSortBlock)
 k_radix_pass(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
              uint32_t *__restrict__ vout, const uint32_t *__restrict__ n_dev, int64_t n_max, int shift,
              const uint32_t *__restrict__ ghist, uint32_t *__restrict__ status,
-             uint32_t *__restrict__ status_next, uint32_t *__restrict__ stall, uint2 *__restrict__ ranges) {
+             uint32_t *__restrict__ status_next, uint32_t *__restrict__ stall, uint2 *__restrict__ ranges,
+             const uint32_t *__restrict__ tprefix, int64_t tstride) {
     constexpr int R = 1 << DB;
     __shared__ uint32_t wcnt[kSortWaves][R];
     __shared__ uint32_t dstart[R];
@@ -253,6 +324,9 @@ k_radix_pass(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
     const int64_t tile = blockIdx.x;
     if (tile >= sort_active_tiles(n)) return;  // block-uniform
     const uint32_t gcount = threadIdx.x < R ? ghist[threadIdx.x] : 0u;
+    // With tprefix: the digit's count in all earlier tiles, loaded now so that its latency
+    // passes while the tile is ranked.
+    const uint32_t tpre = tprefix && threadIdx.x < R ? tprefix[threadIdx.x * tstride + tile] : 0u;
     for (int d = lane; d < R; d += kWave) wcnt[wid][d] = 0u;
     __builtin_amdgcn_wave_barrier();
     const int64_t tile_begin = tile * kSortTile;
@@ -298,7 +372,7 @@ k_radix_pass(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
             acc += c;
         }
         tot = acc;
-        store_status(status + tile * R + d, (tile == 0 ? kStatInc : kStatAgg) | tot);
+        if (!tprefix) store_status(status + tile * R + d, (tile == 0 ? kStatInc : kStatAgg) | tot);
         status_next[tile * R + d] = 0u;  // the next pass's word for this tile
     }
     uint32_t all;
@@ -309,7 +383,9 @@ k_radix_pass(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
         dstart[d] = pre;
         dcount[d] = tot;
         uint32_t prefix = 0;
-        if (tile > 0) {
+        if (tprefix) {
+            prefix = tpre;
+        } else if (tile > 0) {
             // Words of kLookback earlier tiles are read at once (one memory latency per
             // window instead of per tile), then taken nearest first.
             int64_t j = tile - 1;
@@ -630,10 +706,12 @@ hipError_t launch_compact(const uint32_t *counts, const uint32_t *dkey, int64_t 
 static int64_t sort_tiles(int64_t n_max) { return (n_max + kSortTile - 1) / kSortTile; }
 
 // Scratch words: digit histograms [kSortMaxPasses << digit_bits], published words
-// [2][tiles << digit_bits] (alternating passes).
+// [2][tiles << digit_bits] (alternating passes), the first pass's per-tile digit offsets
+// [tiles << digit_bits] and the histogram blocks' partial counts.
 int64_t radix_hist_words(int64_t n_max, int digit_bits) {
     const int64_t t = sort_tiles(n_max) > 0 ? sort_tiles(n_max) : 1;
-    return ((int64_t)kSortMaxPasses << digit_bits) + 2 * (t << digit_bits);
+    const int64_t hb = t < kHistBlocks ? t : kHistBlocks;
+    return ((int64_t)kSortMaxPasses << digit_bits) * (1 + hb) + 3 * (t << digit_bits);
 }
 
 template <int DB>
@@ -644,10 +722,14 @@ static void sort_passes(const uint32_t *keys_in, const uint32_t *vals_in, uint32
     const int64_t tiles = sort_tiles(n_max);
     uint32_t *ghist = scratch;
     uint32_t *status[2] = {ghist + (int64_t)kSortMaxPasses * R, ghist + (int64_t)kSortMaxPasses * R + tiles * R};
-    (void)launch_fill_u32(ghist, 0u, (int64_t)kSortMaxPasses * R, s);
-    int64_t hb = tiles < 1024 ? tiles : 1024;
-    hipLaunchKernelGGL(k_radix_hist<DB>, dim3((unsigned)(hb > 0 ? hb : 1)), dim3(kSortBlock), 0, s, keys_in, n_dev,
-                       n_max, passes, ghist, status[0]);
+    uint32_t *tprefix = status[1] + tiles * R;  // [R][tiles]: the first pass's per-tile digit offsets
+    uint32_t *bhist = tprefix + tiles * R;      // [hist blocks][passes][R]
+    int64_t hb = tiles < kHistBlocks ? tiles : kHistBlocks;
+    if (hb < 1) hb = 1;
+    hipLaunchKernelGGL(k_radix_hist<DB>, dim3((unsigned)hb), dim3(kSortBlock), 0, s, keys_in, n_dev, n_max, passes,
+                       bhist, tprefix, tiles);
+    hipLaunchKernelGGL(k_radix_tile_prefix<DB>, dim3(R), dim3(kScanBlock), 0, s, tprefix, tiles, n_dev, n_max, passes,
+                       bhist, (int)hb, ghist);
     const uint32_t *kin = keys_in, *vin = vals_in;
     for (int p = 0; p < passes; ++p) {
         // The last pass writes to *_out; earlier passes alternate so that this holds.
@@ -656,7 +738,7 @@ static void sort_passes(const uint32_t *keys_in, const uint32_t *vals_in, uint32
         uint32_t *vo = to_out ? vals_out : vals_tmp;
         hipLaunchKernelGGL(k_radix_pass<DB>, dim3((unsigned)tiles), dim3(kSortBlock), 0, s, kin, vin, ko, vo, n_dev,
                            n_max, p * DB, ghist + (int64_t)p * R, status[p & 1], status[(p + 1) & 1], stall,
-                           p == passes - 1 ? ranges : nullptr);
+                           p == passes - 1 ? ranges : nullptr, p == 0 ? tprefix : nullptr, tiles);
         kin = ko;
         vin = vo;
     }
