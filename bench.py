@@ -34,11 +34,13 @@ if ROOT not in sys.path:
 
 METRIC = "fwd+bwd ms/mapping iter & Gaussian-px evals/s, batched vs per-view, at oracle tol"
 
-# Algorithmic work per contributing fragment: about 20 float32 operations and one
-# exponential in the forward, about 60 and one exponential in the backward (the exponential
-# counts as one operation).
-FWD_FLOPS_PER_FRAG = 21
-BWD_FLOPS_PER_FRAG = 61
+# Algorithmic work per contributing fragment, counted on the definition's operations with a
+# fused multiply-add as two flops (the convention of the peak figure): 29 in the forward
+# (the exponent, exp, the alpha clamp, 1 - alpha, the transmittance update, the weight and 7
+# weighted accumulations) and 64 in the backward (recomputation, the dL/dalpha formula and
+# the 13 gradient terms); the exponential counts as one.
+FWD_FLOPS_PER_FRAG = 29
+BWD_FLOPS_PER_FRAG = 64
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0
 # Measured HBM traffic of the dominant kernel (rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by
