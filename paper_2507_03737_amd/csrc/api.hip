@@ -217,7 +217,7 @@ hipError_t ensure_records(gspm_ctx *c, int64_t R, int digit_bits) {
     if ((e = grow(c->offsets, 4 * w))) return e;
     if ((e = grow(c->spans, 16 * w))) return e;
     if ((e = grow(c->hist, 4 * radix_hist_words(w, digit_bits)))) return e;
-    if ((e = grow(c->scan_part, 4 * 1024))) return e;
+    if ((e = grow(c->scan_part, 4 * kScanMaxBlocks))) return e;
     if ((e = grow(c->misc, 256))) return e;
     return hipSuccess;
 }

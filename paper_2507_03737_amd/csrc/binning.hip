@@ -29,6 +29,13 @@ __device__ inline uint32_t load_count(const uint32_t *counts, const uint32_t *id
     return flag ? (c != 0u ? 1u : 0u) : c;
 }
 
+// Elements per block of the device-wide scans: a multiple of kScanItems, so that every
+// thread's group of kScanItems consecutive words starts 32-byte aligned.
+__device__ inline int64_t scan_chunk(int64_t n) {
+    const int64_t c = (n + gridDim.x - 1) / gridDim.x;
+    return (c + kScanItems - 1) / kScanItems * kScanItems;
+}
+
 __device__ inline int64_t scan_n(const uint32_t *n_dev, int64_t n_max) {
     if (!n_dev) return n_max;
     const int64_t n = (int64_t)*n_dev;
@@ -59,24 +66,41 @@ k_scan_reduce(const uint32_t *__restrict__ counts, const uint32_t *__restrict__ 
               int64_t n_max, int flag, uint32_t *__restrict__ part, uint32_t *__restrict__ gathered) {
     __shared__ uint32_t lds[kScanBlock / kWave];
     const int64_t n = scan_n(n_dev, n_max);
-    const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
-    const int64_t b0 = (int64_t)blockIdx.x * chunk;
+    const int64_t chunk = scan_chunk(n);
+    const int64_t b0 = (int64_t)blockIdx.x * chunk < n ? (int64_t)blockIdx.x * chunk : n;
     const int64_t b1 = b0 + chunk < n ? b0 + chunk : n;
     uint32_t acc = 0;
-    for (int64_t p = b0 + threadIdx.x; p < b1; p += kScanBlock) {
-        const uint32_t c = load_count(counts, idx, p, flag);
-        if (gathered) gathered[p] = c;
-        acc += c;
+    // kScanItems loads per thread in flight at once, each instruction over consecutive words.
+    for (int64_t base = b0; base < b1; base += kScanTile) {
+        uint32_t c[kScanItems];
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            const int64_t p = base + k * kScanBlock + threadIdx.x;
+            c[k] = p < b1 ? load_count(counts, idx, p, flag) : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            const int64_t p = base + k * kScanBlock + threadIdx.x;
+            if (gathered && p < b1) gathered[p] = c[k];
+            acc += c[k];
+        }
     }
     uint32_t tot;
     block_exclusive_scan(acc, lds, tot);
     if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
+// Exclusive scan of the nb <= kScanMaxBlocks block partials in place (4 per thread).
 __global__ void __launch_bounds__(1024) k_scan_partials(uint32_t *part, int nb, uint32_t *total) {
+    constexpr int kPer = kScanMaxBlocks / 1024;
     __shared__ uint32_t lds[1024 / kWave];
     const int t = threadIdx.x;
-    const uint32_t x = t < nb ? part[t] : 0u;
+    uint32_t v[kPer], x = 0u;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        v[q] = kPer * t + q < nb ? part[kPer * t + q] : 0u;
+        x += v[q];
+    }
     const int lane = lane_id(), wid = t / kWave;
     const uint32_t inc = wave_inclusive_scan(x);
     if (lane == kWave - 1) lds[wid] = inc;
@@ -86,7 +110,12 @@ __global__ void __launch_bounds__(1024) k_scan_partials(uint32_t *part, int nb, 
         if (k < wid) base += lds[k];
         tot += lds[k];
     }
-    if (t < nb) part[t] = base + inc - x;
+    uint32_t pre = base + inc - x;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        if (kPer * t + q < nb) part[kPer * t + q] = pre;
+        pre += v[q];
+    }
     if (t == 0) *total = tot;
 }
 
@@ -95,27 +124,43 @@ k_scan_apply(const uint32_t *__restrict__ counts, const uint32_t *__restrict__ i
              int64_t n_max, int flag, const uint32_t *__restrict__ part, uint32_t *__restrict__ out) {
     __shared__ uint32_t lds[kScanBlock / kWave];
     const int64_t n = scan_n(n_dev, n_max);
-    const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
-    const int64_t b0 = (int64_t)blockIdx.x * chunk;
+    const int64_t chunk = scan_chunk(n);
+    const int64_t b0 = (int64_t)blockIdx.x * chunk < n ? (int64_t)blockIdx.x * chunk : n;
     const int64_t b1 = b0 + chunk < n ? b0 + chunk : n;
     uint32_t running = part[blockIdx.x];
     for (int64_t base = b0; base < b1; base += kScanTile) {
         uint32_t v[kScanItems];
         uint32_t sum = 0;
         const int64_t p0 = base + (int64_t)threadIdx.x * kScanItems;
+        const bool whole = p0 + kScanItems <= b1;
+        if (whole && !idx && flag == 0) {  // two 16-byte loads
+            const uint4 a = *reinterpret_cast<const uint4 *>(counts + p0);
+            const uint4 b = *reinterpret_cast<const uint4 *>(counts + p0 + 4);
+            v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+        } else {
 #pragma unroll
-        for (int k = 0; k < kScanItems; ++k) {
-            const int64_t p = p0 + k;
-            v[k] = p < b1 ? load_count(counts, idx, p, flag) : 0u;
-            sum += v[k];
+            for (int k = 0; k < kScanItems; ++k) {
+                const int64_t p = p0 + k;
+                v[k] = p < b1 ? load_count(counts, idx, p, flag) : 0u;
+            }
         }
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) sum += v[k];
         uint32_t tot;
         uint32_t pre = running + block_exclusive_scan(sum, lds, tot);
+        uint32_t o[kScanItems];
 #pragma unroll
         for (int k = 0; k < kScanItems; ++k) {
-            const int64_t p = p0 + k;
-            if (p < b1) out[p] = pre;
+            o[k] = pre;
             pre += v[k];
+        }
+        if (whole) {
+            *reinterpret_cast<uint4 *>(out + p0) = make_uint4(o[0], o[1], o[2], o[3]);
+            *reinterpret_cast<uint4 *>(out + p0 + 4) = make_uint4(o[4], o[5], o[6], o[7]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < kScanItems; ++k)
+                if (p0 + k < b1) out[p0 + k] = o[k];
         }
         running += tot;
     }
@@ -123,38 +168,55 @@ k_scan_apply(const uint32_t *__restrict__ counts, const uint32_t *__restrict__ i
 
 // The flag scan's second half fused with the compaction: the records with counts[r] != 0
 // go to consecutive positions in record order, with the depth key in ckey and the record
-// index (with pack, also its pair count) in cval.  Same chunking as k_scan_apply; part
-// holds each block's exclusive prefix of live records.
+// index (with pack, also its pair count) in cval.  Same chunking as k_scan_reduce; part
+// holds each block's exclusive prefix of live records.  Element base + 256 k + t of a
+// tile is thread t's k-th: every load and store instruction covers consecutive words, and
+// a live record's position is the live count of earlier (row, wave) groups plus its rank
+// among its wave's live lanes (a ballot).
 __global__ void __launch_bounds__(kScanBlock)
 k_scan_compact(const uint32_t *__restrict__ counts, const uint32_t *__restrict__ dkey, int64_t n,
                const uint32_t *__restrict__ part, uint32_t *__restrict__ ckey, uint32_t *__restrict__ cval,
                int pack) {
-    __shared__ uint32_t lds[kScanBlock / kWave];
-    const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
-    const int64_t b0 = (int64_t)blockIdx.x * chunk;
+    constexpr int NW = kScanBlock / kWave;
+    __shared__ uint32_t gcnt[kScanItems][NW];  // live records per (row, wave)
+    const int64_t chunk = scan_chunk(n);
+    const int64_t b0 = (int64_t)blockIdx.x * chunk < n ? (int64_t)blockIdx.x * chunk : n;
     const int64_t b1 = b0 + chunk < n ? b0 + chunk : n;
+    const int wid = threadIdx.x / kWave, lane = lane_id();
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     uint32_t running = part[blockIdx.x];
     for (int64_t base = b0; base < b1; base += kScanTile) {
-        uint32_t c[kScanItems];
-        uint32_t live = 0;
-        const int64_t p0 = base + (int64_t)threadIdx.x * kScanItems;
+        uint32_t c[kScanItems], dk[kScanItems];
+        uint64_t m[kScanItems];
 #pragma unroll
         for (int k = 0; k < kScanItems; ++k) {
-            const int64_t p = p0 + k;
+            const int64_t p = base + k * kScanBlock + threadIdx.x;
             c[k] = p < b1 ? counts[p] : 0u;
-            live += c[k] != 0u ? 1u : 0u;
+            dk[k] = p < b1 ? dkey[p] : 0u;
         }
-        uint32_t tot;
-        uint32_t pos = running + block_exclusive_scan(live, lds, tot);
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            m[k] = ballot(c[k] != 0u);
+            if (lane == 0) gcnt[k][wid] = (uint32_t)__popcll(m[k]);
+        }
+        __syncthreads();
+        uint32_t pre[kScanItems], acc = 0u;
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k)
+            for (int w = 0; w < NW; ++w) {
+                if (w == wid) pre[k] = acc;
+                acc += gcnt[k][w];
+            }
 #pragma unroll
         for (int k = 0; k < kScanItems; ++k) {
             if (c[k] == 0u) continue;
-            const int64_t p = p0 + k;
-            ckey[pos] = dkey[p];
+            const int64_t p = base + k * kScanBlock + threadIdx.x;
+            const uint32_t pos = running + pre[k] + (uint32_t)__popcll(m[k] & lt);
+            ckey[pos] = dk[k];
             cval[pos] = pack ? (uint32_t)p | (min(c[k], kPackCountMax) << kPackShift) : (uint32_t)p;
-            ++pos;
         }
-        running += tot;
+        running += acc;
+        __syncthreads();  // the counts are read before the next tile writes them
     }
 }
 
@@ -663,9 +725,11 @@ hipError_t launch_sum_u64(const uint32_t *x, int64_t n, unsigned long long *out,
 
 // ------------------------------- host wrappers ----------------------------------------
 
+// One block per tile of kScanTile elements (up to kScanMaxBlocks): every block then does
+// one round of loads, scan and stores, where fewer blocks would each wait on several.
 static int64_t scan_blocks(int64_t n) {
     int64_t nb = (n + kScanTile - 1) / kScanTile;
-    if (nb > 1024) nb = 1024;
+    if (nb > kScanMaxBlocks) nb = kScanMaxBlocks;
     return nb < 1 ? 1 : nb;
 }
 

@@ -62,6 +62,7 @@ constexpr int kG2 = 16;
 // The radix sorts publish 30-bit counts in their look-back words, so a sort takes fewer
 // than 2^30 keys: records per window and tile pairs per frame are bounded by this.
 constexpr int64_t kMaxSortKeys = int64_t(1) << 30;
+constexpr int kScanMaxBlocks = 4096;  // blocks of a device-wide scan (scratch: one word each)
 
 // Records with more tile pairs than this are counted and emitted by whole waves.
 constexpr uint32_t kBigRecord = 64;
