@@ -382,12 +382,11 @@ gspm_status gspm_render_forward(gspm_ctx *ctx, const gspm_gaussians *g, const gs
     uint32_t *hist = static_cast<uint32_t *>(ctx->hist.p);
     uint32_t *part = static_cast<uint32_t *>(ctx->scan_part.p);
 
-    GSPM_HIP(launch_fill_u32(&hdr->sort_stall, 0u, 1, hs));
     // 1. Project every (Gaussian, view) record.
     PhaseTimer t_pre(ctx, hs, GSPM_PHASE_PREPROCESS);
     GSPM_HIP(launch_preprocess(*g, P.vt, views->T_cw, P.rs, records, counts, static_cast<uint32_t *>(ctx->dkey.p),
                                static_cast<uint4 *>(ctx->spans.p), static_cast<uint32_t *>(ctx->big.p), total + 1,
-                               hs));
+                               &hdr->sort_stall, hs));
     t_pre.stop();
     // Device-side counts: total[0] tile pairs, total[1] queued large records, total[2] live records.
     uint32_t *n_live = total + 2;
@@ -412,7 +411,7 @@ gspm_status gspm_render_forward(gspm_ctx *ctx, const gspm_gaussians *g, const gs
         // in depth order, unpacked (or gathered) once by the scan.
         GSPM_HIP(launch_scan_indirect(counts, static_cast<uint32_t *>(ctx->dval_s.p), R,
                                       static_cast<uint32_t *>(ctx->offsets.p), total, part, hs, n_live, pack ? 2 : 0,
-                                      static_cast<uint32_t *>(ctx->dkey_s.p)));
+                                      static_cast<uint32_t *>(ctx->dkey_s.p), total + 1));  // + the emitter's queue count
     } else {
         GSPM_HIP(launch_fill_u32(total, 0u, 3, hs));
     }

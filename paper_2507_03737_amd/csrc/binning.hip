@@ -91,7 +91,7 @@ k_scan_reduce(const uint32_t *__restrict__ counts, const uint32_t *__restrict__ 
 }
 
 // Exclusive scan of the nb <= kScanMaxBlocks block partials in place (4 per thread).
-__global__ void __launch_bounds__(1024) k_scan_partials(uint32_t *part, int nb, uint32_t *total) {
+__global__ void __launch_bounds__(1024) k_scan_partials(uint32_t *part, int nb, uint32_t *total, uint32_t *clear) {
     constexpr int kPer = kScanMaxBlocks / 1024;
     __shared__ uint32_t lds[1024 / kWave];
     const int t = threadIdx.x;
@@ -116,7 +116,10 @@ __global__ void __launch_bounds__(1024) k_scan_partials(uint32_t *part, int nb, 
         if (kPer * t + q < nb) part[kPer * t + q] = pre;
         pre += v[q];
     }
-    if (t == 0) *total = tot;
+    if (t == 0) {
+        *total = tot;
+        if (clear) *clear = 0u;  // a counter of the next kernel, cleared here to save a launch
+    }
 }
 
 __global__ void __launch_bounds__(kScanBlock)
@@ -737,14 +740,14 @@ int64_t scan_partials(int64_t n) { return scan_blocks(n); }
 
 hipError_t launch_scan_indirect(const uint32_t *counts, const uint32_t *idx, int64_t n, uint32_t *offsets,
                                 uint32_t *total, uint32_t *part, hipStream_t s, const uint32_t *n_dev, int flag,
-                                uint32_t *gathered) {
+                                uint32_t *gathered, uint32_t *clear) {
     const int64_t nb = scan_blocks(n);
     // With `gathered`, the reduce pass stores counts[idx[p]] (or its flag) there and the
     // apply pass reads it back contiguously instead of gathering a second time.
     if (!idx) gathered = nullptr;
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanBlock), 0, s, counts, idx, n_dev, n, flag, part,
                        gathered);
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, part, (int)nb, total);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, part, (int)nb, total, clear);
     if (gathered)
         hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kScanBlock), 0, s, gathered, nullptr, n_dev, n, 0,
                            part, offsets);
@@ -761,7 +764,7 @@ hipError_t launch_compact(const uint32_t *counts, const uint32_t *dkey, int64_t 
     const int64_t nb = scan_blocks(n);
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanBlock), 0, s, counts, nullptr, nullptr, n, 1, part,
                        nullptr);
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, part, (int)nb, n_live);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, part, (int)nb, n_live, nullptr);
     hipLaunchKernelGGL(k_scan_compact, dim3((unsigned)nb), dim3(kScanBlock), 0, s, counts, dkey, n, part, ckey, cval,
                        pack ? 1 : 0);
     return hipGetLastError();
@@ -836,8 +839,6 @@ hipError_t launch_keygen(const uint32_t *sorted_rec, uint32_t rec_mask, const ui
                          const ViewTable &vt, uint32_t *pkey, uint32_t *pval, FrameHeader *hdr, uint32_t capacity,
                          const uint32_t *total, uint32_t *big_list, uint32_t *big_count, const uint32_t *n_dev,
                          hipStream_t s) {
-    hipError_t e = launch_fill_u32(big_count, 0u, 1, s);
-    if (e != hipSuccess) return e;
     const float4 *rec = reinterpret_cast<const float4 *>(records);
     const int64_t nb = n_records > 0 ? (n_records + 255) / 256 : 1;
     hipLaunchKernelGGL(k_keygen, dim3((unsigned)nb), dim3(256), 0, s, sorted_rec, rec_mask, sorted_counts, offsets, rec,
@@ -856,6 +857,7 @@ hipError_t launch_keygen(const uint32_t *sorted_rec, uint32_t rec_mask, const ui
 constexpr int kOrderBlock = 1024;
 constexpr int kOrderClasses = 256;
 constexpr int kOrderShift = 5;
+constexpr int kOrderItems = 8;
 
 __global__ void __launch_bounds__(kOrderBlock)
 k_order_tiles(uint2 *__restrict__ ranges, const uint32_t *__restrict__ work, int64_t n,
@@ -864,13 +866,30 @@ k_order_tiles(uint2 *__restrict__ ranges, const uint32_t *__restrict__ work, int
     __shared__ uint32_t scan_lds[kOrderBlock / kWave];
     for (int b = threadIdx.x; b < kOrderClasses; b += kOrderBlock) cnt[b] = 0u;
     __syncthreads();
-    auto cls = [&](int64_t t) {
-        const uint32_t w = ranges ? ranges[t].y - ranges[t].x : work[t];
+    auto cls_of = [&](uint32_t w) {
         return (uint32_t)(kOrderClasses - 1) - min((uint32_t)(kOrderClasses - 1), w >> kOrderShift);
     };
-    for (int64_t t = threadIdx.x; t < n; t += kOrderBlock) {
-        if (ranges && ranges[t].x > ranges[t].y) ranges[t] = make_uint2(0u, 0u);
-        atomicAdd(&cnt[cls(t)], 1u);
+    // kOrderItems tiles per thread and step, their reads issued together: one memory latency
+    // per step rather than one per tile.
+    for (int64_t t0 = threadIdx.x; t0 < n; t0 += (int64_t)kOrderBlock * kOrderItems) {
+        uint2 rg[kOrderItems];
+        uint32_t wk[kOrderItems];
+#pragma unroll
+        for (int q = 0; q < kOrderItems; ++q) {
+            const int64_t t = t0 + (int64_t)q * kOrderBlock;
+            rg[q] = ranges && t < n ? ranges[t] : make_uint2(0u, 0u);
+            wk[q] = !ranges && t < n ? work[t] : 0u;
+        }
+#pragma unroll
+        for (int q = 0; q < kOrderItems; ++q) {
+            const int64_t t = t0 + (int64_t)q * kOrderBlock;
+            if (t >= n) continue;
+            if (ranges && rg[q].x > rg[q].y) {
+                rg[q] = make_uint2(0u, 0u);
+                ranges[t] = rg[q];
+            }
+            atomicAdd(&cnt[cls_of(ranges ? rg[q].y - rg[q].x : wk[q])], 1u);
+        }
     }
     __syncthreads();
     // Class starts: a block-wide scan (one class per thread), not a serial loop of 256
@@ -880,7 +899,22 @@ k_order_tiles(uint2 *__restrict__ ranges, const uint32_t *__restrict__ work, int
     const uint32_t start = block_exclusive_scan<kOrderBlock / kWave>(c, scan_lds, total);
     if (threadIdx.x < kOrderClasses) cnt[threadIdx.x] = start;
     __syncthreads();
-    for (int64_t t = threadIdx.x; t < n; t += kOrderBlock) order[atomicAdd(&cnt[cls(t)], 1u)] = (uint32_t)t;
+    for (int64_t t0 = threadIdx.x; t0 < n; t0 += (int64_t)kOrderBlock * kOrderItems) {
+        uint32_t wk[kOrderItems];
+#pragma unroll
+        for (int q = 0; q < kOrderItems; ++q) {
+            const int64_t t = t0 + (int64_t)q * kOrderBlock;
+            if (t < n) {
+                const uint2 r = ranges ? ranges[t] : make_uint2(0u, 0u);
+                wk[q] = ranges ? r.y - r.x : work[t];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kOrderItems; ++q) {
+            const int64_t t = t0 + (int64_t)q * kOrderBlock;
+            if (t < n) order[atomicAdd(&cnt[cls_of(wk[q])], 1u)] = (uint32_t)t;
+        }
+    }
 }
 
 hipError_t launch_order_tiles(uint2 *ranges, const uint32_t *work, int64_t n_tiles, uint32_t *order,

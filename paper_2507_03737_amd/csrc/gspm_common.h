@@ -402,11 +402,11 @@ hipError_t launch_fill_f32(float *p, float value, int64_t n, hipStream_t s);
 
 // Projects every record and counts its tile pairs, caching the tile-row spans of records
 // with pairs in spans [N V]; big_list / big_count are scratch for the records counted by
-// whole waves (big_count is zeroed here).
+// whole waves (big_count is zeroed here, and clear_also, if not NULL, in the same launch).
 hipError_t launch_preprocess(const gspm_gaussians &g, const ViewTable &vt, const float *T_cw,
                              const RasterSettings &rs, float *records, uint32_t *counts,
                              uint32_t *dkey, uint4 *spans, uint32_t *big_list, uint32_t *big_count,
-                             hipStream_t s);
+                             uint32_t *clear_also, hipStream_t s);
 
 // A window of at most 2^kPackShift records carries each live record through the depth sort
 // as its index with its pair count in the top bits, so that the pair-offset scan reads
@@ -423,7 +423,8 @@ constexpr uint32_t kPackCountMax = (1u << (32 - kPackShift)) - 1u;
 int64_t scan_partials(int64_t n);
 hipError_t launch_scan_indirect(const uint32_t *counts, const uint32_t *idx, int64_t n,
                                 uint32_t *offsets, uint32_t *total, uint32_t *part, hipStream_t s,
-                                const uint32_t *n_dev = nullptr, int flag = 0, uint32_t *gathered = nullptr);
+                                const uint32_t *n_dev = nullptr, int flag = 0, uint32_t *gathered = nullptr,
+                                uint32_t *clear = nullptr);
 
 // Compacts (depth key, record index) of the records with counts[r] != 0, in record order,
 // and writes their number to *n_live; with pack, the value also carries the pair count
@@ -446,8 +447,8 @@ hipError_t radix_sort(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t
                       uint2 *ranges, hipStream_t s);
 
 // Emits the (global tile, record) pairs of every record in depth order.  Records with
-// more than kBigRecord pairs are queued in big_list (big_count zeroed here) and emitted
-// by whole waves.  records: the projected records (for the support footprint of records
+// more than kBigRecord pairs are queued in big_list (big_count must be zero on entry: the
+// pair-offset scan clears it) and emitted by whole waves.  records: the projected records (for the support footprint of records
 // whose spans are not cached in spans).
 // rec_mask: kPackMask if sorted_rec carries packed counts, else all ones.
 hipError_t launch_keygen(const uint32_t *sorted_rec, uint32_t rec_mask, const uint32_t *sorted_counts,

@@ -468,6 +468,14 @@ k_pose_reduce(const double *__restrict__ part, int64_t nblocks, float *__restric
     }
 }
 
+// Zeroes one or two counters in one launch.
+__global__ void k_clear2(uint32_t *a, uint32_t *b) {
+    if (threadIdx.x == 0) {
+        *a = 0u;
+        if (b) *b = 0u;
+    }
+}
+
 __global__ void k_fill_u32(uint32_t *p, uint32_t value, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = value;
@@ -540,11 +548,10 @@ hipError_t launch_fill_f32(float *p, float value, int64_t n, hipStream_t s) {
 hipError_t launch_preprocess(const gspm_gaussians &g, const ViewTable &vt, const float *T_cw,
                              const RasterSettings &rs, float *records, uint32_t *counts,
                              uint32_t *dkey, uint4 *spans, uint32_t *big_list, uint32_t *big_count,
-                             hipStream_t s) {
+                             uint32_t *clear_also, hipStream_t s) {
     const int64_t R = g.n * vt.n_views;
-    if (R <= 0) return hipSuccess;
-    hipError_t e = launch_fill_u32(big_count, 0u, 1, s);
-    if (e != hipSuccess) return e;
+    if (R <= 0) return clear_also ? launch_fill_u32(clear_also, 0u, 1, s) : hipSuccess;
+    hipLaunchKernelGGL(k_clear2, dim3(1), dim3(64), 0, s, big_count, clear_also);
     hipLaunchKernelGGL(k_preprocess, dim3((unsigned)((g.n + 255) / 256), 1u), dim3(256), 0, s, g,
                        vt, T_cw, rs, reinterpret_cast<float4 *>(records), counts, dkey, spans, big_list, big_count);
     hipLaunchKernelGGL(k_count_big, dim3(1024), dim3(256), 0, s, reinterpret_cast<const float4 *>(records), vt, rs,
