@@ -401,7 +401,7 @@ gspm_status gspm_render_forward(gspm_ctx *ctx, const gspm_gaussians *g, const gs
         GSPM_HIP(radix_sort(static_cast<uint32_t *>(ctx->dval.p), static_cast<uint32_t *>(ctx->live.p),
                             static_cast<uint32_t *>(ctx->dkey_tmp.p), static_cast<uint32_t *>(ctx->dval_tmp.p),
                             static_cast<uint32_t *>(ctx->dkey_s.p), static_cast<uint32_t *>(ctx->dval_s.p), R, n_live,
-                            32, db, hist, &hdr->sort_stall, nullptr, hs));
+                            32, db, hist, &hdr->sort_stall, nullptr, hs, false));
         t_ds.stop();
     }
     PhaseTimer t_bin(ctx, hs, GSPM_PHASE_BINNING);
@@ -431,7 +431,7 @@ gspm_status gspm_render_forward(gspm_ctx *ctx, const gspm_gaussians *g, const gs
         GSPM_HIP(radix_sort(static_cast<uint32_t *>(ctx->pkey.p), static_cast<uint32_t *>(ctx->pval.p),
                             static_cast<uint32_t *>(ctx->pkey_tmp.p), static_cast<uint32_t *>(ctx->pval_tmp.p),
                             static_cast<uint32_t *>(ctx->pkey_s.p), pair_vals, cap, &hdr->pairs,
-                            tile_bits(P.n_tiles), db, hist, &hdr->sort_stall, ranges, hs));
+                            tile_bits(P.n_tiles), db, hist, &hdr->sort_stall, ranges, hs, false));
         t_ts.stop();
     }
     // Heaviest tiles first: by list length for the forward; the forward measures each

@@ -502,7 +502,7 @@ k_radix_pass(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
         const uint32_t k = lk[j];
         const uint32_t d = (k >> shift) & (R - 1);
         const uint32_t pos = gbase[d] + ((uint32_t)j - dstart[d]);
-        kout[pos] = k;
+        if (kout) kout[pos] = k;  // the last pass may drop the keys: only the values are used
         vout[pos] = lv[j];
         if (ranges) {
             // Final pass over tile ids: the tile is sorted in LDS, so the output neighbours of
@@ -784,7 +784,7 @@ int64_t radix_hist_words(int64_t n_max, int digit_bits) {
 template <int DB>
 static void sort_passes(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_tmp, uint32_t *vals_tmp,
                         uint32_t *keys_out, uint32_t *vals_out, int64_t n_max, const uint32_t *n_dev, int passes,
-                        uint32_t *scratch, uint32_t *stall, uint2 *ranges, hipStream_t s) {
+                        uint32_t *scratch, uint32_t *stall, uint2 *ranges, bool keep_keys, hipStream_t s) {
     constexpr int R = 1 << DB;
     const int64_t tiles = sort_tiles(n_max);
     uint32_t *ghist = scratch;
@@ -803,7 +803,8 @@ static void sort_passes(const uint32_t *keys_in, const uint32_t *vals_in, uint32
         const bool to_out = ((passes - 1 - p) % 2) == 0;
         uint32_t *ko = to_out ? keys_out : keys_tmp;
         uint32_t *vo = to_out ? vals_out : vals_tmp;
-        hipLaunchKernelGGL(k_radix_pass<DB>, dim3((unsigned)tiles), dim3(kSortBlock), 0, s, kin, vin, ko, vo, n_dev,
+        hipLaunchKernelGGL(k_radix_pass<DB>, dim3((unsigned)tiles), dim3(kSortBlock), 0, s, kin, vin,
+                           p == passes - 1 && !keep_keys ? nullptr : ko, vo, n_dev,
                            n_max, p * DB, ghist + (int64_t)p * R, status[p & 1], status[(p + 1) & 1], stall,
                            p == passes - 1 ? ranges : nullptr, p == 0 ? tprefix : nullptr, tiles);
         kin = ko;
@@ -813,7 +814,8 @@ static void sort_passes(const uint32_t *keys_in, const uint32_t *vals_in, uint32
 
 hipError_t radix_sort(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_tmp, uint32_t *vals_tmp,
                       uint32_t *keys_out, uint32_t *vals_out, int64_t n_max, const uint32_t *n_dev, int bits,
-                      int digit_bits, uint32_t *scratch, uint32_t *stall, uint2 *ranges, hipStream_t s) {
+                      int digit_bits, uint32_t *scratch, uint32_t *stall, uint2 *ranges, hipStream_t s,
+                      bool keep_keys) {
     if (n_max <= 0) return hipSuccess;
     if (bits < 1) bits = 1;
     if (digit_bits < 4 || digit_bits > 8) return hipErrorInvalidValue;
@@ -824,11 +826,11 @@ hipError_t radix_sort(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t
     int db = (bits + passes - 1) / passes;
     if (db < 4) db = 4;
     switch (db) {
-        case 4: sort_passes<4>(keys_in, vals_in, keys_tmp, vals_tmp, keys_out, vals_out, n_max, n_dev, passes, scratch, stall, ranges, s); break;
-        case 5: sort_passes<5>(keys_in, vals_in, keys_tmp, vals_tmp, keys_out, vals_out, n_max, n_dev, passes, scratch, stall, ranges, s); break;
-        case 6: sort_passes<6>(keys_in, vals_in, keys_tmp, vals_tmp, keys_out, vals_out, n_max, n_dev, passes, scratch, stall, ranges, s); break;
-        case 7: sort_passes<7>(keys_in, vals_in, keys_tmp, vals_tmp, keys_out, vals_out, n_max, n_dev, passes, scratch, stall, ranges, s); break;
-        default: sort_passes<8>(keys_in, vals_in, keys_tmp, vals_tmp, keys_out, vals_out, n_max, n_dev, passes, scratch, stall, ranges, s); break;
+        case 4: sort_passes<4>(keys_in, vals_in, keys_tmp, vals_tmp, keys_out, vals_out, n_max, n_dev, passes, scratch, stall, ranges, keep_keys, s); break;
+        case 5: sort_passes<5>(keys_in, vals_in, keys_tmp, vals_tmp, keys_out, vals_out, n_max, n_dev, passes, scratch, stall, ranges, keep_keys, s); break;
+        case 6: sort_passes<6>(keys_in, vals_in, keys_tmp, vals_tmp, keys_out, vals_out, n_max, n_dev, passes, scratch, stall, ranges, keep_keys, s); break;
+        case 7: sort_passes<7>(keys_in, vals_in, keys_tmp, vals_tmp, keys_out, vals_out, n_max, n_dev, passes, scratch, stall, ranges, keep_keys, s); break;
+        default: sort_passes<8>(keys_in, vals_in, keys_tmp, vals_tmp, keys_out, vals_out, n_max, n_dev, passes, scratch, stall, ranges, keep_keys, s); break;
     }
     return hipGetLastError();
 }

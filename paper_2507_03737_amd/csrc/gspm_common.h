@@ -439,12 +439,13 @@ hipError_t launch_compact(const uint32_t *counts, const uint32_t *dkey, int64_t 
 // *stall (device) is set if a pass gave up waiting for an earlier tile (the result is
 // then invalid); the caller clears it.  ranges (optional): the keys are tile ids and the
 // final pass writes each tile's [first, end) positions; the caller fills it with
-// (0xffffffff, 0) beforehand, which empty tiles keep.
+// (0xffffffff, 0) beforehand, which empty tiles keep.  keep_keys = false: the final pass
+// writes only the values (keys_out then holds an earlier pass's keys).
 int64_t radix_hist_words(int64_t n_max, int digit_bits);
 hipError_t radix_sort(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_tmp,
                       uint32_t *vals_tmp, uint32_t *keys_out, uint32_t *vals_out, int64_t n_max,
                       const uint32_t *n_dev, int bits, int digit_bits, uint32_t *scratch, uint32_t *stall,
-                      uint2 *ranges, hipStream_t s);
+                      uint2 *ranges, hipStream_t s, bool keep_keys = true);
 
 // Emits the (global tile, record) pairs of every record in depth order.  Records with
 // more than kBigRecord pairs are queued in big_list (big_count must be zero on entry: the
