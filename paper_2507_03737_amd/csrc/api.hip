@@ -416,14 +416,13 @@ gspm_status gspm_render_forward(gspm_ctx *ctx, const gspm_gaussians *g, const gs
         GSPM_HIP(launch_fill_u32(total, 0u, 3, hs));
     }
     // 4. Emit (tile, record) pairs; the header gets the pair count and overflow flag.
-    GSPM_HIP(launch_fill_ranges(ranges, P.n_tiles, hs));
     GSPM_HIP(launch_keygen(static_cast<uint32_t *>(ctx->dval_s.p), pack ? kPackMask : 0xffffffffu,
                            static_cast<uint32_t *>(ctx->dkey_s.p),
                            static_cast<uint32_t *>(ctx->offsets.p),
                            records, static_cast<const uint4 *>(ctx->spans.p), P.rs, R, g->n > 0 ? g->n : 1, P.vt,
                            static_cast<uint32_t *>(ctx->pkey.p),
                            static_cast<uint32_t *>(ctx->pval.p), hdr, (uint32_t)cap, total,
-                           static_cast<uint32_t *>(ctx->big.p), total + 1, n_live, hs));
+                           static_cast<uint32_t *>(ctx->big.p), total + 1, n_live, ranges, P.n_tiles, hs));
     t_bin.stop();
     // 5. Stable sort by tile id; its final pass writes the per-tile ranges (6).
     if (cap > 0) {

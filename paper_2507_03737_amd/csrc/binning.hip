@@ -90,47 +90,44 @@ k_scan_reduce(const uint32_t *__restrict__ counts, const uint32_t *__restrict__ 
     if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
-// Exclusive scan of the nb <= kScanMaxBlocks block partials in place (4 per thread).
-__global__ void __launch_bounds__(1024) k_scan_partials(uint32_t *part, int nb, uint32_t *total, uint32_t *clear) {
-    constexpr int kPer = kScanMaxBlocks / 1024;
-    __shared__ uint32_t lds[1024 / kWave];
-    const int t = threadIdx.x;
-    uint32_t v[kPer], x = 0u;
+// The sum of the block partials before this block, and in `all` the sum of every block's:
+// each block adds them itself (at most kScanMaxBlocks words, all loads in flight at once),
+// which spares a separate launch that would scan them.
+__device__ inline uint32_t partial_prefix(const uint32_t *__restrict__ part, uint32_t *lds, uint32_t &all) {
+    constexpr int kPer = kScanMaxBlocks / kScanBlock;
+    uint32_t v[kPer];
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
-        v[q] = kPer * t + q < nb ? part[kPer * t + q] : 0u;
-        x += v[q];
+        const int b = (int)threadIdx.x + q * kScanBlock;
+        v[q] = b < (int)gridDim.x ? part[b] : 0u;
     }
-    const int lane = lane_id(), wid = t / kWave;
-    const uint32_t inc = wave_inclusive_scan(x);
-    if (lane == kWave - 1) lds[wid] = inc;
-    __syncthreads();
-    uint32_t base = 0, tot = 0;
-    for (int k = 0; k < 1024 / kWave; ++k) {
-        if (k < wid) base += lds[k];
-        tot += lds[k];
-    }
-    uint32_t pre = base + inc - x;
+    uint32_t before = 0u, every = 0u;
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
-        if (kPer * t + q < nb) part[kPer * t + q] = pre;
-        pre += v[q];
+        every += v[q];
+        before += (int)threadIdx.x + q * kScanBlock < (int)blockIdx.x ? v[q] : 0u;
     }
-    if (t == 0) {
-        *total = tot;
-        if (clear) *clear = 0u;  // a counter of the next kernel, cleared here to save a launch
-    }
+    uint32_t pre;
+    block_exclusive_scan(before, lds, pre);
+    block_exclusive_scan(every, lds, all);
+    return pre;
 }
 
 __global__ void __launch_bounds__(kScanBlock)
 k_scan_apply(const uint32_t *__restrict__ counts, const uint32_t *__restrict__ idx, const uint32_t *__restrict__ n_dev,
-             int64_t n_max, int flag, const uint32_t *__restrict__ part, uint32_t *__restrict__ out) {
+             int64_t n_max, int flag, const uint32_t *__restrict__ part, uint32_t *__restrict__ out,
+             uint32_t *__restrict__ total, uint32_t *__restrict__ clear) {
     __shared__ uint32_t lds[kScanBlock / kWave];
     const int64_t n = scan_n(n_dev, n_max);
     const int64_t chunk = scan_chunk(n);
     const int64_t b0 = (int64_t)blockIdx.x * chunk < n ? (int64_t)blockIdx.x * chunk : n;
     const int64_t b1 = b0 + chunk < n ? b0 + chunk : n;
-    uint32_t running = part[blockIdx.x];
+    uint32_t all;
+    uint32_t running = partial_prefix(part, lds, all);
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        *total = all;
+        if (clear) *clear = 0u;  // a counter of the next kernel, cleared here to save a launch
+    }
     for (int64_t base = b0; base < b1; base += kScanTile) {
         uint32_t v[kScanItems];
         uint32_t sum = 0;
@@ -172,22 +169,25 @@ k_scan_apply(const uint32_t *__restrict__ counts, const uint32_t *__restrict__ i
 // The flag scan's second half fused with the compaction: the records with counts[r] != 0
 // go to consecutive positions in record order, with the depth key in ckey and the record
 // index (with pack, also its pair count) in cval.  Same chunking as k_scan_reduce; part
-// holds each block's exclusive prefix of live records.  Element base + 256 k + t of a
+// holds each block's count of live records (k_scan_reduce's), and *n_live gets their sum.  Element base + 256 k + t of a
 // tile is thread t's k-th: every load and store instruction covers consecutive words, and
 // a live record's position is the live count of earlier (row, wave) groups plus its rank
 // among its wave's live lanes (a ballot).
 __global__ void __launch_bounds__(kScanBlock)
 k_scan_compact(const uint32_t *__restrict__ counts, const uint32_t *__restrict__ dkey, int64_t n,
                const uint32_t *__restrict__ part, uint32_t *__restrict__ ckey, uint32_t *__restrict__ cval,
-               int pack) {
+               int pack, uint32_t *__restrict__ n_live) {
     constexpr int NW = kScanBlock / kWave;
     __shared__ uint32_t gcnt[kScanItems][NW];  // live records per (row, wave)
+    __shared__ uint32_t lds[kScanBlock / kWave];
     const int64_t chunk = scan_chunk(n);
     const int64_t b0 = (int64_t)blockIdx.x * chunk < n ? (int64_t)blockIdx.x * chunk : n;
     const int64_t b1 = b0 + chunk < n ? b0 + chunk : n;
     const int wid = threadIdx.x / kWave, lane = lane_id();
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    uint32_t running = part[blockIdx.x];
+    uint32_t all;
+    uint32_t running = partial_prefix(part, lds, all);
+    if (threadIdx.x == 0 && blockIdx.x == 0) *n_live = all;
     for (int64_t base = b0; base < b1; base += kScanTile) {
         uint32_t c[kScanItems], dk[kScanItems];
         uint64_t m[kScanItems];
@@ -551,7 +551,7 @@ k_keygen(const uint32_t *__restrict__ sorted_rec, uint32_t rec_mask, const uint3
          RasterSettings rs, int64_t n_records, int64_t n_per_view, ViewTable vt, uint32_t *__restrict__ pkey,
          uint32_t *__restrict__ pval, FrameHeader *__restrict__ hdr, uint32_t cap,
          const uint32_t *__restrict__ total, uint32_t *__restrict__ big_list, uint32_t *__restrict__ big_count,
-         const uint32_t *__restrict__ n_dev) {
+         const uint32_t *__restrict__ n_dev, uint2 *__restrict__ ranges, int64_t n_tiles) {
     __shared__ uint32_t row_pos[kKeygenWaves][kKeygenRows];   // first output position
     __shared__ uint32_t row_tile[kKeygenWaves][kKeygenRows];  // global tile id of the first tile
     __shared__ uint32_t row_rec[kKeygenWaves][kKeygenRows];   // record index
@@ -559,6 +559,8 @@ k_keygen(const uint32_t *__restrict__ sorted_rec, uint32_t rec_mask, const uint3
     __shared__ uint8_t starts[kKeygenWaves][kWave];          // rows starting at window position
     const int wid = threadIdx.x / kWave, lane = lane_id();
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // Empty tile ranges, for the tile sort's last pass to narrow (here to save a launch).
+    for (int64_t t = p; t < n_tiles; t += (int64_t)gridDim.x * blockDim.x) ranges[t] = make_uint2(0xffffffffu, 0u);
     if (p == 0) {
         // Everything a backward checks before it reads the frame state.
         const uint32_t t = *total;
@@ -747,13 +749,12 @@ hipError_t launch_scan_indirect(const uint32_t *counts, const uint32_t *idx, int
     if (!idx) gathered = nullptr;
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanBlock), 0, s, counts, idx, n_dev, n, flag, part,
                        gathered);
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, part, (int)nb, total, clear);
     if (gathered)
         hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kScanBlock), 0, s, gathered, nullptr, n_dev, n, 0,
-                           part, offsets);
+                           part, offsets, total, clear);
     else
         hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kScanBlock), 0, s, counts, idx, n_dev, n, flag,
-                           part, offsets);
+                           part, offsets, total, clear);
     return hipGetLastError();
 }
 
@@ -764,9 +765,8 @@ hipError_t launch_compact(const uint32_t *counts, const uint32_t *dkey, int64_t 
     const int64_t nb = scan_blocks(n);
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanBlock), 0, s, counts, nullptr, nullptr, n, 1, part,
                        nullptr);
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, part, (int)nb, n_live, nullptr);
     hipLaunchKernelGGL(k_scan_compact, dim3((unsigned)nb), dim3(kScanBlock), 0, s, counts, dkey, n, part, ckey, cval,
-                       pack ? 1 : 0);
+                       pack ? 1 : 0, n_live);
     return hipGetLastError();
 }
 
@@ -840,12 +840,12 @@ hipError_t launch_keygen(const uint32_t *sorted_rec, uint32_t rec_mask, const ui
                          int64_t n_records, int64_t n_per_view,
                          const ViewTable &vt, uint32_t *pkey, uint32_t *pval, FrameHeader *hdr, uint32_t capacity,
                          const uint32_t *total, uint32_t *big_list, uint32_t *big_count, const uint32_t *n_dev,
-                         hipStream_t s) {
+                         uint2 *ranges, int64_t n_tiles, hipStream_t s) {
     const float4 *rec = reinterpret_cast<const float4 *>(records);
     const int64_t nb = n_records > 0 ? (n_records + 255) / 256 : 1;
     hipLaunchKernelGGL(k_keygen, dim3((unsigned)nb), dim3(256), 0, s, sorted_rec, rec_mask, sorted_counts, offsets, rec,
                        spans, rs, n_records, n_per_view, vt, pkey, pval, hdr, capacity, total, big_list, big_count,
-                       n_dev);
+                       n_dev, ranges, n_tiles);
     if (n_records > 0)
         hipLaunchKernelGGL(k_keygen_big, dim3(1024), dim3(256), 0, s, sorted_rec, rec_mask, offsets, rec, rs,
                            n_per_view, vt, pkey, pval, capacity, big_list, big_count);
@@ -924,19 +924,6 @@ hipError_t launch_order_tiles(uint2 *ranges, const uint32_t *work, int64_t n_til
     if (n_tiles <= 0) return hipSuccess;
     if ((ranges == nullptr) == (work == nullptr)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_order_tiles, dim3(1), dim3(kOrderBlock), 0, s, ranges, work, n_tiles, order);
-    return hipGetLastError();
-}
-
-__global__ void k_fill_ranges(uint2 *ranges, int64_t n) {
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
-        ranges[t] = make_uint2(0xffffffffu, 0u);
-}
-
-hipError_t launch_fill_ranges(uint2 *ranges, int64_t n_tiles, hipStream_t s) {
-    if (n_tiles <= 0) return hipSuccess;
-    int64_t nb = (n_tiles + 255) / 256;
-    if (nb > 1024) nb = 1024;
-    hipLaunchKernelGGL(k_fill_ranges, dim3((unsigned)nb), dim3(256), 0, s, ranges, n_tiles);
     return hipGetLastError();
 }
 

@@ -450,14 +450,15 @@ hipError_t radix_sort(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t
 // Emits the (global tile, record) pairs of every record in depth order.  Records with
 // more than kBigRecord pairs are queued in big_list (big_count must be zero on entry: the
 // pair-offset scan clears it) and emitted by whole waves.  records: the projected records (for the support footprint of records
-// whose spans are not cached in spans).
+// whose spans are not cached in spans).  It also fills ranges [n_tiles] with the empty
+// range (0xffffffff, 0) that the tile sort's last pass narrows.
 // rec_mask: kPackMask if sorted_rec carries packed counts, else all ones.
 hipError_t launch_keygen(const uint32_t *sorted_rec, uint32_t rec_mask, const uint32_t *sorted_counts,
                          const uint32_t *offsets, const float *records, const uint4 *spans, const RasterSettings &rs,
                          int64_t n_records, int64_t n_per_view,
                          const ViewTable &vt, uint32_t *pkey, uint32_t *pval, FrameHeader *hdr,
                          uint32_t capacity, const uint32_t *total, uint32_t *big_list, uint32_t *big_count,
-                         const uint32_t *n_dev, hipStream_t s);
+                         const uint32_t *n_dev, uint2 *ranges, int64_t n_tiles, hipStream_t s);
 
 hipError_t launch_sum_u64(const uint32_t *x, int64_t n, unsigned long long *out, hipStream_t s);
 
@@ -490,9 +491,6 @@ hipError_t launch_covisibility(const uint8_t *visible, int64_t n, int V, const F
 int64_t median_scratch_words(int V);
 hipError_t launch_median_depth(const ViewTable &vt, const float *depth, uint32_t *scratch, float *out,
                                hipStream_t s);
-
-// Fills the ranges with (0xffffffff, 0) for radix_sort's final pass to narrow.
-hipError_t launch_fill_ranges(uint2 *ranges, int64_t n_tiles, hipStream_t s);
 
 // Launch order of the raster workgroups, heaviest tiles first: the tiles' work is the list
 // length (ranges) or a per-tile estimate (work); exactly one of the two is given.  Ranges
