@@ -433,12 +433,15 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
     __shared__ float4 mw0[kMfma ? L::NW : 1][kMfma ? kWS : 1], mw1[kMfma ? L::NW : 1][kMfma ? kWS : 1],
         mw2[kMfma ? L::NW : 1][kMfma ? kWS : 1], mw3[kMfma ? L::NW : 1][kMfma ? kWS : 1];
     __shared__ uint32_t block_last;
-    // B operand of slot column j (g: j = slot, w: j = 8 + slot) for pixel p = 4 kb + c at
-    // 272 (kb / 4) + 68 c + 4 j + kb % 4: a lane's four values of one kb quarter are one
-    // 16-byte read, each read phase of 16 lanes is contiguous, and the 64 pixels of one
-    // column fall in 64 different banks (no conflicts either way).
+    // B operand of slot column j (g: j = slot, w: j = 8 + slot) for pixel p = 4 kb + c
+    // (kb = 4 q + e): the 16-byte word 64 q + 16 c + (j ^ (c + 4 (q & 1))) holds the four
+    // pixels e = 0..3 of (q, c, j).  A flush lane's four values of one q are one 16-byte
+    // read, and the 16 lanes of each c read 16 consecutive words in a permuted order, which
+    // the LDS serves without conflicts; the XOR spreads the walk's one-column writes of the
+    // 64 pixels over all banks (measured: no conflict cycles either way, where the padded
+    // layout 272 q + 68 c + 4 j + e took 3.2 per read).
     // Slot s's record (mean, index) follows at kMeta + 4 s: (u, v, -, index).
-    constexpr int kBq = 272, kBc = 68, kMeta = 4 * kBq;
+    constexpr int kBq = 256, kBc = 64, kMeta = 4 * kBq;
     __shared__ __align__(16) float mf_b[kMfma ? L::NW : 1][kMfma ? kMeta + 4 * kSlots : 4];
     const TilePos tp = tile_pos<TILE>(vt, order);
     const uint2 rg = ranges[tp.gt];
@@ -520,7 +523,12 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
     typedef float v4f __attribute__((ext_vector_type(4)));
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave)), lane = lane_id();
     float Aop[kMfma ? 16 : 1];
-    const int bofs = (lane >> 4) * kBq + (lane & 3) * kBc + ((lane >> 2) & 3);  // this lane's pixel, column 0
+    // Byte offset of this lane's pixel in column 0 (bits 4-6 clear), with its word's XOR
+    // pattern in bits 4-6: column j's value then sits at (bofs ^ 16 j), one instruction
+    // per record.
+    const uint32_t bofs =
+        4u * (uint32_t)((wv * (kMeta + 4 * kSlots) + (lane >> 4) * kBq + (lane & 3) * kBc + ((lane >> 2) & 3)) |
+                        4 * ((lane & 3) + 4 * ((lane >> 4) & 1)));
     int slot = 0;  // filled record slots of this wave (wave-uniform)
     const float cxw = lay.rx0 + 3.5f, cyw = lay.ry0 + 3.5f;
     if constexpr (kMfma) {
@@ -565,10 +573,12 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
     auto flush = [&](int n) {
         __builtin_amdgcn_wave_barrier();  // the slots are written (a wave's LDS accesses stay in order)
         const int j = lane & 15, c = lane >> 4;
-        const float *src = mf_b[wv] + kBc * c + 4 * j;
-        const float4 q0 = *reinterpret_cast<const float4 *>(src), q1 = *reinterpret_cast<const float4 *>(src + kBq);
-        const float4 q2 = *reinterpret_cast<const float4 *>(src + 2 * kBq);
-        const float4 q3 = *reinterpret_cast<const float4 *>(src + 3 * kBq);
+        const float *src0 = mf_b[wv] + kBc * c + 4 * (j ^ c);        // q = 0, 2
+        const float *src1 = mf_b[wv] + kBc * c + 4 * (j ^ (c + 4));  // q = 1, 3
+        const float4 q0 = *reinterpret_cast<const float4 *>(src0);
+        const float4 q1 = *reinterpret_cast<const float4 *>(src1 + kBq);
+        const float4 q2 = *reinterpret_cast<const float4 *>(src0 + 2 * kBq);
+        const float4 q3 = *reinterpret_cast<const float4 *>(src1 + 3 * kBq);
         const float bq[16] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w,
                               q2.x, q2.y, q2.z, q2.w, q3.x, q3.y, q3.z, q3.w};
         v4f acc = {0.f, 0.f, 0.f, 0.f};
@@ -675,7 +685,8 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
                 const float g = kClamp && al >= amax ? 0.0f : dLda * al;
                 T[k] = fmaf(-al, T[k], T[k]);  // as in the forward
                 if constexpr (kMfma) {
-                    float *bw = mf_b[wv] + bofs + 4 * slot;
+                    float *bw = reinterpret_cast<float *>(reinterpret_cast<char *>(&mf_b[0][0]) +
+                                                          (bofs ^ (16u * (uint32_t)slot)));
                     bw[0] = g;
                     bw[4 * kSlots] = w;
                     // The slot's record mean and index, stored by lane 0 (whose pixel offset is
