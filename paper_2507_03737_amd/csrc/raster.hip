@@ -76,8 +76,10 @@ __device__ inline TilePos tile_pos(const ViewTable &vt, const uint32_t *order) {
 //   s0 = (u, v, a, b), s1 = (c, -e_min, opacity, record index), s2 = (colour, z), s3 = point
 // with (a, b, c) the factored conic of the record.
 // The acceptance test reads s0 and s1 only.
+// With a list position pos, it replaces the point's unused fourth component (one 16-byte
+// write instead of that write and a 4-byte one at a 16-byte stride, a 4-way conflict).
 __device__ inline void stage(const float4 *__restrict__ rec, uint32_t r, float x0, float y0, float alpha_min,
-                             float4 *s0, float4 *s1, float4 *s2, float4 *s3, int q) {
+                             float4 *s0, float4 *s1, float4 *s2, float4 *s3, int q, const uint32_t *pos = nullptr) {
     const float4 *src = rec + 4 * (int64_t)r;
     const float4 a = src[0], b = src[1], c = src[2], d = src[3];
     const float ul = (a.x - x0) + a.z;
@@ -85,7 +87,7 @@ __device__ inline void stage(const float4 *__restrict__ rec, uint32_t r, float x
     s0[q] = make_float4(ul, vl, b.x, b.y);
     s1[q] = make_float4(b.z, -__log2f(alpha_min / b.w), b.w, __uint_as_float(r));
     s2[q] = c;
-    s3[q] = d;
+    s3[q] = pos ? make_float4(d.x, d.y, d.z, __uint_as_float(*pos)) : d;
 }
 
 // min(alpha_max, a) for a >= 0, as one median instruction (min would first quiet a
@@ -761,8 +763,8 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
                 if (mine && sub >= 0 && sub < kWS) {
                     const uint32_t si = (uint32_t)__popc(mh & ((1u << sub) - 1u));
                     const uint32_t p = pos + (uint32_t)lane;
-                    stage(rec, my_rec, tp.x0, tp.y0, amin, w0, w1, w2, w3, (int)si);
-                    w3[si].w = __uint_as_float(p - rg.x);
+                    const uint32_t rel = p - rg.x;
+                    stage(rec, my_rec, tp.x0, tp.y0, amin, w0, w1, w2, w3, (int)si, &rel);
                 }
                 __builtin_amdgcn_wave_barrier();  // staged (a wave's LDS accesses stay in order)
                 const int n_st = __popc(mh);
