@@ -160,8 +160,12 @@ __device__ inline uint64_t batch_mask(const float4 *s0, const float4 *s1, int c,
                                       float y0, float y1) {
     const int n = cnt - c;
     if (!CULL) return n >= kWave ? ~0ull : ((1ull << n) - 1ull);
-    const int q = c + lane_id();
-    return ballot(q < cnt && meets_rect(s0[q], s1[q], x0, x1, y0, y1));
+    const int q = c + lane_id();  // below NT: c < cnt <= NT, both multiples of 64 apart from cnt
+    const float4 a = s0[q], b = s1[q];
+    // Whole 16-byte reads of consecutive records: the parts the test uses, read alone at a
+    // 16-byte stride, would meet bank conflicts.
+    asm volatile("" ::"v"(a.x), "v"(a.y), "v"(a.z), "v"(a.w), "v"(b.x), "v"(b.y), "v"(b.z), "v"(b.w));
+    return ballot(q < cnt && meets_rect(a, b, x0, x1, y0, y1));
 }
 
 // FRAME is the pointmap frame (0 world, 1 camera, 2 from the depth, Eq. 5).  In the
