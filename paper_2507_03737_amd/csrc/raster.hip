@@ -544,8 +544,10 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
         if (V::kColour) { wg[m++] = gC0[0]; wg[m++] = gC1[0]; wg[m++] = gC2[0]; }
         if (V::kDepth) wg[m++] = gD[0];
         if (V::kPoint) { wg[m++] = gX0[0]; wg[m++] = gX1[0]; wg[m++] = gX2[0]; }
+        // Pixel-major at a pitch of 9 words (coprime with the 32 banks): neither these writes
+        // nor the reads below meet bank conflicts.
 #pragma unroll
-        for (int t = 0; t < V::NW; ++t) buf[8 * lane + t] = wg[t];  // pixel-major: the reads below spread over the banks
+        for (int t = 0; t < V::NW; ++t) buf[9 * lane + t] = wg[t];
         __builtin_amdgcn_wave_barrier();
         const int f = lane & 15, c = lane >> 4;
 #pragma unroll
@@ -553,7 +555,7 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
             const int p = 4 * kb + c;
             const float x = (float)(p & 7) - 3.5f, y = (float)(p >> 3) - 3.5f;
             float av = f == 0 ? 1.0f : f == 1 ? x : f == 2 ? y : f == 3 ? x * x : f == 4 ? x * y : y * y;
-            if (f >= 6) av = f < 6 + V::NW ? buf[8 * p + f - 6] : 0.0f;
+            if (f >= 6) av = f < 6 + V::NW ? buf[9 * p + f - 6] : 0.0f;
             Aop[kb] = av;
         }
         __builtin_amdgcn_wave_barrier();  // read before the walk overwrites the buffer
