@@ -278,9 +278,8 @@ k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
                 for (int k = 0; k < PPT; ++k) {
                     const float al = fminf(amax, b.z * __builtin_amdgcn_exp2f(-sq[k]));
                     const float Tn = fmaf(-al, T[k], T[k]);  // T (1 - alpha), rounded once
-                    const bool low = Tn < tmin;
-                    const bool stop = ok[k] && low;
-                    const bool add = ok[k] && !low;
+                    const bool add = ok[k] && !(Tn < tmin);
+                    const bool stop = ok[k] && !add;  // one comparison; the masks combine in scalar code
                     const float w = add ? __fmul_rn(al, T[k]) : 0.0f;
                     C0[k] = fmaf(w, cc.x, C0[k]);
                     C1[k] = fmaf(w, cc.y, C1[k]);
