@@ -514,13 +514,13 @@ hipError_t launch_raster_backward(const ViewTable &vt, const RasterSettings &rs,
                                   const gspm_const_images &up, float *grad2d, bool pose_only,
                                   const uint32_t *order, FrameHeader *hdr, int64_t n_records, hipStream_t s);
 
-// Image-plane gradient rows -> parameter gradients (added into out) and per-block pose
+// Image-plane gradient rows -> parameter gradients (added into out) and per-wave pose
 // partials; every row read as nonzero is cleared, so grad2d is all zero afterwards.
 hipError_t launch_preprocess_backward(const gspm_gaussians &g, const ViewTable &vt, const float *T_cw,
                                       const RasterSettings &rs, float *grad2d,
                                       const gspm_gaussian_grads &out, bool want_pose,
                                       double *pose_partials, hipStream_t s);
-int64_t pose_partial_blocks(int64_t n);
+int64_t pose_partial_blocks(int64_t n);  // pose partials per view (one per wave of the launch)
 hipError_t launch_pose_reduce(const double *pose_partials, int64_t n_blocks, int n_views,
                               float *pose_grad, bool overwrite, hipStream_t s);
 

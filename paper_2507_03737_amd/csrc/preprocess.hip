@@ -5,7 +5,7 @@
 // opacity-aware support box, tile rectangle and depth key.  Backward (one lane per
 // Gaussian, looping over views): chain rule from the image-plane gradients accumulated
 // by the raster backward to means, log-scales, quaternions, opacity logits and colours,
-// plus the per-view se(3) pose contribution (Sec. 3.2.2, Eq. 11) reduced per block.
+// plus the per-view se(3) pose contribution (Sec. 3.2.2, Eq. 11) reduced per wave.
 //
 // This geometry is per Gaussian, not per pixel, so it runs in float64 (MI355X's vector
 // FP64 rate is half its FP32 rate) and rounds once to the float32 record: the mean2D is
@@ -235,23 +235,7 @@ k_count_big(const float4 *__restrict__ rec, ViewTable vt, RasterSettings rs, int
 
 constexpr int kBwdBlock = 256;
 
-// Fixed-order block reduction of 6 values (deterministic for a fixed launch shape); the
-// sums are valid in thread 0.
-__device__ inline void block_sum6(double x[6], double *lds) {
-    const int wid = threadIdx.x / 64;
-#pragma unroll
-    for (int k = 0; k < 6; ++k)
-        for (int off = 32; off > 0; off >>= 1) x[k] += __shfl_xor(x[k], off, 64);
-    if (lane_id() == 0)
-        for (int k = 0; k < 6; ++k) lds[wid * 6 + k] = x[k];
-    __syncthreads();
-    if (threadIdx.x == 0)
-        for (int k = 0; k < 6; ++k) {
-            double t = 0.0;
-            for (int w = 0; w < kBwdBlock / 64; ++w) t += lds[w * 6 + k];
-            x[k] = t;
-        }
-}
+constexpr int kBwdWaves = kBwdBlock / kWave;
 
 __global__ void __launch_bounds__(kBwdBlock)
 k_preprocess_backward(gspm_gaussians G, ViewTable vt, const float *__restrict__ T_cw, RasterSettings rs,
@@ -262,8 +246,7 @@ k_preprocess_backward(gspm_gaussians G, ViewTable vt, const float *__restrict__ 
     // parameter, not one per view), and its parameters stay in cache across the views.
     // The view-independent part of the projection is computed once, and the next view's
     // image-plane gradient row is loaded while this view's is processed.
-    // Pose partials per block and view in FP64.
-    __shared__ double lds[6 * (kBwdBlock / 64)];
+    // Pose partials per wave and view in FP64.
     const int64_t n = G.n;
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double gmu[3] = {0, 0, 0}, gls[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go = 0.0, gc[3] = {0, 0, 0};
@@ -420,11 +403,16 @@ k_preprocess_backward(gspm_gaussians G, ViewTable vt, const float *__restrict__ 
         }
         touched |= any;
         if (want_pose) {
-            // Every thread of the block takes part (uniform branch).
-            block_sum6(pose, lds);
-            if (threadIdx.x == 0)
-                for (int k = 0; k < 6; ++k) pose_part[((int64_t)v * gridDim.x + blockIdx.x) * 6 + k] = pose[k];
-            __syncthreads();  // the sums are read before the next view's reduction reuses lds
+            // The wave's sums in a fixed shuffle order, one partial per wave and view (no
+            // block barrier: at 2 waves per SIMD a barrier per view stalls the block).
+#pragma unroll
+            for (int k = 0; k < 6; ++k)
+                for (int off = 32; off > 0; off >>= 1) pose[k] += __shfl_xor(pose[k], off, kWave);
+            if (lane_id() == 0) {
+                const int64_t gw = (int64_t)blockIdx.x * kBwdWaves + threadIdx.x / kWave;
+                double *dst = pose_part + ((int64_t)v * gridDim.x * kBwdWaves + gw) * 6;
+                for (int k = 0; k < 6; ++k) dst[k] = pose[k];
+            }
         }
     }
     if (g >= n) return;
@@ -559,14 +547,15 @@ hipError_t launch_preprocess(const gspm_gaussians &g, const ViewTable &vt, const
     return hipGetLastError();
 }
 
-int64_t pose_partial_blocks(int64_t n) { return (n + kBwdBlock - 1) / kBwdBlock; }
+static int64_t bwd_blocks(int64_t n) { return (n + kBwdBlock - 1) / kBwdBlock; }
+int64_t pose_partial_blocks(int64_t n) { return bwd_blocks(n) * kBwdWaves; }
 
 hipError_t launch_preprocess_backward(const gspm_gaussians &g, const ViewTable &vt, const float *T_cw,
                                       const RasterSettings &rs, float *grad2d,
                                       const gspm_gaussian_grads &out, bool want_pose,
                                       double *pose_partials, hipStream_t s) {
     if (g.n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_preprocess_backward, dim3((unsigned)pose_partial_blocks(g.n)), dim3(kBwdBlock), 0, s,
+    hipLaunchKernelGGL(k_preprocess_backward, dim3((unsigned)bwd_blocks(g.n)), dim3(kBwdBlock), 0, s,
                        g, vt, T_cw, rs, reinterpret_cast<float4 *>(grad2d), out, want_pose ? 1 : 0,
                        pose_partials);
     return hipGetLastError();
