@@ -240,7 +240,10 @@ k_scan_compact(const uint32_t *__restrict__ counts, const uint32_t *__restrict__
 // blocks on one atomic address, tens of nanoseconds each.)  A wait is still bounded (then
 // the sort is abandoned and the stall flag set) so that a broken ordering assumption or
 // a fault elsewhere cannot leave the kernel spinning.  The tile is staged in LDS in sorted order and
-// written so that consecutive lanes write consecutive addresses within each digit's run.
+// written so that consecutive lanes write consecutive addresses within each digit's run;
+// its keys and then its values pass through one array, so that a block needs about 40 KB
+// of LDS and, at 80 VGPRs, three blocks share a CU (two when both were staged at once:
+// the last of the tiles then ran as a second, mostly empty round of blocks).
 // The key count may be read from device memory; only its ceil(n / 8192) tiles are used.
 
 constexpr int kSortBlock = 512;
@@ -275,10 +278,18 @@ __global__ void __launch_bounds__(kSortBlock)
 k_radix_hist(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ n_dev, int64_t n_max, int passes,
              uint32_t *__restrict__ bhist, uint32_t *__restrict__ tcount, int64_t tstride) {
     constexpr int R = 1 << DB;
-    __shared__ uint32_t h[kSortMaxPasses * R];
+    constexpr int kCopies = 4;
+    __shared__ uint32_t h[kSortMaxPasses * R * kCopies];
     __shared__ uint32_t tc[kSortWaves][R];  // this tile's first-pass digits, one row per wave
     const int wid = threadIdx.x / kWave, lane = lane_id();
-    for (int i = threadIdx.x; i < passes * R; i += kSortBlock) h[i] = 0u;
+    // The later passes' counters. The high digits of 32-bit depth keys (exponent and top
+    // mantissa bits) take few values, so most lanes of a wave add to the same counter and the
+    // LDS atomics serialise: with more than two passes each counter has kCopies interleaved
+    // copies, lane l adding to copy l % kCopies. Tile ids' high digits are spread, and there
+    // a single copy is cheaper.
+    const int cshift = passes > 2 ? 2 : 0;
+    const int cmask = (1 << cshift) - 1;
+    for (int i = threadIdx.x; i < (passes * R) << cshift; i += kSortBlock) h[i] = 0u;
     const int64_t n = sort_count(n_dev, n_max);
     const int64_t tiles = sort_active_tiles(n);
     for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
@@ -292,7 +303,8 @@ k_radix_hist(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ n_d
         for (int st = 0; st < kSortSteps; ++st) {
             if (b + st * kSortBlock >= n) continue;
             atomicAdd(&tc[wid][k[st] & (R - 1)], 1u);
-            for (int p = 1; p < passes; ++p) atomicAdd(&h[p * R + ((k[st] >> (p * DB)) & (R - 1))], 1u);
+            for (int p = 1; p < passes; ++p)
+                atomicAdd(&h[((p * R + ((k[st] >> (p * DB)) & (R - 1))) << cshift) + (lane & cmask)], 1u);
         }
         __syncthreads();
         for (int d = threadIdx.x; d < R; d += kSortBlock) {
@@ -307,7 +319,11 @@ k_radix_hist(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ n_d
     // This block's counts of the later passes' digits (summed over the blocks by
     // k_radix_tile_prefix: plain stores, where atomics from every block on the same few
     // hundred words would queue behind each other).
-    for (int i = R + threadIdx.x; i < passes * R; i += kSortBlock) bhist[(int64_t)blockIdx.x * passes * R + i] = h[i];
+    for (int i = R + threadIdx.x; i < passes * R; i += kSortBlock) {
+        uint32_t t = 0u;
+        for (int c = 0; c <= cmask; ++c) t += h[(i << cshift) + c];
+        bhist[(int64_t)blockIdx.x * passes * R + i] = t;
+    }
 }
 
 // Exclusive prefix over the tiles of each first-pass digit's per-tile counts, in place:
@@ -369,7 +385,7 @@ __device__ inline void store_status(uint32_t *p, uint32_t v) {
 }
 
 template <int DB>
-__global__ void __launch_bounds__(kSortBlock)
+__global__ void __launch_bounds__(kSortBlock) __attribute__((amdgpu_waves_per_eu(6)))  // 3 blocks per CU
 k_radix_pass(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
              uint32_t *__restrict__ vout, const uint32_t *__restrict__ n_dev, int64_t n_max, int shift,
              const uint32_t *__restrict__ ghist, uint32_t *__restrict__ status,
@@ -381,8 +397,7 @@ k_radix_pass(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
     __shared__ uint32_t dcount[R];
     __shared__ uint32_t gbase[R];
     __shared__ uint32_t scan_lds[kSortWaves];
-    __shared__ uint32_t lk[kSortTile];
-    __shared__ uint32_t lv[kSortTile];
+    __shared__ uint32_t lk[kSortTile];  // the tile in sorted order: keys, then values
     const int wid = threadIdx.x / kWave, lane = lane_id();
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int64_t n = sort_count(n_dev, n_max);
@@ -397,12 +412,11 @@ k_radix_pass(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
     const int64_t tile_begin = tile * kSortTile;
     const int64_t b = tile_begin + (int64_t)wid * (kSortTile / kSortWaves);
     uint32_t key[kSortSteps], val[kSortSteps], rank[kSortSteps];
-    // All loads first, so that the tile is in flight at once rather than one step at a time.
+    // All key loads first, so that the tile is in flight at once rather than one step at a time.
 #pragma unroll
     for (int st = 0; st < kSortSteps; ++st) {
         const int64_t i = b + st * kWave + lane;
         key[st] = i < n ? kin[i] : 0u;
-        val[st] = i < n ? vin[i] : 0u;
     }
 #pragma unroll
     for (int st = 0; st < kSortSteps; ++st) {
@@ -444,9 +458,27 @@ k_radix_pass(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
     const uint32_t gpre = block_exclusive_scan<kSortWaves>(gcount, scan_lds, all);
     const uint32_t pre = block_exclusive_scan<kSortWaves>(tot, scan_lds, all);
     if (threadIdx.x < R) {
+        dstart[threadIdx.x] = pre;
+        dcount[threadIdx.x] = tot;
+    }
+    __syncthreads();
+    // The keys go to their place in the sorted tile now (it depends on this tile alone), and
+    // the values are loaded: fewer registers are live through the look-back, and the loads'
+    // latency passes during it. rank[] becomes the position in the sorted tile.
+#pragma unroll
+    for (int st = 0; st < kSortSteps; ++st) {
+        if (rank[st] == 0xffffffffu) continue;
+        const uint32_t d = (key[st] >> shift) & (R - 1);
+        rank[st] += dstart[d] + wcnt[wid][d];
+        lk[rank[st]] = key[st];
+    }
+#pragma unroll
+    for (int st = 0; st < kSortSteps; ++st) {
+        const int64_t i = b + st * kWave + lane;
+        val[st] = i < n ? vin[i] : 0u;
+    }
+    if (threadIdx.x < R) {
         const int d = threadIdx.x;
-        dstart[d] = pre;
-        dcount[d] = tot;
         uint32_t prefix = 0;
         if (tprefix) {
             prefix = tpre;
@@ -488,33 +520,44 @@ k_radix_pass(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
         gbase[d] = gpre + prefix;
     }
     __syncthreads();
+    // The sorted keys are read back (key[] now holds them in the tile's sorted order) before
+    // the values take their place in the same array: half the LDS of staging both at once,
+    // so that three blocks fit on a CU.
+    const int cnt = (int)(n - tile_begin < kSortTile ? n - tile_begin : kSortTile);
 #pragma unroll
     for (int st = 0; st < kSortSteps; ++st) {
-        if (rank[st] == 0xffffffffu) continue;
-        const uint32_t d = (key[st] >> shift) & (R - 1);
-        const uint32_t lp = dstart[d] + wcnt[wid][d] + rank[st];
-        lk[lp] = key[st];
-        lv[lp] = val[st];
-    }
-    __syncthreads();
-    const int cnt = (int)(n - tile_begin < kSortTile ? n - tile_begin : kSortTile);
-    for (int j = threadIdx.x; j < cnt; j += kSortBlock) {
+        const int j = threadIdx.x + st * kSortBlock;
+        if (j >= cnt) continue;
         const uint32_t k = lk[j];
-        const uint32_t d = (k >> shift) & (R - 1);
-        const uint32_t pos = gbase[d] + ((uint32_t)j - dstart[d]);
-        if (kout) kout[pos] = k;  // the last pass may drop the keys: only the values are used
-        vout[pos] = lv[j];
+        key[st] = k;
         if (ranges) {
             // Final pass over tile ids: the tile is sorted in LDS, so the output neighbours of
             // an element inside its digit's run are its LDS neighbours.  At the ends of the
             // run they belong to other blocks: the first and last element then take the
             // extreme position by atomics (the true start or end, wherever it lies, wins).
+            const uint32_t d = (k >> shift) & (R - 1);
+            const uint32_t pos = gbase[d] + ((uint32_t)j - dstart[d]);
             const uint32_t first = dstart[d], last = dstart[d] + dcount[d] - 1u;
             if ((uint32_t)j == first) atomicMin(&ranges[k].x, pos);
             else if (lk[j - 1] != k) ranges[k].x = pos;
             if ((uint32_t)j == last) atomicMax(&ranges[k].y, pos + 1u);
             else if (lk[j + 1] != k) ranges[k].y = pos + 1u;
         }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int st = 0; st < kSortSteps; ++st)
+        if (rank[st] != 0xffffffffu) lk[rank[st]] = val[st];
+    __syncthreads();
+#pragma unroll
+    for (int st = 0; st < kSortSteps; ++st) {
+        const int j = threadIdx.x + st * kSortBlock;
+        if (j >= cnt) continue;
+        const uint32_t k = key[st];
+        const uint32_t d = (k >> shift) & (R - 1);
+        const uint32_t pos = gbase[d] + ((uint32_t)j - dstart[d]);
+        if (kout) kout[pos] = k;  // the last pass may drop the keys: only the values are used
+        vout[pos] = lk[j];
     }
 }
 
