@@ -422,13 +422,18 @@ k_radix_pass(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
     for (int st = 0; st < kSortSteps; ++st) {
         const bool act = b + st * kWave + lane < n;
         const uint32_t d = (key[st] >> shift) & (R - 1);
-        uint64_t m = ballot(act);
+        const uint64_t a = ballot(act);
+        uint32_t mlo = (uint32_t)a, mhi = (uint32_t)(a >> 32);
 #pragma unroll
         for (int bit = 0; bit < DB; ++bit) {
-            const bool set = (d >> bit) & 1u;
-            const uint64_t bb = ballot(set);
-            m &= set ? bb : ~bb;
+            // t is all ones where the bit is set: the lanes agreeing with this one are
+            // ballot ^ ~t.
+            const uint32_t t = (uint32_t)(((int32_t)(d << (31 - bit))) >> 31);
+            const uint64_t bb = ballot(t != 0u);
+            mlo &= ~((uint32_t)bb ^ t);
+            mhi &= ~((uint32_t)(bb >> 32) ^ t);
         }
+        const uint64_t m = ((uint64_t)mhi << 32) | mlo;
         rank[st] = 0xffffffffu;
         if (act) {
             const uint32_t r = (uint32_t)__popcll(m & lt);
