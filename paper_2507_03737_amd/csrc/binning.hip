@@ -282,14 +282,11 @@ k_radix_hist(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ n_d
     __shared__ uint32_t h[kSortMaxPasses * R * kCopies];
     __shared__ uint32_t tc[kSortWaves][R];  // this tile's first-pass digits, one row per wave
     const int wid = threadIdx.x / kWave, lane = lane_id();
-    // The later passes' counters. The high digits of 32-bit depth keys (exponent and top
-    // mantissa bits) take few values, so most lanes of a wave add to the same counter and the
-    // LDS atomics serialise: with more than two passes each counter has kCopies interleaved
-    // copies, lane l adding to copy l % kCopies. Tile ids' high digits are spread, and there
-    // a single copy is cheaper.
-    const int cshift = passes > 2 ? 2 : 0;
-    const int cmask = (1 << cshift) - 1;
-    for (int i = threadIdx.x; i < (passes * R) << cshift; i += kSortBlock) h[i] = 0u;
+    // The later passes' counters, kCopies interleaved copies of each, lane l adding to copy
+    // l % kCopies. High digits take few values within a wave (the exponent and top mantissa
+    // bits of depths; the tile row of one Gaussian's tiles), so most lanes would add to one
+    // counter and the LDS atomics would serialise.
+    for (int i = threadIdx.x; i < passes * R * kCopies; i += kSortBlock) h[i] = 0u;
     const int64_t n = sort_count(n_dev, n_max);
     const int64_t tiles = sort_active_tiles(n);
     for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
@@ -304,7 +301,7 @@ k_radix_hist(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ n_d
             if (b + st * kSortBlock >= n) continue;
             atomicAdd(&tc[wid][k[st] & (R - 1)], 1u);
             for (int p = 1; p < passes; ++p)
-                atomicAdd(&h[((p * R + ((k[st] >> (p * DB)) & (R - 1))) << cshift) + (lane & cmask)], 1u);
+                atomicAdd(&h[(p * R + ((k[st] >> (p * DB)) & (R - 1))) * kCopies + (lane & (kCopies - 1))], 1u);
         }
         __syncthreads();
         for (int d = threadIdx.x; d < R; d += kSortBlock) {
@@ -321,7 +318,8 @@ k_radix_hist(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ n_d
     // hundred words would queue behind each other).
     for (int i = R + threadIdx.x; i < passes * R; i += kSortBlock) {
         uint32_t t = 0u;
-        for (int c = 0; c <= cmask; ++c) t += h[(i << cshift) + c];
+#pragma unroll
+        for (int c = 0; c < kCopies; ++c) t += h[i * kCopies + c];
         bhist[(int64_t)blockIdx.x * passes * R + i] = t;
     }
 }

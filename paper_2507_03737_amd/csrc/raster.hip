@@ -135,20 +135,26 @@ __device__ inline float edge_max(float P, float Q, float R, float d, float lo, f
 }
 
 // Whether a staged record (s0 = (u, v, a, b), s1 = (c, -e_min, ...)) can reach its threshold
-// at a pixel centre of the rectangle [x0, x1] x [y0, y1].  The exponent is concave, so its
-// maximum over the rectangle is 0 when the mean lies inside and otherwise lies on an edge,
-// where it is a one-dimensional concave quadratic.  The margin exceeds the float rounding
-// of this evaluation plus that of the per-pixel evaluation (a few units in the last place
-// of the sum of the terms' magnitudes), so the test never drops a record that a pixel
-// accepts; it may keep a few that none does.
+// at a pixel centre of the rectangle [x0, x1] x [y0, y1].  The exponent is concave with its
+// maximum 0 at the mean, so it increases along any segment towards the mean: its maximum
+// over the rectangle lies on an edge that faces the mean (a point elsewhere could move
+// towards the mean inside the rectangle), or at the mean if that lies inside.  Both are
+// covered by two segments: the column x = clamp(u, x0, x1) over [y0, y1] and the row
+// y = clamp(v, y0, y1) over [x0, x1], each a one-dimensional concave quadratic (when the
+// mean's x lies in [x0, x1], the column passes through the rectangle and the facing row
+// holds the maximum; likewise for y).  The margin exceeds the float rounding of this
+// evaluation plus that of the per-pixel evaluation (a few units in the last place of the
+// sum of the terms' magnitudes), so the test never drops a record that a pixel accepts; it
+// may keep a few that none does.
 __device__ inline bool meets_rect(const float4 a, const float4 b, float x0, float x1, float y0, float y1) {
     // Expanded coefficients e = A dx^2 + B dx dy + C dy^2 of the factored conic (their
     // rounding is far inside the margin below).
     const float A = -a.z * a.z, B = -2.0f * a.z * a.w, C = -fmaf(a.w, a.w, b.x * b.x);
     const float ax = x0 - a.x, bx = x1 - a.x, ay = y0 - a.y, by = y1 - a.y;
-    if (ax <= 0.f && bx >= 0.f && ay <= 0.f && by >= 0.f) return -b.y <= 0x1p-10f;
-    float m = fmaxf(edge_max(A, B, C, ax, ay, by), edge_max(A, B, C, bx, ay, by));
-    m = fmaxf(m, fmaxf(edge_max(C, B, A, ay, ax, bx), edge_max(C, B, A, by, ax, bx)));
+    // Offsets of the column and the row from the mean: 0 where the mean's coordinate lies
+    // inside the range, else that of the nearer edge (ax <= bx, ay <= by).
+    const float cx = __builtin_amdgcn_fmed3f(0.0f, ax, bx), cy = __builtin_amdgcn_fmed3f(0.0f, ay, by);
+    const float m = fmaxf(edge_max(A, B, C, cx, ay, by), edge_max(C, B, A, cy, ax, bx));
     const float DX = fmaxf(fabsf(ax), fabsf(bx)), DY = fmaxf(fabsf(ay), fabsf(by));
     const float S = fmaf(fabsf(A) * DX, DX, fmaf(fabsf(B) * DX, DY, fabsf(C) * DY * DY));
     return m >= -b.y - fmaf(0x1p-16f, S, 0x1p-10f);
