@@ -759,13 +759,27 @@ k_raster_bwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
         // in the staged point's fourth component.
         float4 *w0 = mw0[wv], *w1 = mw1[wv], *w2 = mw2[wv], *w3 = mw3[wv];
         const uint32_t wend = rg.x + wave_last;
+        // The next 64 positions' bits and record indices are loaded one step ahead, so that
+        // a step waits on one global read (its records) rather than three dependent ones.
+        uint64_t m_next = 0ull;
+        uint32_t rec_next = 0u;
+        if (rg.x < wend) {
+            m_next = use_bits ? wave_bits(rg.x) : ~0ull;  // without bits every entry is tested
+            rec_next = rg.x + (uint32_t)lane < wend ? vals[rg.x + (uint32_t)lane] : 0u;
+        }
         for (uint32_t pos = rg.x; pos < wend; pos += kWave) {
-            uint64_t m = use_bits ? wave_bits(pos) : ~0ull;  // without bits every entry is tested
+            uint64_t m = m_next;
+            const uint32_t rec_here = rec_next;
+            const uint32_t np = pos + (uint32_t)kWave;
+            if (np < wend) {
+                m_next = use_bits ? wave_bits(np) : ~0ull;
+                rec_next = np + (uint32_t)lane < wend ? vals[np + (uint32_t)lane] : 0u;
+            }
             const uint32_t lim = wend - pos;
             if (lim < (uint32_t)kWave) m &= (1ull << lim) - 1ull;
-            // Lane L reads the record index of position pos + L (if marked) for the whole word.
+            // Lane L holds the record index of position pos + L.
             const bool mine = (m >> lane) & 1ull;
-            const uint32_t my_rec = mine ? vals[pos + (uint32_t)lane] : 0u;
+            const uint32_t my_rec = rec_here;
 #pragma unroll
             for (int h = 0; h < kWave / kWS; ++h) {
                 const uint32_t mh = (uint32_t)((m >> (kWS * h)) & kWSMask);
