@@ -253,8 +253,13 @@ k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
             while (m != 0ull) {
                 const int q = c + (int)__builtin_ctzll(m);
                 m &= m - 1ull;
+                // All four words of the entry at once, before the test: the colour and point
+                // reads share the address register, and their latency passes during the test
+                // (most walked entries are composited).
                 const float4 a = s0[q];
                 const float4 b = s1[q];
+                const float4 cc = s2[q];
+                const float4 d = s3[q];
                 // One 16-byte read now rather than a second, split read after the test.
                 asm volatile("" ::"v"(b.z), "v"(b.w));
                 const float dx = px - a.x;
@@ -273,8 +278,6 @@ k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
                 // The backward walks these entries (a superset of those it finds a valid
                 // pixel for; it skips the rest), scalar work only.
                 composited |= 1ull << (q - c);
-                const float4 cc = s2[q];
-                const float4 d = s3[q];
                 // Whole 16-byte reads: a 12-byte read of one address for the whole wave keeps
                 // the LDS busy twice as long as a 16-byte one.
                 asm volatile("" ::"v"(cc.w), "v"(d.w));
