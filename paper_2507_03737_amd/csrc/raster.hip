@@ -241,9 +241,14 @@ k_raster_fwd(ViewTable vt, RasterSettings rs, const uint2 *__restrict__ ranges, 
     };
     if (wave_live) live_rect();
     uint32_t n_walked = 0u, n_accepted = 0u;  // COUNT: this wave's walked and accepted entries
+    // The next batch's record indices are loaded one batch ahead, so staging waits on one
+    // global read (the record) rather than two dependent ones.
+    uint32_t vnext = rg.x + threadIdx.x < rg.y ? vals[rg.x + threadIdx.x] : 0u;
     for (uint32_t base = rg.x; base < rg.y; base += NT) {
         const uint32_t kk = base + threadIdx.x;
-        if (kk < rg.y) stage(rec, vals[kk], tp.x0, tp.y0, amin, s0, s1, s2, s3, threadIdx.x);
+        const uint32_t vcur = vnext;
+        if (kk + NT < rg.y) vnext = vals[kk + NT];
+        if (kk < rg.y) stage(rec, vcur, tp.x0, tp.y0, amin, s0, s1, s2, s3, threadIdx.x);
         __syncthreads();
         const int cnt = (int)min((uint32_t)NT, rg.y - base);
         for (int c = 0; c < cnt && wave_live; c += kWave) {
